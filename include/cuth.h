@@ -1,0 +1,201 @@
+/*
+ * cuth.h - C ABI of the MI355X (gfx950) layered-stencil thermal solver.
+ *
+ * The library solves the symmetric positive definite 7-point finite-volume
+ * system of a layered 3D-IC grid (paper Section 3.2):
+ *
+ *   steady:     sum_i g_{0,i}(T_0 - T_i) + h S_0 T_0 = p_0 V_0 + h S_0 T_amb
+ *               (eq. "steady-state"), i.e. G T = P;
+ *   transient:  C_0 V_0 (T_{0,n+1} - T_{0,n}) / dt + sum_i g_{0,i}(T_{0,n+1} - T_{i,n+1})
+ *               + h S_0 T_{0,n+1} = p_{0,n+1} V_0 + h S_0 T_amb
+ *               (eq. "transient", backward Euler), i.e. (C/dt + G) T_{n+1} = P + (C/dt) T_n;
+ *
+ * with preconditioned conjugate gradient (Algorithm 1), the Chebyshev polynomial
+ * preconditioner (Section 4.3, "Chebyshev Polynomial Preconditioning") and
+ * spectral bounds from an FP32 Lanczos process with an FP64 eigensolve of the
+ * tridiagonal on the host (Section 4.3 last paragraph, Section 4.4
+ * "component-wise precision in Lanczos").  In mixed precision the inner PCG runs
+ * in FP32 and the residual r = P - G T and the update of T run in FP64
+ * (iterative refinement; the FP64 "true residual" and "hot restart" of
+ * Section 4.4).
+ *
+ * Grid: cell (i, j, l), i along x, j along y, l the layer counted from the
+ * bottom; every vector is contiguous in the flat order  i + nx*(j + ny*l).
+ * Units: lengths m, conductivity W/(m K), heat capacity J/(m^3 K), h W/(m^2 K),
+ * power W per cell (the p_0 V_0 product), temperature K.
+ *
+ * Conventions for every call:
+ *  - Vectors named "device" are caller-owned device memory on the handle's
+ *    device (e.g. torch tensor data pointers), contiguous, of the stated type.
+ *    The library never frees them.  Host arrays are copied before returning.
+ *  - All device work is ordered on the HIP stream given at create time.  Calls
+ *    that return results or statistics synchronise that stream before return.
+ *  - Errors are reported by return code only; cuth_last_error() gives a
+ *    thread-local message for the last non-OK status of the calling thread.
+ *    CUTH_E_INVALID is returned before any device work when host-side
+ *    arguments are bad.
+ *  - A handle may be used by one thread at a time.
+ */
+#ifndef CUTH_H
+#define CUTH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cuth_grid_s *cuth_grid;
+
+typedef enum {
+    CUTH_OK = 0,
+    CUTH_E_INVALID = 1,        /* bad argument (checked before device work)          */
+    CUTH_E_NOMEM = 2,          /* device allocation failed                            */
+    CUTH_E_DEVICE = 3,         /* a HIP call failed                                   */
+    CUTH_E_NOT_CONVERGED = 4,  /* iteration limit hit; best iterate returned          */
+    CUTH_E_BREAKDOWN = 5       /* p^T A p <= 0 or a non-finite value in the iteration */
+} cuth_status;
+
+typedef enum {
+    CUTH_FP64 = 0,   /* every step in FP64                                          */
+    CUTH_MIXED = 1   /* FP32 inner PCG + FP64 residual and refinement update         */
+} cuth_precision;
+
+/* Grid descriptor.  Conductances follow the series (harmonic) half-cell rule:
+ * a lateral face between cells a and b of layer l has
+ *   g = (face area) / (d/(2 k_a) + d/(2 k_b)),  k = k_lat[l] * k_lat_mult[cell];
+ * a vertical face between layers l and l+1 has
+ *   g = dx dy / (dz[l]/(2 k_vert[l]) + dz[l+1]/(2 k_vert[l+1])).
+ * The top layer has a convective conductance h_top*dx*dy to ambient, the bottom
+ * layer h_bottom*dx*dy; the four sides are adiabatic. */
+typedef struct {
+    int32_t nx, ny, nz;          /* cells per axis, each >= 1, nz <= 64               */
+    double dx, dy;               /* lateral cell pitch (m), > 0                       */
+    const double *dz;            /* host [nz] layer thickness (m), > 0                */
+    const double *k_lat;         /* host [nz] lateral conductivity, > 0               */
+    const double *k_vert;        /* host [nz] vertical conductivity, > 0              */
+    const double *k_lat_mult;    /* device [nx*ny*nz] lateral multiplier (> 0, finite)
+                                    or NULL for per-layer-uniform conductivity        */
+    const double *heat_cap;      /* host [nz] volumetric heat capacity (> 0), or NULL
+                                    (then transient calls are invalid)                */
+    double h_top, h_bottom;      /* >= 0; steady solves need h_top + h_bottom > 0     */
+    double t_amb;                /* ambient temperature (K), finite                    */
+} cuth_grid_desc;
+
+typedef struct {
+    int32_t precision;           /* cuth_precision                                     */
+    double tol;                  /* CUTH_MIXED: target relative error of the rise
+                                    T - T_amb (inf-norm), default 1e-8.
+                                    CUTH_FP64: relative residual ||P - G T|| / ||P||,
+                                    default 1e-10.                                     */
+    int32_t cheb_degree;         /* Chebyshev degree k >= 1 (default 30)               */
+    int32_t lanczos_steps;       /* Lanczos steps m, 2..256 (default 30)               */
+    int32_t max_inner;           /* CG iterations per inner solve (default 2000)       */
+    int32_t max_outer;           /* refinement cycles, CUTH_MIXED (default 12)         */
+    int32_t use_initial_guess;   /* 1: T holds the initial guess on entry (cuth_solve) */
+    int32_t check_period;        /* iterations between true-residual checks, 0 = the
+                                    default (20 steady, 5 transient)                   */
+} cuth_options;
+
+typedef struct {
+    int32_t outer_cycles;        /* FP64 residual evaluations that fed an inner solve  */
+    int32_t cg_iters;            /* total CG iterations                                */
+    int64_t stencil_applies;     /* operator applications incl. Chebyshev and checks   */
+    int32_t stop_reason;         /* last inner solve: 1 tol, 2 drift, 3 stagnation,
+                                    4 breakdown, 5 iteration limit                      */
+    int32_t _pad;
+    double rel_residual;         /* final ||b - A theta||_2 / ||b||_2 (FP64)           */
+    double err_est;              /* mixed: last correction ||delta||_inf/||theta||_inf */
+    double setup_ms;             /* coefficient/Lanczos setup inside this call         */
+    double solve_ms;             /* solve phase                                        */
+    double alg_bytes;            /* algorithmic HBM bytes of the solve phase           */
+    double lambda_min, lambda_max; /* spectral bounds used by the preconditioner       */
+} cuth_stats;
+
+/* Fill *o with the defaults listed above. */
+void cuth_default_options(cuth_options *o);
+
+/* Create a handle for one grid on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL = the default stream).  Builds the face conductances on the
+ * device (FP64 and FP32 copies when k_lat_mult is given).  Validates the
+ * descriptor on the host; the multiplier field is checked on the device
+ * (CUTH_E_INVALID if any entry is <= 0 or not finite). */
+cuth_status cuth_grid_create(const cuth_grid_desc *desc, void *hip_stream, cuth_grid *out);
+
+/* Release every allocation of the handle (NULL is a no-op). */
+void cuth_grid_destroy(cuth_grid g);
+
+/* Steady solve G T = P (paper Section 3.2 eq. "steady-state"; PCG of
+ * Algorithm 1 with the Chebyshev preconditioner).  P: device double [N] W per
+ * cell; T: device double [N] K, output (input too if use_initial_guess).
+ * opt/stats may be NULL (defaults / not reported).  CUTH_E_NOT_CONVERGED and
+ * CUTH_E_BREAKDOWN leave the best iterate in T. */
+cuth_status cuth_solve(cuth_grid g, const double *P, double *T,
+                       const cuth_options *opt, cuth_stats *stats);
+
+/* One backward-Euler step (eq. "transient"): solves
+ * (C/dt + G) T_next = P_next + (C/dt) T_n, warm-started from T_n.  Spectral
+ * bounds are computed once per distinct dt and cached in the handle.  T_next
+ * may alias T_n.  dt > 0; the handle needs heat_cap. */
+cuth_status cuth_transient_step(cuth_grid g, double dt, const double *P_next,
+                                const double *T_n, double *T_next,
+                                const cuth_options *opt, cuth_stats *stats);
+
+/* Solve nsys independent steady systems, each with nrhs right-hand sides,
+ * advancing all of them together.  P[s] / T[s]: device double [nrhs * N_s]
+ * (right-hand side q at offset q*N_s).  stats: NULL or [nsys*nrhs].
+ * All grids must live on the same device; the first grid's stream is used. */
+cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
+                             const double *const *P, double *const *T,
+                             const cuth_options *opt, cuth_stats *stats);
+
+/* Adjoint of the steady solve.  Given the forward solution T (device double
+ * [N]) and dL/dT (device double [N]), solves G lambda = dL/dT (G = G^T) and
+ * returns dL/dP = lambda (device double [N], W^-1 per cell) and the
+ * conductivity gradients (device double [2*nz]):
+ *   dL_dk[l]      = dL/dk_lat[l]  = -(1/k_lat[l]) sum over lateral faces f of
+ *                   layer l of g_f (lambda_a - lambda_b)(theta_a - theta_b);
+ *   dL_dk[nz + l] = dL/dk_vert[l] = -sum over vertical faces touching layer l of
+ *                   (dg_f/dk_vert[l]) (lambda_a - lambda_b)(theta_a - theta_b),
+ *                   dg/dk_vert[l] = g^2 dz[l] / (2 k_vert[l]^2 dx dy);
+ * theta = T - T_amb.  When k_lat[l] == k_vert[l] the gradient with respect to a
+ * layer's conductivity is dL_dk[l] + dL_dk[nz + l]. */
+cuth_status cuth_adjoint(cuth_grid g, const double *T, const double *dL_dT,
+                         double *dL_dP, double *dL_dk,
+                         const cuth_options *opt, cuth_stats *stats);
+
+/* Thread-local message of the last non-OK status ("" if none). */
+const char *cuth_last_error(void);
+
+/* ---- step-level entry points (each runs one step of the solve path) ---- */
+
+/* y = A x for the steady (dt == 0) or transient (dt > 0) operator.
+ * precision CUTH_FP64: x, y device double [N]; CUTH_MIXED: the FP32 operator,
+ * x, y device float [N].  Paper Algorithm 2 computes the same product. */
+cuth_status cuth_apply(cuth_grid g, double dt, int32_t precision, const void *x, void *y);
+
+/* r = b - A (T - t_amb) in FP64 (the true residual of Section 4.4).
+ * b, T, r: device double [N]. */
+cuth_status cuth_residual(cuth_grid g, double dt, const double *b, const double *T, double *r);
+
+/* z = q(A) r: one application of the Chebyshev polynomial preconditioner of
+ * degree `degree` on [lmin, lmax] (Section 4.3).  precision selects FP64
+ * (double vectors) or FP32 (float vectors, FP32 operator). */
+cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, double lmin,
+                               double lmax, int32_t degree, const void *r, void *z);
+
+/* FP32 Lanczos with `steps` steps on the FP32 operator, start vector v0
+ * (device float [N], or NULL for the library's own counter-based start vector),
+ * followed by the FP64 host eigensolve of the tridiagonal.  alpha (host
+ * [steps]) and beta (host [steps-1]) receive the tridiagonal (either may be
+ * NULL); ritz_min/ritz_max its extreme eigenvalues; lmin/lmax the bounds the
+ * solver uses: lmin = ritz_min, lmax = min(Gershgorin bound, 1.05 ritz_max). */
+cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t steps, const float *v0,
+                                 double *alpha, double *beta, double *ritz_min,
+                                 double *ritz_max, double *lmin, double *lmax);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTH_H */
