@@ -1,0 +1,240 @@
+"""GPU parity: every step of the solve path through the C ABI against the CPU oracle.
+
+Tolerances ("Parity bar"):
+* FP64 operator / residual: |gpu - ref| <= 1e-14 * (|A| |x|)_i element-wise
+  (a 7-term sum in a different order differs by a few ulps of the row scale);
+* FP32 operator: <= 2e-6 * (|A| |x|)_i (inputs rounded to FP32, 7 terms);
+* FP64 Chebyshev application: <= 1e-10 * ||z||_inf (29 sweeps of rounding
+  amplified by the polynomial's norm);
+* solves: plain FP64 <= 1e-10 and mixed <= 1e-8 rise-relative inf-norm error.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle import assembly, cpu_cg, direct, krylov, transient
+from tests.gpu_helpers import dev, grid_of, ragged_stack, rise_err, say, t32, t64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+
+
+CASES = {
+    "ragged_mult": lambda: ragged_stack(70, 9, mult=True),
+    "ragged_uniform": lambda: ragged_stack(131, 6, mult=False),
+    "column": lambda: ragged_stack(1, 1, mult=False),
+    "row": lambda: ragged_stack(67, 1, mult=True),
+    "c0": lambda: w.config0()[0],
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("dt", [None, 1e-4])
+def test_apply_matches_csr(case, dt):
+    say(f"apply {case} dt={dt}")
+    st = CASES[case]()
+    A = assembly.assemble(st, dt=dt)
+    Aabs = abs(A)
+    g = grid_of(st)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, st.n) + 2.0
+    y = g.apply(t64(x), dt=dt or 0.0).cpu().numpy()
+    ref = A @ x
+    scale = Aabs @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+    x32 = x.astype(np.float32)
+    y32 = g.apply(t32(x32), dt=dt or 0.0).cpu().numpy().astype(np.float64)
+    ref32 = A @ x32.astype(np.float64)
+    assert np.all(np.abs(y32 - ref32) <= 2e-6 * (Aabs @ np.abs(x32.astype(np.float64))))
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["ragged_mult", "c0"])
+def test_residual_matches_oracle(case):
+    say(f"residual {case}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    rng = np.random.default_rng(4)
+    th = rng.uniform(0, 50, st.n)
+    b = rng.uniform(0, 1e-3, st.n)
+    r = g.residual(t64(b), t64(st.t_amb + th)).cpu().numpy()
+    ref = b - A @ th
+    scale = np.abs(b) + abs(A) @ np.abs(th)
+    assert np.all(np.abs(r - ref) <= 2e-14 * scale)
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["ragged_mult", "ragged_uniform", "c0"])
+@pytest.mark.parametrize("degree", [1, 2, 3, 30])
+def test_chebyshev_matches_oracle(case, degree):
+    say(f"chebyshev {case} k={degree}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    lmin, lmax = krylov.spectral_bounds(A, w.lanczos_start(st.n))
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(st.n)
+    ref = krylov.chebyshev_precondition(lambda v: A @ v, r, lmin, lmax, degree)
+    z = g.precond_apply(t64(r), lmin, lmax, degree).cpu().numpy()
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+    # FP32: same polynomial in single precision
+    z32 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
+    assert np.abs(z32 - ref).max() <= 2e-3 * np.abs(ref).max()
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["c0", "ragged_mult"])
+def test_lanczos_matches_oracle(case):
+    say(f"lanczos {case}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    v0 = w.lanczos_start(st.n)
+    b = g.spectral_bounds(steps=30, v0=t32(v0.astype(np.float32)))
+    a_ref, b_ref = krylov.lanczos(lambda v: A @ v, v0.astype(np.float32).astype(np.float64), 30)
+    ritz = krylov.ritz_values(a_ref, b_ref)
+    # the first steps agree closely; extreme Ritz values agree to FP32-level
+    np.testing.assert_allclose(b["alpha"][:5], a_ref[:5], rtol=1e-4)
+    assert b["ritz_max"] == pytest.approx(ritz[-1], rel=1e-4)
+    assert b["ritz_min"] == pytest.approx(ritz[0], rel=5e-2)
+    # a safe upper bound and a lower bound no smaller than the spectrum
+    ev_hi = krylov.gershgorin_max(A)
+    assert b["lmax"] <= ev_hi * (1 + 1e-12)
+    if st.k_lat_mult is None:
+        lo, hi = direct.exact_extremes(st)
+        assert b["lmax"] >= hi
+        assert b["ritz_min"] >= lo * (1 - 1e-4)
+    g.close()
+
+
+def _ref_steady(st, P):
+    A = assembly.assemble(st)
+    b = P.ravel()
+    if st.k_lat_mult is None:
+        return st.t_amb + direct.solve_separable(st, b)
+    if st.n <= 300000:
+        return st.t_amb + direct.solve_splu(A, b)
+    x, _, _ = cpu_cg.jacobi_cg(A, b, rtol=1e-14)
+    return st.t_amb + x
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_solve_config0(prec, tol):
+    say(f"solve c0 {prec}")
+    st, P = w.config0()
+    ref = _ref_steady(st, P)
+    g = grid_of(st)
+    T, stats = g.solve(t64(P), precision=prec)
+    err = rise_err(T.cpu().numpy(), ref, st.t_amb)
+    say(f"  err {err:.3e} stats {stats}")
+    assert err <= tol
+    assert stats["rel_residual"] < 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_solve_lognormal_small(prec, tol):
+    say(f"solve c4-small {prec}")
+    st, P = w.config4_small()
+    ref = _ref_steady(st, P)
+    g = grid_of(st)
+    T, stats = g.solve(t64(P), precision=prec)
+    err = rise_err(T.cpu().numpy(), ref, st.t_amb)
+    say(f"  err {err:.3e} cg {stats['cg_iters']} cycles {stats['outer_cycles']}")
+    assert err <= tol
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_solve_ragged(prec, tol):
+    say(f"solve ragged {prec}")
+    st = ragged_stack(70, 9, mult=True)
+    P = np.zeros(st.shape)
+    P[0] = np.random.default_rng(6).uniform(0, 2e-3, (st.ny, st.nx))
+    ref = _ref_steady(st, P)
+    g = grid_of(st)
+    T, stats = g.solve(t64(P), precision=prec)
+    assert rise_err(T.cpu().numpy(), ref, st.t_amb) <= tol
+    g.close()
+
+
+def test_solve_single_cell_and_zero_power():
+    say("solve single cell / zero power")
+    st = w.Stack(1, 1, ["Cu"])
+    g = grid_of(st)
+    T, _ = g.solve(t64(np.array([2e-3])), precision="mixed")
+    exact = st.t_amb + 2e-3 / (st.h_top * st.dx * st.dy)
+    assert T.cpu().numpy()[0] == pytest.approx(exact, rel=1e-10)
+    g.close()
+    st2, _ = w.config0()
+    g2 = grid_of(st2)
+    T0, stats = g2.solve(t64(np.zeros(st2.n)), precision="mixed")
+    assert np.all(T0.cpu().numpy() == st2.t_amb)
+    g2.close()
+
+
+def test_transient_steps_match_oracle():
+    say("transient c0-stack 4 steps")
+    st = w.uniform_stack(64, 48, ["Si", "BEOL", "bond", "Si", "BEOL", "bond", "TIM", "Cu"])
+    rng = np.random.default_rng(7)
+    Ps = [rng.uniform(0, 2e-3, st.n) for _ in range(2)]
+    dt = 1e-4
+    g = grid_of(st)
+    for prec, tol in (("mixed", 1e-8), ("fp64", 1e-10)):
+        th = np.zeros(st.n)
+        T = t64(st.t_amb + th)
+        for s in range(4):
+            P = Ps[s // 2]
+            ref_th = transient.step(st, P, th, dt)
+            T, stats = g.transient_step(dt, t64(P), T, precision=prec)
+            got = T.cpu().numpy()
+            err = np.abs(got - (st.t_amb + ref_th)).max() / np.abs(ref_th).max()
+            say(f"  {prec} step {s} err {err:.2e} cg {stats['cg_iters']}")
+            assert err <= tol
+            th = got - st.t_amb      # strict per-step parity from the GPU's own state
+    g.close()
+
+
+def test_invalid_and_failure_paths():
+    import paper_2606_17850_amd as cuth
+    say("failure paths")
+    st = w.Stack(8, 8, ["Si", "Cu"], h_top=0.0)
+    g = grid_of(st)
+    with pytest.raises(cuth.CuthError) as e:
+        g.solve(t64(np.ones(st.n) * 1e-3))
+    assert e.value.status == cuth._lib.CUTH_E_INVALID
+    st2, P = w.config0()
+    g2 = grid_of(st2)
+    with pytest.raises(cuth.CuthError) as e:
+        g2.transient_step(-1.0, t64(P), t64(np.full(st2.n, 300.0)))
+    assert e.value.status == cuth._lib.CUTH_E_INVALID
+    bad = P.ravel().copy()
+    bad[5] = np.nan
+    with pytest.raises(cuth.CuthError) as e:
+        g2.solve(t64(bad))
+    assert e.value.status == cuth._lib.CUTH_E_BREAKDOWN
+    with pytest.raises(cuth.CuthError) as e:
+        g2.solve(t64(P), precision="mixed", max_inner=1, max_outer=1)
+    assert e.value.status == cuth._lib.CUTH_E_NOT_CONVERGED
+    assert e.value.stats is not None and e.value.stats["cg_iters"] >= 1
+    g.close()
+    g2.close()
+
+
+def test_run_twice_bitwise_identical():
+    say("determinism")
+    st, P = w.config4_small()
+    g = grid_of(st)
+    T1, _ = g.solve(t64(P), precision="mixed")
+    T2, _ = g.solve(t64(P), precision="mixed")
+    assert torch.equal(T1, T2)
+    g.close()
