@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the layered-stencil PCG on one MI355X.
+
+Workload: the 512 x 512 x 16 layered stack with lognormal lateral conductivity
+(4,194,304 unknowns; block floorplans + hotspots on three dies), solved to 1e-8
+relative temperature-rise error by the mixed FP32-inner / FP64-refined
+Chebyshev-PCG, next to the plain FP64 Chebyshev-PCG on the same grid.
+
+A timed step is one complete mixed solve from a zero initial guess, including
+the Lanczos spectral-bound setup (the cached bounds are dropped before every
+step); the coefficient planes are built once when the grid is created, inputs
+are resident in HBM before timing starts.
+
+value  = algorithmic bytes of the solve phase / wall time of the step (GB/s).
+roofline = the dominant kernel, the general Chebyshev sweep: its algorithmic
+bytes per launch (24 B per unknown: z_j, z_{j-1}, r, z_{j+1}, gx, gy in FP32)
+over its average duration from HIP events recorded on the library's stream
+during the timed steps.  traffic = HBM bytes per launch from rocprofv3
+FETCH_SIZE + WRITE_SIZE counters (profiles/), when they were taken on the
+current kernel source; else null.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "cheb_sweep_512x512x16_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_17850_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles():
+    """HBM bytes per launch of the sweep kernel from committed counter runs."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(stack, P, iters: int):
+    """The CPU oracle (FP64 CSR Jacobi-CG, C + OpenMP) on the same system for a
+    bounded number of iterations; GB/s of its own algorithmic bytes."""
+    import numpy as np
+    from oracle import assembly, cpu_cg
+
+    A = assembly.assemble(stack)
+    b = P.ravel()
+    t0 = time.perf_counter()
+    _, it, _ = cpu_cg.jacobi_cg(A, b, rtol=1e-300, maxit=iters)
+    dt = time.perf_counter() - t0
+    n = A.shape[0]
+    # per iteration: CSR SpMV (8 B value + 4 B index per nonzero, 8 B row
+    # pointer, x and y) + the vector updates and dots (about 12 vectors)
+    per_it = A.nnz * 12 + n * 8 * (1 + 2) + n * 8 * 12
+    return {
+        "value": round(per_it * it / dt / 1e9, 3),
+        "unit": "GB/s",
+        "cores": cpu_cg.threads(),
+        "kind": "oracle",
+        "sample": (f"{it} iterations of the oracle's FP64 CSR Jacobi-CG on the same "
+                   f"{stack.nx}x{stack.ny}x{stack.nz} system ({n} unknowns) in {dt:.1f} s "
+                   f"= {n * it / dt:.3e} unknown-iterations/s; assembly not timed"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--cpu-iters", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stack, P = w.config1()
+    Pt = torch.as_tensor(P.ravel(), device=dev)
+    T = torch.empty_like(Pt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = cuth.Grid.from_stack(stack, device=dev)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+
+    mixed = cuth.options("mixed")
+    fp64 = cuth.options("fp64")
+
+    def step(opts):
+        g.reset_bounds()
+        _, st = g.solve(Pt, T, opts=opts)
+        return st
+
+    def timed(opts, k):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stats = []
+        e0.record()
+        h0 = time.perf_counter()
+        for _ in range(k):
+            stats.append(step(opts))
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - h0) * 1e3
+        return max(e0.elapsed_time(e1), wall), stats
+
+    for _ in range(args.warmup):
+        step(mixed)
+    g.profile_enable(True)
+    ms_mixed, st_mixed = timed(mixed, args.steps)
+    prof = g.profile_read()
+    g.profile_enable(False)
+    T_mixed = T.clone()
+
+    k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
+    for _ in range(min(args.warmup, 1)):
+        step(fp64)
+    ms_fp64, st_fp64 = timed(fp64, k64)
+    T_fp64 = T.clone()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    rise = float((T_fp64 - stack.t_amb).abs().max())
+    diff = float((T_mixed - T_fp64).abs().max()) / rise
+
+    per_step = ms_mixed / args.steps
+    bytes_step = sum(s["alg_bytes"] for s in st_mixed) / args.steps
+    value = bytes_step / (per_step / 1e3) / 1e9
+    avg_launch_ms = prof["total_ms"] / max(prof["launches"], 1)
+    achieved = prof["bytes_per_launch"] / (avg_launch_ms / 1e3) / 1e9 if prof["launches"] else None
+    per64 = ms_fp64 / k64
+
+    out = {
+        "metric": "PCG loop HBM GB/s + time to 1e-8 rel. error, mixed vs plain FP64, 1 GPU",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {
+            "workload": "steady 512x512x16 layered stack, lognormal(0.3) lateral k, "
+                        "3 dies, block floorplans + 32 hotspots/die; mixed FP32/FP64 "
+                        "Chebyshev(k=30)-PCG to 1e-8 relative rise error",
+            "unknowns": stack.n,
+            "cheb_degree": 30,
+        },
+        "time_to_tol_ms": {"mixed": round(per_step, 3), "fp64": round(per64, 3),
+                           "speedup_mixed_vs_fp64": round(per64 / per_step, 3)},
+        "solve_detail": {
+            "mixed_cg_iters": st_mixed[-1]["cg_iters"],
+            "mixed_outer_cycles": st_mixed[-1]["outer_cycles"],
+            "mixed_setup_ms": round(st_mixed[-1]["setup_ms"], 3),
+            "mixed_rel_residual": st_mixed[-1]["rel_residual"],
+            "fp64_cg_iters": st_fp64[-1]["cg_iters"],
+            "fp64_rel_residual": st_fp64[-1]["rel_residual"],
+            "fp64_GBps": round(sum(s["alg_bytes"] for s in st_fp64) / k64 / (per64 / 1e3) / 1e9, 2),
+            "mixed_vs_fp64_max_rise_rel_diff": diff,
+            "grid_create_ms": round(create_ms, 3),
+            "unknown_stencils_per_s": round(st_mixed[-1]["stencil_applies"] * stack.n
+                                            / (per_step / 1e3), 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_cheb (general Chebyshev sweep, FP32, per-cell lateral conductances)",
+            "achieved": round(achieved, 2) if achieved else None,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
+            "traffic": traffic_from_profiles(),
+            "bytes_per_launch": prof["bytes_per_launch"],
+            "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+            "timed_launches": prof["launches"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(stack, P, args.cpu_iters)
+    g.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -84,10 +84,11 @@ typedef struct {
 
 typedef struct {
     int32_t precision;           /* cuth_precision                                     */
-    double tol;                  /* CUTH_MIXED: target relative error of the rise
-                                    T - T_amb (inf-norm), default 1e-8.
-                                    CUTH_FP64: relative residual ||P - G T|| / ||P||,
-                                    default 1e-10.                                     */
+    double tol;                  /* 0 selects the default.  CUTH_MIXED: target
+                                    relative error of the rise T - T_amb (inf-norm),
+                                    default 1e-8.  CUTH_FP64: relative residual
+                                    ||b - A T|| / ||b||, default 1e-10 for steady and
+                                    1e-12 for transient solves.                       */
     int32_t cheb_degree;         /* Chebyshev degree k >= 1 (default 30)               */
     int32_t lanczos_steps;       /* Lanczos steps m, 2..256 (default 30)               */
     int32_t max_inner;           /* CG iterations per inner solve (default 2000)       */
@@ -193,6 +194,22 @@ cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, double
 cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t steps, const float *v0,
                                  double *alpha, double *beta, double *ritz_min,
                                  double *ritz_max, double *lmin, double *lmax);
+
+/* ---- setup control and measurement ---- */
+
+/* Drop the cached spectral bounds of every operator of the handle, so the next
+ * solve reruns the Lanczos setup (Section 4.3 last paragraph).  No device work. */
+cuth_status cuth_grid_reset_bounds(cuth_grid g);
+
+/* Kernel timing for measurement.  When on, each preconditioner application
+ * brackets its first general Chebyshev sweep with HIP events on the handle's
+ * stream; cuth_profile_read returns the summed duration (ms), the number of
+ * timed launches and the algorithmic bytes of one such launch (N times the
+ * bytes per unknown of the sweep).  Enabling resets the counters and
+ * synchronises the stream. */
+cuth_status cuth_profile_enable(cuth_grid g, int32_t on);
+cuth_status cuth_profile_read(cuth_grid g, double *total_ms, int64_t *launches,
+                              double *bytes_per_launch);
 
 #ifdef __cplusplus
 }

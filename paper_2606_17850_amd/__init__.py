@@ -48,7 +48,7 @@ def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: 
     o = _lib.Options()
     library().cuth_default_options(ctypes.byref(o))
     o.precision = CUTH_MIXED if precision == "mixed" else CUTH_FP64
-    o.tol = tol if tol is not None else (1e-8 if precision == "mixed" else 1e-10)
+    o.tol = 0.0 if tol is None else float(tol)
     o.cheb_degree = cheb_degree
     o.lanczos_steps = lanczos_steps
     o.max_inner = max_inner
@@ -212,6 +212,18 @@ class Grid:
                                                 int(degree), self._vec(r, "r", r.dtype),
                                                 z.data_ptr()))
         return z
+
+    def reset_bounds(self):
+        _check(library().cuth_grid_reset_bounds(self._h))
+
+    def profile_enable(self, on: bool = True):
+        _check(library().cuth_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        ms, cnt, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(library().cuth_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
+                                           ctypes.byref(by)))
+        return {"total_ms": ms.value, "launches": cnt.value, "bytes_per_launch": by.value}
 
     def spectral_bounds(self, dt: float = 0.0, steps: int = 30,
                         v0: Optional[torch.Tensor] = None) -> dict:

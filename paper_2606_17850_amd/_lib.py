@@ -23,6 +23,7 @@ EXPORTED = (
     "cuth_default_options", "cuth_grid_create", "cuth_grid_destroy", "cuth_solve",
     "cuth_transient_step", "cuth_solve_batch", "cuth_adjoint", "cuth_last_error",
     "cuth_apply", "cuth_residual", "cuth_precond_apply", "cuth_spectral_bounds",
+    "cuth_grid_reset_bounds", "cuth_profile_enable", "cuth_profile_read",
 )
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -93,6 +94,10 @@ def load() -> ctypes.CDLL:
         "cuth_precond_apply": (ctypes.c_int, [vp, dbl, i32, dbl, dbl, i32, vp, vp]),
         "cuth_spectral_bounds": (ctypes.c_int, [vp, dbl, i32, vp, c_double_p, c_double_p,
                                                 c_double_p, c_double_p, c_double_p, c_double_p]),
+        "cuth_grid_reset_bounds": (ctypes.c_int, [vp]),
+        "cuth_profile_enable": (ctypes.c_int, [vp, i32]),
+        "cuth_profile_read": (ctypes.c_int, [vp, c_double_p, ctypes.POINTER(ctypes.c_int64),
+                                             c_double_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -35,9 +35,9 @@ def build(verbose: bool = False) -> str:
         jobs = []
         for src, is_dev in (("kernels.hip", True), ("solver.cpp", False), ("api.cpp", False)):
             obj = os.path.join(tmp, src + ".o")
-            cmd = [hipcc] + COMMON
+            cmd = [hipcc] + COMMON + [f"--offload-arch={ARCH}"] + DEVICE_FLAGS
             if is_dev:
-                cmd += [f"--offload-arch={ARCH}"] + DEVICE_FLAGS + ["-x", "hip"]
+                cmd += ["-x", "hip"]
             cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
             jobs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
             objs.append(obj)

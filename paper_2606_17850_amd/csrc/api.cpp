@@ -34,8 +34,8 @@ cuth_status check_desc(const cuth_grid_desc *d) {
     if (d->nx < 1 || d->ny < 1 || d->nz < 1)
         return fail(CUTH_E_INVALID, "nx, ny, nz must be >= 1");
     if (d->nz > cuth::kMaxLayers) return fail(CUTH_E_INVALID, "nz exceeds 64");
-    if ((d->ny + cuth::kBY - 1) / cuth::kBY > 65535)
-        return fail(CUTH_E_INVALID, "ny too large for the tile grid");
+    if ((int64_t)d->nx * d->ny * d->nz > ((int64_t)1 << 36))
+        return fail(CUTH_E_INVALID, "grid too large (more than 2^36 cells)");
     if (!finite_pos(d->dx) || !finite_pos(d->dy))
         return fail(CUTH_E_INVALID, "dx and dy must be finite and > 0");
     if (!d->dz || !d->k_lat || !d->k_vert)
@@ -56,7 +56,8 @@ cuth_status check_desc(const cuth_grid_desc *d) {
 cuth_status check_opts(const cuth_options &o) {
     if (o.precision != CUTH_FP64 && o.precision != CUTH_MIXED)
         return fail(CUTH_E_INVALID, "precision must be CUTH_FP64 or CUTH_MIXED");
-    if (!finite_pos(o.tol) || o.tol >= 1.0) return fail(CUTH_E_INVALID, "tol must be in (0, 1)");
+    if (!(o.tol == 0.0 || (finite_pos(o.tol) && o.tol < 1.0)))
+        return fail(CUTH_E_INVALID, "tol must be 0 (default) or in (0, 1)");
     if (o.cheb_degree < 1 || o.cheb_degree > 1000)
         return fail(CUTH_E_INVALID, "cheb_degree must be in 1..1000");
     if (o.lanczos_steps < 2 || o.lanczos_steps > 256)
@@ -72,7 +73,6 @@ cuth_options resolve(const cuth_options *o, bool &ok) {
     cuth_default_options(&r);
     if (o) {
         r = *o;
-        if (r.tol == 0.0) r.tol = (r.precision == CUTH_MIXED) ? 1e-8 : 1e-10;
         if (r.cheb_degree == 0) r.cheb_degree = 30;
         if (r.lanczos_steps == 0) r.lanczos_steps = 30;
         if (r.max_inner == 0) r.max_inner = 2000;
@@ -109,7 +109,7 @@ extern "C" {
 void cuth_default_options(cuth_options *o) {
     if (!o) return;
     o->precision = CUTH_MIXED;
-    o->tol = 1e-8;
+    o->tol = 0.0;
     o->cheb_degree = 30;
     o->lanczos_steps = 30;
     o->max_inner = 2000;
@@ -289,6 +289,48 @@ cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t steps, const fl
         if (!(ln > 0.0) || !(lx > ln * (1.0 + 1e-6))) ln = 0.5 * lx;
         if (lmin) *lmin = ln;
         if (lmax) *lmax = lx;
+        return CUTH_OK;
+    });
+}
+
+cuth_status cuth_grid_reset_bounds(cuth_grid h) {
+    return guarded([&]() -> cuth_status {
+        if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
+        for (cuth::Setup &su : h->g->setups) su.have_bounds = false;
+        return CUTH_OK;
+    });
+}
+
+cuth_status cuth_profile_enable(cuth_grid h, int32_t on) {
+    return guarded([&]() -> cuth_status {
+        if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
+        cuth::Grid &g = *h->g;
+        if (hipStreamSynchronize(g.stream) != hipSuccess)
+            return fail(CUTH_E_DEVICE, "hipStreamSynchronize failed");
+        if (on && g.pev.empty()) {
+            g.pev.resize(512, nullptr);
+            for (hipEvent_t &e : g.pev)
+                if (hipEventCreate(&e) != hipSuccess) return fail(CUTH_E_DEVICE, "hipEventCreate failed");
+        }
+        g.prof = on != 0;
+        g.pev_used = 0;
+        g.prof_ms = 0.0;
+        g.prof_count = 0;
+        return CUTH_OK;
+    });
+}
+
+cuth_status cuth_profile_read(cuth_grid h, double *total_ms, int64_t *launches,
+                              double *bytes_per_launch) {
+    return guarded([&]() -> cuth_status {
+        if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
+        cuth::Grid &g = *h->g;
+        if (hipStreamSynchronize(g.stream) != hipSuccess)
+            return fail(CUTH_E_DEVICE, "hipStreamSynchronize failed");
+        (void)cuth::prof_flush(g);
+        if (total_ms) *total_ms = g.prof_ms;
+        if (launches) *launches = g.prof_count;
+        if (bytes_per_launch) *bytes_per_launch = g.prof_bytes;
         return CUTH_OK;
     });
 }

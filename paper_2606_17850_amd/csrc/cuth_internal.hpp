@@ -15,9 +15,9 @@
 namespace cuth {
 
 constexpr int kMaxLayers = 64;
-constexpr int kBX = 64;            // stencil tile: one wavefront along x
-constexpr int kBY = 4;             // four wavefronts along y
-constexpr int kThreads = kBX * kBY;
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kMaxBY = 8;          // rows (wavefronts) per workgroup
+constexpr int kRedBlocks = 1024;   // workgroups of the 1-D (non-stencil) reduction kernels
 
 // Per-layer coefficients (uniform within a layer).
 template <typename T>
@@ -30,95 +30,100 @@ struct LayerCoef {
 
 // Operator view handed to kernels.  gx/gy are null for per-layer-uniform grids;
 // otherwise gx[c] couples c and c+1 (0 on the last column), gy[c] couples c and
-// c+nx (0 on the last row).
+// c+nx (0 on the last row).  vx, by, zc: launch shape (cells per lane along
+// x, wavefront rows per workgroup, layers per vertical march); vx divides nx.
 template <typename T>
 struct OpView {
     int nx, ny, nz;
     const T *gx;
     const T *gy;
     const LayerCoef<T> *lc;   // device [nz]
+    int vx, by, zc;
 };
 
-// Scalars of one PCG run (Algorithm 1), resident on the device.
+// Number of workgroups of a stencil launch (one 64*vx by `by` tile and one
+// chunk of zc layers each).
+inline int tiles_x(int nx, int vx) { return (nx + kWave * vx - 1) / (kWave * vx); }
+inline int tiles_y(int ny, int by) { return (ny + by - 1) / by; }
+inline int tiles_z(int nz, int zc) { return (nz + zc - 1) / zc; }
 template <typename T>
-struct CgState {
-    T rz;         // r_k^T z_k
-    T rz_new;     // r_{k+1}^T z_{k+1} from the last preconditioner sweep
-    T alpha;
-    T beta;
-    T pmu;        // p^T A p
-    T rr;         // recursive ||r||^2
-    T rr0;        // ||rhat||^2 of the inner right-hand side
-    T tol2;       // stop when rr <= tol2
-    T true_rr;    // last ||rhat - A x||^2
-    T drift_rr;   // last ||(rhat - A x) - r||^2
-    T true_prev;  // previous true residual norm (< 0: none yet)
-    int done;     // 0 running, 1 tolerance, 2 drift, 3 stagnation, 4 breakdown
-    int iter;     // completed CG iterations
-    int first;    // 1 until the first search direction has been formed
-    int pad;
-};
-
-// FP64 quantities of one outer residual evaluation.
-struct OuterStats {
-    double rr;       // ||b - A theta||_2^2
-    double bb;       // ||b||_2^2
-    double dinf;     // ||delta||_inf of the correction just applied
-    double thinf;    // ||theta||_inf after the correction
-    double bad;      // count of non-finite residual entries
-    double pad[3];
-};
-
-// Reduction scratch: per-block partial values and the arrival counter used by
-// the last block to finish a kernel (one cross-block pass, fixed order).
-struct RedScratch {
-    void *partials;
-    unsigned *counter;
-};
-
-// Sizes of the grid handled by one launch (tile grid over x, y).
-inline dim3 tile_grid(int nx, int ny) {
-    return dim3((unsigned)((nx + kBX - 1) / kBX), (unsigned)((ny + kBY - 1) / kBY), 1);
+inline int stencil_blocks(const OpView<T> &op) {
+    return tiles_x(op.nx, op.vx) * tiles_y(op.ny, op.by) * tiles_z(op.nz, op.zc);
+}
+inline int red_blocks(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b));
 }
 
+// Scalars of one PCG run (Algorithm 1) resident on the device.  Kernels never
+// read a field that a workgroup of the same launch writes, except `done`, which
+// every workgroup of a launch sets to the same value from the same data.
+template <typename T>
+struct CgState {
+    T rz[2];      // r_k^T z_k in slot k & 1 (written by the direction kernel of k)
+    T rr;         // last recursive ||r||^2
+    T rr0;        // ||rhat||^2 of the inner right-hand side (host)
+    T tol2;       // converged when rr <= tol2 (host)
+    T pad;
+    int done;     // 0 running, 1 tolerance, 4 breakdown
+    int iter;     // completed CG iterations (updates followed by a convergence test)
+    int pad2[2];
+};
+
 // ---- launchers (kernels.hip) -------------------------------------------------
+// Every reduction writes one partial per workgroup into `part` (value v of
+// workgroup b at part[v*nb + b]); the consumer (next kernel, or the host)
+// reduces them in a fixed order.
+
 template <typename T>
 void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 
 // Chebyshev sweep z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 (r - A z_j).
 // mode 1: z_j = r*inv_th, z_{j-1} = 0 (j = 1); mode 2: z_{j-1} = r*inv_th
 // (j = 2); mode 0: z_{j-1} read from zo.  The result is written to zo.
-// last: also reduce r^T z_{j+1} into st->rz_new.
+// last: also write partials of r^T z_{j+1} to part_out.  chk: first kernel
+// after a CG update: reduce the update's partials (part_in, np_in) and stop
+// (st->done = 1) if rr <= tol2; writes st->rr and st->iter = k + 1.
 template <typename T>
-void launch_cheb(const OpView<T> &op, int mode, bool last, const T *z, T *zo, const T *r,
-                 T c1, T c2, T inv_th, CgState<T> *st, RedScratch red, hipStream_t s);
+void launch_cheb(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
+                 const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *part_in, int np_in,
+                 T *part_out, hipStream_t s);
 
+// Degree-1 preconditioner z = a r with the same last/chk behaviour.
 template <typename T>
-void launch_scale(int64_t n, const T *x, T a, T *y, CgState<T> *st, bool set_rz_from, const T *r,
-                  RedScratch red, hipStream_t s);
+void launch_scale(int64_t n, const T *r, T a, T *z, bool chk, int k, CgState<T> *st,
+                  const T *part_in, int np_in, T *part_out, hipStream_t s);
 
+// CG iteration k: reduce r^T z (part_in) into rz_k; p = z + (rz_k/rz_{k-1}) p_old;
+// mu = A p; partials of p^T mu.
 template <typename T>
-void launch_cg_dir(const OpView<T> &op, const T *z, const T *pold, T *pnew, T *mu,
-                   CgState<T> *st, RedScratch red, hipStream_t s);
+void launch_cg_dir(const OpView<T> &op, int k, const T *z, const T *pold, T *pnew, T *mu,
+                   CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s);
 
+// x += alpha p (x = alpha p for k = 0), r -= alpha mu with alpha = rz_k / p^T mu;
+// partials of r^T r.
 template <typename T>
-void launch_cg_update(const OpView<T> &op, T *x, const T *p, T *r, const T *mu,
-                      CgState<T> *st, RedScratch red, hipStream_t s);
+void launch_cg_update(const OpView<T> &op, int k, T *x, const T *p, T *r, const T *mu,
+                      CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s);
 
+// True residual rt = rhat - A x (x = 0 if !have_x): partials of ||rt||^2 and
+// ||rt - r||^2 (reduced on the host).
 template <typename T>
-void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r,
-                     CgState<T> *st, int force, RedScratch red, hipStream_t s);
+void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r, bool have_x,
+                     T *part_out, hipStream_t s);
 
 // theta_out = (theta_in - in_off) + delta;  b = P + cap*(Tn - tn_off);
-// r = b - A theta_out (FP64); optional copies of r in the inner precision.
+// r = b - A theta_out (FP64); optional copies of r in the inner precision;
+// partials (reduced on the host) of ||r||^2, ||b||^2, max|delta|, max|theta_out|,
+// count of non-finite r.
 template <typename TD, typename TI>
 void launch_residual(const OpView<double> &op, const double *th_in, double in_off,
                      const TD *delta, const double *P, const double *Tn, double tn_off,
-                     double *th_out, double *r64, TI *r_in, TI *rhat, OuterStats *os,
-                     CgState<TI> *st, double inner_tol, RedScratch red, hipStream_t s);
+                     double *th_out, double *r64, TI *r_in, TI *rhat, double *part_out,
+                     hipStream_t s);
+constexpr int kResidualValues = 5;
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s);
-void launch_copy_to_float(int64_t n, const double *x, float *y, hipStream_t s);
 
 // Face conductances of a grid with a per-cell lateral multiplier.  Writes the
 // FP64 and FP32 planes and the per-layer maximum lateral off-diagonal row sum
@@ -129,25 +134,25 @@ void launch_build_lateral(int nx, int ny, int nz, double dx, double dy, const do
                           float *gx32, float *gy32, unsigned long long *maxrow,
                           unsigned int *bad, hipStream_t s);
 
-// Lanczos building blocks (FP32).
+// Lanczos building blocks (FP32).  lz: device scalars, alpha_j at lz[j],
+// beta_j at lz[256 + j].
 void launch_fill_random(int64_t n, uint64_t seed, float *v, hipStream_t s);
-void launch_norm2(int64_t n, const float *v, float *out, RedScratch red, hipStream_t s);
-void launch_scale_by_rsqrt(int64_t n, const float *v, const float *nrm2, float *out, hipStream_t s);
-void launch_lanczos_av(const OpView<float> &op, const float *v, const float *vprev,
-                       const float *beta_prev, float *w, float *alpha_out, RedScratch red,
-                       hipStream_t s);
-void launch_lanczos_orth(int64_t n, float *w, const float *v, const float *alpha,
-                         float *beta_out, RedScratch red, hipStream_t s);
-void launch_div_scalar(int64_t n, float *w, const float *den, hipStream_t s);
+void launch_norm2(int64_t n, const float *v, float *part_out, hipStream_t s);
+void launch_scale_rsqrt(int64_t n, const float *v, const float *part_in, int np_in, float *out,
+                        hipStream_t s);
+void launch_lanczos_av(const OpView<float> &op, int j, const float *v, const float *vprev,
+                       const float *lz, float *w, float *part_out, hipStream_t s);
+void launch_lanczos_orth(int64_t n, int j, float *w, const float *v, float *lz,
+                         const float *part_in, int np_in, float *part_out, hipStream_t s);
+void launch_lanczos_div(int64_t n, int j, float *w, float *lz, const float *part_in, int np_in,
+                        hipStream_t s);
 
-// Adjoint gradient sums: per layer, S_lat[l] = sum over lateral faces of
+// Adjoint gradient: per layer l, S_lat[l] = sum over lateral faces of
 // g (la_a - la_b)(th_a - th_b) and S_vert[l] = sum over the faces between l and
-// l+1 of (la_l - la_{l+1})(th_l - th_{l+1}); both FP64, written to out[0..nz) and
-// out[nz..2nz).
-void launch_adjoint_sums(const OpView<double> &op, const double *lam, const double *T,
-                         double t_amb, double *out, RedScratch red, hipStream_t s);
-void launch_adjoint_finish(int nz, const double *sums, const double *fac_lat,
-                           const double *fac_vert_up, const double *fac_vert_dn, double *dL_dk,
-                           hipStream_t s);
+// l+1 of (la_l - la_{l+1})(th_l - th_{l+1}); then
+// dL/dk_lat[l] = -fac_lat[l] S_lat[l],
+// dL/dk_vert[l] = -(fac_up[l] S_vert[l] + fac_dn[l] S_vert[l-1]).
+void launch_adjoint(const OpView<double> &op, const double *lam, const double *T, double t_amb,
+                    const double *fac, double *part, double *dL_dk, hipStream_t s);
 
 }  // namespace cuth

@@ -50,6 +50,14 @@ struct Status {
     bool bad() const { return code != CUTH_OK; }
 };
 
+// Launch shape of the stencil kernels of one precision.
+struct Shape {
+    int vx = 1, by = 4, zc = 64;
+};
+
+// Slots of the partials buffer (one per producer/consumer pair).
+enum Slot { S_CHEB = 0, S_DIR, S_UPD, S_CHK, S_RES, S_LZA, S_LZB, S_MISC, S_COUNT };
+
 struct Grid {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -58,6 +66,7 @@ struct Grid {
     double dx = 0, dy = 0, h_top = 0, h_bot = 0, t_amb = 0;
     std::vector<double> dz, k_lat, k_vert, cap;
     bool has_cap = false, per_cell = false;
+    Shape sh32, sh64;
 
     double *gx64 = nullptr, *gy64 = nullptr;
     float *gx32 = nullptr, *gy32 = nullptr;
@@ -68,23 +77,37 @@ struct Grid {
     Work<double> w64;
     double *thA = nullptr, *thB = nullptr;
 
-    RedScratch red{nullptr, nullptr};
-    size_t partial_slots = 0;
+    double *part = nullptr;           // S_COUNT slots of slot_doubles each, then the adjoint slot
+    size_t slot_doubles = 0;
+    double *part_adj = nullptr;
     CgState<float> *st32 = nullptr;
     CgState<double> *st64 = nullptr;
-    OuterStats *os = nullptr;
     float *lz = nullptr;              // Lanczos scalars on the device
-    double *adj = nullptr;            // adjoint sums [2 nz] + factors [3 nz]
+    double *adj_fac = nullptr;        // adjoint factors [3 nz]
 
     // pinned host mirrors for stream-ordered readback
     CgState<float> *h_st32 = nullptr;
     CgState<double> *h_st64 = nullptr;
-    OuterStats *h_os = nullptr;
+    double *h_part = nullptr;         // slot_doubles
     float *h_lz = nullptr;
-    double *h_scal = nullptr;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+
+    // kernel timing (measurement only): event pairs around the first general
+    // Chebyshev sweep of each preconditioner application
+    bool prof = false;
+    std::vector<hipEvent_t> pev;
+    size_t pev_used = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0;
+    int64_t prof_count = 0;
+
+    template <typename T>
+    T *slot(int s) const {
+        return reinterpret_cast<T *>(part + (size_t)s * slot_doubles);
+    }
 };
+
+Status prof_flush(Grid &g);
 
 Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out);
 void grid_destroy(Grid *g);
@@ -100,7 +123,7 @@ OpView<double> view64(const Grid &g, const Setup &su);
 OpView<float> view32(const Grid &g, const Setup &su);
 
 // Solve (dt == 0: G; dt > 0: C/dt + G) theta = P (+ cap*(Tn - t_amb)).  init:
-// optional initial guess given as T (offset out_off).  The result is written as
+// optional initial guess given as T (offset init_off).  The result is written as
 // out = theta + out_off.
 Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const double *init,
                     double init_off, double *out, double out_off, const cuth_options &o,

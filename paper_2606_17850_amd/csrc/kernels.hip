@@ -1,18 +1,24 @@
 // gfx950 kernels of the layered-stencil PCG.
 //
-// Every stencil kernel uses the same mapping: a 64 x 4 workgroup (four
-// wavefronts, one per grid row) owns a 64 x 4 column tile of the lateral grid
-// and marches up through all layers, keeping the values of the layers below,
-// at and above the current one in registers.  Lateral neighbours are read from
-// global memory; they are the same cache lines the neighbouring lanes and rows
-// load, so HBM sees each vector close to once per sweep.  Loads along x are
-// unit-stride and coalesced.
+// Stencil mapping.  A workgroup is `by` wavefronts; wavefront row w owns grid
+// row j of a tile, and lane q owns `vx` consecutive cells along x, so a
+// wavefront covers 64*vx cells of one row with one 16-byte load per lane for
+// FP32 vx = 4 and FP64 vx = 2.  Each lane marches up through all layers with
+// the values of the layers below, at and above in registers; x neighbours come
+// from the adjacent lanes (cross-lane shuffles), y neighbours from the rows
+// above and below (cache hits: the same lines the neighbouring rows load).
 //
-// Reductions (dot products, norms, maxima) are done with wavefront butterflies,
-// then across the four wavefronts in LDS; each workgroup writes one partial and
-// the last workgroup to arrive (atomic ticket) sums all partials in a fixed
-// order and writes the scalars the next kernel needs (alpha, beta, ...).  No
-// host round trip is needed between kernels of a CG iteration, and results are
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the eight
+// XCDs (workgroup b runs on XCD b mod 8), each XCD with its own L2.  Tile rows
+// are therefore handed out in eight contiguous bands, one per XCD, so that the
+// tiles above and below a tile (whose rows it reads as halo) run on the same
+// XCD at about the same time and its halo reads hit that XCD's L2.
+//
+// Reductions.  Each workgroup reduces its values with wavefront butterflies and
+// a fixed-order pass over its wavefronts, and writes one partial per value.
+// The next kernel in the stream (or the host) sums all partials in a fixed
+// order; every workgroup of the consuming kernel computes the same sum, so no
+// grid-wide synchronisation, fence or atomic is needed, and results are
 // run-to-run deterministic.
 #include "cuth_internal.hpp"
 
@@ -21,7 +27,31 @@
 namespace cuth {
 namespace {
 
-__device__ __forceinline__ int tid_lin() { return threadIdx.x + blockDim.x * threadIdx.y; }
+template <typename T, int VX>
+struct alignas(sizeof(T) * VX) Vec {
+    T a[VX];
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> vload(const T *p) {
+    return *reinterpret_cast<const Vec<T, VX> *>(p);
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void vstore(T *p, const Vec<T, VX> &v) {
+    *reinterpret_cast<Vec<T, VX> *>(p) = v;
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> vzero() {
+    Vec<T, VX> v;
+#pragma unroll
+    for (int e = 0; e < VX; ++e) v.a[e] = T(0);
+    return v;
+}
+
+__device__ __forceinline__ int tid_lin() { return threadIdx.x + kWave * threadIdx.y; }
+__device__ __forceinline__ int nthreads() { return kWave * blockDim.y; }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -37,113 +67,144 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
-template <typename T>
-__device__ __forceinline__ T load_coherent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum (or max, for slots whose bit is set in maxmask; those values must be
-// >= 0) of v[k] over the whole grid.  Returns true in the last workgroup to
-// finish, where v[k] then holds the grid-wide results in every thread.
-// Requires blockDim = kThreads and every thread of the workgroup to call it.
+// Sum (or max for the values whose bit is set in maxmask; those are >= 0) of
+// v[k] over the workgroup; written by thread 0 to part[k*nb + blockIdx.x].
 template <typename T, int NV>
-__device__ __forceinline__ bool grid_reduce(T (&v)[NV], unsigned maxmask, T *partials,
-                                            unsigned *counter) {
-    constexpr int NW = kThreads / 64;
-    __shared__ T sh[NV][NW];
-    __shared__ int is_last;
-    const int t = tid_lin(), lane = t & 63, w = t >> 6;
-    const int nb = gridDim.x * gridDim.y;
-    const int b = blockIdx.x + gridDim.x * blockIdx.y;
+__device__ __forceinline__ void block_partials(T (&v)[NV], unsigned maxmask, T *part) {
+    __shared__ T sh[NV][kMaxBY];
+    const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const bool mx = (maxmask >> k) & 1u;
-        T x = mx ? wave_max(v[k]) : wave_sum(v[k]);
+        const T x = mx ? wave_max(v[k]) : wave_sum(v[k]);
         if (lane == 0) sh[k][w] = x;
     }
     __syncthreads();
-    if (t == 0) {
+    if (tid_lin() == 0) {
+        const int nb = gridDim.x;
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const bool mx = (maxmask >> k) & 1u;
             T a = sh[k][0];
-            for (int q = 1; q < NW; ++q) a = mx ? fmax(a, sh[k][q]) : a + sh[k][q];
-            partials[(size_t)k * nb + b] = a;
+            for (int q = 1; q < nw; ++q) a = mx ? fmax(a, sh[k][q]) : a + sh[k][q];
+            part[(size_t)k * nb + blockIdx.x] = a;
         }
-        __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        is_last = (ticket == (unsigned)(nb - 1));
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const bool mx = (maxmask >> k) & 1u;
-        T a = T(0);
-        for (int q = t; q < nb; q += kThreads) {
-            const T p = load_coherent(&partials[(size_t)k * nb + q]);
-            a = mx ? fmax(a, p) : a + p;
-        }
-        a = mx ? wave_max(a) : wave_sum(a);
-        if (lane == 0) sh[k][w] = a;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const bool mx = (maxmask >> k) & 1u;
-        T a = sh[k][0];
-        for (int q = 1; q < NW; ++q) a = mx ? fmax(a, sh[k][q]) : a + sh[k][q];
-        v[k] = a;
-    }
-    if (t == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
 }
 
-// (A x)_c at cell c = (i, j, l): xc, xdn, xup are x at c, c - plane, c + plane;
-// X(q) fetches x at any in-range cell q for the lateral neighbours.
-template <typename T, bool PC, typename F>
-__device__ __forceinline__ T stencil_at(const OpView<T> &op, const LayerCoef<T> &L, int i, int j,
-                                        int l, int64_t c, T xc, T xdn, T xup, F &&X) {
-    T gxm, gxp, gym, gyp;
-    if constexpr (PC) {
-        gxp = op.gx[c];
-        gyp = op.gy[c];
-        gxm = i > 0 ? op.gx[c - 1] : T(0);
-        gym = j > 0 ? op.gy[c - op.nx] : T(0);
-    } else {
-        gxm = gxp = L.gx;
-        gym = gyp = L.gy;
-    }
-    T a = L.sink * xc;
-    if (i > 0) a += gxm * (xc - X(c - 1));
-    if (i < op.nx - 1) a += gxp * (xc - X(c + 1));
-    if (j > 0) a += gym * (xc - X(c - op.nx));
-    if (j < op.ny - 1) a += gyp * (xc - X(c + op.nx));
-    if (l > 0) a += L.gzd * (xc - xdn);
-    if (l < op.nz - 1) a += L.gzu * (xc - xup);
-    return a;
+// Fixed-order sum of np partials written by the previous kernel; every thread
+// of every workgroup obtains the same value.
+template <typename T>
+__device__ __forceinline__ T reduce_prev(const T *part, int np) {
+    __shared__ T sh[kMaxBY];
+    T a = T(0);
+    for (int q = tid_lin(); q < np; q += nthreads()) a += part[q];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) sh[threadIdx.y] = a;
+    __syncthreads();
+    T s = sh[0];
+    for (int q = 1; q < (int)blockDim.y; ++q) s += sh[q];
+    __syncthreads();
+    return s;
 }
 
-// March one (i, j) column through all layers; emit(l, c, x_c, (A x)_c).
-template <typename T, bool PC, typename F, typename E>
-__device__ __forceinline__ void column(const OpView<T> &op, int i, int j, F &&X, E &&emit) {
-    const int64_t plane = (int64_t)op.nx * op.ny;
-    int64_t c = i + (int64_t)op.nx * j;
-    T xdn = T(0), xc = X(c);
-    for (int l = 0; l < op.nz; ++l, c += plane) {
+// XCD-aware tile of this workgroup: contiguous bands of the tile order per
+// XCD, with the layer chunks of one lateral tile adjacent (they share their
+// boundary layers), then x, then y.
+__device__ __forceinline__ void my_tile(int ntx, int ntz, int &tx, int &ty, int &tz) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, k = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    const int lin = xcd * per + (xcd < rem ? xcd : rem) + k;
+    tz = lin % ntz;
+    const int t = lin / ntz;
+    tx = t % ntx;
+    ty = t / ntx;
+}
+
+struct Lane {
+    int lane, i0, j, l0, l1;
+    bool act;
+};
+
+template <int VX, typename T>
+__device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
+    int tx, ty, tz;
+    my_tile((op.nx + kWave * VX - 1) / (kWave * VX), (op.nz + op.zc - 1) / op.zc, tx, ty, tz);
+    Lane L;
+    L.lane = threadIdx.x;
+    L.i0 = (tx * kWave + L.lane) * VX;
+    L.j = ty * blockDim.y + threadIdx.y;
+    L.l0 = tz * op.zc;
+    L.l1 = min(op.nz, L.l0 + op.zc);
+    L.act = L.i0 < op.nx && L.j < op.ny;
+    return L;
+}
+
+// March the VX cells of one lane through all layers; emit(l, c, x, A x) per layer
+// (only for active lanes).  XV(q) fetches VX consecutive values of the operand
+// starting at cell q, XS(q) one value.  Every lane of the wavefront must call
+// this (the x halo comes through cross-lane shuffles).
+template <typename T, bool PC, int VX, typename FV, typename FS, typename E>
+__device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
+                                       E &&emit) {
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const bool act = ln.act;
+    const bool has_l = act && ln.i0 > 0, has_r = act && ln.i0 + VX < nx;
+    const bool has_s = act && ln.j > 0, has_n = act && ln.j < ny - 1;
+    int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
+    const Vec<T, VX> zero = vzero<T, VX>();
+    Vec<T, VX> xdn = (act && ln.l0 > 0) ? XV(c - plane) : zero;
+    Vec<T, VX> xc = act ? XV(c) : zero;
+    for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
         const LayerCoef<T> L = op.lc[l];
-        const T xup = (l + 1 < op.nz) ? X(c + plane) : T(0);
-        const T ax = stencil_at<T, PC>(op, L, i, j, l, c, xc, xdn, xup, X);
-        emit(l, c, xc, ax);
+        const Vec<T, VX> xup = (act && l + 1 < nz) ? XV(c + plane) : zero;
+        const Vec<T, VX> xso = has_s ? XV(c - nx) : zero;
+        const Vec<T, VX> xno = has_n ? XV(c + nx) : zero;
+        T left = __shfl_up(xc.a[VX - 1], 1, 64);
+        T right = __shfl_down(xc.a[0], 1, 64);
+        if (ln.lane == 0) left = has_l ? XS(c - 1) : T(0);
+        if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
+        Vec<T, VX> gxp, gyp, gym;
+        T gxl = T(0);
+        if constexpr (PC) {
+            gxp = act ? vload<T, VX>(op.gx + c) : zero;
+            gyp = act ? vload<T, VX>(op.gy + c) : zero;
+            gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+            if (ln.lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
+        }
+        Vec<T, VX> ax;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            const int i = ln.i0 + e;
+            const T x = xc.a[e];
+            const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
+            const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
+            T gm, gp, gs, gn;
+            if constexpr (PC) {
+                gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                gp = gxp.a[e];
+                gs = gym.a[e];
+                gn = gyp.a[e];
+            } else {
+                gm = gp = L.gx;
+                gs = gn = L.gy;
+            }
+            T a = L.sink * x;
+            if (i > 0) a += gm * (x - xl);
+            if (i < nx - 1) a += gp * (x - xr);
+            if (ln.j > 0) a += gs * (x - xso.a[e]);
+            if (ln.j < ny - 1) a += gn * (x - xno.a[e]);
+            if (l > 0) a += L.gzd * (x - xdn.a[e]);
+            if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
+            ax.a[e] = a;
+        }
+        if (act) emit(l, c, xc, ax);
         xdn = xc;
         xc = xup;
     }
-}
-
-__device__ __forceinline__ void tile_ij(int &i, int &j) {
-    i = blockIdx.x * kBX + threadIdx.x;
-    j = blockIdx.y * kBY + threadIdx.y;
 }
 
 template <typename T>
@@ -152,272 +213,254 @@ __device__ __forceinline__ bool finite_val(T v) {
 }
 
 // ------------------------------------------------------------------ apply
-template <typename T, bool PC>
-__global__ __launch_bounds__(kThreads) void k_apply(OpView<T> op, const T *__restrict__ x,
-                                                    T *__restrict__ y) {
-    int i, j;
-    tile_ij(i, j);
-    if (i >= op.nx || j >= op.ny) return;
-    column<T, PC>(
-        op, i, j, [&](int64_t q) { return x[q]; },
-        [&](int, int64_t c, T, T ax) { y[c] = ax; });
+template <typename T, bool PC, int VX>
+__global__ __launch_bounds__(512) void k_apply(OpView<T> op, const T *__restrict__ x,
+                                               T *__restrict__ y) {
+    const Lane ln = lane_of<VX>(op);
+    column<T, PC, VX>(
+        op, ln, [&](int64_t q) { return vload<T, VX>(x + q); }, [&](int64_t q) { return x[q]; },
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax) { vstore<T, VX>(y + c, ax); });
+}
+
+// Convergence test of the first kernel after a CG update (all workgroups agree).
+template <typename T>
+__device__ __forceinline__ bool conv_test(int k, CgState<T> *st, const T *part, int np) {
+    const T rr = reduce_prev(part, np);
+    const bool stop = !(rr > st->tol2) || !finite_val(rr);
+    if (blockIdx.x == 0 && tid_lin() == 0) {
+        st->rr = rr;
+        st->iter = k + 1;
+        if (stop) st->done = finite_val(rr) ? 1 : 4;
+    }
+    return stop;
 }
 
 // ------------------------------------------------------------ Chebyshev sweep
-template <typename T, bool PC, int MODE, bool LAST>
-__global__ __launch_bounds__(kThreads) void k_cheb(OpView<T> op, const T *__restrict__ z, T *zo,
-                                                   const T *__restrict__ r, T c1, T c2, T inv_th,
-                                                   CgState<T> *st, T *partials,
-                                                   unsigned *counter) {
+template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK>
+__global__ __launch_bounds__(512) void k_cheb(OpView<T> op, int k, const T *__restrict__ z, T *zo,
+                                              const T *__restrict__ r, T c1, T c2, T inv_th,
+                                              CgState<T> *st, const T *__restrict__ part_in,
+                                              int np_in, T *__restrict__ part_out) {
     if (st->done) return;
-    int i, j;
-    tile_ij(i, j);
+    if constexpr (CHK) {
+        if (conv_test(k, st, part_in, np_in)) return;
+    }
+    const Lane ln = lane_of<VX>(op);
     T acc[1] = {T(0)};
-    if (i < op.nx && j < op.ny) {
-        auto X = [&](int64_t q) -> T {
-            if constexpr (MODE == 1) return r[q] * inv_th;
-            else return z[q];
-        };
-        column<T, PC>(op, i, j, X, [&](int, int64_t c, T zj, T az) {
-            const T rc = r[c];
-            T zm;
-            if constexpr (MODE == 0) zm = zo[c];
-            else if constexpr (MODE == 2) zm = rc * inv_th;
-            else zm = T(0);
-            const T zn = zj + c1 * (zj - zm) + c2 * (rc - az);
-            zo[c] = zn;
-            if constexpr (LAST) acc[0] += rc * zn;
-        });
-    }
-    if constexpr (LAST) {
-        if (grid_reduce<T, 1>(acc, 0u, partials, counter)) {
-            if (tid_lin() == 0) {
-                st->rz_new = acc[0];
-                if (!(acc[0] > T(0)) || !finite_val(acc[0])) st->done = 4;
-            }
+    auto XV = [&](int64_t q) -> Vec<T, VX> {
+        if constexpr (MODE == 1) {
+            Vec<T, VX> v = vload<T, VX>(r + q);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) v.a[e] *= inv_th;
+            return v;
+        } else {
+            return vload<T, VX>(z + q);
         }
-    }
+    };
+    auto XS = [&](int64_t q) -> T {
+        if constexpr (MODE == 1) return r[q] * inv_th;
+        else return z[q];
+    };
+    column<T, PC, VX>(op, ln, XV, XS,
+                      [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az) {
+                          const Vec<T, VX> rc = vload<T, VX>(r + c);
+                          Vec<T, VX> zm;
+                          if constexpr (MODE == 0) zm = vload<T, VX>(zo + c);
+                          Vec<T, VX> zn;
+#pragma unroll
+                          for (int e = 0; e < VX; ++e) {
+                              T m;
+                              if constexpr (MODE == 0) m = zm.a[e];
+                              else if constexpr (MODE == 2) m = rc.a[e] * inv_th;
+                              else m = T(0);
+                              zn.a[e] = zj.a[e] + c1 * (zj.a[e] - m) + c2 * (rc.a[e] - az.a[e]);
+                              if constexpr (LAST) acc[0] += rc.a[e] * zn.a[e];
+                          }
+                          vstore<T, VX>(zo + c, zn);
+                      });
+    if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out);
 }
 
-// z = a*r, and r^T z into st->rz_new (degree-1 preconditioner).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scale_dot(int64_t n, const T *__restrict__ r, T a,
-                                                        T *__restrict__ z, CgState<T> *st,
-                                                        T *partials, unsigned *counter) {
+// z = a r (degree-1 preconditioner), partials of r^T z.
+template <typename T, bool CHK>
+__global__ __launch_bounds__(256) void k_scale(int64_t n, const T *__restrict__ r, T a,
+                                               T *__restrict__ z, int k, CgState<T> *st,
+                                               const T *__restrict__ part_in, int np_in,
+                                               T *__restrict__ part_out) {
     if (st->done) return;
+    if constexpr (CHK) {
+        if (conv_test(k, st, part_in, np_in)) return;
+    }
     T acc[1] = {T(0)};
-    const int64_t stride = (int64_t)gridDim.x * gridDim.y * kThreads;
-    for (int64_t q = (int64_t)(blockIdx.x + gridDim.x * blockIdx.y) * kThreads + tid_lin(); q < n;
-         q += stride) {
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride) {
         const T v = a * r[q];
         z[q] = v;
         acc[0] += r[q] * v;
     }
-    if (grid_reduce<T, 1>(acc, 0u, partials, counter)) {
-        if (tid_lin() == 0) {
-            st->rz_new = acc[0];
-            if (!(acc[0] > T(0)) || !finite_val(acc[0])) st->done = 4;
-        }
-    }
+    block_partials<T, 1>(acc, 0u, part_out);
 }
 
 // ---------------------------------------------- CG: direction + SpMV + p^T A p
-template <typename T, bool PC>
-__global__ __launch_bounds__(kThreads) void k_cg_dir(OpView<T> op, const T *__restrict__ z,
-                                                     const T *__restrict__ pold,
-                                                     T *__restrict__ pnew, T *__restrict__ mu,
-                                                     CgState<T> *st, T *partials,
-                                                     unsigned *counter) {
+template <typename T, bool PC, int VX>
+__global__ __launch_bounds__(512) void k_cg_dir(OpView<T> op, int k, const T *__restrict__ z,
+                                                const T *__restrict__ pold,
+                                                T *__restrict__ pnew, T *__restrict__ mu,
+                                                CgState<T> *st, const T *__restrict__ part_in,
+                                                int np_in, T *__restrict__ part_out) {
     if (st->done) return;
-    const int first = st->first;
-    const T rz_new = st->rz_new;
-    const T beta = first ? T(0) : rz_new / st->rz;
-    int i, j;
-    tile_ij(i, j);
+    const T rz = reduce_prev(part_in, np_in);
+    const bool bad = !(rz > T(0)) || !finite_val(rz);
+    if (blockIdx.x == 0 && tid_lin() == 0) {
+        st->rz[k & 1] = rz;
+        if (bad) st->done = 4;
+    }
+    if (bad) return;
+    const T beta = (k == 0) ? T(0) : rz / st->rz[(k - 1) & 1];
+    const Lane ln = lane_of<VX>(op);
     T acc[1] = {T(0)};
-    if (i < op.nx && j < op.ny) {
-        auto X = [&](int64_t q) -> T { return first ? z[q] : z[q] + beta * pold[q]; };
-        column<T, PC>(op, i, j, X, [&](int, int64_t c, T pc, T ap) {
-            pnew[c] = pc;
-            mu[c] = ap;
-            acc[0] += pc * ap;
-        });
-    }
-    if (grid_reduce<T, 1>(acc, 0u, partials, counter)) {
-        if (tid_lin() == 0) {
-            const T pmu = acc[0];
-            st->pmu = pmu;
-            st->beta = beta;
-            st->rz = rz_new;
-            st->first = 0;
-            if (!(pmu > T(0)) || !finite_val(pmu)) {
-                st->done = 4;
-                st->alpha = T(0);
-            } else {
-                st->alpha = rz_new / pmu;
-            }
+    auto XV = [&](int64_t q) -> Vec<T, VX> {
+        Vec<T, VX> v = vload<T, VX>(z + q);
+        if (k > 0) {
+            const Vec<T, VX> p = vload<T, VX>(pold + q);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) v.a[e] += beta * p.a[e];
         }
-    }
+        return v;
+    };
+    auto XS = [&](int64_t q) -> T { return k > 0 ? z[q] + beta * pold[q] : z[q]; };
+    column<T, PC, VX>(op, ln, XV, XS,
+                      [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap) {
+                          vstore<T, VX>(pnew + c, p);
+                          vstore<T, VX>(mu + c, ap);
+#pragma unroll
+                          for (int e = 0; e < VX; ++e) acc[0] += p.a[e] * ap.a[e];
+                      });
+    block_partials<T, 1>(acc, 0u, part_out);
 }
 
 // ------------------------------------------------- CG: x += a p, r -= a mu, r^T r
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_update(int nx, int ny, int nz, T *__restrict__ x,
-                                                        const T *__restrict__ p,
-                                                        T *__restrict__ r,
-                                                        const T *__restrict__ mu,
-                                                        CgState<T> *st, T *partials,
-                                                        unsigned *counter) {
+template <typename T, int VX>
+__global__ __launch_bounds__(512) void k_cg_update(OpView<T> op, int k, T *__restrict__ x,
+                                                   const T *__restrict__ p, T *__restrict__ r,
+                                                   const T *__restrict__ mu, CgState<T> *st,
+                                                   const T *__restrict__ part_in, int np_in,
+                                                   T *__restrict__ part_out) {
     if (st->done) return;
-    const T alpha = st->alpha;
-    const bool fresh = (st->iter == 0);
-    int i, j;
-    tile_ij(i, j);
+    const T pmu = reduce_prev(part_in, np_in);
+    const bool bad = !(pmu > T(0)) || !finite_val(pmu);
+    if (bad) {
+        if (blockIdx.x == 0 && tid_lin() == 0) st->done = 4;
+        return;
+    }
+    const T alpha = st->rz[k & 1] / pmu;
+    const Lane ln = lane_of<VX>(op);
     T acc[1] = {T(0)};
-    if (i < nx && j < ny) {
-        const int64_t plane = (int64_t)nx * ny;
-        int64_t c = i + (int64_t)nx * j;
-        for (int l = 0; l < nz; ++l, c += plane) {
-            const T xn = (fresh ? T(0) : x[c]) + alpha * p[c];
-            const T rn = r[c] - alpha * mu[c];
-            x[c] = xn;
-            r[c] = rn;
-            acc[0] += rn * rn;
+    if (ln.act) {
+        const int64_t plane = (int64_t)op.nx * op.ny;
+        int64_t c = ln.i0 + (int64_t)op.nx * ln.j + plane * ln.l0;
+        for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
+            const Vec<T, VX> pv = vload<T, VX>(p + c), mv = vload<T, VX>(mu + c);
+            Vec<T, VX> rv = vload<T, VX>(r + c);
+            Vec<T, VX> xv = (k == 0) ? vzero<T, VX>() : vload<T, VX>(x + c);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                xv.a[e] += alpha * pv.a[e];
+                rv.a[e] -= alpha * mv.a[e];
+                acc[0] += rv.a[e] * rv.a[e];
+            }
+            vstore<T, VX>(x + c, xv);
+            vstore<T, VX>(r + c, rv);
         }
     }
-    if (grid_reduce<T, 1>(acc, 0u, partials, counter)) {
-        if (tid_lin() == 0) {
-            const T rr = acc[0];
-            st->rr = rr;
-            st->iter = st->iter + 1;
-            if (!finite_val(rr)) st->done = 4;
-            else if (rr <= st->tol2) st->done = 1;
-        }
-    }
+    block_partials<T, 1>(acc, 0u, part_out);
 }
 
-// ----------------------------- CG: true residual, drift and stagnation checks
-template <typename T, bool PC>
-__global__ __launch_bounds__(kThreads) void k_cg_check(OpView<T> op, const T *__restrict__ rhat,
-                                                       const T *__restrict__ x,
-                                                       const T *__restrict__ r, CgState<T> *st,
-                                                       int force, T *partials,
-                                                       unsigned *counter) {
-    if (st->done && !force) return;
-    const bool have_x = st->iter > 0;
-    int i, j;
-    tile_ij(i, j);
+// ----------------------------------------------------- CG: true residual check
+template <typename T, bool PC, int VX>
+__global__ __launch_bounds__(512) void k_cg_check(OpView<T> op, const T *__restrict__ rhat,
+                                                  const T *__restrict__ x,
+                                                  const T *__restrict__ r, int have_x,
+                                                  T *__restrict__ part_out) {
+    const Lane ln = lane_of<VX>(op);
     T acc[2] = {T(0), T(0)};
-    if (i < op.nx && j < op.ny) {
-        auto X = [&](int64_t q) -> T { return have_x ? x[q] : T(0); };
-        column<T, PC>(op, i, j, X, [&](int, int64_t c, T, T ax) {
-            const T rt = rhat[c] - ax;
-            const T d = rt - r[c];
-            acc[0] += rt * rt;
-            acc[1] += d * d;
-        });
-    }
-    if (grid_reduce<T, 2>(acc, 0u, partials, counter)) {
-        if (tid_lin() == 0) {
-            st->true_rr = acc[0];
-            st->drift_rr = acc[1];
-            if (!force) {
-                const T tn = sqrt(acc[0]);
-                // switching criteria of Section 4.4: drift ||r_true - r_low|| >=
-                // 0.5 ||r_true||, stagnation ||r_true^k|| > 0.9 ||r_true^{k-1}||
-                if (!finite_val(tn)) st->done = 4;
-                else if (sqrt(acc[1]) >= T(0.5) * tn) st->done = 2;
-                else if (st->true_prev >= T(0) && tn > T(0.9) * st->true_prev) st->done = 3;
-                st->true_prev = tn;
+    column<T, PC, VX>(
+        op, ln,
+        [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
+        [&](int64_t q) { return have_x ? x[q] : T(0); },
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax) {
+            const Vec<T, VX> rh = vload<T, VX>(rhat + c), rr = vload<T, VX>(r + c);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const T rt = rh.a[e] - ax.a[e];
+                const T d = rt - rr.a[e];
+                acc[0] += rt * rt;
+                acc[1] += d * d;
             }
-        }
-    }
+        });
+    block_partials<T, 2>(acc, 0u, part_out);
 }
 
 // ------------------------------------------------------- FP64 outer residual
-template <bool PC, typename TD, typename TI>
-__global__ __launch_bounds__(kThreads) void k_residual(
+template <bool PC, int VX, typename TD, typename TI>
+__global__ __launch_bounds__(512) void k_residual(
     OpView<double> op, const double *__restrict__ th_in, double in_off,
     const TD *__restrict__ delta, const double *__restrict__ P, const double *__restrict__ Tn,
     double tn_off, double *__restrict__ th_out, double *__restrict__ r64, TI *__restrict__ r_in,
-    TI *__restrict__ rhat, OuterStats *os, CgState<TI> *st, double inner_tol, double *partials,
-    unsigned *counter) {
-    int i, j;
-    tile_ij(i, j);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (i < op.nx && j < op.ny) {
-        auto X = [&](int64_t q) -> double {
-            double v = th_in ? th_in[q] - in_off : 0.0;
-            if (delta) v += (double)delta[q];
-            return v;
-        };
-        column<double, PC>(op, i, j, X, [&](int l, int64_t c, double th, double ath) {
-            double b = P[c];
-            if (Tn) b += op.lc[l].cap * (Tn[c] - tn_off);
-            const double rc = b - ath;
-            if (th_out) th_out[c] = th;
-            if (r64) r64[c] = rc;
-            if (r_in) {
-                const TI v = (TI)rc;
-                r_in[c] = v;
-                rhat[c] = v;
+    TI *__restrict__ rhat, double *__restrict__ part_out) {
+    const Lane ln = lane_of<VX>(op);
+    double acc[kResidualValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    auto XS = [&](int64_t q) -> double {
+        double v = th_in ? th_in[q] - in_off : 0.0;
+        if (delta) v += (double)delta[q];
+        return v;
+    };
+    auto XV = [&](int64_t q) -> Vec<double, VX> {
+        Vec<double, VX> v;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v.a[e] = XS(q + e);
+        return v;
+    };
+    column<double, PC, VX>(
+        op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
+            const double cap = op.lc[l].cap;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                double b = P[c + e];
+                if (Tn) b += cap * (Tn[c + e] - tn_off);
+                const double rc = b - ath.a[e];
+                if (th_out) th_out[c + e] = th.a[e];
+                if (r64) r64[c + e] = rc;
+                if (r_in) {
+                    const TI v = (TI)rc;
+                    r_in[c + e] = v;
+                    rhat[c + e] = v;
+                }
+                acc[0] += rc * rc;
+                acc[1] += b * b;
+                if (delta) acc[2] = fmax(acc[2], fabs((double)delta[c + e]));
+                acc[3] = fmax(acc[3], fabs(th.a[e]));
+                acc[4] += isfinite(rc) ? 0.0 : 1.0;
             }
-            acc[0] += rc * rc;
-            acc[1] += b * b;
-            if (delta) acc[2] = fmax(acc[2], fabs((double)delta[c]));
-            acc[3] = fmax(acc[3], fabs(th));
-            acc[4] += isfinite(rc) ? 0.0 : 1.0;
         });
-    }
-    if (grid_reduce<double, 5>(acc, (1u << 2) | (1u << 3), partials, counter)) {
-        if (tid_lin() == 0) {
-            os->rr = acc[0];
-            os->bb = acc[1];
-            os->dinf = acc[2];
-            os->thinf = acc[3];
-            os->bad = acc[4];
-            if (st) {
-                const TI rr0 = (TI)acc[0];
-                st->rr0 = rr0;
-                st->rr = rr0;
-                st->tol2 = (TI)(inner_tol * inner_tol * acc[0]);
-                st->done = (acc[0] > 0.0 && acc[4] == 0.0) ? 0 : (acc[4] == 0.0 ? 1 : 4);
-                st->iter = 0;
-                st->first = 1;
-                st->true_prev = TI(-1);
-                st->true_rr = rr0;
-                st->drift_rr = TI(0);
-                st->rz = TI(0);
-                st->rz_new = TI(0);
-                st->alpha = TI(0);
-                st->beta = TI(0);
-            }
-        }
-    }
+    block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out);
 }
 
-__global__ __launch_bounds__(kThreads) void k_add_scalar(int64_t n, const double *__restrict__ x,
-                                                         double a, double *__restrict__ y) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid_lin(); q < n; q += stride)
+__global__ __launch_bounds__(256) void k_add_scalar(int64_t n, const double *__restrict__ x,
+                                                    double a, double *__restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride)
         y[q] = x[q] + a;
 }
 
-__global__ __launch_bounds__(kThreads) void k_to_float(int64_t n, const double *__restrict__ x,
-                                                       float *__restrict__ y) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid_lin(); q < n; q += stride)
-        y[q] = (float)x[q];
-}
-
 // ------------------------------------------------------ coefficient build
-__global__ __launch_bounds__(kThreads) void k_build_lateral(
+__global__ __launch_bounds__(256) void k_build_lateral(
     int nx, int ny, int nz, double dx, double dy, const double *__restrict__ dz,
     const double *__restrict__ k_lat, const double *__restrict__ mult, double *__restrict__ gx64,
     double *__restrict__ gy64, float *__restrict__ gx32, float *__restrict__ gy32,
-    unsigned long long *maxrow, unsigned int *bad) {
-    int i, j;
-    tile_ij(i, j);
+    unsigned int *bad) {
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const int64_t plane = (int64_t)nx * ny;
     int64_t c = i + (int64_t)nx * j;
@@ -437,14 +480,13 @@ __global__ __launch_bounds__(kThreads) void k_build_lateral(
     }
 }
 
-// Per-layer max over cells of the lateral off-diagonal row sum, after the planes exist.
-__global__ __launch_bounds__(kThreads) void k_lateral_rowmax(int nx, int ny, int nz,
-                                                             const double *__restrict__ gx,
-                                                             const double *__restrict__ gy,
-                                                             unsigned long long *maxrow) {
-    int i, j;
-    tile_ij(i, j);
-    const int t = tid_lin(), lane = t & 63;
+// Per-layer max over cells of the lateral off-diagonal row sum (after the planes exist).
+__global__ __launch_bounds__(256) void k_lateral_rowmax(int nx, int ny, int nz,
+                                                        const double *__restrict__ gx,
+                                                        const double *__restrict__ gy,
+                                                        unsigned long long *maxrow) {
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const bool act = (i < nx && j < ny);
     const int64_t plane = (int64_t)nx * ny;
     for (int l = 0; l < nz; ++l) {
@@ -454,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_lateral_rowmax(int nx, int ny, int
             s = gx[c] + gy[c] + (i > 0 ? gx[c - 1] : 0.0) + (j > 0 ? gy[c - nx] : 0.0);
         }
         s = wave_max(s);
-        if (lane == 0) atomicMax(&maxrow[l], (unsigned long long)__double_as_longlong(s));
+        if (threadIdx.x == 0) atomicMax(&maxrow[l], (unsigned long long)__double_as_longlong(s));
     }
 }
 
@@ -467,105 +509,102 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-__global__ __launch_bounds__(kThreads) void k_fill_random(int64_t n, uint64_t seed,
-                                                          float *__restrict__ v) {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid_lin(); q < n; q += stride) {
+__global__ __launch_bounds__(256) void k_fill_random(int64_t n, uint64_t seed,
+                                                     float *__restrict__ v) {
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride) {
         const uint64_t h = splitmix64(seed ^ (uint64_t)q * 0xD1B54A32D192ED03ull);
         // uniform in [-1, 1) from the top 24 bits
         v[q] = (float)((double)(h >> 40) * (2.0 / 16777216.0) - 1.0);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_norm2(int64_t n, const float *__restrict__ v,
-                                                    float *out, float *partials,
-                                                    unsigned *counter) {
+__global__ __launch_bounds__(256) void k_norm2(int64_t n, const float *__restrict__ v,
+                                               float *__restrict__ part_out) {
     float acc[1] = {0.f};
-    const int64_t stride = (int64_t)gridDim.x * gridDim.y * kThreads;
-    for (int64_t q = (int64_t)(blockIdx.x + gridDim.x * blockIdx.y) * kThreads + tid_lin(); q < n;
-         q += stride)
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride)
         acc[0] += v[q] * v[q];
-    if (grid_reduce<float, 1>(acc, 0u, partials, counter))
-        if (tid_lin() == 0) *out = acc[0];
+    block_partials<float, 1>(acc, 0u, part_out);
 }
 
-__global__ __launch_bounds__(kThreads) void k_scale_rsqrt(int64_t n, const float *__restrict__ v,
-                                                          const float *nrm2,
-                                                          float *__restrict__ out) {
-    const float s = 1.0f / sqrtf(*nrm2);
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid_lin(); q < n; q += stride)
+__global__ __launch_bounds__(256) void k_scale_rsqrt(int64_t n, const float *__restrict__ v,
+                                                     const float *__restrict__ part_in,
+                                                     int np_in, float *__restrict__ out) {
+    const float s = 1.0f / sqrtf(reduce_prev(part_in, np_in));
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride)
         out[q] = v[q] * s;
 }
 
-template <bool PC>
-__global__ __launch_bounds__(kThreads) void k_lanczos_av(OpView<float> op,
-                                                         const float *__restrict__ v,
-                                                         const float *__restrict__ vprev,
-                                                         const float *beta_prev,
-                                                         float *__restrict__ w, float *alpha_out,
-                                                         float *partials, unsigned *counter) {
-    const float bp = beta_prev ? *beta_prev : 0.f;
-    int i, j;
-    tile_ij(i, j);
+template <bool PC, int VX>
+__global__ __launch_bounds__(512) void k_lanczos_av(OpView<float> op, int j,
+                                                    const float *__restrict__ v,
+                                                    const float *__restrict__ vprev,
+                                                    const float *__restrict__ lz,
+                                                    float *__restrict__ w,
+                                                    float *__restrict__ part_out) {
+    const float bp = j > 0 ? lz[256 + j - 1] : 0.f;
+    const Lane ln = lane_of<VX>(op);
     float acc[1] = {0.f};
-    if (i < op.nx && j < op.ny) {
-        column<float, PC>(
-            op, i, j, [&](int64_t q) { return v[q]; },
-            [&](int, int64_t c, float vc, float av) {
-                const float wc = vprev ? av - bp * vprev[c] : av;
-                w[c] = wc;
-                acc[0] += vc * wc;
-            });
-    }
-    if (grid_reduce<float, 1>(acc, 0u, partials, counter))
-        if (tid_lin() == 0) *alpha_out = acc[0];
+    column<float, PC, VX>(
+        op, ln, [&](int64_t q) { return vload<float, VX>(v + q); }, [&](int64_t q) { return v[q]; },
+        [&](int, int64_t c, const Vec<float, VX> &vc, const Vec<float, VX> &av) {
+            Vec<float, VX> wc;
+            Vec<float, VX> pv = vzero<float, VX>();
+            if (j > 0) pv = vload<float, VX>(vprev + c);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                wc.a[e] = av.a[e] - bp * pv.a[e];
+                acc[0] += vc.a[e] * wc.a[e];
+            }
+            vstore<float, VX>(w + c, wc);
+        });
+    block_partials<float, 1>(acc, 0u, part_out);
 }
 
-__global__ __launch_bounds__(kThreads) void k_lanczos_orth(int64_t n, float *__restrict__ w,
-                                                           const float *__restrict__ v,
-                                                           const float *alpha, float *beta_out,
-                                                           float *partials, unsigned *counter) {
-    const float a = *alpha;
+__global__ __launch_bounds__(256) void k_lanczos_orth(int64_t n, int j, float *__restrict__ w,
+                                                      const float *__restrict__ v,
+                                                      float *__restrict__ lz,
+                                                      const float *__restrict__ part_in,
+                                                      int np_in, float *__restrict__ part_out) {
+    const float a = reduce_prev(part_in, np_in);
+    if (blockIdx.x == 0 && tid_lin() == 0) lz[j] = a;
     float acc[1] = {0.f};
-    const int64_t stride = (int64_t)gridDim.x * gridDim.y * kThreads;
-    for (int64_t q = (int64_t)(blockIdx.x + gridDim.x * blockIdx.y) * kThreads + tid_lin(); q < n;
-         q += stride) {
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride) {
         const float wc = w[q] - a * v[q];
         w[q] = wc;
         acc[0] += wc * wc;
     }
-    if (grid_reduce<float, 1>(acc, 0u, partials, counter))
-        if (tid_lin() == 0) *beta_out = sqrtf(acc[0]);
+    block_partials<float, 1>(acc, 0u, part_out);
 }
 
-__global__ __launch_bounds__(kThreads) void k_div_scalar(int64_t n, float *__restrict__ w,
-                                                         const float *den) {
-    const float s = 1.0f / *den;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid_lin(); q < n; q += stride) w[q] *= s;
+__global__ __launch_bounds__(256) void k_lanczos_div(int64_t n, int j, float *__restrict__ w,
+                                                     float *__restrict__ lz,
+                                                     const float *__restrict__ part_in,
+                                                     int np_in) {
+    const float b = sqrtf(reduce_prev(part_in, np_in));
+    if (blockIdx.x == 0 && tid_lin() == 0) lz[256 + j] = b;
+    const float s = 1.0f / b;
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride) w[q] *= s;
 }
 
 // --------------------------------------------------------------- adjoint
-// Per-layer sums with one partial per workgroup and layer; the last workgroup
-// reduces each layer's partials in a fixed order.
 template <bool PC>
-__global__ __launch_bounds__(kThreads) void k_adjoint_sums(OpView<double> op,
-                                                           const double *__restrict__ lam,
-                                                           const double *__restrict__ T,
-                                                           double t_amb, double *out,
-                                                           double *partials, unsigned *counter) {
-    constexpr int NW = kThreads / 64;
-    __shared__ double sh[NW][2 * kMaxLayers];
-    __shared__ int is_last;
-    int i, j;
-    tile_ij(i, j);
-    const int t = tid_lin(), lane = t & 63, w = t >> 6;
-    const int nb = gridDim.x * gridDim.y, b = blockIdx.x + gridDim.x * blockIdx.y;
+__global__ __launch_bounds__(256) void k_adjoint_sums(OpView<double> op,
+                                                      const double *__restrict__ lam,
+                                                      const double *__restrict__ T, double t_amb,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[kMaxBY][2 * kMaxLayers];
+    const int i = blockIdx.x % ((op.nx + kWave - 1) / kWave) * kWave + threadIdx.x;
+    const int j = blockIdx.x / ((op.nx + kWave - 1) / kWave) * blockDim.y + threadIdx.y;
+    const int lane = threadIdx.x, w = threadIdx.y;
     const bool act = (i < op.nx && j < op.ny);
     const int nz = op.nz, nx = op.nx, ny = op.ny;
     const int64_t plane = (int64_t)nx * ny;
-    int64_t c = i + (int64_t)nx * j;
+    int64_t c = act ? i + (int64_t)nx * j : 0;
     for (int l = 0; l < nz; ++l, c += plane) {
         const LayerCoef<double> L = op.lc[l];
         double slat = 0.0, svert = 0.0;
@@ -589,256 +628,248 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_sums(OpView<double> op,
         }
     }
     __syncthreads();
-    if (t == 0) {
+    if (tid_lin() == 0) {
+        const int nb = gridDim.x;
         for (int l = 0; l < nz; ++l) {
             double a = 0.0, v = 0.0;
-            for (int q = 0; q < NW; ++q) {
+            for (int q = 0; q < (int)blockDim.y; ++q) {
                 a += sh[q][l];
                 v += sh[q][kMaxLayers + l];
             }
-            partials[(size_t)l * nb + b] = a;
-            partials[(size_t)(nz + l) * nb + b] = v;
+            part[(size_t)l * nb + blockIdx.x] = a;
+            part[(size_t)(nz + l) * nb + blockIdx.x] = v;
         }
-        __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        is_last = (ticket == (unsigned)(nb - 1));
+    }
+}
+
+// One workgroup: per-layer fixed-order sums of the partials, then the gradient.
+__global__ __launch_bounds__(256) void k_adjoint_finish(int nz, int np,
+                                                        const double *__restrict__ part,
+                                                        const double *__restrict__ fac,
+                                                        double *__restrict__ dk) {
+    __shared__ double sums[2 * kMaxLayers];
+    for (int k = 0; k < 2 * nz; ++k) {
+        const double s = reduce_prev(part + (size_t)k * np, np);
+        if (tid_lin() == 0) sums[k] = s;
     }
     __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    for (int k = 0; k < 2 * nz; ++k) {
-        double a = 0.0;
-        for (int q = t; q < nb; q += kThreads) a += load_coherent(&partials[(size_t)k * nb + q]);
-        a = wave_sum(a);
-        __syncthreads();
-        if (lane == 0) sh[w][0] = a;
-        __syncthreads();
-        if (t == 0) {
-            double s = 0.0;
-            for (int q = 0; q < NW; ++q) s += sh[q][0];
-            out[k] = s;
-        }
+    const int l = tid_lin();
+    if (l < nz) {
+        const double *fac_lat = fac, *fac_up = fac + nz, *fac_dn = fac + 2 * nz;
+        dk[l] = -fac_lat[l] * sums[l];
+        double v = 0.0;
+        if (l < nz - 1) v += fac_up[l] * sums[nz + l];
+        if (l > 0) v += fac_dn[l] * sums[nz + l - 1];
+        dk[nz + l] = -v;
     }
-    if (t == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_adjoint_finish(int nz, const double *__restrict__ sums,
-                                 const double *__restrict__ fac_lat,
-                                 const double *__restrict__ fac_up,
-                                 const double *__restrict__ fac_dn, double *__restrict__ dk) {
-    const int l = threadIdx.x;
-    if (l >= nz) return;
-    dk[l] = -fac_lat[l] * sums[l];
-    double v = 0.0;
-    if (l < nz - 1) v += fac_up[l] * sums[nz + l];
-    if (l > 0) v += fac_dn[l] * sums[nz + l - 1];
-    dk[nz + l] = -v;
-}
-
-inline unsigned blocks_1d(int64_t n) {
-    int64_t b = (n + kThreads - 1) / kThreads;
-    if (b > 65536) b = 65536;
-    if (b < 1) b = 1;
-    return (unsigned)b;
+template <typename T>
+dim3 block_of(const OpView<T> &op) {
+    return dim3(kWave, (unsigned)op.by, 1);
 }
 
 }  // namespace
 
 // =================================================================== launchers
+// CALL is a parenthesised statement using the compile-time VX chosen from the
+// runtime lane width VXV (FP32: 1, 2, 4; FP64: 1, 2).
+#define CUTH_STRIP(...) __VA_ARGS__
+#define CUTH_VX_DISPATCH(T, VXV, CALL)                                          \
+    do {                                                                        \
+        if (VXV == 4 && sizeof(T) == 4) { constexpr int VX = 4; CUTH_STRIP CALL; } \
+        else if (VXV == 2) { constexpr int VX = 2; CUTH_STRIP CALL; }           \
+        else { constexpr int VX = 1; CUTH_STRIP CALL; }                         \
+    } while (0)
+
 template <typename T>
 void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
-    if (op.gx) hipLaunchKernelGGL((k_apply<T, true>), g, b, 0, s, op, x, y);
-    else hipLaunchKernelGGL((k_apply<T, false>), g, b, 0, s, op, x, y);
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
+    if (op.gx) CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_apply<T, true, VX>), g, b, 0, s, op, x, y)));
+    else CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_apply<T, false, VX>), g, b, 0, s, op, x, y)));
 }
 
-template <typename T, bool PC>
-static void cheb_dispatch(const OpView<T> &op, int mode, bool last, const T *z, T *zo, const T *r,
-                          T c1, T c2, T inv_th, CgState<T> *st, RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
-    T *pp = (T *)red.partials;
-#define CUTH_CHEB(M, LST)                                                                       \
-    hipLaunchKernelGGL((k_cheb<T, PC, M, LST>), g, b, 0, s, op, z, zo, r, c1, c2, inv_th, st, pp, \
-                       red.counter)
-    if (mode == 0) {
-        if (last) CUTH_CHEB(0, true); else CUTH_CHEB(0, false);
-    } else if (mode == 1) {
-        if (last) CUTH_CHEB(1, true); else CUTH_CHEB(1, false);
+template <typename T, bool PC, int VX>
+static void cheb_modes(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
+                       const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *pin, int npin,
+                       T *pout, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
+#define CUTH_CHEB(M, LST, CK)                                                                     \
+    hipLaunchKernelGGL((k_cheb<T, PC, VX, M, LST, CK>), g, b, 0, s, op, k, z, zo, r, c1, c2,       \
+                       inv_th, st, pin, npin, pout)
+    if (mode == 1) {
+        if (chk) {
+            if (last) CUTH_CHEB(1, true, true); else CUTH_CHEB(1, false, true);
+        } else {
+            if (last) CUTH_CHEB(1, true, false); else CUTH_CHEB(1, false, false);
+        }
+    } else if (mode == 2) {
+        if (last) CUTH_CHEB(2, true, false); else CUTH_CHEB(2, false, false);
     } else {
-        if (last) CUTH_CHEB(2, true); else CUTH_CHEB(2, false);
+        if (last) CUTH_CHEB(0, true, false); else CUTH_CHEB(0, false, false);
     }
 #undef CUTH_CHEB
 }
 
 template <typename T>
-void launch_cheb(const OpView<T> &op, int mode, bool last, const T *z, T *zo, const T *r, T c1,
-                 T c2, T inv_th, CgState<T> *st, RedScratch red, hipStream_t s) {
-    if (op.gx) cheb_dispatch<T, true>(op, mode, last, z, zo, r, c1, c2, inv_th, st, red, s);
-    else cheb_dispatch<T, false>(op, mode, last, z, zo, r, c1, c2, inv_th, st, red, s);
-}
-
-template <typename T>
-void launch_scale(int64_t n, const T *x, T a, T *y, CgState<T> *st, bool, const T *,
-                  RedScratch red, hipStream_t s) {
-    hipLaunchKernelGGL((k_scale_dot<T>), dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, x, a, y, st,
-                       (T *)red.partials, red.counter);
-}
-
-template <typename T>
-void launch_cg_dir(const OpView<T> &op, const T *z, const T *pold, T *pnew, T *mu, CgState<T> *st,
-                   RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
+void launch_cheb(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
+                 const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *part_in, int np_in,
+                 T *part_out, hipStream_t s) {
     if (op.gx)
-        hipLaunchKernelGGL((k_cg_dir<T, true>), g, b, 0, s, op, z, pold, pnew, mu, st,
-                           (T *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(T, op.vx, (cheb_modes<T, true, VX>(op, mode, last, chk, k, z, zo, r, c1, c2,
+                                                            inv_th, st, part_in, np_in, part_out, s)));
     else
-        hipLaunchKernelGGL((k_cg_dir<T, false>), g, b, 0, s, op, z, pold, pnew, mu, st,
-                           (T *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(T, op.vx, (cheb_modes<T, false, VX>(op, mode, last, chk, k, z, zo, r, c1,
+                                                             c2, inv_th, st, part_in, np_in,
+                                                             part_out, s)));
 }
 
 template <typename T>
-void launch_cg_update(const OpView<T> &op, T *x, const T *p, T *r, const T *mu, CgState<T> *st,
-                      RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
-    hipLaunchKernelGGL((k_cg_update<T>), g, b, 0, s, op.nx, op.ny, op.nz, x, p, r, mu, st,
-                       (T *)red.partials, red.counter);
+void launch_scale(int64_t n, const T *r, T a, T *z, bool chk, int k, CgState<T> *st,
+                  const T *part_in, int np_in, T *part_out, hipStream_t s) {
+    const dim3 g(red_blocks(n)), b(kWave, 4);
+    if (chk) hipLaunchKernelGGL((k_scale<T, true>), g, b, 0, s, n, r, a, z, k, st, part_in, np_in, part_out);
+    else hipLaunchKernelGGL((k_scale<T, false>), g, b, 0, s, n, r, a, z, k, st, part_in, np_in, part_out);
 }
 
 template <typename T>
-void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r, CgState<T> *st,
-                     int force, RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
+void launch_cg_dir(const OpView<T> &op, int k, const T *z, const T *pold, T *pnew, T *mu,
+                   CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
     if (op.gx)
-        hipLaunchKernelGGL((k_cg_check<T, true>), g, b, 0, s, op, rhat, x, r, st, force,
-                           (T *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_dir<T, true, VX>), g, b, 0, s, op, k, z,
+                                                       pold, pnew, mu, st, part_in, np_in, part_out)));
     else
-        hipLaunchKernelGGL((k_cg_check<T, false>), g, b, 0, s, op, rhat, x, r, st, force,
-                           (T *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_dir<T, false, VX>), g, b, 0, s, op, k, z,
+                                                       pold, pnew, mu, st, part_in, np_in, part_out)));
+}
+
+template <typename T>
+void launch_cg_update(const OpView<T> &op, int k, T *x, const T *p, T *r, const T *mu,
+                      CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
+    CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_update<T, VX>), g, b, 0, s, op, k, x, p, r,
+                                                   mu, st, part_in, np_in, part_out)));
+}
+
+template <typename T>
+void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r, bool have_x,
+                     T *part_out, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
+    const int hx = have_x ? 1 : 0;
+    if (op.gx)
+        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_check<T, true, VX>), g, b, 0, s, op, rhat,
+                                                       x, r, hx, part_out)));
+    else
+        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_check<T, false, VX>), g, b, 0, s, op,
+                                                       rhat, x, r, hx, part_out)));
 }
 
 template <typename TD, typename TI>
 void launch_residual(const OpView<double> &op, const double *th_in, double in_off, const TD *delta,
-                     const double *P, const double *Tn, double tn_off, double *th_out,
-                     double *r64, TI *r_in, TI *rhat, OuterStats *os, CgState<TI> *st,
-                     double inner_tol, RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
+                     const double *P, const double *Tn, double tn_off, double *th_out, double *r64,
+                     TI *r_in, TI *rhat, double *part_out, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
     if (op.gx)
-        hipLaunchKernelGGL((k_residual<true, TD, TI>), g, b, 0, s, op, th_in, in_off, delta, P, Tn,
-                           tn_off, th_out, r64, r_in, rhat, os, st, inner_tol,
-                           (double *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(double, op.vx, (hipLaunchKernelGGL((k_residual<true, VX, TD, TI>), g, b, 0, s,
+                                                            op, th_in, in_off, delta, P, Tn, tn_off,
+                                                            th_out, r64, r_in, rhat, part_out)));
     else
-        hipLaunchKernelGGL((k_residual<false, TD, TI>), g, b, 0, s, op, th_in, in_off, delta, P,
-                           Tn, tn_off, th_out, r64, r_in, rhat, os, st, inner_tol,
-                           (double *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(double, op.vx, (hipLaunchKernelGGL((k_residual<false, VX, TD, TI>), g, b, 0,
+                                                            s, op, th_in, in_off, delta, P, Tn,
+                                                            tn_off, th_out, r64, r_in, rhat,
+                                                            part_out)));
 }
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_add_scalar, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, x, a, y);
-}
-
-void launch_copy_to_float(int64_t n, const double *x, float *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_float, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, x, y);
+    hipLaunchKernelGGL(k_add_scalar, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, x, a, y);
 }
 
 void launch_build_lateral(int nx, int ny, int nz, double dx, double dy, const double *dz,
                           const double *k_lat, const double *mult, double *gx64, double *gy64,
                           float *gx32, float *gy32, unsigned long long *maxrow, unsigned int *bad,
                           hipStream_t s) {
-    const dim3 g = tile_grid(nx, ny), b(kBX, kBY);
+    const dim3 g((nx + kWave - 1) / kWave, (ny + 3) / 4), b(kWave, 4);
     hipLaunchKernelGGL(k_build_lateral, g, b, 0, s, nx, ny, nz, dx, dy, dz, k_lat, mult, gx64,
-                       gy64, gx32, gy32, maxrow, bad);
+                       gy64, gx32, gy32, bad);
     hipLaunchKernelGGL(k_lateral_rowmax, g, b, 0, s, nx, ny, nz, (const double *)gx64,
                        (const double *)gy64, maxrow);
 }
 
 void launch_fill_random(int64_t n, uint64_t seed, float *v, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_random, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, seed, v);
+    hipLaunchKernelGGL(k_fill_random, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, seed, v);
 }
 
-void launch_norm2(int64_t n, const float *v, float *out, RedScratch red, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm2, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, v, out,
-                       (float *)red.partials, red.counter);
+void launch_norm2(int64_t n, const float *v, float *part_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm2, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, v, part_out);
 }
 
-void launch_scale_by_rsqrt(int64_t n, const float *v, const float *nrm2, float *out,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_rsqrt, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, v, nrm2, out);
+void launch_scale_rsqrt(int64_t n, const float *v, const float *part_in, int np_in, float *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_rsqrt, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, v, part_in,
+                       np_in, out);
 }
 
-void launch_lanczos_av(const OpView<float> &op, const float *v, const float *vprev,
-                       const float *beta_prev, float *w, float *alpha_out, RedScratch red,
-                       hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
+void launch_lanczos_av(const OpView<float> &op, int j, const float *v, const float *vprev,
+                       const float *lz, float *w, float *part_out, hipStream_t s) {
+    const dim3 g(stencil_blocks(op)), b = block_of(op);
     if (op.gx)
-        hipLaunchKernelGGL((k_lanczos_av<true>), g, b, 0, s, op, v, vprev, beta_prev, w,
-                           alpha_out, (float *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(float, op.vx, (hipLaunchKernelGGL((k_lanczos_av<true, VX>), g, b, 0, s, op, j,
+                                                           v, vprev, lz, w, part_out)));
     else
-        hipLaunchKernelGGL((k_lanczos_av<false>), g, b, 0, s, op, v, vprev, beta_prev, w,
-                           alpha_out, (float *)red.partials, red.counter);
+        CUTH_VX_DISPATCH(float, op.vx, (hipLaunchKernelGGL((k_lanczos_av<false, VX>), g, b, 0, s, op, j,
+                                                           v, vprev, lz, w, part_out)));
 }
 
-void launch_lanczos_orth(int64_t n, float *w, const float *v, const float *alpha,
-                         float *beta_out, RedScratch red, hipStream_t s) {
-    hipLaunchKernelGGL(k_lanczos_orth, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, w, v, alpha,
-                       beta_out, (float *)red.partials, red.counter);
+void launch_lanczos_orth(int64_t n, int j, float *w, const float *v, float *lz,
+                         const float *part_in, int np_in, float *part_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_orth, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, j, w, v, lz,
+                       part_in, np_in, part_out);
 }
 
-void launch_div_scalar(int64_t n, float *w, const float *den, hipStream_t s) {
-    hipLaunchKernelGGL(k_div_scalar, dim3(blocks_1d(n)), dim3(kBX, kBY), 0, s, n, w, den);
+void launch_lanczos_div(int64_t n, int j, float *w, float *lz, const float *part_in, int np_in,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_div, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, j, w, lz,
+                       part_in, np_in);
 }
 
-void launch_adjoint_sums(const OpView<double> &op, const double *lam, const double *T,
-                         double t_amb, double *out, RedScratch red, hipStream_t s) {
-    const dim3 g = tile_grid(op.nx, op.ny), b(kBX, kBY);
+void launch_adjoint(const OpView<double> &op, const double *lam, const double *T, double t_amb,
+                    const double *fac, double *part, double *dL_dk, hipStream_t s) {
+    const int nb = ((op.nx + kWave - 1) / kWave) * ((op.ny + 3) / 4);
     if (op.gx)
-        hipLaunchKernelGGL((k_adjoint_sums<true>), g, b, 0, s, op, lam, T, t_amb, out,
-                           (double *)red.partials, red.counter);
+        hipLaunchKernelGGL((k_adjoint_sums<true>), dim3(nb), dim3(kWave, 4), 0, s, op, lam, T,
+                           t_amb, part);
     else
-        hipLaunchKernelGGL((k_adjoint_sums<false>), g, b, 0, s, op, lam, T, t_amb, out,
-                           (double *)red.partials, red.counter);
+        hipLaunchKernelGGL((k_adjoint_sums<false>), dim3(nb), dim3(kWave, 4), 0, s, op, lam, T,
+                           t_amb, part);
+    hipLaunchKernelGGL(k_adjoint_finish, dim3(1), dim3(kWave, 4), 0, s, op.nz, nb,
+                       (const double *)part, fac, dL_dk);
 }
 
-void launch_adjoint_finish(int nz, const double *sums, const double *fac_lat,
-                           const double *fac_vert_up, const double *fac_vert_dn, double *dL_dk,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_adjoint_finish, dim3(1), dim3(kMaxLayers), 0, s, nz, sums, fac_lat,
-                       fac_vert_up, fac_vert_dn, dL_dk);
-}
+#define CUTH_INST(T)                                                                              \
+    template void launch_apply<T>(const OpView<T> &, const T *, T *, hipStream_t);                \
+    template void launch_cheb<T>(const OpView<T> &, int, bool, bool, int, const T *, T *,         \
+                                 const T *, T, T, T, CgState<T> *, const T *, int, T *,           \
+                                 hipStream_t);                                                    \
+    template void launch_scale<T>(int64_t, const T *, T, T *, bool, int, CgState<T> *, const T *, \
+                                  int, T *, hipStream_t);                                         \
+    template void launch_cg_dir<T>(const OpView<T> &, int, const T *, const T *, T *, T *,        \
+                                   CgState<T> *, const T *, int, T *, hipStream_t);               \
+    template void launch_cg_update<T>(const OpView<T> &, int, T *, const T *, T *, const T *,     \
+                                      CgState<T> *, const T *, int, T *, hipStream_t);            \
+    template void launch_cg_check<T>(const OpView<T> &, const T *, const T *, const T *, bool,   \
+                                     T *, hipStream_t);
+CUTH_INST(float)
+CUTH_INST(double)
+#undef CUTH_INST
 
-// explicit instantiations
-template void launch_apply<float>(const OpView<float> &, const float *, float *, hipStream_t);
-template void launch_apply<double>(const OpView<double> &, const double *, double *, hipStream_t);
-template void launch_cheb<float>(const OpView<float> &, int, bool, const float *, float *,
-                                 const float *, float, float, float, CgState<float> *, RedScratch,
-                                 hipStream_t);
-template void launch_cheb<double>(const OpView<double> &, int, bool, const double *, double *,
-                                  const double *, double, double, double, CgState<double> *,
-                                  RedScratch, hipStream_t);
-template void launch_scale<float>(int64_t, const float *, float, float *, CgState<float> *, bool,
-                                  const float *, RedScratch, hipStream_t);
-template void launch_scale<double>(int64_t, const double *, double, double *, CgState<double> *,
-                                   bool, const double *, RedScratch, hipStream_t);
-template void launch_cg_dir<float>(const OpView<float> &, const float *, const float *, float *,
-                                   float *, CgState<float> *, RedScratch, hipStream_t);
-template void launch_cg_dir<double>(const OpView<double> &, const double *, const double *,
-                                    double *, double *, CgState<double> *, RedScratch, hipStream_t);
-template void launch_cg_update<float>(const OpView<float> &, float *, const float *, float *,
-                                      const float *, CgState<float> *, RedScratch, hipStream_t);
-template void launch_cg_update<double>(const OpView<double> &, double *, const double *, double *,
-                                       const double *, CgState<double> *, RedScratch, hipStream_t);
-template void launch_cg_check<float>(const OpView<float> &, const float *, const float *,
-                                     const float *, CgState<float> *, int, RedScratch, hipStream_t);
-template void launch_cg_check<double>(const OpView<double> &, const double *, const double *,
-                                      const double *, CgState<double> *, int, RedScratch,
-                                      hipStream_t);
 template void launch_residual<float, float>(const OpView<double> &, const double *, double,
                                             const float *, const double *, const double *, double,
-                                            double *, double *, float *, float *, OuterStats *,
-                                            CgState<float> *, double, RedScratch, hipStream_t);
+                                            double *, double *, float *, float *, double *,
+                                            hipStream_t);
 template void launch_residual<double, double>(const OpView<double> &, const double *, double,
                                               const double *, const double *, const double *,
                                               double, double *, double *, double *, double *,
-                                              OuterStats *, CgState<double> *, double, RedScratch,
-                                              hipStream_t);
+                                              double *, hipStream_t);
 
 }  // namespace cuth

@@ -2,13 +2,16 @@
 // the Chebyshev-preconditioned CG (Algorithm 1 + the Chebyshev algorithm of
 // Section 4.3) and FP64 iterative refinement around an FP32 inner solve.
 //
-// Everything numeric runs in the kernels of kernels.hip.  The host only
-// enqueues launches on the handle's stream, reads back a few scalars once per
-// chunk of CG iterations (done flag, norms) and decides what to launch next.
+// Everything numeric on vectors runs in the kernels of kernels.hip.  The host
+// enqueues launches on the handle's stream, reads back a few scalars or
+// per-workgroup partials once per chunk of CG iterations and decides what to
+// launch next.
 #include "grid.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 
@@ -26,6 +29,19 @@ namespace cuth {
         Status s_ = (expr);          \
         if (s_.bad()) return s_;     \
     } while (0)
+
+// Accumulate the durations of the recorded sweep events (stream already synced).
+Status prof_flush(Grid &g) {
+    for (size_t i = 0; i + 1 < g.pev_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g.pev[i], g.pev[i + 1]) == hipSuccess) {
+            g.prof_ms += ms;
+            g.prof_count += 1;
+        }
+    }
+    g.pev_used = 0;
+    return Status::ok();
+}
 
 namespace {
 
@@ -48,9 +64,7 @@ void dev_free(P *&p) {
     p = nullptr;
 }
 
-template <typename S>
-Status readback(Grid &g, S *h, const S *d) {
-    CUTH_HIP(hipMemcpyAsync(h, d, sizeof(S), hipMemcpyDeviceToHost, g.stream));
+Status sync(Grid &g) {
     CUTH_HIP(hipStreamSynchronize(g.stream));
     return Status::ok();
 }
@@ -99,7 +113,7 @@ ChebConsts make_cheb(double lmin, double lmax, int k) {
     return cc;
 }
 
-// Byte accounting (algorithmic bytes per unknown of each kernel).
+// Algorithmic bytes per unknown of each kernel (what the method must move).
 template <typename T>
 struct Bytes {
     double coef;   // per-cell lateral conductances read by one stencil sweep
@@ -109,33 +123,46 @@ struct Bytes {
     double update() const { return 6.0 * sizeof(T); }
     double check() const { return 3.0 * sizeof(T) + coef; }
     double scale() const { return 2.0 * sizeof(T); }
+    double precond(int k) const {
+        if (k == 1) return scale();
+        double b = cheb(1);
+        for (int j = 2; j < k; ++j) b += cheb(j == 2 ? 2 : 0);
+        return b;
+    }
 };
 
-// z = q(A) r by k-1 stencil sweeps (k >= 2) or one scaling (k == 1).  The last
-// sweep also reduces r^T z into st->rz_new.  Returns the buffer holding z.
+// z = q(A) r by k-1 stencil sweeps (k >= 2) or one scaling (k == 1).  chk: the
+// first kernel first tests convergence of CG iteration `it` from the update's
+// partials (part_in, np_in).  The last kernel writes partials of r^T z to
+// part_out (np_out of them).  Returns the buffer holding z.
 template <typename T>
-T *precond_seq(const Grid &g, const OpView<T> &op, const ChebConsts &cc, const T *r, T *zA, T *zB,
-               CgState<T> *st, int64_t &stencils, double &bytes) {
+T *precond_seq(Grid &g, const OpView<T> &op, const ChebConsts &cc, const T *r, T *zA, T *zB,
+               CgState<T> *st, bool chk, int it, const T *part_in, int np_in, T *part_out,
+               int &np_out) {
     const Bytes<T> by(g);
-    const double n = (double)g.N;
-    if (cc.k == 1) {
-        launch_scale<T>(g.N, r, (T)cc.inv_th, zA, st, true, r, g.red, g.stream);
-        bytes += by.scale() * n;
+    const int k = cc.k;
+    if (k == 1) {
+        launch_scale<T>(g.N, r, (T)cc.inv_th, zA, chk, it, st, part_in, np_in, part_out, g.stream);
+        np_out = red_blocks(g.N);
         return zA;
     }
-    const int k = cc.k;
-    launch_cheb<T>(op, 1, k == 2, (const T *)nullptr, zB, r, (T)cc.c1[1], (T)cc.c2[1],
-                   (T)cc.inv_th, st, g.red, g.stream);
-    bytes += by.cheb(1) * n;
+    launch_cheb<T>(op, 1, k == 2, chk, it, r, zB, r, (T)cc.c1[1], (T)cc.c2[1], (T)cc.inv_th, st,
+                   part_in, np_in, part_out, g.stream);
     T *cur = zB, *prev = zA;
     for (int j = 2; j < k; ++j) {
         const int mode = (j == 2) ? 2 : 0;
-        launch_cheb<T>(op, mode, j == k - 1, cur, prev, r, (T)cc.c1[j], (T)cc.c2[j],
-                       (T)cc.inv_th, st, g.red, g.stream);
-        bytes += by.cheb(mode) * n;
+        const bool timed = g.prof && j == 3 && g.pev_used + 2 <= g.pev.size();
+        if (timed) (void)hipEventRecord(g.pev[g.pev_used], g.stream);
+        launch_cheb<T>(op, mode, j == k - 1, false, it, cur, prev, r, (T)cc.c1[j], (T)cc.c2[j],
+                       (T)cc.inv_th, st, part_in, np_in, part_out, g.stream);
+        if (timed) {
+            (void)hipEventRecord(g.pev[g.pev_used + 1], g.stream);
+            g.pev_used += 2;
+            g.prof_bytes = by.cheb(0) * (double)g.N;
+        }
         std::swap(cur, prev);
     }
-    stencils += k - 1;
+    np_out = stencil_blocks(op);
     return cur;
 }
 
@@ -152,90 +179,132 @@ CgState<float> *hstate_of<float>(Grid &g) { return g.h_st32; }
 template <>
 CgState<double> *hstate_of<double>(Grid &g) { return g.h_st64; }
 
-// Inner PCG on A_T x = rhat with x_0 = 0.  Requires r = rhat and the state
-// initialised (k_residual does both) and st->tol2 set.  Runs chunks of
-// `period` iterations; after each chunk a true-residual kernel evaluates the
-// drift and stagnation criteria and the host reads the state once.
 template <typename T>
-InnerResult inner_pcg(Grid &g, const OpView<T> &op, Work<T> &w, const ChebConsts &cc, int maxit,
-                      int period, Status &status) {
+Status write_state(Grid &g, double rr0, double tol2) {
+    CgState<T> *h = hstate_of<T>(g);
+    std::memset(h, 0, sizeof(CgState<T>));
+    h->rr = (T)rr0;
+    h->rr0 = (T)rr0;
+    h->tol2 = (T)tol2;
+    h->done = rr0 > 0.0 ? 0 : 1;
+    CUTH_HIP(hipMemcpyAsync(state_of<T>(g), h, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
+    return Status::ok();
+}
+
+// Read back the state and nv*np partials of slot s; host sums in a fixed order.
+template <typename T>
+Status read_state_and_partials(Grid &g, int s, int nv, int np, double *sums) {
+    CUTH_HIP(hipMemcpyAsync(hstate_of<T>(g), state_of<T>(g), sizeof(CgState<T>),
+                            hipMemcpyDeviceToHost, g.stream));
+    CUTH_HIP(hipMemcpyAsync(g.h_part, g.slot<T>(s), sizeof(T) * (size_t)nv * np,
+                            hipMemcpyDeviceToHost, g.stream));
+    CUTH_TRY(sync(g));
+    const T *p = reinterpret_cast<const T *>(g.h_part);
+    for (int v = 0; v < nv; ++v) {
+        double a = 0.0;
+        for (int q = 0; q < np; ++q) a += (double)p[(size_t)v * np + q];
+        sums[v] = a;
+    }
+    return Status::ok();
+}
+
+// Inner PCG on A_T x = rhat with x_0 = 0 (r = rhat on entry).  Runs chunks of
+// `period` iterations; after each chunk a true-residual kernel gives the
+// drift (||r_true - r_low|| >= 0.5 ||r_true||) and stagnation
+// (||r_true^k|| > 0.9 ||r_true^{k-1}||) criteria of Section 4.4, evaluated
+// here together with the device's convergence flag.
+template <typename T>
+InnerResult inner_pcg(Grid &g, const OpView<T> &op, Work<T> &w, const ChebConsts &cc, double rr0,
+                      double tol2, int maxit, int period, Status &status) {
     InnerResult res;
+    status = Status::ok();
     CgState<T> *st = state_of<T>(g);
     CgState<T> *hst = hstate_of<T>(g);
     const Bytes<T> by(g);
     const double n = (double)g.N;
-    int64_t stencils = 0;
-    double bytes = 0;
-    int nprec = 0, nchecks = 0;
-    T *z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, stencils, bytes);
-    nprec = 1;
+    const int nbs = stencil_blocks(op);
+    status = write_state<T>(g, rr0, tol2);
+    if (status.bad()) return res;
+    int np_z = 0, nchecks = 0;
+    T *z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, false, 0, nullptr, 0, g.slot<T>(S_CHEB),
+                          np_z);
     T *pold = w.pA, *pnew = w.pB;
-    int it = 0;
-    status = Status::ok();
+    int it = 0, reason = 0;
+    double true_prev = -1.0, sums[2] = {0, 0};
     while (it < maxit) {
         const int nb = std::min(period, maxit - it);
         for (int q = 0; q < nb; ++q) {
-            launch_cg_dir<T>(op, z, pold, pnew, w.mu, st, g.red, g.stream);
-            launch_cg_update<T>(op, w.x, pnew, w.r, w.mu, st, g.red, g.stream);
-            z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, stencils, bytes);
+            const int k = it + q;
+            launch_cg_dir<T>(op, k, z, pold, pnew, w.mu, st, g.slot<T>(S_CHEB), np_z,
+                             g.slot<T>(S_DIR), g.stream);
+            launch_cg_update<T>(op, k, w.x, pnew, w.r, w.mu, st, g.slot<T>(S_DIR), nbs,
+                                g.slot<T>(S_UPD), g.stream);
+            z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, true, k, g.slot<T>(S_UPD), nbs,
+                               g.slot<T>(S_CHEB), np_z);
             std::swap(pold, pnew);
         }
         it += nb;
-        launch_cg_check<T>(op, w.rhat, w.x, w.r, st, 0, g.red, g.stream);
+        launch_cg_check<T>(op, w.rhat, w.x, w.r, true, g.slot<T>(S_CHK), g.stream);
         ++nchecks;
-        Status s = readback(g, hst, st);
-        if (s.bad()) {
-            status = s;
-            return res;
+        status = read_state_and_partials<T>(g, S_CHK, 2, nbs, sums);
+        if (status.bad()) return res;
+        if (g.prof) (void)prof_flush(g);
+        const double tn = std::sqrt(sums[0]);
+        if (hst->done) {
+            reason = hst->done;
+            break;
         }
-        if (hst->done) break;
+        if (!std::isfinite(tn)) {
+            reason = 4;
+            break;
+        }
+        if (std::sqrt(sums[1]) >= 0.5 * tn) {
+            reason = 2;
+            break;
+        }
+        if (true_prev >= 0.0 && tn > 0.9 * true_prev) {
+            reason = 3;
+            break;
+        }
+        true_prev = tn;
     }
-    launch_cg_check<T>(op, w.rhat, w.x, w.r, st, 1, g.red, g.stream);
-    ++nchecks;
-    Status s = readback(g, hst, st);
-    if (s.bad()) {
-        status = s;
-        return res;
-    }
+    if (reason == 0) reason = 5;
     res.iters = hst->iter;
-    res.reason = hst->done ? hst->done : 5;
-    const double rr0 = (double)hst->rr0;
-    res.true_red = rr0 > 0 ? std::sqrt((double)hst->true_rr / rr0) : 0.0;
-    // launches after the stopping point exit early and move no data: count
-    // what ran (each iteration: direction+SpMV, update, preconditioner)
+    res.reason = reason;
+    res.true_red = rr0 > 0 ? std::sqrt(sums[0] / rr0) : 0.0;
+    // launches after the stopping point exit early and move no data
     const int iters = res.iters;
-    const int precs_run = 1 + iters - (res.reason == 1 ? 1 : 0);
-    const double per_prec = (nprec > 0) ? 0.0 : 0.0;
-    (void)per_prec;
-    double prec_bytes = 0;
-    {
-        int64_t dummy = 0;
-        // bytes of one preconditioner application
-        if (cc.k == 1) prec_bytes = by.scale() * n;
-        else {
-            prec_bytes = by.cheb(1) * n;
-            for (int j = 2; j < cc.k; ++j) prec_bytes += by.cheb(j == 2 ? 2 : 0) * n;
-        }
-        (void)dummy;
-    }
-    res.bytes = precs_run * prec_bytes + iters * (by.dir() + by.update()) * n +
+    const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
+    res.bytes = precs_run * by.precond(cc.k) * n + iters * (by.dir() + by.update()) * n +
                 nchecks * by.check() * n;
     res.stencils = (int64_t)precs_run * (cc.k - 1) + iters + nchecks;
-    if (res.reason == 4) status = Status::err(CUTH_E_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite value)");
+    if (reason == 4) status = Status::err(CUTH_E_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite value)");
     return res;
 }
 
-Status set_tol2_f(Grid &g, float v) {
-    float *hs = reinterpret_cast<float *>(g.h_scal);
-    hs[0] = v;
-    CUTH_HIP(hipMemcpyAsync(&g.st32->tol2, hs, sizeof(float), hipMemcpyHostToDevice, g.stream));
-    return Status::ok();
-}
+struct OuterRes {
+    double rr = 0, bb = 0, dinf = 0, thinf = 0, bad = 0;
+};
 
-Status set_tol2_d(Grid &g, double v) {
-    g.h_scal[1] = v;
-    CUTH_HIP(hipMemcpyAsync(&g.st64->tol2, &g.h_scal[1], sizeof(double), hipMemcpyHostToDevice,
-                            g.stream));
+template <typename TD, typename TI>
+Status outer_residual(Grid &g, const OpView<double> &op, const double *th_in, double in_off,
+                      const TD *delta, const double *P, const double *Tn, double *th_out,
+                      double *r64, TI *r_in, TI *rhat, OuterRes &o) {
+    launch_residual<TD, TI>(op, th_in, in_off, delta, P, Tn, g.t_amb, th_out, r64, r_in, rhat,
+                            g.slot<double>(S_RES), g.stream);
+    const int nb = stencil_blocks(op);
+    CUTH_HIP(hipMemcpyAsync(g.h_part, g.slot<double>(S_RES), sizeof(double) * kResidualValues * nb,
+                            hipMemcpyDeviceToHost, g.stream));
+    CUTH_TRY(sync(g));
+    const double *p = g.h_part;
+    o = OuterRes();
+    for (int q = 0; q < nb; ++q) {
+        o.rr += p[q];
+        o.bb += p[nb + q];
+        o.dinf = std::max(o.dinf, p[2 * nb + q]);
+        o.thinf = std::max(o.thinf, p[3 * nb + q]);
+        o.bad += p[4 * nb + q];
+    }
     return Status::ok();
 }
 
@@ -261,6 +330,20 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
         else lo = mid;
     }
     return 0.5 * (lo + hi);
+}
+
+Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
+    Shape s = def;
+    if (const char *e = std::getenv(name)) {
+        int vx = 0, by = 0, zc = 0;
+        if (std::sscanf(e, "%d,%d,%d", &vx, &by, &zc) == 3) {
+            if ((vx == 1 || vx == 2 || vx == 4) && vx <= maxvx) s.vx = vx;
+            if (by >= 1 && by <= kMaxBY) s.by = by;
+            if (zc >= 1) s.zc = zc;
+        }
+    }
+    while (s.vx > 1 && nx % s.vx != 0) s.vx /= 2;
+    return s;
 }
 
 }  // namespace
@@ -308,35 +391,43 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
     if (g->has_cap) g->cap.assign(d.heat_cap, d.heat_cap + d.nz);
     g->per_cell = d.k_lat_mult != nullptr;
 
-    const dim3 tg = tile_grid(g->nx, g->ny);
-    const size_t tile_blocks = (size_t)tg.x * tg.y;
-    g->partial_slots = std::max(tile_blocks * (size_t)std::max(8, 2 * g->nz), (size_t)65536 * 2);
+    // launch shapes: one 16-byte load per lane where the row length allows, one
+    // wavefront per workgroup, vertical marches of 8 layers (measured best on
+    // gfx950 for the 512 x 512 x 16 stack: FP32 sweep 5.9 TB/s, FP64 6.8 TB/s);
+    // CUTH_SHAPE32 / CUTH_SHAPE64 = "vx,by,zc" override them
+    g->sh32 = shape_from_env("CUTH_SHAPE32", Shape{4, 1, 8}, g->nx, 4);
+    g->sh64 = shape_from_env("CUTH_SHAPE64", Shape{2, 1, 8}, g->nx, 2);
+    auto nblocks = [&](const Shape &sh) {
+        return (size_t)tiles_x(g->nx, sh.vx) * tiles_y(g->ny, sh.by) * tiles_z(g->nz, sh.zc);
+    };
+    const size_t nb_max = std::max({nblocks(g->sh32), nblocks(g->sh64), (size_t)kRedBlocks});
+    g->slot_doubles = 8 * nb_max;
+    const size_t nb_adj = (size_t)((g->nx + kWave - 1) / kWave) * ((g->ny + 3) / 4);
     Status st;
-    if ((st = dev_alloc((double **)&g->red.partials, g->partial_slots)).bad()) return fail(st);
-    if ((st = dev_alloc(&g->red.counter, 4)).bad()) return fail(st);
+    if ((st = dev_alloc(&g->part, g->slot_doubles * S_COUNT + (size_t)2 * g->nz * nb_adj)).bad())
+        return fail(st);
+    g->part_adj = g->part + g->slot_doubles * S_COUNT;
     if ((st = dev_alloc(&g->st32, 1)).bad()) return fail(st);
     if ((st = dev_alloc(&g->st64, 1)).bad()) return fail(st);
-    if ((st = dev_alloc(&g->os, 1)).bad()) return fail(st);
     if ((st = dev_alloc(&g->lz, 1024)).bad()) return fail(st);
-    if ((st = dev_alloc(&g->adj, (size_t)5 * g->nz)).bad()) return fail(st);
+    if ((st = dev_alloc(&g->adj_fac, (size_t)3 * g->nz)).bad()) return fail(st);
     if ((st = dev_alloc(&g->thA, (size_t)g->N)).bad()) return fail(st);
     if ((st = dev_alloc(&g->thB, (size_t)g->N)).bad()) return fail(st);
     if ((st = alloc_work(g->w32, g->N)).bad()) return fail(st);
     if (hipHostMalloc((void **)&g->h_st32, sizeof(CgState<float>), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&g->h_st64, sizeof(CgState<double>), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_os, sizeof(OuterStats), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_lz, 1024 * sizeof(float), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_scal, 256 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void **)&g->h_part, g->slot_doubles * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->h_lz, 1024 * sizeof(float), hipHostMallocDefault) != hipSuccess)
         return fail(Status::err(CUTH_E_NOMEM, "hipHostMalloc failed"));
-    if (hipMemset(g->red.counter, 0, 4 * sizeof(unsigned)) != hipSuccess ||
-        hipMemset(g->st32, 0, sizeof(CgState<float>)) != hipSuccess ||
+    if (hipMemset(g->st32, 0, sizeof(CgState<float>)) != hipSuccess ||
         hipMemset(g->st64, 0, sizeof(CgState<double>)) != hipSuccess)
         return fail(Status::err(CUTH_E_DEVICE, "hipMemset failed"));
     if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess ||
         hipEventCreate(&g->ev2) != hipSuccess)
         return fail(Status::err(CUTH_E_DEVICE, "hipEventCreate failed"));
 
-    // adjoint factors: 1/k_lat[l], and dg/dk_vert of the faces above / below layer l
+    // adjoint factors: 1/k_lat[l], and dg/dk_vert[l] of the faces above / below layer l
+    // (g = dx dy / (dz_a/(2 k_a) + dz_b/(2 k_b)) gives dg/dk_a = g^2 dz_a / (2 k_a^2 dx dy))
     {
         const int nz = g->nz;
         std::vector<double> fac((size_t)3 * nz, 0.0);
@@ -353,7 +444,7 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
                 fac[2 * nz + l] = gz * gz * g->dz[l] / (2.0 * kv * kv * dxdy);
             }
         }
-        if (hipMemcpy(g->adj + 2 * nz, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(g->adj_fac, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
             return fail(Status::err(CUTH_E_DEVICE, "hipMemcpy failed"));
     }
 
@@ -400,7 +491,7 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
 
 void grid_destroy(Grid *g) {
     if (!g) return;
-    if (g->stream || true) (void)hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
     for (Setup &su : g->setups) {
         dev_free(su.lc64);
         dev_free(su.lc32);
@@ -413,32 +504,32 @@ void grid_destroy(Grid *g) {
     free_work(g->w64);
     dev_free(g->thA);
     dev_free(g->thB);
-    if (g->red.partials) (void)hipFree(g->red.partials);
-    dev_free(g->red.counter);
+    dev_free(g->part);
     dev_free(g->st32);
     dev_free(g->st64);
-    dev_free(g->os);
     dev_free(g->lz);
-    dev_free(g->adj);
+    dev_free(g->adj_fac);
     if (g->h_st32) (void)hipHostFree(g->h_st32);
     if (g->h_st64) (void)hipHostFree(g->h_st64);
-    if (g->h_os) (void)hipHostFree(g->h_os);
+    if (g->h_part) (void)hipHostFree(g->h_part);
     if (g->h_lz) (void)hipHostFree(g->h_lz);
-    if (g->h_scal) (void)hipHostFree(g->h_scal);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
     if (g->ev2) (void)hipEventDestroy(g->ev2);
+    for (hipEvent_t e : g->pev) (void)hipEventDestroy(e);
     delete g;
 }
 
 OpView<double> view64(const Grid &g, const Setup &su) {
     return OpView<double>{g.nx, g.ny, g.nz, g.per_cell ? g.gx64 : nullptr,
-                          g.per_cell ? g.gy64 : nullptr, su.lc64};
+                          g.per_cell ? g.gy64 : nullptr, su.lc64, g.sh64.vx, g.sh64.by,
+                          g.sh64.zc};
 }
 
 OpView<float> view32(const Grid &g, const Setup &su) {
     return OpView<float>{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr,
-                         g.per_cell ? g.gy32 : nullptr, su.lc32};
+                         g.per_cell ? g.gy32 : nullptr, su.lc32, g.sh32.vx, g.sh32.by,
+                         g.sh32.zc};
 }
 
 Setup *get_setup(Grid &g, double dt, Status &status) {
@@ -467,8 +558,6 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
                                       : std::min(2, g.nx - 1) * L.gx + std::min(2, g.ny - 1) * L.gy;
         gersh = std::max(gersh, 2.0 * (lat + L.gzu + L.gzd) + L.sink);
     }
-    // the vertical term gzd of layer l must be the same number as gzu of l-1
-    for (int l = 1; l < nz; ++l) su.hlc[l].gzd = su.hlc[l - 1].gzu;
     su.gersh = gersh;
     std::vector<LayerCoef<float>> h32(nz);
     for (int l = 0; l < nz; ++l) {
@@ -503,32 +592,30 @@ Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<d
     steps = (int)std::max<int64_t>(1, std::min<int64_t>(steps, g.N));
     steps = std::min(steps, 256);
     const OpView<float> op = view32(g, su);
-    float *A_ = g.lz, *B_ = g.lz + 256, *nrm = g.lz + 512;
+    const int nbs = stencil_blocks(op), nb1 = red_blocks(g.N);
+    float *pa = g.slot<float>(S_LZA), *pb = g.slot<float>(S_LZB);
     float *bufs[3] = {g.w32.pA, g.w32.pB, g.w32.mu};
     if (v0) {
-        launch_norm2(g.N, v0, nrm, g.red, g.stream);
-        launch_scale_by_rsqrt(g.N, v0, nrm, bufs[1], g.stream);
+        launch_norm2(g.N, v0, pa, g.stream);
+        launch_scale_rsqrt(g.N, v0, pa, nb1, bufs[1], g.stream);
     } else {
         launch_fill_random(g.N, 0x2606178500ull, bufs[0], g.stream);
-        launch_norm2(g.N, bufs[0], nrm, g.red, g.stream);
-        launch_scale_by_rsqrt(g.N, bufs[0], nrm, bufs[1], g.stream);
+        launch_norm2(g.N, bufs[0], pa, g.stream);
+        launch_scale_rsqrt(g.N, bufs[0], pa, nb1, bufs[1], g.stream);
     }
     int ip = 0, iv = 1, iw = 2;
-    bool have_prev = false;
     for (int j = 0; j < steps; ++j) {
-        launch_lanczos_av(op, bufs[iv], have_prev ? bufs[ip] : nullptr,
-                          have_prev ? B_ + (j - 1) : nullptr, bufs[iw], A_ + j, g.red, g.stream);
+        launch_lanczos_av(op, j, bufs[iv], j > 0 ? bufs[ip] : nullptr, g.lz, bufs[iw], pa, g.stream);
+        launch_lanczos_orth(g.N, j, bufs[iw], bufs[iv], g.lz, pa, nbs, pb, g.stream);
         if (j == steps - 1) break;
-        launch_lanczos_orth(g.N, bufs[iw], bufs[iv], A_ + j, B_ + j, g.red, g.stream);
-        launch_div_scalar(g.N, bufs[iw], B_ + j, g.stream);
+        launch_lanczos_div(g.N, j, bufs[iw], g.lz, pb, nb1, g.stream);
         const int old = ip;
         ip = iv;
         iv = iw;
         iw = old;
-        have_prev = true;
     }
     CUTH_HIP(hipMemcpyAsync(g.h_lz, g.lz, 512 * sizeof(float), hipMemcpyDeviceToHost, g.stream));
-    CUTH_HIP(hipStreamSynchronize(g.stream));
+    CUTH_TRY(sync(g));
     alpha.clear();
     beta.clear();
     double amax = 0.0;
@@ -577,6 +664,11 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps));
     CUTH_HIP(hipEventRecord(g.ev1, g.stream));
     const ChebConsts cc = make_cheb(su->lmin, su->lmax, o.cheb_degree);
+    // tol == 0 selects the default of the precision: mixed, relative rise error
+    // 1e-8; FP64, relative residual 1e-10 (steady) or 1e-12 (transient, where
+    // ||b|| is dominated by the C/dt T_n term and the residual bound is looser)
+    const double tol = o.tol > 0.0 ? o.tol
+                                   : (o.precision == CUTH_MIXED ? 1e-8 : (dt > 0.0 ? 1e-12 : 1e-10));
     const int period = o.check_period > 0 ? o.check_period : (transient_defaults ? 5 : 20);
     const OpView<double> op64 = view64(g, *su);
     const double n = (double)g.N;
@@ -587,10 +679,9 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     Status result = Status::ok();
     double *final_theta = nullptr;
 
-    auto resid_bytes = [&](bool th_in, bool delta_f32, bool delta_f64, int inner_sz) {
-        double b = (th_in ? 8.0 : 0.0) + (delta_f32 ? 4.0 : 0.0) + (delta_f64 ? 8.0 : 0.0) + 8.0 +
-                   (Tn ? 8.0 : 0.0) + 8.0 + 2.0 * inner_sz + coef64;
-        return b * n;
+    auto resid_bytes = [&](bool th_in, int delta_sz, int inner_sz) {
+        return ((th_in ? 8.0 : 0.0) + delta_sz + 8.0 + (Tn ? 8.0 : 0.0) + 8.0 + 2.0 * inner_sz +
+                coef64) * n;
     };
 
     if (o.precision == CUTH_MIXED) {
@@ -601,13 +692,11 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         double *th_out = g.thA;
         double last_red = 1.0, d_prev = 1.0, est = 1.0;
         for (int cyc = 0;; ++cyc) {
-            launch_residual<float, float>(op64, th_in, in_off, delta, P, Tn, g.t_amb, th_out,
-                                          nullptr, g.w32.r, g.w32.rhat, g.os, g.st32, 0.0, g.red,
-                                          g.stream);
-            bytes += resid_bytes(th_in != nullptr, delta != nullptr, false, 4);
+            OuterRes os;
+            CUTH_TRY((outer_residual<float, float>(g, op64, th_in, in_off, delta, P, Tn, th_out,
+                                                   nullptr, g.w32.r, g.w32.rhat, os)));
+            bytes += resid_bytes(th_in != nullptr, delta ? 4 : 0, 4);
             ++stencils;
-            CUTH_TRY(readback(g, g.h_os, g.os));
-            const OuterStats os = *g.h_os;
             final_theta = th_out;
             relres = os.bb > 0 ? std::sqrt(os.rr / os.bb) : std::sqrt(os.rr);
             if (os.bad > 0) {
@@ -622,17 +711,18 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
                 d_prev = d;
                 // the last correction is below tol and its inner solve cut the
                 // residual at least tenfold: the error left is about q*d << tol
-                if (d <= o.tol && last_red <= 0.1) break;
+                if (d <= tol && last_red <= 0.1) break;
             }
             if (os.rr == 0.0) break;
             if (cyc >= o.max_outer) {
                 result = Status::err(CUTH_E_NOT_CONVERGED, "refinement cycle limit reached");
                 break;
             }
-            const double tau = cyc == 0 ? 1e-5 : std::min(0.1, std::max(1e-5, 0.1 * o.tol / est));
-            CUTH_TRY(set_tol2_f(g, (float)(tau * tau * os.rr)));
+            const double tau = cyc == 0 ? 1e-5 : std::min(0.1, std::max(1e-5, 0.1 * tol / est));
+            const double rr0 = (double)(float)os.rr;
             Status is;
-            InnerResult ir = inner_pcg<float>(g, op32, g.w32, cc, o.max_inner, period, is);
+            InnerResult ir = inner_pcg<float>(g, op32, g.w32, cc, rr0, tau * tau * rr0,
+                                              o.max_inner, period, is);
             cg_iters += ir.iters;
             stencils += ir.stencils;
             bytes += ir.bytes;
@@ -648,10 +738,7 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
             th_in = th_out;
             in_off = 0.0;
             th_out = (th_out == g.thA) ? g.thB : g.thA;
-            if (is.bad() && ir.reason == 4) {
-                // keep the partial correction, report breakdown after one more residual
-                result = is;
-            }
+            if (is.bad()) result = is;   // breakdown: keep the partial correction
         }
     } else {
         CUTH_TRY(alloc_work(g.w64, g.N));
@@ -660,13 +747,11 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         const double *delta = nullptr;
         double *th_out = g.thA;
         for (int cyc = 0;; ++cyc) {
-            launch_residual<double, double>(op64, th_in, in_off, delta, P, Tn, g.t_amb, th_out,
-                                            nullptr, g.w64.r, g.w64.rhat, g.os, g.st64, 0.0, g.red,
-                                            g.stream);
-            bytes += resid_bytes(th_in != nullptr, false, delta != nullptr, 8);
+            OuterRes os;
+            CUTH_TRY((outer_residual<double, double>(g, op64, th_in, in_off, delta, P, Tn, th_out,
+                                                     nullptr, g.w64.r, g.w64.rhat, os)));
+            bytes += resid_bytes(th_in != nullptr, delta ? 8 : 0, 8);
             ++stencils;
-            CUTH_TRY(readback(g, g.h_os, g.os));
-            const OuterStats os = *g.h_os;
             final_theta = th_out;
             relres = os.bb > 0 ? std::sqrt(os.rr / os.bb) : std::sqrt(os.rr);
             if (cyc >= 1 && os.thinf > 0) err_est = os.dinf / os.thinf;
@@ -674,15 +759,15 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
                 result = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
                 break;
             }
-            if (relres <= o.tol || os.rr == 0.0) break;
+            if (relres <= tol || os.rr == 0.0) break;
             if (cyc >= o.max_outer) {
                 result = Status::err(CUTH_E_NOT_CONVERGED, "restart limit reached");
                 break;
             }
             // hot restart: r and p recomputed from their definitions, x kept
-            CUTH_TRY(set_tol2_d(g, o.tol * o.tol * os.bb));
             Status is;
-            InnerResult ir = inner_pcg<double>(g, view64(g, *su), g.w64, cc, o.max_inner, period, is);
+            InnerResult ir = inner_pcg<double>(g, op64, g.w64, cc, os.rr, tol * tol * os.bb,
+                                               o.max_inner, period, is);
             cg_iters += ir.iters;
             stencils += ir.stencils;
             bytes += ir.bytes;
@@ -697,9 +782,7 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
             th_in = th_out;
             in_off = 0.0;
             th_out = (th_out == g.thA) ? g.thB : g.thA;
-            if (ir.reason == 5 && cyc + 1 >= o.max_outer) {
-                // one more residual below reports the final state
-            }
+            if (is.bad()) result = is;
         }
     }
     if (final_theta) {
@@ -707,7 +790,7 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         bytes += 16.0 * n;
     }
     CUTH_HIP(hipEventRecord(g.ev2, g.stream));
-    CUTH_HIP(hipStreamSynchronize(g.stream));
+    CUTH_TRY(sync(g));
     if (stats) {
         float ms_setup = 0, ms_solve = 0;
         (void)hipEventElapsedTime(&ms_setup, g.ev0, g.ev1);
@@ -734,8 +817,7 @@ Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
     if (precision == CUTH_MIXED) launch_apply<float>(view32(g, *su), (const float *)x, (float *)y, g.stream);
     else launch_apply<double>(view64(g, *su), (const double *)x, (double *)y, g.stream);
     CUTH_HIP(hipGetLastError());
-    CUTH_HIP(hipStreamSynchronize(g.stream));
-    return Status::ok();
+    return sync(g);
 }
 
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r) {
@@ -743,28 +825,26 @@ Status residual(Grid &g, double dt, const double *b, const double *T, double *r)
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
     launch_residual<double, double>(view64(g, *su), T, g.t_amb, (const double *)nullptr, b, nullptr,
-                                    0.0, nullptr, r, nullptr, nullptr, g.os, nullptr, 0.0, g.red,
+                                    0.0, nullptr, r, nullptr, nullptr, g.slot<double>(S_RES),
                                     g.stream);
     CUTH_HIP(hipGetLastError());
-    CUTH_HIP(hipStreamSynchronize(g.stream));
-    return Status::ok();
+    return sync(g);
 }
 
 template <typename T>
-static Status precond_typed(Grid &g, const OpView<T> &op, Work<T> &w, CgState<T> *st,
-                            const ChebConsts &cc, const T *r, T *z) {
+static Status precond_typed(Grid &g, const OpView<T> &op, Work<T> &w, const ChebConsts &cc,
+                            const T *r, T *z) {
     // the result lands in zA for k == 1 or odd k, in zB for even k >= 2
     const bool in_b = cc.k >= 2 && ((cc.k - 1) % 2 == 1);
     T *zA = in_b ? w.zA : z;
     T *zB = in_b ? z : w.zB;
-    CUTH_HIP(hipMemsetAsync(st, 0, sizeof(CgState<T>), g.stream));
-    int64_t s = 0;
-    double b = 0;
-    T *res = precond_seq<T>(g, op, cc, r, zA, zB, st, s, b);
+    CUTH_TRY(write_state<T>(g, 1.0, 0.0));
+    int np = 0;
+    T *res = precond_seq<T>(g, op, cc, r, zA, zB, state_of<T>(g), false, 0, nullptr, 0,
+                            g.slot<T>(S_CHEB), np);
     if (res != z) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
     CUTH_HIP(hipGetLastError());
-    CUTH_HIP(hipStreamSynchronize(g.stream));
-    return Status::ok();
+    return sync(g);
 }
 
 Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax, int degree,
@@ -774,22 +854,21 @@ Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax
     if (!su) return st;
     const ChebConsts cc = make_cheb(lmin, lmax, degree);
     if (precision == CUTH_MIXED)
-        return precond_typed<float>(g, view32(g, *su), g.w32, g.st32, cc, (const float *)r, (float *)z);
+        return precond_typed<float>(g, view32(g, *su), g.w32, cc, (const float *)r, (float *)z);
     CUTH_TRY(alloc_work(g.w64, g.N));
-    return precond_typed<double>(g, view64(g, *su), g.w64, g.st64, cc, (const double *)r, (double *)z);
+    return precond_typed<double>(g, view64(g, *su), g.w64, cc, (const double *)r, (double *)z);
 }
 
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,
                const cuth_options &o, cuth_stats *stats) {
     Status st = solve_system(g, 0.0, dL_dT, nullptr, nullptr, 0.0, dL_dP, 0.0, o, stats, false);
-    if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_INVALID) return st;
-    Setup *su = get_setup(g, 0.0, st);
-    if (!su) return st;
-    launch_adjoint_sums(view64(g, *su), dL_dP, T, g.t_amb, g.adj, g.red, g.stream);
-    launch_adjoint_finish(g.nz, g.adj, g.adj + 2 * g.nz, g.adj + 3 * g.nz, g.adj + 4 * g.nz, dL_dk,
-                          g.stream);
+    if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_INVALID || st.code == CUTH_E_NOMEM) return st;
+    Status s2;
+    Setup *su = get_setup(g, 0.0, s2);
+    if (!su) return s2;
+    launch_adjoint(view64(g, *su), dL_dP, T, g.t_amb, g.adj_fac, g.part_adj, dL_dk, g.stream);
     CUTH_HIP(hipGetLastError());
-    CUTH_HIP(hipStreamSynchronize(g.stream));
+    CUTH_TRY(sync(g));
     return st;
 }
 

@@ -38,7 +38,7 @@ def test_default_options(lib):
     from paper_2606_17850_amd import _lib
     o = _lib.Options()
     lib.cuth_default_options(ctypes.byref(o))
-    assert o.precision == _lib.CUTH_MIXED and o.tol == 1e-8
+    assert o.precision == _lib.CUTH_MIXED and o.tol == 0.0
     assert o.cheb_degree == 30 and o.lanczos_steps == 30
 
 
