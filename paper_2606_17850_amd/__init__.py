@@ -275,6 +275,7 @@ class ThermalSolve(torch.autograd.Function):
         ctx.grid = g
         ctx.opts = opts
         ctx.k_base = k_scale.detach().cpu().numpy()
+        ctx.k_device = k_scale.device
         ctx.save_for_backward(T)
         return T
 
@@ -289,4 +290,4 @@ class ThermalSolve(torch.autograd.Function):
         kv = torch.as_tensor(g._kv, device=dk.device)
         s = torch.as_tensor(ctx.k_base, device=dk.device, dtype=torch.float64)
         dscale = (dk[:nz] * kl + dk[nz:] * kv) / s
-        return dP, dscale, None, None
+        return dP, dscale.to(ctx.k_device), None, None

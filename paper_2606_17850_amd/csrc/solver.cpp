@@ -332,6 +332,15 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
     return 0.5 * (lo + hi);
 }
 
+// CUTH_LOG=1: one line per refinement cycle on stderr.
+bool log_on() {
+    static const bool on = [] {
+        const char *e = std::getenv("CUTH_LOG");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
     Shape s = def;
     if (const char *e = std::getenv(name)) {
@@ -709,9 +718,16 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
                 est = q * d;
                 err_est = d;
                 d_prev = d;
-                // the last correction is below tol and its inner solve cut the
-                // residual at least tenfold: the error left is about q*d << tol
-                if (d <= tol && last_red <= 0.1) break;
+                // d is about the error before the last correction; that
+                // correction's inner solve cut the residual by last_red, which
+                // leaves an error of about last_red * d, but never less than the
+                // FP32 rounding floor of the inner solve (about 16 ulps, 1e-6:
+                // an FP32 residual can be exactly zero while the correction is
+                // only FP32-accurate).  Stop when this is a tenth of tol, or
+                // when the correction itself is below tol and cut the residual
+                // at least tenfold.
+                const double red_eff = std::max(last_red, 1e-6);
+                if (red_eff * d <= 0.1 * tol || (d <= tol && last_red <= 0.1)) break;
             }
             if (os.rr == 0.0) break;
             if (cyc >= o.max_outer) {
@@ -733,6 +749,11 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
                 result = is.bad() ? is : Status::err(CUTH_E_BREAKDOWN, "inner solve made no progress");
                 break;
             }
+            if (log_on())
+                std::fprintf(stderr,
+                             "cuth: cycle %d relres %.3e tau %.1e inner %d its (stop %d) "
+                             "true reduction %.3e est %.3e\n",
+                             cyc, relres, tau, ir.iters, ir.reason, ir.true_red, est);
             last_red = ir.true_red;
             delta = g.w32.x;
             th_in = th_out;
@@ -746,6 +767,7 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         double in_off = init_off;
         const double *delta = nullptr;
         double *th_out = g.thA;
+        double prev_relres = INFINITY;
         for (int cyc = 0;; ++cyc) {
             OuterRes os;
             CUTH_TRY((outer_residual<double, double>(g, op64, th_in, in_off, delta, P, Tn, th_out,
@@ -764,6 +786,14 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
                 result = Status::err(CUTH_E_NOT_CONVERGED, "restart limit reached");
                 break;
             }
+            // a restart that did not halve the true residual has hit the
+            // attainable accuracy of FP64 for this system: report, do not loop
+            if (cyc >= 1 && relres > 0.5 * prev_relres) {
+                result = Status::err(CUTH_E_NOT_CONVERGED,
+                                     "true residual stagnated above tol (attainable accuracy)");
+                break;
+            }
+            prev_relres = relres;
             // hot restart: r and p recomputed from their definitions, x kept
             Status is;
             InnerResult ir = inner_pcg<double>(g, op64, g.w64, cc, os.rr, tol * tol * os.bb,

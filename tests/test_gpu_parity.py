@@ -137,7 +137,8 @@ def test_solve_config0(prec, tol):
     err = rise_err(T.cpu().numpy(), ref, st.t_amb)
     say(f"  err {err:.3e} stats {stats}")
     assert err <= tol
-    assert stats["rel_residual"] < 1e-9
+    # the FP64 residual of the result (the mixed path stops on the error estimate)
+    assert stats["rel_residual"] < (1e-9 if prec == "fp64" else 1e-7)
     g.close()
 
 
