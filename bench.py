@@ -81,6 +81,125 @@ def cpu_baseline(stack, P, iters: int):
     }
 
 
+def _base(args, metric_workload: str, unknowns: int, value: float, per_step: float) -> dict:
+    return {
+        "metric": "PCG loop HBM GB/s + time to 1e-8 rel. error, mixed vs plain FP64, 1 GPU",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-inner/f64-outer",
+        "data": "synthetic", "config": {"workload": metric_workload, "unknowns": unknowns,
+                                        "cheb_degree": 30},
+    }
+
+
+def bench_transient(args) -> int:
+    """1024x1024x20 backward-Euler steps (dt = 1e-4 s, warm start from T_n, power
+    map switching every 20 steps among 5 floorplans); a step is one time step."""
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    st = w.config2_stack()
+    maps = {}
+
+    def pmap(s):
+        f = w.config2_floorplan_index(s)
+        if f not in maps:
+            maps[f] = torch.as_tensor(w.config2_power(st, f).ravel(), device=dev)
+        return maps[f]
+
+    g = cuth.Grid.from_stack(st, device=dev)
+    dt = 1e-4
+
+    def run(prec, nsteps, profile):
+        T = torch.full((st.n,), st.t_amb, dtype=torch.float64, device=dev)
+        T2 = torch.empty_like(T)
+        o = cuth.options(prec)
+        for s in range(args.warmup):
+            g.transient_step(dt, pmap(s), T, T2, opts=o)
+        T.fill_(st.t_amb)
+        if profile:
+            g.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for s in range(nsteps):
+            _, sd = g.transient_step(dt, pmap(s), T, T2, opts=o)
+            T, T2 = T2, T
+            stats.append(sd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        prof = g.profile_read() if profile else None
+        if profile:
+            g.profile_enable(False)
+        return ms, stats, prof, T
+
+    ms, stats, prof, Tm = run("mixed", args.steps, True)
+    ms64, stats64, _, T64 = run("fp64", args.steps, False)
+    rise = float((T64 - st.t_amb).abs().max())
+    per = ms / args.steps
+    value = sum(s["alg_bytes"] for s in stats) / (ms / 1e3) / 1e9
+    avg = prof["total_ms"] / max(prof["launches"], 1)
+    ach = prof["bytes_per_launch"] / (avg / 1e3) / 1e9 if prof["launches"] else None
+    out = _base(args, "transient 1024x1024x20 layered stack (4 dies), dt = 1e-4 s, warm start, "
+                      "floorplan switch every 20 steps; mixed FP32/FP64 per step to 1e-8",
+                st.n, value, per)
+    out["time_to_tol_ms"] = {"mixed": round(per, 3), "fp64": round(ms64 / args.steps, 3),
+                             "speedup_mixed_vs_fp64": round(ms64 / ms, 3)}
+    out["solve_detail"] = {"mixed_cg_iters_per_step": [s["cg_iters"] for s in stats][:10],
+                           "fp64_cg_iters_per_step": [s["cg_iters"] for s in stats64][:10],
+                           "mixed_vs_fp64_max_rise_rel_diff": float((Tm - T64).abs().max()) / rise}
+    out["roofline"] = {"bound": "hbm", "kernel": "k_cheb_b general sweep, FP32, matrix-free",
+                       "achieved": round(ach, 2) if ach else None, "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4) if ach else None,
+                       "traffic": None, "bytes_per_launch": prof["bytes_per_launch"],
+                       "avg_launch_us": round(avg * 1e3, 3), "timed_launches": prof["launches"]}
+    g.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args) -> int:
+    """64 uneven stacks x 4 power maps in one batched mixed solve per step."""
+    import numpy as np
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    items = w.config3()
+    grids = [cuth.Grid.from_stack(st, device=dev) for st, _ in items]
+    P = [torch.as_tensor(np.concatenate([m.ravel() for m in maps]), device=dev) for _, maps in items]
+    T = [torch.empty_like(p) for p in P]
+    o = cuth.options("mixed")
+    for _ in range(max(args.warmup, 1)):
+        cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, stats = cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    per = ms / args.steps
+    unknowns = sum(st.n for st, _ in items)
+    value = sum(s["alg_bytes"] for s in stats) / (per / 1e3) / 1e9
+    out = _base(args, "batch of 64 uneven stacks (edge 128-384, 8-16 layers) x 4 power maps, "
+                      "one batched mixed solve to 1e-8", unknowns, value, per)
+    its = [s["cg_iters"] for s in stats]
+    out["solve_detail"] = {"problems": len(stats), "cg_iters_min": min(its), "cg_iters_max": max(its),
+                           "unknown_rhs": unknowns * 4}
+    out["roofline"] = None
+    for gg in grids:
+        gg.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +210,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--workload", choices=("c1", "c2", "c3"), default="c1",
+                    help="c1: 512x512x16 steady (default, the headline); c2: 1024x1024x20 "
+                         "transient steps; c3: 64-stack batch")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -98,6 +220,10 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
+    if args.workload == "c2":
+        return bench_transient(args)
+    if args.workload == "c3":
+        return bench_batch(args)
 
     import numpy as np
     import torch
@@ -206,7 +332,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cheb (general Chebyshev sweep, FP32, per-cell lateral conductances)",
+            "kernel": "k_cheb_b (general Chebyshev sweep, FP32, per-cell lateral conductances)",
             "achieved": round(achieved, 2) if achieved else None,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

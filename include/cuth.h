@@ -89,7 +89,7 @@ typedef struct {
                                     default 1e-8.  CUTH_FP64: relative residual
                                     ||b - A T|| / ||b||, default 1e-10 for steady and
                                     1e-12 for transient solves.                       */
-    int32_t cheb_degree;         /* Chebyshev degree k >= 1 (default 30)               */
+    int32_t cheb_degree;         /* Chebyshev degree k, 1..256 (default 30)            */
     int32_t lanczos_steps;       /* Lanczos steps m, 2..256 (default 30)               */
     int32_t max_inner;           /* CG iterations per inner solve (default 2000)       */
     int32_t max_outer;           /* refinement cycles, CUTH_MIXED (default 12)         */
@@ -142,10 +142,18 @@ cuth_status cuth_transient_step(cuth_grid g, double dt, const double *P_next,
                                 const double *T_n, double *T_next,
                                 const cuth_options *opt, cuth_stats *stats);
 
-/* Solve nsys independent steady systems, each with nrhs right-hand sides,
- * advancing all of them together.  P[s] / T[s]: device double [nrhs * N_s]
- * (right-hand side q at offset q*N_s).  stats: NULL or [nsys*nrhs].
- * All grids must live on the same device; the first grid's stream is used. */
+/* Solve nsys independent steady systems, each with nrhs right-hand sides.
+ * Every (system, right-hand side) pair is one problem; all problems advance
+ * together: each kernel launch covers every active problem (per-problem
+ * scalars, spectral bounds and convergence flags), a chunk of CG iterations is
+ * captured once into a HIP graph and replayed, and the tile shape is picked by
+ * timing candidate shapes on the batch (cached per batch signature, and in the
+ * file named by the CUTH_AUTOTUNE_CACHE environment variable if set).
+ * P[s] / T[s]: device double [nrhs * N_s] (right-hand side q at offset q*N_s).
+ * stats: NULL or [nsys*nrhs] (setup_ms/solve_ms are 0 per problem).  All grids
+ * must live on the same device; work is ordered after the first grid's stream.
+ * The call allocates its work vectors (about 40 B per unknown and right-hand
+ * side in mixed precision) for its duration. */
 cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
                              const double *const *P, double *const *T,
                              const cuth_options *opt, cuth_stats *stats);

@@ -8,6 +8,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 struct cuth_grid_s {
     cuth::Grid *g;
@@ -58,8 +59,8 @@ cuth_status check_opts(const cuth_options &o) {
         return fail(CUTH_E_INVALID, "precision must be CUTH_FP64 or CUTH_MIXED");
     if (!(o.tol == 0.0 || (finite_pos(o.tol) && o.tol < 1.0)))
         return fail(CUTH_E_INVALID, "tol must be 0 (default) or in (0, 1)");
-    if (o.cheb_degree < 1 || o.cheb_degree > 1000)
-        return fail(CUTH_E_INVALID, "cheb_degree must be in 1..1000");
+    if (o.cheb_degree < 1 || o.cheb_degree > 256)
+        return fail(CUTH_E_INVALID, "cheb_degree must be in 1..256");
     if (o.lanczos_steps < 2 || o.lanczos_steps > 256)
         return fail(CUTH_E_INVALID, "lanczos_steps must be in 2..256");
     if (o.max_inner < 1 || o.max_outer < 1)
@@ -188,23 +189,13 @@ cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
             if (!steady_ok(*grids[s]->g))
                 return fail(CUTH_E_INVALID, "steady solve needs a convective face");
         }
-        cuth_status worst = CUTH_OK;
+        std::vector<cuth::Grid *> gs(nsys);
         for (int s = 0; s < nsys; ++s) {
-            cuth::Grid &g = *grids[s]->g;
-            for (int q = 0; q < nrhs; ++q) {
-                const int64_t off = (int64_t)q * g.N;
-                cuth_stats *so = stats ? &stats[(int64_t)s * nrhs + q] : nullptr;
-                cuth::Status st = cuth::solve_system(
-                    g, 0.0, P[s] + off, nullptr, o.use_initial_guess ? T[s] + off : nullptr, g.t_amb,
-                    T[s] + off, g.t_amb, o, so, false);
-                if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_NOMEM) return report(st);
-                if (st.bad() && worst == CUTH_OK) {
-                    worst = st.code;
-                    g_last_error = st.msg;
-                }
-            }
+            gs[s] = grids[s]->g;
+            if (gs[s]->device != gs[0]->device)
+                return fail(CUTH_E_INVALID, "all grids of a batch must be on one device");
         }
-        return worst;
+        return report(cuth::solve_batch(nsys, gs.data(), nrhs, P, T, o, stats));
     });
 }
 
@@ -255,7 +246,7 @@ cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, double
         if (precision != CUTH_FP64 && precision != CUTH_MIXED) return fail(CUTH_E_INVALID, "bad precision");
         if (!finite_pos(lmin) || !finite_pos(lmax) || !(lmax > lmin))
             return fail(CUTH_E_INVALID, "need 0 < lmin < lmax");
-        if (degree < 1 || degree > 1000) return fail(CUTH_E_INVALID, "degree must be in 1..1000");
+        if (degree < 1 || degree > 256) return fail(CUTH_E_INVALID, "degree must be in 1..256");
         if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
         if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
         return report(cuth::precond_apply(g, dt, precision, lmin, lmax, degree, r, z));

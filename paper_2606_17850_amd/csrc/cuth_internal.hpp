@@ -57,70 +57,108 @@ inline int red_blocks(int64_t n) {
 
 // Scalars of one PCG run (Algorithm 1) resident on the device.  Kernels never
 // read a field that a workgroup of the same launch writes, except `done`, which
-// every workgroup of a launch sets to the same value from the same data.
+// every workgroup of a problem sets to the same value from the same data.
 template <typename T>
 struct CgState {
-    T rz[2];      // r_k^T z_k in slot k & 1 (written by the direction kernel of k)
+    T rz[2];      // r_k^T z_k in slot k & 1 (direction kernel of k); the host sets
+                  // slot 1 to +inf before iteration 0, which marks "no previous p"
     T rr;         // last recursive ||r||^2
     T rr0;        // ||rhat||^2 of the inner right-hand side (host)
     T tol2;       // converged when rr <= tol2 (host)
     T pad;
-    int done;     // 0 running, 1 tolerance, 4 breakdown
+    int done;     // 0 running, 1 tolerance, 2 drift, 3 stagnation, 4 breakdown
     int iter;     // completed CG iterations (updates followed by a convergence test)
     int pad2[2];
 };
 
+// One inner PCG problem (one system and right-hand side) of a batched launch.
+// The launch covers the problems' workgroup slots [tile0, tile0 + ntiles) back
+// to back; slot s is given to the workgroup of XCD-banded index s.
+template <typename T>
+struct InnerProb {
+    OpView<T> op;
+    int ntx, ntz;             // tiles along x and z (the launch shape is op.vx/by/zc)
+    int tile0, ntiles;
+    T *x, *r, *rhat, *mu;
+    T *p[2];
+    T *z[2];
+    CgState<T> *st;
+    const T *cheb;            // 1/theta at [0], c1_j at [1 + j], c2_j at [1 + kcap + j]
+    int kcap, pad;
+};
+
+// One FP64 outer-residual problem of a batched launch:
+// theta_out = (theta_in - in_off) + delta;  b = P + cap*(Tn - tn_off);
+// r = b - A theta_out, with optional copies of r in the inner precision.
+template <typename TD, typename TI>
+struct OuterProb {
+    OpView<double> op;
+    int ntx, ntz, tile0, ntiles;
+    const double *th_in;
+    double in_off;
+    const TD *delta;
+    const double *P;
+    const double *Tn;
+    double tn_off;
+    double *th_out, *r64;
+    TI *r_in, *rhat;
+};
+
 // ---- launchers (kernels.hip) -------------------------------------------------
-// Every reduction writes one partial per workgroup into `part` (value v of
-// workgroup b at part[v*nb + b]); the consumer (next kernel, or the host)
-// reduces them in a fixed order.
+// Every reduction writes one partial per workgroup slot into `part` (value v of
+// slot s at part[v*nb + s], nb = total slots of the launch); the consumer (next
+// kernel, or the host) sums a problem's slots in a fixed order.  A consumer
+// launched with red = true instead reads problem p's sum at part_in[p], written
+// by launch_reduce_b.
 
 template <typename T>
 void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 
-// Chebyshev sweep z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 (r - A z_j).
-// mode 1: z_j = r*inv_th, z_{j-1} = 0 (j = 1); mode 2: z_{j-1} = r*inv_th
-// (j = 2); mode 0: z_{j-1} read from zo.  The result is written to zo.
-// last: also write partials of r^T z_{j+1} to part_out.  chk: first kernel
-// after a CG update: reduce the update's partials (part_in, np_in) and stop
-// (st->done = 1) if rr <= tol2; writes st->rr and st->iter = k + 1.
+// Chebyshev sweep j (Section 4.3, two-term form):
+//   z_{j+1} = z_j + c1_j (z_j - z_{j-1}) + c2_j (r - A z_j).
+// mode 1 (j = 1): z_1 = r/theta and z_0 = 0 are implicit; mode 2 (j = 2):
+// z_{j-1} = r/theta implicit; mode 0: z_{j-1} read.  z_j is in z[zin]; the result
+// goes to z[1 - zin].  last: partials of r^T z_{j+1}.  chk: the first kernel after
+// a CG update reduces the update's partials (part_in) and stops converged
+// problems (rr <= tol2).
 template <typename T>
-void launch_cheb(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
-                 const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *part_in, int np_in,
-                 T *part_out, hipStream_t s);
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+                   int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
+                   T *part_out, hipStream_t s);
 
-// Degree-1 preconditioner z = a r with the same last/chk behaviour.
+// Degree-1 preconditioner z[0] = r/theta (same chk/last behaviour).
 template <typename T>
-void launch_scale(int64_t n, const T *r, T a, T *z, bool chk, int k, CgState<T> *st,
-                  const T *part_in, int np_in, T *part_out, hipStream_t s);
+void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, bool chk,
+                    const T *part_in, bool red, T *part_out, hipStream_t s);
 
-// CG iteration k: reduce r^T z (part_in) into rz_k; p = z + (rz_k/rz_{k-1}) p_old;
-// mu = A p; partials of p^T mu.
+// CG iteration of parity par: rz = sum(part_in); p[par] = z[zfin] + (rz / rz_prev) p[1-par];
+// mu = A p[par]; partials of p^T mu.
 template <typename T>
-void launch_cg_dir(const OpView<T> &op, int k, const T *z, const T *pold, T *pnew, T *mu,
-                   CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s);
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int par,
+                  int zfin, const T *part_in, bool red, T *part_out, hipStream_t s);
 
-// x += alpha p (x = alpha p for k = 0), r -= alpha mu with alpha = rz_k / p^T mu;
-// partials of r^T r.
+// x += alpha p[par] (x = alpha p on the first iteration), r -= alpha mu with
+// alpha = rz / p^T mu; partials of r^T r.
 template <typename T>
-void launch_cg_update(const OpView<T> &op, int k, T *x, const T *p, T *r, const T *mu,
-                      CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s);
+void launch_update_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, int par,
+                     const T *part_in, bool red, T *part_out, hipStream_t s);
 
-// True residual rt = rhat - A x (x = 0 if !have_x): partials of ||rt||^2 and
-// ||rt - r||^2 (reduced on the host).
+// red_out[p] = fixed-order sum of problem p's partials in part_in (one
+// workgroup per problem).
 template <typename T>
-void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r, bool have_x,
-                     T *part_out, hipStream_t s);
+void launch_reduce_b(const InnerProb<T> *probs, int nprob, const T *part_in, T *red_out,
+                     hipStream_t s);
 
-// theta_out = (theta_in - in_off) + delta;  b = P + cap*(Tn - tn_off);
-// r = b - A theta_out (FP64); optional copies of r in the inner precision;
-// partials (reduced on the host) of ||r||^2, ||b||^2, max|delta|, max|theta_out|,
+// True residual rt = rhat - A x: partials of ||rt||^2 and ||rt - r||^2.
+template <typename T>
+void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+                    T *part_out, hipStream_t s);
+
+// FP64 outer residual; partials of ||r||^2, ||b||^2, max|delta|, max|theta_out|,
 // count of non-finite r.
 template <typename TD, typename TI>
-void launch_residual(const OpView<double> &op, const double *th_in, double in_off,
-                     const TD *delta, const double *P, const double *Tn, double tn_off,
-                     double *th_out, double *r64, TI *r_in, TI *rhat, double *part_out,
-                     hipStream_t s);
+void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool pc, int vx, int by,
+                       double *part_out, hipStream_t s);
 constexpr int kResidualValues = 5;
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s);

@@ -28,15 +28,6 @@ struct Setup {
     double lmin = 0, lmax = 0, ritz_min = 0, ritz_max = 0, gersh = 0;
 };
 
-// Result of one inner PCG run.
-struct InnerResult {
-    int iters = 0;
-    int reason = 0;        // 1 tol, 2 drift, 3 stagnation, 4 breakdown, 5 iteration limit
-    double true_red = 1;   // ||rhat - A x|| / ||rhat||
-    int64_t stencils = 0;
-    double bytes = 0;      // algorithmic bytes moved
-};
-
 struct Status {
     cuth_status code = CUTH_OK;
     std::string msg;
@@ -52,11 +43,29 @@ struct Status {
 
 // Launch shape of the stencil kernels of one precision.
 struct Shape {
-    int vx = 1, by = 4, zc = 64;
+    int vx = 1, by = 1, zc = 8;
 };
 
-// Slots of the partials buffer (one per producer/consumer pair).
-enum Slot { S_CHEB = 0, S_DIR, S_UPD, S_CHK, S_RES, S_LZA, S_LZB, S_MISC, S_COUNT };
+// Device descriptors, states and reduction partials for up to `cap` problems
+// solved together (a single solve uses a set of one).
+struct Engine {
+    int cap = 0, kcap = 0;
+    size_t slot_doubles = 0;
+    InnerProb<float> *in32 = nullptr, *h_in32 = nullptr;
+    InnerProb<double> *in64 = nullptr, *h_in64 = nullptr;
+    OuterProb<float, float> *out32 = nullptr, *h_out32 = nullptr;
+    OuterProb<double, double> *out64 = nullptr, *h_out64 = nullptr;
+    CgState<float> *st32 = nullptr, *h_st32 = nullptr;
+    CgState<double> *st64 = nullptr, *h_st64 = nullptr;
+    float *cheb32 = nullptr, *h_cheb32 = nullptr;
+    double *cheb64 = nullptr, *h_cheb64 = nullptr;
+    double *part = nullptr, *h_part = nullptr;   // 5 slots of slot_doubles
+    hipStream_t own = nullptr;                   // stream for graph capture
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+// Slots of a grid's own partials buffer (Lanczos, adjoint).
+enum Slot { S_LZA = 0, S_LZB, S_COUNT };
 
 struct Grid {
     int device = 0;
@@ -77,19 +86,13 @@ struct Grid {
     Work<double> w64;
     double *thA = nullptr, *thB = nullptr;
 
-    double *part = nullptr;           // S_COUNT slots of slot_doubles each, then the adjoint slot
+    double *part = nullptr;           // S_COUNT slots of slot_doubles, then the adjoint slot
     size_t slot_doubles = 0;
     double *part_adj = nullptr;
-    CgState<float> *st32 = nullptr;
-    CgState<double> *st64 = nullptr;
     float *lz = nullptr;              // Lanczos scalars on the device
     double *adj_fac = nullptr;        // adjoint factors [3 nz]
-
-    // pinned host mirrors for stream-ordered readback
-    CgState<float> *h_st32 = nullptr;
-    CgState<double> *h_st64 = nullptr;
-    double *h_part = nullptr;         // slot_doubles
     float *h_lz = nullptr;
+    Engine eng;                       // single-problem engine of this grid
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 
@@ -97,6 +100,7 @@ struct Grid {
     // Chebyshev sweep of each preconditioner application
     bool prof = false;
     std::vector<hipEvent_t> pev;
+    std::vector<int> pev_tag;   // CG iteration of each recorded pair (-1: initial)
     size_t pev_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
     int64_t prof_count = 0;
@@ -107,7 +111,7 @@ struct Grid {
     }
 };
 
-Status prof_flush(Grid &g);
+Status prof_flush(Grid &g, int valid_below = 1 << 30);
 
 Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out);
 void grid_destroy(Grid *g);
@@ -128,6 +132,11 @@ OpView<float> view32(const Grid &g, const Setup &su);
 Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const double *init,
                     double init_off, double *out, double out_off, const cuth_options &o,
                     cuth_stats *stats, bool transient_defaults);
+
+// Steady solves of nsys grids with nrhs right-hand sides each, all advanced
+// together in batched launches.
+Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
+                   double *const *T, const cuth_options &o, cuth_stats *stats);
 
 Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax, int degree,
                      const void *r, void *z);

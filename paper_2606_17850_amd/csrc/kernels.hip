@@ -3,22 +3,32 @@
 // Stencil mapping.  A workgroup is `by` wavefronts; wavefront row w owns grid
 // row j of a tile, and lane q owns `vx` consecutive cells along x, so a
 // wavefront covers 64*vx cells of one row with one 16-byte load per lane for
-// FP32 vx = 4 and FP64 vx = 2.  Each lane marches up through all layers with
-// the values of the layers below, at and above in registers; x neighbours come
-// from the adjacent lanes (cross-lane shuffles), y neighbours from the rows
-// above and below (cache hits: the same lines the neighbouring rows load).
+// FP32 vx = 4 and FP64 vx = 2.  Each lane marches up through a chunk of zc
+// layers with the values of the layers below, at and above in registers; x
+// neighbours come from the adjacent lanes (cross-lane shuffles), y neighbours
+// from the rows above and below (cache hits: the same lines the neighbouring
+// rows load).
 //
-// XCD-aware tile order.  Workgroups are dispatched round-robin over the eight
-// XCDs (workgroup b runs on XCD b mod 8), each XCD with its own L2.  Tile rows
-// are therefore handed out in eight contiguous bands, one per XCD, so that the
-// tiles above and below a tile (whose rows it reads as halo) run on the same
-// XCD at about the same time and its halo reads hit that XCD's L2.
+// XCD-aware order.  Workgroups are dispatched round-robin over the eight XCDs
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  Workgroup b is
+// given slot s of a banded order: the slots are split into eight contiguous
+// bands, one per XCD, and slots are laid out problem by problem, tile row by
+// tile row, with the layer chunks of one lateral tile adjacent.  The tiles above
+// and below a tile (whose rows it reads as halo) and the chunks sharing its
+// boundary layers thus run on the same XCD at about the same time and their
+// shared lines hit that XCD's L2.
+//
+// Batches.  The inner-PCG kernels take an array of problem descriptors (one per
+// system and right-hand side); a workgroup finds its problem by binary search
+// over the problems' first slots.  A single solve is a batch of one.  Kernel
+// arguments depend on the iteration only through its parity, so a chunk of an
+// even number of CG iterations can be captured once into a graph and replayed.
 //
 // Reductions.  Each workgroup reduces its values with wavefront butterflies and
 // a fixed-order pass over its wavefronts, and writes one partial per value.
-// The next kernel in the stream (or the host) sums all partials in a fixed
-// order; every workgroup of the consuming kernel computes the same sum, so no
-// grid-wide synchronisation, fence or atomic is needed, and results are
+// The next kernel in the stream (or the host) sums a problem's partials in a
+// fixed order; every workgroup of the consuming kernel computes the same sum,
+// so no grid-wide synchronisation, fence or atomic is needed, and results are
 // run-to-run deterministic.
 #include "cuth_internal.hpp"
 
@@ -67,10 +77,16 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+template <typename T>
+__device__ __forceinline__ bool finite_val(T v) {
+    return isfinite(v);
+}
+
 // Sum (or max for the values whose bit is set in maxmask; those are >= 0) of
-// v[k] over the workgroup; written by thread 0 to part[k*nb + blockIdx.x].
+// v[k] over the workgroup; written by thread 0 to part[k*nb + slot].
 template <typename T, int NV>
-__device__ __forceinline__ void block_partials(T (&v)[NV], unsigned maxmask, T *part) {
+__device__ __forceinline__ void block_partials(T (&v)[NV], unsigned maxmask, T *part, int nb,
+                                               int slot) {
     __shared__ T sh[NV][kMaxBY];
     const int lane = threadIdx.x, w = threadIdx.y, nw = blockDim.y;
 #pragma unroll
@@ -81,13 +97,12 @@ __device__ __forceinline__ void block_partials(T (&v)[NV], unsigned maxmask, T *
     }
     __syncthreads();
     if (tid_lin() == 0) {
-        const int nb = gridDim.x;
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const bool mx = (maxmask >> k) & 1u;
             T a = sh[k][0];
             for (int q = 1; q < nw; ++q) a = mx ? fmax(a, sh[k][q]) : a + sh[k][q];
-            part[(size_t)k * nb + blockIdx.x] = a;
+            part[(size_t)k * nb + slot] = a;
         }
     }
 }
@@ -97,8 +112,24 @@ __device__ __forceinline__ void block_partials(T (&v)[NV], unsigned maxmask, T *
 template <typename T>
 __device__ __forceinline__ T reduce_prev(const T *part, int np) {
     __shared__ T sh[kMaxBY];
+    // 16 independent loads in flight per lane (one L2 round trip per 1024
+    // partials of a 64-lane workgroup), then a fixed-order combine
+    constexpr int U = 16;
+    const int n = nthreads();
+    T acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = T(0);
+    int q = tid_lin();
+    for (; q + (U - 1) * n < np; q += U * n) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += part[q + u * n];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (q + u * n < np) acc[u] += part[q + u * n];
     T a = T(0);
-    for (int q = tid_lin(); q < np; q += nthreads()) a += part[q];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a += acc[u];
     a = wave_sum(a);
     if (threadIdx.x == 0) sh[threadIdx.y] = a;
     __syncthreads();
@@ -108,18 +139,23 @@ __device__ __forceinline__ T reduce_prev(const T *part, int np) {
     return s;
 }
 
-// XCD-aware tile of this workgroup: contiguous bands of the tile order per
-// XCD, with the layer chunks of one lateral tile adjacent (they share their
-// boundary layers), then x, then y.
-__device__ __forceinline__ void my_tile(int ntx, int ntz, int &tx, int &ty, int &tz) {
+// Slot of this workgroup in the XCD-banded order.
+__device__ __forceinline__ int xcd_slot() {
     const int nb = gridDim.x, b = blockIdx.x;
     const int xcd = b & 7, k = b >> 3;
     const int per = nb >> 3, rem = nb & 7;
-    const int lin = xcd * per + (xcd < rem ? xcd : rem) + k;
-    tz = lin % ntz;
-    const int t = lin / ntz;
-    tx = t % ntx;
-    ty = t / ntx;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+template <typename D>
+__device__ __forceinline__ int find_prob(const D *probs, int nprob, int slot) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile0 <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 struct Lane {
@@ -127,10 +163,12 @@ struct Lane {
     bool act;
 };
 
+// Lane coordinates for tile `local` of an operator tiled ntx wide, ntz deep.
 template <int VX, typename T>
-__device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
-    int tx, ty, tz;
-    my_tile((op.nx + kWave * VX - 1) / (kWave * VX), (op.nz + op.zc - 1) / op.zc, tx, ty, tz);
+__device__ __forceinline__ Lane lane_at(const OpView<T> &op, int local, int ntx, int ntz) {
+    const int tz = local % ntz;
+    const int t = local / ntz;
+    const int tx = t % ntx, ty = t / ntx;
     Lane L;
     L.lane = threadIdx.x;
     L.i0 = (tx * kWave + L.lane) * VX;
@@ -141,13 +179,23 @@ __device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
     return L;
 }
 
-// March the VX cells of one lane through all layers; emit(l, c, x, A x) per layer
-// (only for active lanes).  XV(q) fetches VX consecutive values of the operand
-// starting at cell q, XS(q) one value.  Every lane of the wavefront must call
-// this (the x halo comes through cross-lane shuffles).
-template <typename T, bool PC, int VX, typename FV, typename FS, typename E>
-__device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
-                                       E &&emit) {
+template <int VX, typename T>
+__device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
+    return lane_at<VX>(op, xcd_slot(), (op.nx + kWave * VX - 1) / (kWave * VX),
+                       (op.nz + op.zc - 1) / op.zc);
+}
+
+// March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
+// layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
+// starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
+// (issued with the layer's stencil loads).  Every lane of the wavefront must
+// call this (the x halo comes through cross-lane shuffles).  (Issuing the next
+// layer's loads before computing the current one was measured slower on gfx950:
+// more registers, no gain in overlap.)
+template <typename T, bool PC, int VX, typename FV, typename FS, typename FP, typename E>
+__device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
+                                           FP &&PRE, E &&emit) {
+    using Ex = decltype(PRE(int64_t(0)));
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const bool act = ln.act;
@@ -155,23 +203,33 @@ __device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &
     const bool has_s = act && ln.j > 0, has_n = act && ln.j < ny - 1;
     int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
     const Vec<T, VX> zero = vzero<T, VX>();
-    Vec<T, VX> xdn = (act && ln.l0 > 0) ? XV(c - plane) : zero;
-    Vec<T, VX> xc = act ? XV(c) : zero;
+    Vec<T, VX> xdn = zero, xc = zero;
+    if (act) {
+        if (ln.l0 > 0) xdn = XV(c - plane);
+        xc = XV(c);
+    }
     for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
         const LayerCoef<T> L = op.lc[l];
-        const Vec<T, VX> xup = (act && l + 1 < nz) ? XV(c + plane) : zero;
-        const Vec<T, VX> xso = has_s ? XV(c - nx) : zero;
-        const Vec<T, VX> xno = has_n ? XV(c + nx) : zero;
+        Vec<T, VX> xup = zero, xso = zero, xno = zero;
+        Ex ex{};
+        if (act) {
+            if (l + 1 < nz) xup = XV(c + plane);
+            if (has_s) xso = XV(c - nx);
+            if (has_n) xno = XV(c + nx);
+            ex = PRE(c);
+        }
         T left = __shfl_up(xc.a[VX - 1], 1, 64);
         T right = __shfl_down(xc.a[0], 1, 64);
         if (ln.lane == 0) left = has_l ? XS(c - 1) : T(0);
         if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
-        Vec<T, VX> gxp, gyp, gym;
+        Vec<T, VX> gxp = zero, gyp = zero, gym = zero;
         T gxl = T(0);
         if constexpr (PC) {
-            gxp = act ? vload<T, VX>(op.gx + c) : zero;
-            gyp = act ? vload<T, VX>(op.gy + c) : zero;
-            gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+            if (act) {
+                gxp = vload<T, VX>(op.gx + c);
+                gyp = vload<T, VX>(op.gy + c);
+            }
+            if (has_s) gym = vload<T, VX>(op.gy + c - nx);
             gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
             if (ln.lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
         }
@@ -201,15 +259,31 @@ __device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &
             if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
             ax.a[e] = a;
         }
-        if (act) emit(l, c, xc, ax);
+        if (act) emit(l, c, xc, ax, ex);
         xdn = xc;
         xc = xup;
     }
 }
 
-template <typename T>
-__device__ __forceinline__ bool finite_val(T v) {
-    return isfinite(v);
+struct NoEx {};
+
+template <typename T, bool PC, int VX, typename FV, typename FS, typename E>
+__device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
+                                       E &&emit) {
+    column_pre<T, PC, VX>(
+        op, ln, XV, XS, [](int64_t) { return NoEx{}; },
+        [&](int l, int64_t c, const Vec<T, VX> &x, const Vec<T, VX> &ax, const NoEx &) {
+            emit(l, c, x, ax);
+        });
+}
+
+// Elementwise march over the cells of one lane (no stencil).
+template <typename T, int VX, typename E>
+__device__ __forceinline__ void cells(const OpView<T> &op, const Lane &ln, E &&emit) {
+    if (!ln.act) return;
+    const int64_t plane = (int64_t)op.nx * op.ny;
+    int64_t c = ln.i0 + (int64_t)op.nx * ln.j + plane * ln.l0;
+    for (int l = ln.l0; l < ln.l1; ++l, c += plane) emit(l, c);
 }
 
 // ------------------------------------------------------------------ apply
@@ -222,30 +296,54 @@ __global__ __launch_bounds__(512) void k_apply(OpView<T> op, const T *__restrict
         [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax) { vstore<T, VX>(y + c, ax); });
 }
 
-// Convergence test of the first kernel after a CG update (all workgroups agree).
+// Problem pidx's sum of the previous kernel's partials: summed here by every
+// workgroup (red == 0), or already summed by k_reduce_b into part_in[pidx].
 template <typename T>
-__device__ __forceinline__ bool conv_test(int k, CgState<T> *st, const T *part, int np) {
-    const T rr = reduce_prev(part, np);
-    const bool stop = !(rr > st->tol2) || !finite_val(rr);
-    if (blockIdx.x == 0 && tid_lin() == 0) {
+__device__ __forceinline__ T prev_sum(const T *part_in, int red, int pidx, const InnerProb<T> &P) {
+    if (red) return part_in[pidx];
+    return reduce_prev(part_in + P.tile0, P.ntiles);
+}
+
+// Convergence test of the first kernel after a CG update: every workgroup of
+// the problem obtains the same r^T r and agrees.
+template <typename T>
+__device__ __forceinline__ bool conv_test(CgState<T> *st, const T *part_in, int red, int pidx,
+                                          const InnerProb<T> &P, bool lead) {
+    const T tol2 = st->tol2;
+    const T rr = prev_sum(part_in, red, pidx, P);
+    const bool stop = !(rr > tol2) || !finite_val(rr);
+    if (lead && tid_lin() == 0) {
         st->rr = rr;
-        st->iter = k + 1;
+        st->iter = st->iter + 1;
         if (stop) st->done = finite_val(rr) ? 1 : 4;
     }
     return stop;
 }
 
-// ------------------------------------------------------------ Chebyshev sweep
+// ---------------------------------------------------- batched Chebyshev sweep
 template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK>
-__global__ __launch_bounds__(512) void k_cheb(OpView<T> op, int k, const T *__restrict__ z, T *zo,
-                                              const T *__restrict__ r, T c1, T c2, T inv_th,
-                                              CgState<T> *st, const T *__restrict__ part_in,
-                                              int np_in, T *__restrict__ part_out) {
-    if (st->done) return;
+__global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                                int j, int zin, const T *__restrict__ part_in,
+                                                int red, T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const int pidx = find_prob(probs, nprob, slot);
+    const InnerProb<T> &P = probs[pidx];
+    CgState<T> *st = P.st;
+    // the sweep's constants are fetched together with the stop flag
+    const T inv_th = P.cheb[0], c1 = P.cheb[1 + j], c2 = P.cheb[1 + P.kcap + j];
+    const int done = st->done;
     if constexpr (CHK) {
-        if (conv_test(k, st, part_in, np_in)) return;
+        // the partial sums are fetched while the stop flag is in flight
+        const bool stop = conv_test(st, part_in, red, pidx, P, !done && slot == P.tile0);
+        if (done || stop) return;
+    } else {
+        if (done) return;
     }
-    const Lane ln = lane_of<VX>(op);
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
+    const T *__restrict__ r = P.r;
+    const T *__restrict__ z = P.z[zin];
+    T *zo = P.z[1 - zin];
     T acc[1] = {T(0)};
     auto XV = [&](int64_t q) -> Vec<T, VX> {
         if constexpr (MODE == 1) {
@@ -261,11 +359,20 @@ __global__ __launch_bounds__(512) void k_cheb(OpView<T> op, int k, const T *__re
         if constexpr (MODE == 1) return r[q] * inv_th;
         else return z[q];
     };
-    column<T, PC, VX>(op, ln, XV, XS,
-                      [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az) {
-                          const Vec<T, VX> rc = vload<T, VX>(r + c);
-                          Vec<T, VX> zm;
-                          if constexpr (MODE == 0) zm = vload<T, VX>(zo + c);
+    struct Ex {
+        Vec<T, VX> r, zm;
+    };
+    auto PRE = [&](int64_t c) {
+        Ex e;
+        e.r = vload<T, VX>(r + c);
+        if constexpr (MODE == 0) e.zm = vload<T, VX>(zo + c);
+        else e.zm = vzero<T, VX>();
+        return e;
+    };
+    column_pre<T, PC, VX>(op, ln, XV, XS, PRE,
+                      [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az, const Ex &ex) {
+                          const Vec<T, VX> &rc = ex.r;
+                          const Vec<T, VX> &zm = ex.zm;
                           Vec<T, VX> zn;
 #pragma unroll
                           for (int e = 0; e < VX; ++e) {
@@ -278,57 +385,83 @@ __global__ __launch_bounds__(512) void k_cheb(OpView<T> op, int k, const T *__re
                           }
                           vstore<T, VX>(zo + c, zn);
                       });
-    if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out);
+    if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
-// z = a r (degree-1 preconditioner), partials of r^T z.
-template <typename T, bool CHK>
-__global__ __launch_bounds__(256) void k_scale(int64_t n, const T *__restrict__ r, T a,
-                                               T *__restrict__ z, int k, CgState<T> *st,
-                                               const T *__restrict__ part_in, int np_in,
-                                               T *__restrict__ part_out) {
-    if (st->done) return;
+// Degree-1 preconditioner z[0] = r/theta, partials of r^T z.
+template <typename T, int VX, bool CHK>
+__global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                                 const T *__restrict__ part_in, int red,
+                                                 T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const int pidx = find_prob(probs, nprob, slot);
+    const InnerProb<T> &P = probs[pidx];
+    CgState<T> *st = P.st;
+    const int done = st->done;
     if constexpr (CHK) {
-        if (conv_test(k, st, part_in, np_in)) return;
+        const bool stop = conv_test(st, part_in, red, pidx, P, !done && slot == P.tile0);
+        if (done || stop) return;
+    } else {
+        if (done) return;
     }
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
+    const T inv_th = P.cheb[0];
+    const T *__restrict__ r = P.r;
+    T *__restrict__ z0 = P.z[0];
     T acc[1] = {T(0)};
-    const int64_t stride = (int64_t)gridDim.x * nthreads();
-    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride) {
-        const T v = a * r[q];
-        z[q] = v;
-        acc[0] += r[q] * v;
-    }
-    block_partials<T, 1>(acc, 0u, part_out);
+    cells<T, VX>(op, ln, [&](int, int64_t c) {
+        const Vec<T, VX> rv = vload<T, VX>(r + c);
+        Vec<T, VX> zv;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            zv.a[e] = rv.a[e] * inv_th;
+            acc[0] += rv.a[e] * zv.a[e];
+        }
+        vstore<T, VX>(z0 + c, zv);
+    });
+    block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
 // ---------------------------------------------- CG: direction + SpMV + p^T A p
 template <typename T, bool PC, int VX>
-__global__ __launch_bounds__(512) void k_cg_dir(OpView<T> op, int k, const T *__restrict__ z,
-                                                const T *__restrict__ pold,
-                                                T *__restrict__ pnew, T *__restrict__ mu,
-                                                CgState<T> *st, const T *__restrict__ part_in,
-                                                int np_in, T *__restrict__ part_out) {
-    if (st->done) return;
-    const T rz = reduce_prev(part_in, np_in);
+__global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                               int par, int zfin, const T *__restrict__ part_in,
+                                               int red, T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const int pidx = find_prob(probs, nprob, slot);
+    const InnerProb<T> &P = probs[pidx];
+    CgState<T> *st = P.st;
+    const int done = st->done;
+    const T rz_prev = st->rz[1 - par];
+    const T rz = prev_sum(part_in, red, pidx, P);
+    if (done) return;
     const bool bad = !(rz > T(0)) || !finite_val(rz);
-    if (blockIdx.x == 0 && tid_lin() == 0) {
-        st->rz[k & 1] = rz;
+    const bool lead = (slot == P.tile0) && tid_lin() == 0;
+    if (lead) {
+        st->rz[par] = rz;
         if (bad) st->done = 4;
     }
     if (bad) return;
-    const T beta = (k == 0) ? T(0) : rz / st->rz[(k - 1) & 1];
-    const Lane ln = lane_of<VX>(op);
+    const T beta = isinf(rz_prev) ? T(0) : rz / rz_prev;
+    const bool has_p = beta != T(0);
+    const T *__restrict__ z = P.z[zfin];
+    const T *__restrict__ pold = P.p[1 - par];
+    T *__restrict__ pnew = P.p[par];
+    T *__restrict__ mu = P.mu;
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     T acc[1] = {T(0)};
     auto XV = [&](int64_t q) -> Vec<T, VX> {
         Vec<T, VX> v = vload<T, VX>(z + q);
-        if (k > 0) {
+        if (has_p) {
             const Vec<T, VX> p = vload<T, VX>(pold + q);
 #pragma unroll
             for (int e = 0; e < VX; ++e) v.a[e] += beta * p.a[e];
         }
         return v;
     };
-    auto XS = [&](int64_t q) -> T { return k > 0 ? z[q] + beta * pold[q] : z[q]; };
+    auto XS = [&](int64_t q) -> T { return has_p ? z[q] + beta * pold[q] : z[q]; };
     column<T, PC, VX>(op, ln, XV, XS,
                       [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap) {
                           vstore<T, VX>(pnew + c, p);
@@ -336,60 +469,88 @@ __global__ __launch_bounds__(512) void k_cg_dir(OpView<T> op, int k, const T *__
 #pragma unroll
                           for (int e = 0; e < VX; ++e) acc[0] += p.a[e] * ap.a[e];
                       });
-    block_partials<T, 1>(acc, 0u, part_out);
+    block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
 // ------------------------------------------------- CG: x += a p, r -= a mu, r^T r
 template <typename T, int VX>
-__global__ __launch_bounds__(512) void k_cg_update(OpView<T> op, int k, T *__restrict__ x,
-                                                   const T *__restrict__ p, T *__restrict__ r,
-                                                   const T *__restrict__ mu, CgState<T> *st,
-                                                   const T *__restrict__ part_in, int np_in,
-                                                   T *__restrict__ part_out) {
-    if (st->done) return;
-    const T pmu = reduce_prev(part_in, np_in);
+__global__ __launch_bounds__(512) void k_update_b(const InnerProb<T> *__restrict__ probs,
+                                                  int nprob, int par,
+                                                  const T *__restrict__ part_in, int red,
+                                                  T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const int pidx = find_prob(probs, nprob, slot);
+    const InnerProb<T> &P = probs[pidx];
+    CgState<T> *st = P.st;
+    const int done = st->done;
+    const T rz = st->rz[par], rz_prev = st->rz[1 - par];
+    const T pmu = prev_sum(part_in, red, pidx, P);
+    if (done) return;
     const bool bad = !(pmu > T(0)) || !finite_val(pmu);
     if (bad) {
-        if (blockIdx.x == 0 && tid_lin() == 0) st->done = 4;
+        if (slot == P.tile0 && tid_lin() == 0) st->done = 4;
         return;
     }
-    const T alpha = st->rz[k & 1] / pmu;
-    const Lane ln = lane_of<VX>(op);
+    const T alpha = rz / pmu;
+    const bool first = isinf(rz_prev);
+    const T *__restrict__ p = P.p[par];
+    const T *__restrict__ mu = P.mu;
+    T *__restrict__ x = P.x;
+    T *__restrict__ r = P.r;
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     T acc[1] = {T(0)};
-    if (ln.act) {
-        const int64_t plane = (int64_t)op.nx * op.ny;
-        int64_t c = ln.i0 + (int64_t)op.nx * ln.j + plane * ln.l0;
-        for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
-            const Vec<T, VX> pv = vload<T, VX>(p + c), mv = vload<T, VX>(mu + c);
-            Vec<T, VX> rv = vload<T, VX>(r + c);
-            Vec<T, VX> xv = (k == 0) ? vzero<T, VX>() : vload<T, VX>(x + c);
+    cells<T, VX>(op, ln, [&](int, int64_t c) {
+        const Vec<T, VX> pv = vload<T, VX>(p + c), mv = vload<T, VX>(mu + c);
+        Vec<T, VX> rv = vload<T, VX>(r + c);
+        Vec<T, VX> xv = first ? vzero<T, VX>() : vload<T, VX>(x + c);
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                xv.a[e] += alpha * pv.a[e];
-                rv.a[e] -= alpha * mv.a[e];
-                acc[0] += rv.a[e] * rv.a[e];
-            }
-            vstore<T, VX>(x + c, xv);
-            vstore<T, VX>(r + c, rv);
+        for (int e = 0; e < VX; ++e) {
+            xv.a[e] += alpha * pv.a[e];
+            rv.a[e] -= alpha * mv.a[e];
+            acc[0] += rv.a[e] * rv.a[e];
         }
-    }
-    block_partials<T, 1>(acc, 0u, part_out);
+        vstore<T, VX>(x + c, xv);
+        vstore<T, VX>(r + c, rv);
+    });
+    block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
+}
+
+// Per-problem fixed-order sum of the previous kernel's partials (one workgroup
+// per problem), for launches with many workgroups per problem: the consumer
+// then reads one value instead of every workgroup summing every partial.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_b(const InnerProb<T> *__restrict__ probs,
+                                                  const T *__restrict__ part_in,
+                                                  T *__restrict__ red_out) {
+    const InnerProb<T> &P = probs[blockIdx.x];
+    const T s = reduce_prev(part_in + P.tile0, P.ntiles);
+    if (tid_lin() == 0) red_out[blockIdx.x] = s;
 }
 
 // ----------------------------------------------------- CG: true residual check
 template <typename T, bool PC, int VX>
-__global__ __launch_bounds__(512) void k_cg_check(OpView<T> op, const T *__restrict__ rhat,
-                                                  const T *__restrict__ x,
-                                                  const T *__restrict__ r, int have_x,
-                                                  T *__restrict__ part_out) {
-    const Lane ln = lane_of<VX>(op);
+__global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                                 T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const InnerProb<T> &P = probs[find_prob(probs, nprob, slot)];
+    const bool have_x = P.st->iter > 0;
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
+    const T *__restrict__ x = P.x;
+    const T *__restrict__ rhat = P.rhat;
+    const T *__restrict__ rlow = P.r;
     T acc[2] = {T(0), T(0)};
-    column<T, PC, VX>(
+    struct Ex {
+        Vec<T, VX> rh, rr;
+    };
+    column_pre<T, PC, VX>(
         op, ln,
         [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
         [&](int64_t q) { return have_x ? x[q] : T(0); },
-        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax) {
-            const Vec<T, VX> rh = vload<T, VX>(rhat + c), rr = vload<T, VX>(r + c);
+        [&](int64_t c) { return Ex{vload<T, VX>(rhat + c), vload<T, VX>(rlow + c)}; },
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const Ex &ex) {
+            const Vec<T, VX> &rh = ex.rh, &rr = ex.rr;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 const T rt = rh.a[e] - ax.a[e];
@@ -398,17 +559,19 @@ __global__ __launch_bounds__(512) void k_cg_check(OpView<T> op, const T *__restr
                 acc[1] += d * d;
             }
         });
-    block_partials<T, 2>(acc, 0u, part_out);
+    block_partials<T, 2>(acc, 0u, part_out, gridDim.x, slot);
 }
 
 // ------------------------------------------------------- FP64 outer residual
 template <bool PC, int VX, typename TD, typename TI>
-__global__ __launch_bounds__(512) void k_residual(
-    OpView<double> op, const double *__restrict__ th_in, double in_off,
-    const TD *__restrict__ delta, const double *__restrict__ P, const double *__restrict__ Tn,
-    double tn_off, double *__restrict__ th_out, double *__restrict__ r64, TI *__restrict__ r_in,
-    TI *__restrict__ rhat, double *__restrict__ part_out) {
-    const Lane ln = lane_of<VX>(op);
+__global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__restrict__ probs,
+                                                    int nprob, double *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const OuterProb<TD, TI> &P = probs[find_prob(probs, nprob, slot)];
+    const Lane ln = lane_at<VX>(P.op, slot - P.tile0, P.ntx, P.ntz);
+    const double *__restrict__ th_in = P.th_in;
+    const TD *__restrict__ delta = P.delta;
+    const double in_off = P.in_off;
     double acc[kResidualValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
     auto XS = [&](int64_t q) -> double {
         double v = th_in ? th_in[q] - in_off : 0.0;
@@ -416,25 +579,28 @@ __global__ __launch_bounds__(512) void k_residual(
         return v;
     };
     auto XV = [&](int64_t q) -> Vec<double, VX> {
-        Vec<double, VX> v;
+        Vec<double, VX> v = th_in ? vload<double, VX>(th_in + q) : vzero<double, VX>();
 #pragma unroll
-        for (int e = 0; e < VX; ++e) v.a[e] = XS(q + e);
+        for (int e = 0; e < VX; ++e) {
+            if (th_in) v.a[e] -= in_off;
+            if (delta) v.a[e] += (double)delta[q + e];
+        }
         return v;
     };
     column<double, PC, VX>(
-        op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
-            const double cap = op.lc[l].cap;
+        P.op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
+            const double cap = P.op.lc[l].cap;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                double b = P[c + e];
-                if (Tn) b += cap * (Tn[c + e] - tn_off);
+                double b = P.P[c + e];
+                if (P.Tn) b += cap * (P.Tn[c + e] - P.tn_off);
                 const double rc = b - ath.a[e];
-                if (th_out) th_out[c + e] = th.a[e];
-                if (r64) r64[c + e] = rc;
-                if (r_in) {
+                if (P.th_out) P.th_out[c + e] = th.a[e];
+                if (P.r64) P.r64[c + e] = rc;
+                if (P.r_in) {
                     const TI v = (TI)rc;
-                    r_in[c + e] = v;
-                    rhat[c + e] = v;
+                    P.r_in[c + e] = v;
+                    P.rhat[c + e] = v;
                 }
                 acc[0] += rc * rc;
                 acc[1] += b * b;
@@ -443,7 +609,7 @@ __global__ __launch_bounds__(512) void k_residual(
                 acc[4] += isfinite(rc) ? 0.0 : 1.0;
             }
         });
-    block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out);
+    block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out, gridDim.x, slot);
 }
 
 __global__ __launch_bounds__(256) void k_add_scalar(int64_t n, const double *__restrict__ x,
@@ -525,7 +691,7 @@ __global__ __launch_bounds__(256) void k_norm2(int64_t n, const float *__restric
     const int64_t stride = (int64_t)gridDim.x * nthreads();
     for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride)
         acc[0] += v[q] * v[q];
-    block_partials<float, 1>(acc, 0u, part_out);
+    block_partials<float, 1>(acc, 0u, part_out, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_scale_rsqrt(int64_t n, const float *__restrict__ v,
@@ -560,7 +726,7 @@ __global__ __launch_bounds__(512) void k_lanczos_av(OpView<float> op, int j,
             }
             vstore<float, VX>(w + c, wc);
         });
-    block_partials<float, 1>(acc, 0u, part_out);
+    block_partials<float, 1>(acc, 0u, part_out, gridDim.x, xcd_slot());
 }
 
 __global__ __launch_bounds__(256) void k_lanczos_orth(int64_t n, int j, float *__restrict__ w,
@@ -577,7 +743,7 @@ __global__ __launch_bounds__(256) void k_lanczos_orth(int64_t n, int j, float *_
         w[q] = wc;
         acc[0] += wc * wc;
     }
-    block_partials<float, 1>(acc, 0u, part_out);
+    block_partials<float, 1>(acc, 0u, part_out, gridDim.x, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_lanczos_div(int64_t n, int j, float *__restrict__ w,
@@ -664,11 +830,6 @@ __global__ __launch_bounds__(256) void k_adjoint_finish(int nz, int np,
     }
 }
 
-template <typename T>
-dim3 block_of(const OpView<T> &op) {
-    return dim3(kWave, (unsigned)op.by, 1);
-}
-
 }  // namespace
 
 // =================================================================== launchers
@@ -677,26 +838,32 @@ dim3 block_of(const OpView<T> &op) {
 #define CUTH_STRIP(...) __VA_ARGS__
 #define CUTH_VX_DISPATCH(T, VXV, CALL)                                          \
     do {                                                                        \
-        if (VXV == 4 && sizeof(T) == 4) { constexpr int VX = 4; CUTH_STRIP CALL; } \
-        else if (VXV == 2) { constexpr int VX = 2; CUTH_STRIP CALL; }           \
+        if constexpr (sizeof(T) == 4) {                                         \
+            if (VXV == 4) { constexpr int VX = 4; CUTH_STRIP CALL; break; }     \
+        }                                                                       \
+        if (VXV == 2) { constexpr int VX = 2; CUTH_STRIP CALL; }                \
         else { constexpr int VX = 1; CUTH_STRIP CALL; }                         \
+    } while (0)
+#define CUTH_PC_VX_DISPATCH(T, PCV, VXV, CALL)                                  \
+    do {                                                                        \
+        if (PCV) { constexpr bool PC = true; CUTH_VX_DISPATCH(T, VXV, CALL); }  \
+        else { constexpr bool PC = false; CUTH_VX_DISPATCH(T, VXV, CALL); }     \
     } while (0)
 
 template <typename T>
 void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    if (op.gx) CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_apply<T, true, VX>), g, b, 0, s, op, x, y)));
-    else CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_apply<T, false, VX>), g, b, 0, s, op, x, y)));
+    const dim3 g(stencil_blocks(op)), b(kWave, op.by);
+    CUTH_PC_VX_DISPATCH(T, op.gx != nullptr, op.vx,
+                        (hipLaunchKernelGGL((k_apply<T, PC, VX>), g, b, 0, s, op, x, y)));
 }
 
 template <typename T, bool PC, int VX>
-static void cheb_modes(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
-                       const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *pin, int npin,
-                       T *pout, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-#define CUTH_CHEB(M, LST, CK)                                                                     \
-    hipLaunchKernelGGL((k_cheb<T, PC, VX, M, LST, CK>), g, b, 0, s, op, k, z, zo, r, c1, c2,       \
-                       inv_th, st, pin, npin, pout)
+static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int mode, bool last,
+                       bool chk, int j, int zin, const T *pin, bool red, T *pout, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+#define CUTH_CHEB(M, LST, CK)                                                                      \
+    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK>), g, b, 0, s, probs, nprob, j, zin, pin, \
+                       (int)red, pout)
     if (mode == 1) {
         if (chk) {
             if (last) CUTH_CHEB(1, true, true); else CUTH_CHEB(1, false, true);
@@ -712,73 +879,61 @@ static void cheb_modes(const OpView<T> &op, int mode, bool last, bool chk, int k
 }
 
 template <typename T>
-void launch_cheb(const OpView<T> &op, int mode, bool last, bool chk, int k, const T *z, T *zo,
-                 const T *r, T c1, T c2, T inv_th, CgState<T> *st, const T *part_in, int np_in,
-                 T *part_out, hipStream_t s) {
-    if (op.gx)
-        CUTH_VX_DISPATCH(T, op.vx, (cheb_modes<T, true, VX>(op, mode, last, chk, k, z, zo, r, c1, c2,
-                                                            inv_th, st, part_in, np_in, part_out, s)));
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int mode,
+                   bool last, bool chk, int j, int zin, const T *part_in, bool red, T *part_out,
+                   hipStream_t s) {
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX>(probs, nprob, nb, by, mode, last, chk, j,
+                                                          zin, part_in, red, part_out, s)));
+}
+
+template <typename T>
+void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, bool chk,
+                    const T *part_in, bool red, T *part_out, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    if (chk)
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_scale_b<T, VX, true>), g, b, 0, s, probs, nprob,
+                                                    part_in, (int)red, part_out)));
     else
-        CUTH_VX_DISPATCH(T, op.vx, (cheb_modes<T, false, VX>(op, mode, last, chk, k, z, zo, r, c1,
-                                                             c2, inv_th, st, part_in, np_in,
-                                                             part_out, s)));
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_scale_b<T, VX, false>), g, b, 0, s, probs, nprob,
+                                                    part_in, (int)red, part_out)));
 }
 
 template <typename T>
-void launch_scale(int64_t n, const T *r, T a, T *z, bool chk, int k, CgState<T> *st,
-                  const T *part_in, int np_in, T *part_out, hipStream_t s) {
-    const dim3 g(red_blocks(n)), b(kWave, 4);
-    if (chk) hipLaunchKernelGGL((k_scale<T, true>), g, b, 0, s, n, r, a, z, k, st, part_in, np_in, part_out);
-    else hipLaunchKernelGGL((k_scale<T, false>), g, b, 0, s, n, r, a, z, k, st, part_in, np_in, part_out);
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int par,
+                  int zfin, const T *part_in, bool red, T *part_out, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_dir_b<T, PC, VX>), g, b, 0, s, probs, nprob,
+                                                       par, zfin, part_in, (int)red, part_out)));
 }
 
 template <typename T>
-void launch_cg_dir(const OpView<T> &op, int k, const T *z, const T *pold, T *pnew, T *mu,
-                   CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    if (op.gx)
-        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_dir<T, true, VX>), g, b, 0, s, op, k, z,
-                                                       pold, pnew, mu, st, part_in, np_in, part_out)));
-    else
-        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_dir<T, false, VX>), g, b, 0, s, op, k, z,
-                                                       pold, pnew, mu, st, part_in, np_in, part_out)));
+void launch_update_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, int par,
+                     const T *part_in, bool red, T *part_out, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_update_b<T, VX>), g, b, 0, s, probs, nprob, par,
+                                                part_in, (int)red, part_out)));
 }
 
 template <typename T>
-void launch_cg_update(const OpView<T> &op, int k, T *x, const T *p, T *r, const T *mu,
-                      CgState<T> *st, const T *part_in, int np_in, T *part_out, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_update<T, VX>), g, b, 0, s, op, k, x, p, r,
-                                                   mu, st, part_in, np_in, part_out)));
+void launch_reduce_b(const InnerProb<T> *probs, int nprob, const T *part_in, T *red_out,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_b<T>), dim3(nprob), dim3(kWave, 4), 0, s, probs, part_in, red_out);
 }
 
 template <typename T>
-void launch_cg_check(const OpView<T> &op, const T *rhat, const T *x, const T *r, bool have_x,
-                     T *part_out, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    const int hx = have_x ? 1 : 0;
-    if (op.gx)
-        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_check<T, true, VX>), g, b, 0, s, op, rhat,
-                                                       x, r, hx, part_out)));
-    else
-        CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_cg_check<T, false, VX>), g, b, 0, s, op,
-                                                       rhat, x, r, hx, part_out)));
+void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+                    T *part_out, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_check_b<T, PC, VX>), g, b, 0, s, probs,
+                                                       nprob, part_out)));
 }
 
 template <typename TD, typename TI>
-void launch_residual(const OpView<double> &op, const double *th_in, double in_off, const TD *delta,
-                     const double *P, const double *Tn, double tn_off, double *th_out, double *r64,
-                     TI *r_in, TI *rhat, double *part_out, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    if (op.gx)
-        CUTH_VX_DISPATCH(double, op.vx, (hipLaunchKernelGGL((k_residual<true, VX, TD, TI>), g, b, 0, s,
-                                                            op, th_in, in_off, delta, P, Tn, tn_off,
-                                                            th_out, r64, r_in, rhat, part_out)));
-    else
-        CUTH_VX_DISPATCH(double, op.vx, (hipLaunchKernelGGL((k_residual<false, VX, TD, TI>), g, b, 0,
-                                                            s, op, th_in, in_off, delta, P, Tn,
-                                                            tn_off, th_out, r64, r_in, rhat,
-                                                            part_out)));
+void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool pc, int vx, int by,
+                       double *part_out, hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    CUTH_PC_VX_DISPATCH(double, pc, vx, (hipLaunchKernelGGL((k_residual_b<PC, VX, TD, TI>), g, b, 0,
+                                                            s, probs, nprob, part_out)));
 }
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s) {
@@ -812,13 +967,10 @@ void launch_scale_rsqrt(int64_t n, const float *v, const float *part_in, int np_
 
 void launch_lanczos_av(const OpView<float> &op, int j, const float *v, const float *vprev,
                        const float *lz, float *w, float *part_out, hipStream_t s) {
-    const dim3 g(stencil_blocks(op)), b = block_of(op);
-    if (op.gx)
-        CUTH_VX_DISPATCH(float, op.vx, (hipLaunchKernelGGL((k_lanczos_av<true, VX>), g, b, 0, s, op, j,
-                                                           v, vprev, lz, w, part_out)));
-    else
-        CUTH_VX_DISPATCH(float, op.vx, (hipLaunchKernelGGL((k_lanczos_av<false, VX>), g, b, 0, s, op, j,
-                                                           v, vprev, lz, w, part_out)));
+    const dim3 g(stencil_blocks(op)), b(kWave, op.by);
+    CUTH_PC_VX_DISPATCH(float, op.gx != nullptr, op.vx,
+                        (hipLaunchKernelGGL((k_lanczos_av<PC, VX>), g, b, 0, s, op, j, v, vprev, lz,
+                                            w, part_out)));
 }
 
 void launch_lanczos_orth(int64_t n, int j, float *w, const float *v, float *lz,
@@ -848,28 +1000,24 @@ void launch_adjoint(const OpView<double> &op, const double *lam, const double *T
 
 #define CUTH_INST(T)                                                                              \
     template void launch_apply<T>(const OpView<T> &, const T *, T *, hipStream_t);                \
-    template void launch_cheb<T>(const OpView<T> &, int, bool, bool, int, const T *, T *,         \
-                                 const T *, T, T, T, CgState<T> *, const T *, int, T *,           \
-                                 hipStream_t);                                                    \
-    template void launch_scale<T>(int64_t, const T *, T, T *, bool, int, CgState<T> *, const T *, \
-                                  int, T *, hipStream_t);                                         \
-    template void launch_cg_dir<T>(const OpView<T> &, int, const T *, const T *, T *, T *,        \
-                                   CgState<T> *, const T *, int, T *, hipStream_t);               \
-    template void launch_cg_update<T>(const OpView<T> &, int, T *, const T *, T *, const T *,     \
-                                      CgState<T> *, const T *, int, T *, hipStream_t);            \
-    template void launch_cg_check<T>(const OpView<T> &, const T *, const T *, const T *, bool,   \
-                                     T *, hipStream_t);
+    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, bool,     \
+                                   bool, int, int, const T *, bool, T *, hipStream_t);            \
+    template void launch_scale_b<T>(const InnerProb<T> *, int, int, int, int, bool, const T *,    \
+                                    bool, T *, hipStream_t);                                      \
+    template void launch_dir_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, int,       \
+                                  const T *, bool, T *, hipStream_t);                             \
+    template void launch_update_b<T>(const InnerProb<T> *, int, int, int, int, int, const T *,    \
+                                     bool, T *, hipStream_t);                                     \
+    template void launch_reduce_b<T>(const InnerProb<T> *, int, const T *, T *, hipStream_t);     \
+    template void launch_check_b<T>(const InnerProb<T> *, int, int, bool, int, int, T *,          \
+                                    hipStream_t);
 CUTH_INST(float)
 CUTH_INST(double)
 #undef CUTH_INST
 
-template void launch_residual<float, float>(const OpView<double> &, const double *, double,
-                                            const float *, const double *, const double *, double,
-                                            double *, double *, float *, float *, double *,
-                                            hipStream_t);
-template void launch_residual<double, double>(const OpView<double> &, const double *, double,
-                                              const double *, const double *, const double *,
-                                              double, double *, double *, double *, double *,
-                                              double *, hipStream_t);
+template void launch_residual_b<float, float>(const OuterProb<float, float> *, int, int, bool, int,
+                                              int, double *, hipStream_t);
+template void launch_residual_b<double, double>(const OuterProb<double, double> *, int, int, bool,
+                                                int, int, double *, hipStream_t);
 
 }  // namespace cuth

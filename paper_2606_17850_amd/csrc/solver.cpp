@@ -3,9 +3,10 @@
 // Section 4.3) and FP64 iterative refinement around an FP32 inner solve.
 //
 // Everything numeric on vectors runs in the kernels of kernels.hip.  The host
-// enqueues launches on the handle's stream, reads back a few scalars or
-// per-workgroup partials once per chunk of CG iterations and decides what to
-// launch next.
+// enqueues launches, reads back scalars and per-workgroup partials once per
+// chunk of CG iterations or refinement cycle, and decides what to launch next.
+// Solves of several systems and right-hand sides advance together: each launch
+// covers every active problem (a single solve is a set of one).
 #include "grid.hpp"
 
 #include <algorithm>
@@ -14,6 +15,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <sstream>
 
 namespace cuth {
 
@@ -30,10 +34,13 @@ namespace cuth {
         if (s_.bad()) return s_;     \
     } while (0)
 
-// Accumulate the durations of the recorded sweep events (stream already synced).
-Status prof_flush(Grid &g) {
+// Accumulate the durations of the recorded sweep events (stream already
+// synced).  Pairs recorded in CG iterations at or after `valid_below` ran after
+// the device-side stop and did no work; they are dropped.
+Status prof_flush(Grid &g, int valid_below) {
     for (size_t i = 0; i + 1 < g.pev_used; i += 2) {
         float ms = 0.f;
+        if (g.pev_tag.size() > i / 2 && g.pev_tag[i / 2] >= valid_below) continue;
         if (hipEventElapsedTime(&ms, g.pev[i], g.pev[i + 1]) == hipSuccess) {
             g.prof_ms += ms;
             g.prof_count += 1;
@@ -44,6 +51,17 @@ Status prof_flush(Grid &g) {
 }
 
 namespace {
+
+constexpr int P_CHEB = 0, P_DIR = 1, P_UPD = 2, P_CHK = 3, P_RES = 4, P_RED = 5, P_SLOTS = 6;
+
+// Above this many workgroups per problem, the sums the CG kernels need are
+// formed once per problem by a reduce launch (the direct way has every
+// workgroup of the consumer read every partial: quadratic in the workgroups).
+// CUTH_REDUCE_ABOVE overrides the threshold (read at every inner solve).
+int reduce_above() {
+    const char *e = std::getenv("CUTH_REDUCE_ABOVE");
+    return e ? std::atoi(e) : 4096;
+}
 
 template <typename P>
 Status dev_alloc(P **p, size_t count) {
@@ -59,13 +77,31 @@ Status dev_alloc(P **p, size_t count) {
 }
 
 template <typename P>
+Status host_alloc(P **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipHostMalloc((void **)p, sizeof(P) * count, hipHostMallocDefault) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return Status::err(CUTH_E_NOMEM, "hipHostMalloc failed");
+    }
+    return Status::ok();
+}
+
+template <typename P>
 void dev_free(P *&p) {
     if (p) (void)hipFree((void *)p);
     p = nullptr;
 }
 
-Status sync(Grid &g) {
-    CUTH_HIP(hipStreamSynchronize(g.stream));
+template <typename P>
+void host_free(P *&p) {
+    if (p) (void)hipHostFree((void *)p);
+    p = nullptr;
+}
+
+Status sync_stream(hipStream_t s) {
+    CUTH_HIP(hipStreamSynchronize(s));
     return Status::ok();
 }
 
@@ -81,6 +117,25 @@ template <typename T>
 void free_work(Work<T> &w) {
     T **ps[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
     for (T **p : ps) dev_free(*p);
+}
+
+// CUTH_LOG=1: one line per refinement cycle on stderr.
+bool log_on() {
+    static const bool on = [] {
+        const char *e = std::getenv("CUTH_LOG");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
+// CUTH_GRAPH=0/1 overrides whether a chunk of CG iterations is captured once
+// into a HIP graph and replayed (default: batches of more than one problem).
+int graph_env() {
+    static const int v = [] {
+        const char *e = std::getenv("CUTH_GRAPH");
+        return e ? (e[0] == '1' ? 1 : 0) : -1;
+    }();
+    return v;
 }
 
 // Coefficients of the Chebyshev sweeps for degree k on [lmin, lmax]: with
@@ -117,7 +172,7 @@ ChebConsts make_cheb(double lmin, double lmax, int k) {
 template <typename T>
 struct Bytes {
     double coef;   // per-cell lateral conductances read by one stencil sweep
-    explicit Bytes(const Grid &g) : coef(g.per_cell ? 2.0 * sizeof(T) : 0.0) {}
+    explicit Bytes(bool per_cell) : coef(per_cell ? 2.0 * sizeof(T) : 0.0) {}
     double cheb(int mode) const { return (mode == 1 ? 2 : mode == 2 ? 3 : 4) * sizeof(T) + coef; }
     double dir() const { return 4.0 * sizeof(T) + coef; }
     double update() const { return 6.0 * sizeof(T); }
@@ -131,179 +186,573 @@ struct Bytes {
     }
 };
 
-// z = q(A) r by k-1 stencil sweeps (k >= 2) or one scaling (k == 1).  chk: the
-// first kernel first tests convergence of CG iteration `it` from the update's
-// partials (part_in, np_in).  The last kernel writes partials of r^T z to
-// part_out (np_out of them).  Returns the buffer holding z.
-template <typename T>
-T *precond_seq(Grid &g, const OpView<T> &op, const ChebConsts &cc, const T *r, T *zA, T *zB,
-               CgState<T> *st, bool chk, int it, const T *part_in, int np_in, T *part_out,
-               int &np_out) {
-    const Bytes<T> by(g);
-    const int k = cc.k;
-    if (k == 1) {
-        launch_scale<T>(g.N, r, (T)cc.inv_th, zA, chk, it, st, part_in, np_in, part_out, g.stream);
-        np_out = red_blocks(g.N);
-        return zA;
-    }
-    launch_cheb<T>(op, 1, k == 2, chk, it, r, zB, r, (T)cc.c1[1], (T)cc.c2[1], (T)cc.inv_th, st,
-                   part_in, np_in, part_out, g.stream);
-    T *cur = zB, *prev = zA;
-    for (int j = 2; j < k; ++j) {
-        const int mode = (j == 2) ? 2 : 0;
-        const bool timed = g.prof && j == 3 && g.pev_used + 2 <= g.pev.size();
-        if (timed) (void)hipEventRecord(g.pev[g.pev_used], g.stream);
-        launch_cheb<T>(op, mode, j == k - 1, false, it, cur, prev, r, (T)cc.c1[j], (T)cc.c2[j],
-                       (T)cc.inv_th, st, part_in, np_in, part_out, g.stream);
-        if (timed) {
-            (void)hipEventRecord(g.pev[g.pev_used + 1], g.stream);
-            g.pev_used += 2;
-            g.prof_bytes = by.cheb(0) * (double)g.N;
-        }
-        std::swap(cur, prev);
-    }
-    np_out = stencil_blocks(op);
-    return cur;
-}
-
-template <typename T>
-CgState<T> *state_of(Grid &g);
-template <>
-CgState<float> *state_of<float>(Grid &g) { return g.st32; }
-template <>
-CgState<double> *state_of<double>(Grid &g) { return g.st64; }
-template <typename T>
-CgState<T> *hstate_of(Grid &g);
-template <>
-CgState<float> *hstate_of<float>(Grid &g) { return g.h_st32; }
-template <>
-CgState<double> *hstate_of<double>(Grid &g) { return g.h_st64; }
-
-template <typename T>
-Status write_state(Grid &g, double rr0, double tol2) {
-    CgState<T> *h = hstate_of<T>(g);
-    std::memset(h, 0, sizeof(CgState<T>));
-    h->rr = (T)rr0;
-    h->rr0 = (T)rr0;
-    h->tol2 = (T)tol2;
-    h->done = rr0 > 0.0 ? 0 : 1;
-    CUTH_HIP(hipMemcpyAsync(state_of<T>(g), h, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
-    return Status::ok();
-}
-
-// Read back the state and nv*np partials of slot s; host sums in a fixed order.
-template <typename T>
-Status read_state_and_partials(Grid &g, int s, int nv, int np, double *sums) {
-    CUTH_HIP(hipMemcpyAsync(hstate_of<T>(g), state_of<T>(g), sizeof(CgState<T>),
-                            hipMemcpyDeviceToHost, g.stream));
-    CUTH_HIP(hipMemcpyAsync(g.h_part, g.slot<T>(s), sizeof(T) * (size_t)nv * np,
-                            hipMemcpyDeviceToHost, g.stream));
-    CUTH_TRY(sync(g));
-    const T *p = reinterpret_cast<const T *>(g.h_part);
-    for (int v = 0; v < nv; ++v) {
-        double a = 0.0;
-        for (int q = 0; q < np; ++q) a += (double)p[(size_t)v * np + q];
-        sums[v] = a;
-    }
-    return Status::ok();
-}
-
-// Inner PCG on A_T x = rhat with x_0 = 0 (r = rhat on entry).  Runs chunks of
-// `period` iterations; after each chunk a true-residual kernel gives the
-// drift (||r_true - r_low|| >= 0.5 ||r_true||) and stagnation
-// (||r_true^k|| > 0.9 ||r_true^{k-1}||) criteria of Section 4.4, evaluated
-// here together with the device's convergence flag.
-template <typename T>
-InnerResult inner_pcg(Grid &g, const OpView<T> &op, Work<T> &w, const ChebConsts &cc, double rr0,
-                      double tol2, int maxit, int period, Status &status) {
-    InnerResult res;
-    status = Status::ok();
-    CgState<T> *st = state_of<T>(g);
-    CgState<T> *hst = hstate_of<T>(g);
-    const Bytes<T> by(g);
-    const double n = (double)g.N;
-    const int nbs = stencil_blocks(op);
-    status = write_state<T>(g, rr0, tol2);
-    if (status.bad()) return res;
-    int np_z = 0, nchecks = 0;
-    T *z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, false, 0, nullptr, 0, g.slot<T>(S_CHEB),
-                          np_z);
-    T *pold = w.pA, *pnew = w.pB;
-    int it = 0, reason = 0;
-    double true_prev = -1.0, sums[2] = {0, 0};
-    while (it < maxit) {
-        const int nb = std::min(period, maxit - it);
-        for (int q = 0; q < nb; ++q) {
-            const int k = it + q;
-            launch_cg_dir<T>(op, k, z, pold, pnew, w.mu, st, g.slot<T>(S_CHEB), np_z,
-                             g.slot<T>(S_DIR), g.stream);
-            launch_cg_update<T>(op, k, w.x, pnew, w.r, w.mu, st, g.slot<T>(S_DIR), nbs,
-                                g.slot<T>(S_UPD), g.stream);
-            z = precond_seq<T>(g, op, cc, w.r, w.zA, w.zB, st, true, k, g.slot<T>(S_UPD), nbs,
-                               g.slot<T>(S_CHEB), np_z);
-            std::swap(pold, pnew);
-        }
-        it += nb;
-        launch_cg_check<T>(op, w.rhat, w.x, w.r, true, g.slot<T>(S_CHK), g.stream);
-        ++nchecks;
-        status = read_state_and_partials<T>(g, S_CHK, 2, nbs, sums);
-        if (status.bad()) return res;
-        if (g.prof) (void)prof_flush(g);
-        const double tn = std::sqrt(sums[0]);
-        if (hst->done) {
-            reason = hst->done;
-            break;
-        }
-        if (!std::isfinite(tn)) {
-            reason = 4;
-            break;
-        }
-        if (std::sqrt(sums[1]) >= 0.5 * tn) {
-            reason = 2;
-            break;
-        }
-        if (true_prev >= 0.0 && tn > 0.9 * true_prev) {
-            reason = 3;
-            break;
-        }
-        true_prev = tn;
-    }
-    if (reason == 0) reason = 5;
-    res.iters = hst->iter;
-    res.reason = reason;
-    res.true_red = rr0 > 0 ? std::sqrt(sums[0] / rr0) : 0.0;
-    // launches after the stopping point exit early and move no data
-    const int iters = res.iters;
-    const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
-    res.bytes = precs_run * by.precond(cc.k) * n + iters * (by.dir() + by.update()) * n +
-                nchecks * by.check() * n;
-    res.stencils = (int64_t)precs_run * (cc.k - 1) + iters + nchecks;
-    if (reason == 4) status = Status::err(CUTH_E_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite value)");
-    return res;
-}
-
-struct OuterRes {
-    double rr = 0, bb = 0, dinf = 0, thinf = 0, bad = 0;
+// One system and right-hand side of a solve, with its progress.
+struct Problem {
+    Grid *g = nullptr;
+    Setup *su = nullptr;
+    ChebConsts cc;
+    const double *P = nullptr, *Tn = nullptr, *init = nullptr;
+    double init_off = 0.0;
+    double *out = nullptr;
+    double out_off = 0.0;
+    Work<float> w32;
+    Work<double> w64;
+    double *thA = nullptr, *thB = nullptr;
+    double tol = 0.0;
+    // progress of the refinement
+    bool finished = false;
+    const double *th_in = nullptr;
+    double in_off = 0.0;
+    bool have_delta = false;
+    double *th_out = nullptr, *th_final = nullptr;
+    double last_red = 1.0, d_prev = 1.0, est = 1.0, prev_relres = INFINITY;
+    // per inner solve
+    bool inner = false;
+    double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, true_rr = 0.0;
+    int stop = 0;
+    // results
+    int cycles = 0, cg_iters = 0, reason = 0;
+    int64_t stencils = 0;
+    double bytes = 0.0, relres = 0.0, err_est = 0.0;
+    Status status;
+    // slots of the current launches
+    int tile0 = 0, ntiles = 0;
 };
 
-template <typename TD, typename TI>
-Status outer_residual(Grid &g, const OpView<double> &op, const double *th_in, double in_off,
-                      const TD *delta, const double *P, const double *Tn, double *th_out,
-                      double *r64, TI *r_in, TI *rhat, OuterRes &o) {
-    launch_residual<TD, TI>(op, th_in, in_off, delta, P, Tn, g.t_amb, th_out, r64, r_in, rhat,
-                            g.slot<double>(S_RES), g.stream);
-    const int nb = stencil_blocks(op);
-    CUTH_HIP(hipMemcpyAsync(g.h_part, g.slot<double>(S_RES), sizeof(double) * kResidualValues * nb,
-                            hipMemcpyDeviceToHost, g.stream));
-    CUTH_TRY(sync(g));
-    const double *p = g.h_part;
-    o = OuterRes();
-    for (int q = 0; q < nb; ++q) {
-        o.rr += p[q];
-        o.bb += p[nb + q];
-        o.dinf = std::max(o.dinf, p[2 * nb + q]);
-        o.thinf = std::max(o.thinf, p[3 * nb + q]);
-        o.bad += p[4 * nb + q];
+template <typename T> struct Sel;
+template <> struct Sel<float> {
+    static InnerProb<float> *d(Engine &E) { return E.in32; }
+    static InnerProb<float> *h(Engine &E) { return E.h_in32; }
+    static CgState<float> *ds(Engine &E) { return E.st32; }
+    static CgState<float> *hs(Engine &E) { return E.h_st32; }
+    static float *dc(Engine &E) { return E.cheb32; }
+    static float *hc(Engine &E) { return E.h_cheb32; }
+    static Work<float> &w(Problem &p) { return p.w32; }
+    static OpView<float> view(const Problem &p, const Shape &sh) {
+        const Grid &g = *p.g;
+        return OpView<float>{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr,
+                             g.per_cell ? g.gy32 : nullptr, p.su->lc32, sh.vx, sh.by, sh.zc};
+    }
+};
+template <> struct Sel<double> {
+    static InnerProb<double> *d(Engine &E) { return E.in64; }
+    static InnerProb<double> *h(Engine &E) { return E.h_in64; }
+    static CgState<double> *ds(Engine &E) { return E.st64; }
+    static CgState<double> *hs(Engine &E) { return E.h_st64; }
+    static double *dc(Engine &E) { return E.cheb64; }
+    static double *hc(Engine &E) { return E.h_cheb64; }
+    static Work<double> &w(Problem &p) { return p.w64; }
+    static OpView<double> view(const Problem &p, const Shape &sh) {
+        const Grid &g = *p.g;
+        return OpView<double>{g.nx, g.ny, g.nz, g.per_cell ? g.gx64 : nullptr,
+                              g.per_cell ? g.gy64 : nullptr, p.su->lc64, sh.vx, sh.by, sh.zc};
+    }
+};
+
+OpView<double> outer_view(const Problem &p, const Shape &sh) {
+    return Sel<double>::view(p, sh);
+}
+
+int prob_tiles(const Grid &g, const Shape &sh) {
+    return tiles_x(g.nx, sh.vx) * tiles_y(g.ny, sh.by) * tiles_z(g.nz, sh.zc);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ engine
+Status engine_alloc(Engine &E, int cap, int kcap, size_t nb_max) {
+    E.cap = cap;
+    E.kcap = kcap;
+    E.slot_doubles = std::max<size_t>(8 * std::max<size_t>(nb_max, 1), (size_t)3 * cap);
+    const size_t nc = (size_t)cap * (1 + 2 * kcap);
+    CUTH_TRY(dev_alloc(&E.in32, cap));
+    CUTH_TRY(dev_alloc(&E.in64, cap));
+    CUTH_TRY(dev_alloc(&E.out32, cap));
+    CUTH_TRY(dev_alloc(&E.out64, cap));
+    CUTH_TRY(dev_alloc(&E.st32, cap));
+    CUTH_TRY(dev_alloc(&E.st64, cap));
+    CUTH_TRY(dev_alloc(&E.cheb32, nc));
+    CUTH_TRY(dev_alloc(&E.cheb64, nc));
+    CUTH_TRY(dev_alloc(&E.part, E.slot_doubles * P_SLOTS));
+    CUTH_TRY(host_alloc(&E.h_in32, cap));
+    CUTH_TRY(host_alloc(&E.h_in64, cap));
+    CUTH_TRY(host_alloc(&E.h_out32, cap));
+    CUTH_TRY(host_alloc(&E.h_out64, cap));
+    CUTH_TRY(host_alloc(&E.h_st32, cap));
+    CUTH_TRY(host_alloc(&E.h_st64, cap));
+    CUTH_TRY(host_alloc(&E.h_cheb32, nc));
+    CUTH_TRY(host_alloc(&E.h_cheb64, nc));
+    CUTH_TRY(host_alloc(&E.h_part, E.slot_doubles));
+    CUTH_HIP(hipStreamCreateWithFlags(&E.own, hipStreamNonBlocking));
+    CUTH_HIP(hipEventCreateWithFlags(&E.ev_in, hipEventDisableTiming));
+    CUTH_HIP(hipEventCreateWithFlags(&E.ev_out, hipEventDisableTiming));
+    return Status::ok();
+}
+
+void engine_free(Engine &E) {
+    if (E.own) (void)hipStreamSynchronize(E.own);
+    dev_free(E.in32);
+    dev_free(E.in64);
+    dev_free(E.out32);
+    dev_free(E.out64);
+    dev_free(E.st32);
+    dev_free(E.st64);
+    dev_free(E.cheb32);
+    dev_free(E.cheb64);
+    dev_free(E.part);
+    host_free(E.h_in32);
+    host_free(E.h_in64);
+    host_free(E.h_out32);
+    host_free(E.h_out64);
+    host_free(E.h_st32);
+    host_free(E.h_st64);
+    host_free(E.h_cheb32);
+    host_free(E.h_cheb64);
+    host_free(E.h_part);
+    if (E.ev_in) (void)hipEventDestroy(E.ev_in);
+    if (E.ev_out) (void)hipEventDestroy(E.ev_out);
+    if (E.own) (void)hipStreamDestroy(E.own);
+    E = Engine();
+}
+
+namespace {
+
+template <typename T>
+T *eslot(Engine &E, int s) {
+    return reinterpret_cast<T *>(E.part + (size_t)s * E.slot_doubles);
+}
+
+// Upload the Chebyshev constants of every problem (slot i of the set).
+template <typename T>
+Status upload_cheb(Engine &E, std::vector<Problem *> &ps, hipStream_t s) {
+    const int stride = 1 + 2 * E.kcap;
+    T *h = Sel<T>::hc(E);
+    for (size_t i = 0; i < ps.size(); ++i) {
+        const ChebConsts &cc = ps[i]->cc;
+        T *c = h + i * stride;
+        std::fill(c, c + stride, T(0));
+        c[0] = (T)cc.inv_th;
+        for (int j = 1; j < cc.k; ++j) {
+            c[1 + j] = (T)cc.c1[j];
+            c[1 + E.kcap + j] = (T)cc.c2[j];
+        }
+    }
+    CUTH_HIP(hipMemcpyAsync(Sel<T>::dc(E), h, sizeof(T) * stride * ps.size(),
+                            hipMemcpyHostToDevice, s));
+    return Status::ok();
+}
+
+// Inner descriptors for the problems with p->inner set; cheb row = slot index in ps.
+template <typename T>
+int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vector<int> &which) {
+    InnerProb<T> *h = Sel<T>::h(E);
+    int tile = 0, n = 0;
+    which.clear();
+    for (size_t i = 0; i < ps.size(); ++i) {
+        Problem &p = *ps[i];
+        if (!p.inner) continue;
+        Work<T> &w = Sel<T>::w(p);
+        // every vector a kernel of this precision touches must exist
+        if (!w.x || !w.r || !w.rhat || !w.mu || !w.pA || !w.pB || !w.zA || !w.zB) return -1;
+        InnerProb<T> d;
+        d.op = Sel<T>::view(p, sh);
+        d.ntx = tiles_x(p.g->nx, sh.vx);
+        d.ntz = tiles_z(p.g->nz, sh.zc);
+        d.tile0 = tile;
+        d.ntiles = prob_tiles(*p.g, sh);
+        d.x = w.x;
+        d.r = w.r;
+        d.rhat = w.rhat;
+        d.mu = w.mu;
+        d.p[0] = w.pA;
+        d.p[1] = w.pB;
+        d.z[0] = w.zA;
+        d.z[1] = w.zB;
+        d.st = Sel<T>::ds(E) + n;
+        d.cheb = Sel<T>::dc(E) + i * (1 + 2 * E.kcap);
+        d.kcap = E.kcap;
+        d.pad = 0;
+        h[n] = d;
+        p.tile0 = tile;
+        p.ntiles = d.ntiles;
+        tile += d.ntiles;
+        which.push_back((int)i);
+        ++n;
+    }
+    // the check kernel writes two partials per workgroup into one slot
+    if ((size_t)tile * 2 > E.slot_doubles) return -1;
+    return tile;
+}
+
+// Per-problem sums written by launch_reduce_b (red mode): r^T z, p^T A p, r^T r.
+template <typename T>
+T *red_rz(Engine &E) { return eslot<T>(E, P_RED); }
+template <typename T>
+T *red_pmu(Engine &E) { return eslot<T>(E, P_RED) + E.cap; }
+template <typename T>
+T *red_rr(Engine &E) { return eslot<T>(E, P_RED) + 2 * E.cap; }
+
+// z = q(A) r for every problem of the launch; returns the buffer index of z.
+// chk: the first kernel also runs the convergence test on the update's r^T r.
+template <typename T>
+int enqueue_precond(Engine &E, int nprob, int nb, bool pc, const Shape &sh, int k, bool chk,
+                    bool red, hipStream_t s, Grid *prof, int tag = -1) {
+    InnerProb<T> *d = Sel<T>::d(E);
+    const T *rr_in = red ? red_rr<T>(E) : eslot<T>(E, P_UPD);
+    if (k == 1) {
+        launch_scale_b<T>(d, nprob, nb, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
+        if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
+        return 0;
+    }
+    launch_cheb_b<T>(d, nprob, nb, pc, sh.vx, sh.by, 1, k == 2, chk, 1, 0, rr_in, red,
+                     eslot<T>(E, P_CHEB), s);
+    for (int j = 2; j < k; ++j) {
+        const int mode = (j == 2) ? 2 : 0;
+        const bool timed = prof && prof->prof && j == 3 && prof->pev_used + 2 <= prof->pev.size();
+        if (timed) (void)hipEventRecord(prof->pev[prof->pev_used], s);
+        launch_cheb_b<T>(d, nprob, nb, pc, sh.vx, sh.by, mode, j == k - 1, false, j, (j - 1) & 1,
+                         rr_in, red, eslot<T>(E, P_CHEB), s);
+        if (timed) {
+            (void)hipEventRecord(prof->pev[prof->pev_used + 1], s);
+            if (prof->pev_tag.size() < prof->pev.size() / 2) prof->pev_tag.resize(prof->pev.size() / 2);
+            prof->pev_tag[prof->pev_used / 2] = tag;
+            prof->pev_used += 2;
+            prof->prof_bytes = Bytes<T>(pc).cheb(0) * (double)prof->N;
+        }
+    }
+    if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
+    return (k - 1) & 1;
+}
+
+template <typename T>
+void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, const Shape &sh, int k, int first_k,
+                        int count, int zfin, bool red, hipStream_t s, Grid *prof) {
+    InnerProb<T> *d = Sel<T>::d(E);
+    for (int q = 0; q < count; ++q) {
+        const int par = (first_k + q) & 1;
+        launch_dir_b<T>(d, nprob, nb, pc, sh.vx, sh.by, par, zfin,
+                        red ? red_rz<T>(E) : eslot<T>(E, P_CHEB), red, eslot<T>(E, P_DIR), s);
+        if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_DIR), red_pmu<T>(E), s);
+        launch_update_b<T>(d, nprob, nb, sh.vx, sh.by, par, red ? red_pmu<T>(E) : eslot<T>(E, P_DIR),
+                           red, eslot<T>(E, P_UPD), s);
+        if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_UPD), red_rr<T>(E), s);
+        enqueue_precond<T>(E, nprob, nb, pc, sh, k, true, red, s, prof, first_k + q);
+    }
+}
+
+// Inner PCG (Algorithm 1 with the Chebyshev preconditioner) on every problem
+// with p->inner set: A x = rhat from x = 0, r = rhat already written by the
+// residual kernel.  Chunks of `period` iterations run back to back for all
+// problems; after each chunk one true-residual launch gives every problem's
+// drift (||r_true - r_low|| >= 0.5 ||r_true||) and stagnation
+// (||r_true^k|| > 0.9 ||r_true^{k-1}||) tests of Section 4.4.
+template <typename T>
+Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k, int maxit,
+                   int period, bool use_graph, hipStream_t s, Grid *prof) {
+    std::vector<int> which;
+    const int nb = build_inner<T>(E, ps, sh, which);
+    if (nb < 0) return Status::err(CUTH_E_DEVICE, "internal: inner solve does not fit the engine");
+    const int nprob = (int)which.size();
+    if (nprob == 0) return Status::ok();
+    const bool pc = ps[which[0]]->g->per_cell;
+    bool red = false;
+    const int above = reduce_above();
+    for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
+    CUTH_HIP(hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * nprob,
+                            hipMemcpyHostToDevice, s));
+    CgState<T> *hs = Sel<T>::hs(E);
+    for (int n = 0; n < nprob; ++n) {
+        Problem &p = *ps[which[n]];
+        CgState<T> &st = hs[n];
+        std::memset(&st, 0, sizeof(st));
+        st.rz[1] = std::numeric_limits<T>::infinity();
+        st.rr = (T)p.rr0;
+        st.rr0 = (T)p.rr0;
+        st.tol2 = (T)p.tol2;
+        st.done = p.rr0 > 0.0 ? 0 : 1;
+        p.true_prev = -1.0;
+        p.stop = 0;
+    }
+    CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>) * nprob, hipMemcpyHostToDevice, s));
+    const int zfin = enqueue_precond<T>(E, nprob, nb, pc, sh, k, false, red, s, prof);
+    const bool graph = use_graph && period % 2 == 0;
+    hipGraphExec_t exec = nullptr;
+    if (graph) {
+        hipGraph_t gr = nullptr;
+        CUTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        enqueue_iterations<T>(E, nprob, nb, pc, sh, k, 0, period, zfin, red, s, nullptr);
+        CUTH_HIP(hipStreamEndCapture(s, &gr));
+        const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ie != hipSuccess) return Status::err(CUTH_E_DEVICE, "hipGraphInstantiate failed");
+    }
+    std::vector<double> sums(2 * (size_t)nprob, 0.0);
+    int it = 0, nchecks = 0;
+    Status result = Status::ok();
+    while (it < maxit) {
+        const int cnt = graph ? period : std::min(period, maxit - it);
+        if (graph) {
+            const hipError_t le = hipGraphLaunch(exec, s);
+            if (le != hipSuccess) {
+                result = Status::err(CUTH_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+                break;
+            }
+        } else {
+            enqueue_iterations<T>(E, nprob, nb, pc, sh, k, it, cnt, zfin, red, s, prof);
+        }
+        it += cnt;
+        launch_check_b<T>(Sel<T>::d(E), nprob, nb, pc, sh.vx, sh.by, eslot<T>(E, P_CHK), s);
+        ++nchecks;
+        CUTH_HIP(hipMemcpyAsync(hs, Sel<T>::ds(E), sizeof(CgState<T>) * nprob, hipMemcpyDeviceToHost, s));
+        CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<T>(E, P_CHK), sizeof(T) * 2 * (size_t)nb,
+                                hipMemcpyDeviceToHost, s));
+        CUTH_TRY(sync_stream(s));
+        if (prof && prof->prof) {
+            // a stop found on the device at CG iteration t (st.iter = t + 1, or
+            // t for a breakdown in the direction kernel) empties the sweeps of
+            // iteration t and later
+            const int dev_stop = hs[0].done == 1 || hs[0].done == 4;
+            (void)prof_flush(*prof, dev_stop ? hs[0].iter - 1 : 1 << 30);
+        }
+        const T *hp = reinterpret_cast<const T *>(E.h_part);
+        bool all_done = true;
+        for (int n = 0; n < nprob; ++n) {
+            Problem &p = *ps[which[n]];
+            if (p.stop) continue;
+            double a = 0.0, b = 0.0;
+            for (int q = p.tile0; q < p.tile0 + p.ntiles; ++q) {
+                a += (double)hp[q];
+                b += (double)hp[nb + q];
+            }
+            p.true_rr = a;
+            const double tn = std::sqrt(a);
+            int why = hs[n].done;
+            if (!why) {
+                if (!std::isfinite(tn)) why = 4;
+                else if (std::sqrt(b) >= 0.5 * tn) why = 2;
+                else if (p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
+                else if (it >= maxit) why = 5;
+                if (why) {
+                    // stop this problem on the device too (its launches exit early)
+                    hs[n].done = why;
+                    CUTH_HIP(hipMemcpyAsync(&Sel<T>::ds(E)[n].done, &hs[n].done, sizeof(int),
+                                            hipMemcpyHostToDevice, s));
+                }
+            }
+            p.true_prev = tn;
+            if (why) p.stop = why;
+            else all_done = false;
+        }
+        if (all_done) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    CUTH_TRY(sync_stream(s));
+    CUTH_TRY(result);
+    // per-problem results and byte accounting (launches after a problem's stop
+    // exit early and move no data)
+    for (int n = 0; n < nprob; ++n) {
+        Problem &p = *ps[which[n]];
+        const Bytes<T> by(p.g->per_cell);
+        const double N = (double)p.g->N;
+        const int iters = hs[n].iter;
+        const int reason = p.stop ? p.stop : 5;
+        const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
+        p.cg_iters += iters;
+        p.reason = reason;
+        p.bytes += precs_run * by.precond(k) * N + iters * (by.dir() + by.update()) * N +
+                   nchecks * by.check() * N;
+        p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
+        p.last_red = p.rr0 > 0 ? std::sqrt(p.true_rr / p.rr0) : 0.0;
+        p.cycles += 1;
+        p.inner = false;
+        if (iters == 0) {
+            p.status = Status::err(CUTH_E_BREAKDOWN, "inner solve made no progress");
+            p.finished = true;
+        } else if (reason == 4) {
+            p.status = Status::err(CUTH_E_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite value)");
+        }
+    }
+    return Status::ok();
+}
+
+// FP64 residual of every unfinished problem; fills relres, rr0 and the
+// correction statistics.
+template <typename TI>
+Status outer_step(Engine &E, std::vector<Problem *> &ps, const Shape &sh64, hipStream_t s,
+                  std::vector<double> &stats5) {
+    OuterProb<TI, TI> *h = nullptr;
+    OuterProb<TI, TI> *d = nullptr;
+    if constexpr (sizeof(TI) == 4) {
+        h = reinterpret_cast<OuterProb<TI, TI> *>(E.h_out32);
+        d = reinterpret_cast<OuterProb<TI, TI> *>(E.out32);
+    } else {
+        h = reinterpret_cast<OuterProb<TI, TI> *>(E.h_out64);
+        d = reinterpret_cast<OuterProb<TI, TI> *>(E.out64);
+    }
+    int tile = 0, n = 0;
+    std::vector<int> which;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        Problem &p = *ps[i];
+        if (p.finished) continue;
+        Work<TI> &w = Sel<TI>::w(p);
+        OuterProb<TI, TI> o;
+        o.op = outer_view(p, sh64);
+        o.ntx = tiles_x(p.g->nx, sh64.vx);
+        o.ntz = tiles_z(p.g->nz, sh64.zc);
+        o.tile0 = tile;
+        o.ntiles = prob_tiles(*p.g, sh64);
+        o.th_in = p.th_in;
+        o.in_off = p.in_off;
+        o.delta = p.have_delta ? w.x : nullptr;
+        o.P = p.P;
+        o.Tn = p.Tn;
+        o.tn_off = p.g->t_amb;
+        o.th_out = p.th_out;
+        o.r64 = nullptr;
+        o.r_in = w.r;
+        o.rhat = w.rhat;
+        h[n] = o;
+        p.tile0 = tile;
+        p.ntiles = o.ntiles;
+        tile += o.ntiles;
+        which.push_back((int)i);
+        ++n;
+    }
+    stats5.assign(ps.size() * kResidualValues, 0.0);
+    if (n == 0) return Status::ok();
+    if ((size_t)tile * kResidualValues > E.slot_doubles)
+        return Status::err(CUTH_E_DEVICE, "internal: residual launch does not fit the engine");
+    const bool pc = ps[which[0]]->g->per_cell;
+    CUTH_HIP(hipMemcpyAsync(d, h, sizeof(OuterProb<TI, TI>) * n, hipMemcpyHostToDevice, s));
+    launch_residual_b<TI, TI>(d, n, tile, pc, sh64.vx, sh64.by, eslot<double>(E, P_RES), s);
+    CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<double>(E, P_RES),
+                            sizeof(double) * kResidualValues * (size_t)tile, hipMemcpyDeviceToHost, s));
+    CUTH_TRY(sync_stream(s));
+    for (int m = 0; m < n; ++m) {
+        Problem &p = *ps[which[m]];
+        double *o = &stats5[(size_t)which[m] * kResidualValues];
+        for (int q = p.tile0; q < p.tile0 + p.ntiles; ++q) {
+            o[0] += E.h_part[q];
+            o[1] += E.h_part[tile + q];
+            o[2] = std::max(o[2], E.h_part[2 * tile + q]);
+            o[3] = std::max(o[3], E.h_part[3 * tile + q]);
+            o[4] += E.h_part[4 * tile + q];
+        }
+        const double N = (double)p.g->N;
+        p.bytes += ((p.th_in ? 8.0 : 0.0) + (p.have_delta ? (double)sizeof(TI) : 0.0) + 8.0 +
+                    (p.Tn ? 8.0 : 0.0) + 8.0 + 2.0 * sizeof(TI) + (p.g->per_cell ? 16.0 : 0.0)) * N;
+        p.stencils += 1;
+        p.th_final = p.th_out;
+    }
+    return Status::ok();
+}
+
+// Refinement decisions after a residual (Section 4.4 readings):
+// mixed precision stops when the estimated remaining rise error is below
+// tol/10; FP64 stops at the relative-residual tolerance.  Sets p->inner for
+// the problems that need another inner solve and their tolerances.
+void decide(Problem &p, const double *o, bool mixed, int max_outer) {
+    const double rr = o[0], bb = o[1], dinf = o[2], thinf = o[3], bad = o[4];
+    p.relres = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    p.inner = false;
+    const int cyc = p.cycles;
+    if (bad > 0) {
+        p.status = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
+        p.finished = true;
+        return;
+    }
+    if (!p.status.bad()) {
+        if (mixed) {
+            if (cyc >= 1) {
+                const double d = thinf > 0 ? dinf / thinf : (dinf > 0 ? INFINITY : 0.0);
+                const double q = d / p.d_prev;
+                p.est = q * d;
+                p.err_est = d;
+                p.d_prev = d;
+                // d is about the error before the last correction; that
+                // correction's inner solve cut the residual by last_red, which
+                // leaves an error of about last_red * d, but never less than the
+                // FP32 rounding floor of the inner solve (about 16 ulps, 1e-6:
+                // an FP32 residual can be exactly zero while the correction is
+                // only FP32-accurate).  Stop when this is a tenth of tol, or when
+                // the correction itself is below tol and cut the residual at
+                // least tenfold.
+                const double red_eff = std::max(p.last_red, 1e-6);
+                if (red_eff * d <= 0.1 * p.tol || (d <= p.tol && p.last_red <= 0.1)) {
+                    p.finished = true;
+                    return;
+                }
+            }
+        } else {
+            if (cyc >= 1 && thinf > 0) p.err_est = dinf / thinf;
+            if (p.relres <= p.tol) {
+                p.finished = true;
+                return;
+            }
+            // a restart that did not halve the true residual has hit the
+            // attainable accuracy of FP64 for this system: report, do not loop
+            if (cyc >= 1 && p.relres > 0.5 * p.prev_relres) {
+                p.status = Status::err(CUTH_E_NOT_CONVERGED,
+                                       "true residual stagnated above tol (attainable accuracy)");
+                p.finished = true;
+                return;
+            }
+            p.prev_relres = p.relres;
+        }
+    }
+    if (rr == 0.0 || p.status.bad()) {
+        p.finished = true;
+        return;
+    }
+    if (cyc >= max_outer) {
+        p.status = Status::err(CUTH_E_NOT_CONVERGED, "refinement cycle limit reached");
+        p.finished = true;
+        return;
+    }
+    p.inner = true;
+    if (mixed) {
+        const double tau = cyc == 0 ? 1e-5 : std::min(0.1, std::max(1e-5, 0.1 * p.tol / p.est));
+        p.rr0 = (double)(float)rr;
+        p.tol2 = tau * tau * p.rr0;
+    } else {
+        // hot restart: r and p recomputed from their definitions, x kept
+        p.rr0 = rr;
+        p.tol2 = p.tol * p.tol * bb;
+    }
+}
+
+template <typename TI>
+Status run_refinement(Engine &E, std::vector<Problem *> &ps, const Shape &sh_in,
+                      const Shape &sh64, int k, const cuth_options &o, int period, bool use_graph,
+                      hipStream_t s, Grid *prof) {
+    const bool mixed = sizeof(TI) == 4;
+    std::vector<double> st5;
+    CUTH_TRY(upload_cheb<TI>(E, ps, s));
+    for (;;) {
+        CUTH_TRY(outer_step<TI>(E, ps, sh64, s, st5));
+        bool any = false;
+        for (size_t i = 0; i < ps.size(); ++i) {
+            Problem &p = *ps[i];
+            if (p.finished) continue;
+            decide(p, &st5[i * kResidualValues], mixed, o.max_outer);
+            if (log_on() && p.inner)
+                std::fprintf(stderr, "cuth: problem %zu cycle %d relres %.3e last reduction %.3e est %.3e\n",
+                             i, p.cycles, p.relres, p.last_red, p.est);
+            any = any || p.inner;
+        }
+        if (!any) break;
+        std::vector<Problem *> ran;
+        for (Problem *p : ps)
+            if (p->inner) ran.push_back(p);
+        CUTH_TRY(inner_solve<TI>(E, ps, sh_in, k, o.max_inner, period, use_graph, s, prof));
+        for (Problem *p : ran) {
+            if (p->finished) continue;
+            // the next residual applies this correction to the current theta
+            p->th_in = p->th_out;
+            p->in_off = 0.0;
+            p->have_delta = true;
+            p->th_out = (p->th_out == p->thA) ? p->thB : p->thA;
+        }
     }
     return Status::ok();
 }
@@ -330,15 +779,6 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
         else lo = mid;
     }
     return 0.5 * (lo + hi);
-}
-
-// CUTH_LOG=1: one line per refinement cycle on stderr.
-bool log_on() {
-    static const bool on = [] {
-        const char *e = std::getenv("CUTH_LOG");
-        return e && e[0] == '1';
-    }();
-    return on;
 }
 
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
@@ -406,31 +846,21 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
     // CUTH_SHAPE32 / CUTH_SHAPE64 = "vx,by,zc" override them
     g->sh32 = shape_from_env("CUTH_SHAPE32", Shape{4, 1, 8}, g->nx, 4);
     g->sh64 = shape_from_env("CUTH_SHAPE64", Shape{2, 1, 8}, g->nx, 2);
-    auto nblocks = [&](const Shape &sh) {
-        return (size_t)tiles_x(g->nx, sh.vx) * tiles_y(g->ny, sh.by) * tiles_z(g->nz, sh.zc);
-    };
-    const size_t nb_max = std::max({nblocks(g->sh32), nblocks(g->sh64), (size_t)kRedBlocks});
+    const size_t nb_max = std::max({(size_t)prob_tiles(*g, g->sh32), (size_t)prob_tiles(*g, g->sh64),
+                                    (size_t)kRedBlocks});
     g->slot_doubles = 8 * nb_max;
     const size_t nb_adj = (size_t)((g->nx + kWave - 1) / kWave) * ((g->ny + 3) / 4);
     Status st;
     if ((st = dev_alloc(&g->part, g->slot_doubles * S_COUNT + (size_t)2 * g->nz * nb_adj)).bad())
         return fail(st);
     g->part_adj = g->part + g->slot_doubles * S_COUNT;
-    if ((st = dev_alloc(&g->st32, 1)).bad()) return fail(st);
-    if ((st = dev_alloc(&g->st64, 1)).bad()) return fail(st);
     if ((st = dev_alloc(&g->lz, 1024)).bad()) return fail(st);
     if ((st = dev_alloc(&g->adj_fac, (size_t)3 * g->nz)).bad()) return fail(st);
     if ((st = dev_alloc(&g->thA, (size_t)g->N)).bad()) return fail(st);
     if ((st = dev_alloc(&g->thB, (size_t)g->N)).bad()) return fail(st);
     if ((st = alloc_work(g->w32, g->N)).bad()) return fail(st);
-    if (hipHostMalloc((void **)&g->h_st32, sizeof(CgState<float>), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_st64, sizeof(CgState<double>), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_part, g->slot_doubles * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&g->h_lz, 1024 * sizeof(float), hipHostMallocDefault) != hipSuccess)
-        return fail(Status::err(CUTH_E_NOMEM, "hipHostMalloc failed"));
-    if (hipMemset(g->st32, 0, sizeof(CgState<float>)) != hipSuccess ||
-        hipMemset(g->st64, 0, sizeof(CgState<double>)) != hipSuccess)
-        return fail(Status::err(CUTH_E_DEVICE, "hipMemset failed"));
+    if ((st = host_alloc(&g->h_lz, 1024)).bad()) return fail(st);
+    if ((st = engine_alloc(g->eng, 1, 256, nb_max)).bad()) return fail(st);
     if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess ||
         hipEventCreate(&g->ev2) != hipSuccess)
         return fail(Status::err(CUTH_E_DEVICE, "hipEventCreate failed"));
@@ -501,6 +931,7 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
 void grid_destroy(Grid *g) {
     if (!g) return;
     (void)hipStreamSynchronize(g->stream);
+    engine_free(g->eng);
     for (Setup &su : g->setups) {
         dev_free(su.lc64);
         dev_free(su.lc32);
@@ -514,14 +945,9 @@ void grid_destroy(Grid *g) {
     dev_free(g->thA);
     dev_free(g->thB);
     dev_free(g->part);
-    dev_free(g->st32);
-    dev_free(g->st64);
     dev_free(g->lz);
     dev_free(g->adj_fac);
-    if (g->h_st32) (void)hipHostFree(g->h_st32);
-    if (g->h_st64) (void)hipHostFree(g->h_st64);
-    if (g->h_part) (void)hipHostFree(g->h_part);
-    if (g->h_lz) (void)hipHostFree(g->h_lz);
+    host_free(g->h_lz);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
     if (g->ev2) (void)hipEventDestroy(g->ev2);
@@ -624,7 +1050,7 @@ Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<d
         iw = old;
     }
     CUTH_HIP(hipMemcpyAsync(g.h_lz, g.lz, 512 * sizeof(float), hipMemcpyDeviceToHost, g.stream));
-    CUTH_TRY(sync(g));
+    CUTH_TRY(sync_stream(g.stream));
     alpha.clear();
     beta.clear();
     double amax = 0.0;
@@ -662,184 +1088,335 @@ Status ensure_bounds(Grid &g, Setup &su, int steps) {
     return Status::ok();
 }
 
+namespace {
+
+double default_tol(const cuth_options &o, double dt) {
+    // tol == 0 selects the default of the precision: mixed, relative rise error
+    // 1e-8; FP64, relative residual 1e-10 (steady) or 1e-12 (transient, where
+    // ||b|| is dominated by the C/dt T_n term and the residual bound is looser)
+    if (o.tol > 0.0) return o.tol;
+    return o.precision == CUTH_MIXED ? 1e-8 : (dt > 0.0 ? 1e-12 : 1e-10);
+}
+
+void fill_stats(const Problem &p, cuth_stats *stats, float ms_setup, float ms_solve) {
+    if (!stats) return;
+    stats->outer_cycles = p.cycles;
+    stats->cg_iters = p.cg_iters;
+    stats->stencil_applies = p.stencils;
+    stats->stop_reason = p.reason;
+    stats->rel_residual = p.relres;
+    stats->err_est = p.err_est;
+    stats->setup_ms = ms_setup;
+    stats->solve_ms = ms_solve;
+    stats->alg_bytes = p.bytes;
+    stats->lambda_min = p.su->lmin;
+    stats->lambda_max = p.su->lmax;
+}
+
+// Run the refinement for a set of problems on the engine's own stream (waiting
+// for `user` first, and making `user` wait for the result).
+Status run_set(Engine &E, std::vector<Problem *> &ps, hipStream_t user, const Shape &sh32,
+               const Shape &sh64, const cuth_options &o, int period, bool use_graph, Grid *prof) {
+    const hipStream_t s = E.own;
+    CUTH_HIP(hipEventRecord(E.ev_in, user));
+    CUTH_HIP(hipStreamWaitEvent(s, E.ev_in, 0));
+    Status st;
+    if (o.precision == CUTH_MIXED)
+        st = run_refinement<float>(E, ps, sh32, sh64, o.cheb_degree, o, period, use_graph, s, prof);
+    else
+        st = run_refinement<double>(E, ps, sh64, sh64, o.cheb_degree, o, period, use_graph, s, prof);
+    if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_NOMEM) return st;
+    for (Problem *p : ps)
+        if (p->th_final) {
+            launch_add_scalar(p->g->N, p->th_final, p->out_off, p->out, s);
+            p->bytes += 16.0 * (double)p->g->N;
+        }
+    CUTH_HIP(hipEventRecord(E.ev_out, s));
+    CUTH_HIP(hipStreamWaitEvent(user, E.ev_out, 0));
+    CUTH_TRY(sync_stream(s));
+    return st;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------- solve
 Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const double *init,
                     double init_off, double *out, double out_off, const cuth_options &o,
                     cuth_stats *stats, bool transient_defaults) {
     Status st;
+    if (o.cheb_degree > g.eng.kcap) return Status::err(CUTH_E_INVALID, "cheb_degree above 256");
     CUTH_HIP(hipEventRecord(g.ev0, g.stream));
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
     CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps));
     CUTH_HIP(hipEventRecord(g.ev1, g.stream));
-    const ChebConsts cc = make_cheb(su->lmin, su->lmax, o.cheb_degree);
-    // tol == 0 selects the default of the precision: mixed, relative rise error
-    // 1e-8; FP64, relative residual 1e-10 (steady) or 1e-12 (transient, where
-    // ||b|| is dominated by the C/dt T_n term and the residual bound is looser)
-    const double tol = o.tol > 0.0 ? o.tol
-                                   : (o.precision == CUTH_MIXED ? 1e-8 : (dt > 0.0 ? 1e-12 : 1e-10));
+    if (o.precision != CUTH_MIXED) CUTH_TRY(alloc_work(g.w64, g.N));
+    Problem p;
+    p.g = &g;
+    p.su = su;
+    p.cc = make_cheb(su->lmin, su->lmax, o.cheb_degree);
+    p.P = P;
+    p.Tn = Tn;
+    p.init = init;
+    p.init_off = init_off;
+    p.out = out;
+    p.out_off = out_off;
+    p.w32 = g.w32;
+    p.w64 = g.w64;
+    p.thA = g.thA;
+    p.thB = g.thB;
+    p.tol = default_tol(o, dt);
+    p.th_in = init;
+    p.in_off = init_off;
+    p.th_out = g.thA;
+    std::vector<Problem *> ps{&p};
     const int period = o.check_period > 0 ? o.check_period : (transient_defaults ? 5 : 20);
-    const OpView<double> op64 = view64(g, *su);
-    const double n = (double)g.N;
-    const double coef64 = g.per_cell ? 16.0 : 0.0;
-    int cycles = 0, cg_iters = 0, reason = 0;
-    int64_t stencils = 0;
-    double bytes = 0.0, relres = 0.0, err_est = 0.0;
-    Status result = Status::ok();
-    double *final_theta = nullptr;
-
-    auto resid_bytes = [&](bool th_in, int delta_sz, int inner_sz) {
-        return ((th_in ? 8.0 : 0.0) + delta_sz + 8.0 + (Tn ? 8.0 : 0.0) + 8.0 + 2.0 * inner_sz +
-                coef64) * n;
-    };
-
-    if (o.precision == CUTH_MIXED) {
-        const OpView<float> op32 = view32(g, *su);
-        const double *th_in = init;
-        double in_off = init_off;
-        const float *delta = nullptr;
-        double *th_out = g.thA;
-        double last_red = 1.0, d_prev = 1.0, est = 1.0;
-        for (int cyc = 0;; ++cyc) {
-            OuterRes os;
-            CUTH_TRY((outer_residual<float, float>(g, op64, th_in, in_off, delta, P, Tn, th_out,
-                                                   nullptr, g.w32.r, g.w32.rhat, os)));
-            bytes += resid_bytes(th_in != nullptr, delta ? 4 : 0, 4);
-            ++stencils;
-            final_theta = th_out;
-            relres = os.bb > 0 ? std::sqrt(os.rr / os.bb) : std::sqrt(os.rr);
-            if (os.bad > 0) {
-                result = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
-                break;
-            }
-            if (cyc >= 1) {
-                const double d = os.thinf > 0 ? os.dinf / os.thinf : (os.dinf > 0 ? INFINITY : 0.0);
-                const double q = d / d_prev;
-                est = q * d;
-                err_est = d;
-                d_prev = d;
-                // d is about the error before the last correction; that
-                // correction's inner solve cut the residual by last_red, which
-                // leaves an error of about last_red * d, but never less than the
-                // FP32 rounding floor of the inner solve (about 16 ulps, 1e-6:
-                // an FP32 residual can be exactly zero while the correction is
-                // only FP32-accurate).  Stop when this is a tenth of tol, or
-                // when the correction itself is below tol and cut the residual
-                // at least tenfold.
-                const double red_eff = std::max(last_red, 1e-6);
-                if (red_eff * d <= 0.1 * tol || (d <= tol && last_red <= 0.1)) break;
-            }
-            if (os.rr == 0.0) break;
-            if (cyc >= o.max_outer) {
-                result = Status::err(CUTH_E_NOT_CONVERGED, "refinement cycle limit reached");
-                break;
-            }
-            const double tau = cyc == 0 ? 1e-5 : std::min(0.1, std::max(1e-5, 0.1 * tol / est));
-            const double rr0 = (double)(float)os.rr;
-            Status is;
-            InnerResult ir = inner_pcg<float>(g, op32, g.w32, cc, rr0, tau * tau * rr0,
-                                              o.max_inner, period, is);
-            cg_iters += ir.iters;
-            stencils += ir.stencils;
-            bytes += ir.bytes;
-            reason = ir.reason;
-            ++cycles;
-            if (is.code == CUTH_E_DEVICE) return is;
-            if (ir.iters == 0) {
-                result = is.bad() ? is : Status::err(CUTH_E_BREAKDOWN, "inner solve made no progress");
-                break;
-            }
-            if (log_on())
-                std::fprintf(stderr,
-                             "cuth: cycle %d relres %.3e tau %.1e inner %d its (stop %d) "
-                             "true reduction %.3e est %.3e\n",
-                             cyc, relres, tau, ir.iters, ir.reason, ir.true_red, est);
-            last_red = ir.true_red;
-            delta = g.w32.x;
-            th_in = th_out;
-            in_off = 0.0;
-            th_out = (th_out == g.thA) ? g.thB : g.thA;
-            if (is.bad()) result = is;   // breakdown: keep the partial correction
-        }
-    } else {
-        CUTH_TRY(alloc_work(g.w64, g.N));
-        const double *th_in = init;
-        double in_off = init_off;
-        const double *delta = nullptr;
-        double *th_out = g.thA;
-        double prev_relres = INFINITY;
-        for (int cyc = 0;; ++cyc) {
-            OuterRes os;
-            CUTH_TRY((outer_residual<double, double>(g, op64, th_in, in_off, delta, P, Tn, th_out,
-                                                     nullptr, g.w64.r, g.w64.rhat, os)));
-            bytes += resid_bytes(th_in != nullptr, delta ? 8 : 0, 8);
-            ++stencils;
-            final_theta = th_out;
-            relres = os.bb > 0 ? std::sqrt(os.rr / os.bb) : std::sqrt(os.rr);
-            if (cyc >= 1 && os.thinf > 0) err_est = os.dinf / os.thinf;
-            if (os.bad > 0) {
-                result = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
-                break;
-            }
-            if (relres <= tol || os.rr == 0.0) break;
-            if (cyc >= o.max_outer) {
-                result = Status::err(CUTH_E_NOT_CONVERGED, "restart limit reached");
-                break;
-            }
-            // a restart that did not halve the true residual has hit the
-            // attainable accuracy of FP64 for this system: report, do not loop
-            if (cyc >= 1 && relres > 0.5 * prev_relres) {
-                result = Status::err(CUTH_E_NOT_CONVERGED,
-                                     "true residual stagnated above tol (attainable accuracy)");
-                break;
-            }
-            prev_relres = relres;
-            // hot restart: r and p recomputed from their definitions, x kept
-            Status is;
-            InnerResult ir = inner_pcg<double>(g, op64, g.w64, cc, os.rr, tol * tol * os.bb,
-                                               o.max_inner, period, is);
-            cg_iters += ir.iters;
-            stencils += ir.stencils;
-            bytes += ir.bytes;
-            reason = ir.reason;
-            ++cycles;
-            if (is.code == CUTH_E_DEVICE) return is;
-            if (ir.iters == 0) {
-                result = is.bad() ? is : Status::err(CUTH_E_BREAKDOWN, "inner solve made no progress");
-                break;
-            }
-            delta = g.w64.x;
-            th_in = th_out;
-            in_off = 0.0;
-            th_out = (th_out == g.thA) ? g.thB : g.thA;
-            if (is.bad()) result = is;
-        }
-    }
-    if (final_theta) {
-        launch_add_scalar(g.N, final_theta, out_off, out, g.stream);
-        bytes += 16.0 * n;
-    }
+    const bool use_graph = graph_env() == 1 && !g.prof;
+    Status rs = run_set(g.eng, ps, g.stream, g.sh32, g.sh64, o, period, use_graph, &g);
+    if (rs.code == CUTH_E_DEVICE || rs.code == CUTH_E_NOMEM) return rs;
     CUTH_HIP(hipEventRecord(g.ev2, g.stream));
-    CUTH_TRY(sync(g));
-    if (stats) {
-        float ms_setup = 0, ms_solve = 0;
-        (void)hipEventElapsedTime(&ms_setup, g.ev0, g.ev1);
-        (void)hipEventElapsedTime(&ms_solve, g.ev1, g.ev2);
-        stats->outer_cycles = cycles;
-        stats->cg_iters = cg_iters;
-        stats->stencil_applies = stencils;
-        stats->stop_reason = reason;
-        stats->rel_residual = relres;
-        stats->err_est = err_est;
-        stats->setup_ms = ms_setup;
-        stats->solve_ms = ms_solve;
-        stats->alg_bytes = bytes;
-        stats->lambda_min = su->lmin;
-        stats->lambda_max = su->lmax;
+    CUTH_TRY(sync_stream(g.stream));
+    float ms_setup = 0, ms_solve = 0;
+    (void)hipEventElapsedTime(&ms_setup, g.ev0, g.ev1);
+    (void)hipEventElapsedTime(&ms_solve, g.ev1, g.ev2);
+    fill_stats(p, stats, ms_setup, ms_solve);
+    return p.status;
+}
+
+// --------------------------------------------------------------- batched solve
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, Shape> g_tuned;
+
+// A launch shape the batched kernels accept for every problem: whole 16-byte
+// (or narrower) lanes along each row, at most kMaxBY rows, and no more
+// workgroups than the candidate shapes (vx 1, by 1, zc 4) that size the slots.
+template <typename T>
+bool shape_fits(const std::vector<Problem *> &ps, const Shape &sh) {
+    if (!(sh.vx == 1 || sh.vx == 2 || (sh.vx == 4 && sizeof(T) == 4))) return false;
+    if (sh.by < 1 || sh.by > kMaxBY || sh.zc < 4) return false;
+    for (const Problem *p : ps)
+        if (p->g->nx % sh.vx != 0) return false;
+    return true;
+}
+
+// Pick the FP32 (or FP64) launch shape of a batch by timing the general
+// Chebyshev sweep of every candidate on the batch itself; results are kept per
+// batch signature for the process (and in the file named by CUTH_AUTOTUNE_CACHE).
+template <typename T>
+Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::string &sig,
+                Shape &best) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(sig);
+        if (it != g_tuned.end()) {
+            best = it->second;
+            return Status::ok();
+        }
+    }
+    const char *cache = std::getenv("CUTH_AUTOTUNE_CACHE");
+    if (cache) {
+        if (FILE *f = std::fopen(cache, "r")) {
+            char line[4096];
+            while (std::fgets(line, sizeof line, f)) {
+                std::string s(line);
+                const size_t sp = s.rfind(' ');
+                if (sp == std::string::npos || s.substr(0, sp) != sig) continue;
+                int vx, by, zc;
+                if (std::sscanf(s.c_str() + sp + 1, "%d,%d,%d", &vx, &by, &zc) == 3 &&
+                    shape_fits<T>(ps, Shape{vx, by, zc})) {
+                    best = Shape{vx, by, zc};
+                    std::fclose(f);
+                    std::lock_guard<std::mutex> lk(g_tune_mu);
+                    g_tuned[sig] = best;
+                    return Status::ok();
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    int vmax = (sizeof(T) == 4) ? 4 : 2;
+    for (Problem *p : ps)
+        while (vmax > 1 && p->g->nx % vmax != 0) vmax /= 2;
+    std::vector<Shape> cand;
+    const int vxs[3] = {4, 2, 1};
+    for (int vx : vxs) {
+        if (vx > vmax) continue;
+        for (int by : {1, 2})
+            for (int zc : {4, 8, 16}) cand.push_back(Shape{vx, by, zc});
+        if (cand.size() >= 6) break;
+    }
+    const hipStream_t s = E.own;
+    hipEvent_t e0, e1;
+    CUTH_HIP(hipEventCreate(&e0));
+    CUTH_HIP(hipEventCreate(&e1));
+    for (Problem *p : ps) p->inner = true;
+    float best_ms = INFINITY;
+    for (const Shape &sh : cand) {
+        std::vector<int> which;
+        const int nb = build_inner<T>(E, ps, sh, which);
+        if (nb < 0) return Status::err(CUTH_E_DEVICE, "internal: autotune shape does not fit the engine");
+        const int n = (int)which.size();
+        CUTH_HIP(hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * n,
+                                hipMemcpyHostToDevice, s));
+        CUTH_HIP(hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s));
+        const bool pc = ps[0]->g->per_cell;
+        for (int rep = 0; rep < 2; ++rep)
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, sh.vx, sh.by, 0, false, false, 2, 1,
+                             eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
+        CUTH_HIP(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 6; ++rep)
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, sh.vx, sh.by, 0, false, false, 2, rep & 1,
+                             eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
+        CUTH_HIP(hipEventRecord(e1, s));
+        CUTH_TRY(sync_stream(s));
+        float ms = 0;
+        CUTH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (log_on()) std::fprintf(stderr, "cuth: autotune %d,%d,%d %.3f ms\n", sh.vx, sh.by, sh.zc, ms / 6);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    for (Problem *p : ps) p->inner = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)kcheb;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[sig] = best;
+    if (cache)
+        if (FILE *f = std::fopen(cache, "a")) {
+            std::fprintf(f, "%s %d,%d,%d\n", sig.c_str(), best.vx, best.by, best.zc);
+            std::fclose(f);
+        }
+    return Status::ok();
+}
+
+}  // namespace
+
+Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
+                   double *const *T, const cuth_options &o, cuth_stats *stats) {
+    if (o.cheb_degree > 256) return Status::err(CUTH_E_INVALID, "cheb_degree above 256");
+    const bool mixed = o.precision == CUTH_MIXED;
+    const hipStream_t user = grids[0]->stream;
+    // per-system setup (Lanczos bounds cached in each grid)
+    std::vector<Setup *> sus(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        Status st;
+        sus[s] = get_setup(*grids[s], 0.0, st);
+        if (!sus[s]) return st;
+        CUTH_TRY(ensure_bounds(*grids[s], *sus[s], o.lanczos_steps));
+    }
+    // problems grouped by coefficient storage (one launch family per group)
+    Status result = Status::ok();
+    for (int group = 0; group < 2; ++group) {
+        std::vector<int> sys;
+        for (int s = 0; s < nsys; ++s)
+            if ((int)grids[s]->per_cell == group) sys.push_back(s);
+        if (sys.empty()) continue;
+        const int np = (int)sys.size() * nrhs;
+        std::vector<Problem> probs(np);
+        std::vector<Problem *> ps(np);
+        // pooled work vectors
+        int64_t ntot = 0;
+        for (int s : sys) ntot += grids[s]->N * nrhs;
+        float *pool32 = nullptr;
+        double *pool64 = nullptr, *poolth = nullptr;
+        const int nvec = 8;
+        Status st;
+        if ((st = dev_alloc(&poolth, (size_t)ntot * 2)).bad()) return st;
+        if (mixed) st = dev_alloc(&pool32, (size_t)ntot * nvec);
+        else st = dev_alloc(&pool64, (size_t)ntot * nvec);
+        if (st.bad()) {
+            dev_free(poolth);
+            return st;
+        }
+        int64_t off = 0;
+        int n = 0;
+        size_t nb_max = kRedBlocks;
+        std::ostringstream sig;
+        sig << (mixed ? "f32" : "f64") << (group ? "pc" : "mf");
+        for (int s : sys) {
+            Grid &g = *grids[s];
+            sig << ' ' << g.nx << 'x' << g.ny << 'x' << g.nz;
+            for (int q = 0; q < nrhs; ++q, ++n) {
+                Problem &p = probs[n];
+                p.g = &g;
+                p.su = sus[s];
+                p.cc = make_cheb(sus[s]->lmin, sus[s]->lmax, o.cheb_degree);
+                p.P = P[s] + (int64_t)q * g.N;
+                p.out = T[s] + (int64_t)q * g.N;
+                p.out_off = g.t_amb;
+                p.init = o.use_initial_guess ? p.out : nullptr;
+                p.init_off = g.t_amb;
+                const int64_t N = g.N;
+                auto carve32 = [&](Work<float> &w) {
+                    float *b = pool32 + off * nvec;
+                    float **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
+                    for (int i = 0; i < nvec; ++i) *v[i] = b + (int64_t)i * N;
+                };
+                auto carve64 = [&](Work<double> &w) {
+                    double *b = pool64 + off * nvec;
+                    double **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
+                    for (int i = 0; i < nvec; ++i) *v[i] = b + (int64_t)i * N;
+                };
+                if (mixed) carve32(p.w32);
+                else carve64(p.w64);
+                p.thA = poolth + off * 2;
+                p.thB = p.thA + N;
+                off += N;
+                p.tol = default_tol(o, 0.0);
+                p.th_in = p.init;
+                p.in_off = p.init_off;
+                p.th_out = p.thA;
+                ps[n] = &p;
+            }
+        }
+        sig << " r" << nrhs;
+        // workgroup slots: the largest of the candidate launch shapes
+        for (Problem *p : ps)
+            nb_max += (size_t)tiles_x(p->g->nx, 1) * p->g->ny * tiles_z(p->g->nz, 4);
+        Engine E;
+        // the autotuner's timed sweep reads the constants of sweep j = 2, so the
+        // constant rows hold at least 3 sweeps whatever the degree
+        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 3), nb_max)).bad()) {
+            engine_free(E);
+            dev_free(pool32);
+            dev_free(pool64);
+            dev_free(poolth);
+            return st;
+        }
+        // inner shape: autotuned on the problems' own inner work vectors; the
+        // FP64 residual (once per refinement cycle) uses a fixed shape in mixed
+        // precision, since no FP64 work vectors exist then
+        Shape sh_in, sh64{2, 1, 8};
+        for (Problem *p : ps)
+            while (sh64.vx > 1 && p->g->nx % sh64.vx != 0) sh64.vx /= 2;
+        Status ts = mixed ? autotune<float>(E, ps, o.cheb_degree, sig.str() + " in", sh_in)
+                          : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
+        if (!mixed) sh64 = sh_in;
+        if (!ts.bad()) {
+            const int period = o.check_period > 0 ? o.check_period : 20;
+            const bool use_graph = graph_env() != 0;
+            ts = run_set(E, ps, user, sh_in, sh64, o, period, use_graph, nullptr);
+        }
+        engine_free(E);
+        dev_free(pool32);
+        dev_free(pool64);
+        dev_free(poolth);
+        if (ts.code == CUTH_E_DEVICE || ts.code == CUTH_E_NOMEM || ts.code == CUTH_E_INVALID) return ts;
+        n = 0;
+        for (int s : sys)
+            for (int q = 0; q < nrhs; ++q, ++n) {
+                fill_stats(probs[n], stats ? &stats[(int64_t)s * nrhs + q] : nullptr, 0.f, 0.f);
+                if (probs[n].status.bad() && !result.bad()) result = probs[n].status;
+            }
     }
     return result;
 }
 
+// ------------------------------------------------------------ step-level calls
 Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
     Status st;
     Setup *su = get_setup(g, dt, st);
@@ -847,46 +1424,81 @@ Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
     if (precision == CUTH_MIXED) launch_apply<float>(view32(g, *su), (const float *)x, (float *)y, g.stream);
     else launch_apply<double>(view64(g, *su), (const double *)x, (double *)y, g.stream);
     CUTH_HIP(hipGetLastError());
-    return sync(g);
+    return sync_stream(g.stream);
 }
 
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r) {
     Status st;
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    launch_residual<double, double>(view64(g, *su), T, g.t_amb, (const double *)nullptr, b, nullptr,
-                                    0.0, nullptr, r, nullptr, nullptr, g.slot<double>(S_RES),
-                                    g.stream);
+    Engine &E = g.eng;
+    OuterProb<double, double> o;
+    o.op = view64(g, *su);
+    o.ntx = tiles_x(g.nx, g.sh64.vx);
+    o.ntz = tiles_z(g.nz, g.sh64.zc);
+    o.tile0 = 0;
+    o.ntiles = prob_tiles(g, g.sh64);
+    o.th_in = T;
+    o.in_off = g.t_amb;
+    o.delta = nullptr;
+    o.P = b;
+    o.Tn = nullptr;
+    o.tn_off = 0.0;
+    o.th_out = nullptr;
+    o.r64 = r;
+    o.r_in = nullptr;
+    o.rhat = nullptr;
+    E.h_out64[0] = o;
+    CUTH_HIP(hipMemcpyAsync(E.out64, E.h_out64, sizeof(o), hipMemcpyHostToDevice, g.stream));
+    launch_residual_b<double, double>(E.out64, 1, o.ntiles, g.per_cell, g.sh64.vx, g.sh64.by,
+                                      eslot<double>(E, P_RES), g.stream);
     CUTH_HIP(hipGetLastError());
-    return sync(g);
+    return sync_stream(g.stream);
 }
 
 template <typename T>
-static Status precond_typed(Grid &g, const OpView<T> &op, Work<T> &w, const ChebConsts &cc,
+static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, const ChebConsts &cc,
                             const T *r, T *z) {
-    // the result lands in zA for k == 1 or odd k, in zB for even k >= 2
-    const bool in_b = cc.k >= 2 && ((cc.k - 1) % 2 == 1);
-    T *zA = in_b ? w.zA : z;
-    T *zB = in_b ? z : w.zB;
-    CUTH_TRY(write_state<T>(g, 1.0, 0.0));
-    int np = 0;
-    T *res = precond_seq<T>(g, op, cc, r, zA, zB, state_of<T>(g), false, 0, nullptr, 0,
-                            g.slot<T>(S_CHEB), np);
-    if (res != z) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
+    // the result lands in z[0] for k == 1 or odd k, in z[1] for even k >= 2
+    Engine &E = g.eng;
+    const int zfin = cc.k == 1 ? 0 : (cc.k - 1) & 1;
+    Problem p;
+    p.g = &g;
+    p.su = &su;
+    p.cc = cc;
+    Work<T> &pw = Sel<T>::w(p);
+    pw = w;
+    pw.r = const_cast<T *>(r);
+    if (zfin == 0) pw.zA = z;
+    else pw.zB = z;
+    p.inner = true;
+    std::vector<Problem *> ps{&p};
+    std::vector<int> which;
+    const int nb = build_inner<T>(E, ps, sh, which);
+    if (nb < 0) return Status::err(CUTH_E_DEVICE, "internal: preconditioner does not fit the engine");
+    CUTH_TRY(upload_cheb<T>(E, ps, g.stream));
+    CUTH_HIP(hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>), hipMemcpyHostToDevice,
+                            g.stream));
+    CgState<T> *hs = Sel<T>::hs(E);
+    std::memset(hs, 0, sizeof(CgState<T>));
+    CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
+    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, sh, cc.k, false, false, g.stream, nullptr);
+    if (got != zfin) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
     CUTH_HIP(hipGetLastError());
-    return sync(g);
+    return sync_stream(g.stream);
 }
 
 Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax, int degree,
                      const void *r, void *z) {
     Status st;
+    if (degree > g.eng.kcap) return Status::err(CUTH_E_INVALID, "degree above 256");
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
     const ChebConsts cc = make_cheb(lmin, lmax, degree);
     if (precision == CUTH_MIXED)
-        return precond_typed<float>(g, view32(g, *su), g.w32, cc, (const float *)r, (float *)z);
+        return precond_typed<float>(g, *su, g.w32, g.sh32, cc, (const float *)r, (float *)z);
     CUTH_TRY(alloc_work(g.w64, g.N));
-    return precond_typed<double>(g, view64(g, *su), g.w64, cc, (const double *)r, (double *)z);
+    return precond_typed<double>(g, *su, g.w64, g.sh64, cc, (const double *)r, (double *)z);
 }
 
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,
@@ -898,7 +1510,7 @@ Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, dou
     if (!su) return s2;
     launch_adjoint(view64(g, *su), dL_dP, T, g.t_amb, g.adj_fac, g.part_adj, dL_dk, g.stream);
     CUTH_HIP(hipGetLastError());
-    CUTH_TRY(sync(g));
+    CUTH_TRY(sync_stream(g.stream));
     return st;
 }
 

@@ -206,6 +206,30 @@ def test_batch_matches_oracle_and_single_solves():
         gg.close()
 
 
+@pytest.mark.timeout(400)
+def test_batch_config3_subset():
+    """The first 8 of the 64 uneven stacks of the batch workload (each stack is
+    seeded on its own, so these are exactly the full workload's first 8), 4
+    power maps each, in one batched mixed solve; every result against the exact
+    separable oracle."""
+    import paper_2606_17850_amd as cuth
+    say("batch config3 subset")
+    items = w.config3(nstacks=8, nrhs=4)
+    grids = [grid_of(st) for st, _ in items]
+    P = [t64(np.concatenate([m.ravel() for m in maps])) for _, maps in items]
+    T, stats = cuth.solve_batch(grids, P, nrhs=4, precision="mixed")
+    worst = 0.0
+    for s, (st, maps) in enumerate(items):
+        Ts = T[s].cpu().numpy().reshape(4, st.n)
+        for q in range(4):
+            ref = st.t_amb + direct.solve_separable(st, maps[q].ravel())
+            worst = max(worst, rise_err(Ts[q], ref, st.t_amb))
+    say(f"  worst rise err {worst:.2e}; cg iters {[s['cg_iters'] for s in stats[:8]]}")
+    assert worst <= 1e-8
+    for gg in grids:
+        gg.close()
+
+
 def test_autograd_function_matches_oracle():
     import paper_2606_17850_amd as cuth
     say("autograd")
