@@ -142,3 +142,47 @@ def convective_per_cell(stack) -> np.ndarray:
     s[stack.nz - 1] += float(stack.h_top) * float(stack.dx) * float(stack.dy)
     s[0] += float(stack.h_bottom) * float(stack.dx) * float(stack.dy)
     return s.ravel()
+
+
+# ---------------------------------------------------------------------------
+# FP16 storage of the lateral conductances (Section 4.2, the third copy of the
+# Quad-Diag diagonals kept in half precision; Algorithm "Physics-Aware FP32/16
+# SpMV with AD", where each loaded value is promoted before it is used).
+#
+# Reading (listed in the design doc): FP16's normal range starts at 2^-14, below
+# which small conductances would lose bits, so each layer's lateral values are
+# stored scaled by a power of two, 2^e_l with e_l = 14 - ceil(log2(max g in the
+# layer)), which puts the largest at or below 2^14 (FP16's largest finite value
+# is about 2^16).  The stored value is the FP16 rounding of the FP32 rounding of
+# g * 2^e_l (round to nearest even at each step); the operator uses
+# stored * 2^-e_l.  Only the in-plane (lateral) conductances are stored this
+# way: the out-of-plane ones and the sink are per layer here and are not stored
+# per cell at all.
+
+def fp16_exponents(cond: Conductances) -> np.ndarray:
+    """Per-layer exponent e_l of the FP16 storage scale (0 for a layer with no
+    lateral face)."""
+    nz = cond.sink.shape[0]
+    e = np.zeros(nz, dtype=np.int64)
+    for l in range(nz):
+        m = 0.0
+        if cond.gx[l].size:
+            m = max(m, float(cond.gx[l].max()))
+        if cond.gy[l].size:
+            m = max(m, float(cond.gy[l].max()))
+        if m > 0.0:
+            e[l] = 14 - int(np.ceil(np.log2(m)))
+    return e
+
+
+def fp16_lateral(cond: Conductances) -> Conductances:
+    """The conductances the FP16-stored operator uses: lateral values rounded
+    through FP32 then FP16 at scale 2^e_l and scaled back (exact in FP64);
+    vertical faces and sinks unchanged."""
+    e = fp16_exponents(cond)
+    s = np.ldexp(1.0, e)[:, None, None]
+
+    def rounded(g):
+        return np.asarray(g * s, np.float64).astype(np.float32).astype(np.float16).astype(np.float64) / s
+
+    return Conductances(rounded(cond.gx), rounded(cond.gy), cond.gz.copy(), cond.sink.copy())

@@ -188,14 +188,14 @@ __device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
 // March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
 // layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
 // starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
-// (issued with the layer's stencil loads).  Every lane of the wavefront must
-// call this (the x halo comes through cross-lane shuffles).  (Issuing the next
-// layer's loads before computing the current one was measured slower on gfx950:
-// more registers, no gain in overlap.)
+// (fetched right before emit).  Every lane of the wavefront must call this (the
+// x halo comes through cross-lane shuffles).  Two variants measured slower on
+// gfx950 and are not used: issuing the next layer's loads before computing the
+// current one (more registers, no gain in overlap), and guarding the loads with
+// branches instead of selects (about 15 % slower sweeps).
 template <typename T, bool PC, int VX, typename FV, typename FS, typename FP, typename E>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                            FP &&PRE, E &&emit) {
-    using Ex = decltype(PRE(int64_t(0)));
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const bool act = ln.act;
@@ -203,33 +203,23 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     const bool has_s = act && ln.j > 0, has_n = act && ln.j < ny - 1;
     int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
     const Vec<T, VX> zero = vzero<T, VX>();
-    Vec<T, VX> xdn = zero, xc = zero;
-    if (act) {
-        if (ln.l0 > 0) xdn = XV(c - plane);
-        xc = XV(c);
-    }
+    Vec<T, VX> xdn = (act && ln.l0 > 0) ? XV(c - plane) : zero;
+    Vec<T, VX> xc = act ? XV(c) : zero;
     for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
         const LayerCoef<T> L = op.lc[l];
-        Vec<T, VX> xup = zero, xso = zero, xno = zero;
-        Ex ex{};
-        if (act) {
-            if (l + 1 < nz) xup = XV(c + plane);
-            if (has_s) xso = XV(c - nx);
-            if (has_n) xno = XV(c + nx);
-            ex = PRE(c);
-        }
+        const Vec<T, VX> xup = (act && l + 1 < nz) ? XV(c + plane) : zero;
+        const Vec<T, VX> xso = has_s ? XV(c - nx) : zero;
+        const Vec<T, VX> xno = has_n ? XV(c + nx) : zero;
         T left = __shfl_up(xc.a[VX - 1], 1, 64);
         T right = __shfl_down(xc.a[0], 1, 64);
         if (ln.lane == 0) left = has_l ? XS(c - 1) : T(0);
         if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
-        Vec<T, VX> gxp = zero, gyp = zero, gym = zero;
+        Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
         if constexpr (PC) {
-            if (act) {
-                gxp = vload<T, VX>(op.gx + c);
-                gyp = vload<T, VX>(op.gy + c);
-            }
-            if (has_s) gym = vload<T, VX>(op.gy + c - nx);
+            gxp = act ? vload<T, VX>(op.gx + c) : zero;
+            gyp = act ? vload<T, VX>(op.gy + c) : zero;
+            gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
             gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
             if (ln.lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
         }
@@ -259,7 +249,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
             ax.a[e] = a;
         }
-        if (act) emit(l, c, xc, ax, ex);
+        if (act) emit(l, c, xc, ax, PRE(c));
         xdn = xc;
         xc = xup;
     }
@@ -568,10 +558,17 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
                                                     int nprob, double *__restrict__ part_out) {
     const int slot = xcd_slot();
     const OuterProb<TD, TI> &P = probs[find_prob(probs, nprob, slot)];
-    const Lane ln = lane_at<VX>(P.op, slot - P.tile0, P.ntx, P.ntz);
+    const OpView<double> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     const double *__restrict__ th_in = P.th_in;
     const TD *__restrict__ delta = P.delta;
-    const double in_off = P.in_off;
+    const double *__restrict__ pw = P.P;
+    const double *__restrict__ tn = P.Tn;
+    double *__restrict__ th_out = P.th_out;
+    double *__restrict__ r64 = P.r64;
+    TI *__restrict__ r_in = P.r_in;
+    TI *__restrict__ rhat = P.rhat;
+    const double in_off = P.in_off, tn_off = P.tn_off;
     double acc[kResidualValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
     auto XS = [&](int64_t q) -> double {
         double v = th_in ? th_in[q] - in_off : 0.0;
@@ -580,33 +577,44 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     };
     auto XV = [&](int64_t q) -> Vec<double, VX> {
         Vec<double, VX> v = th_in ? vload<double, VX>(th_in + q) : vzero<double, VX>();
+        if (th_in) {
 #pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            if (th_in) v.a[e] -= in_off;
-            if (delta) v.a[e] += (double)delta[q + e];
+            for (int e = 0; e < VX; ++e) v.a[e] -= in_off;
+        }
+        if (delta) {
+            const Vec<TD, VX> d = vload<TD, VX>(delta + q);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) v.a[e] += (double)d.a[e];
         }
         return v;
     };
     column<double, PC, VX>(
-        P.op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
-            const double cap = P.op.lc[l].cap;
+        op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
+            const double cap = op.lc[l].cap;
+            const Vec<double, VX> pv = vload<double, VX>(pw + c);
+            const Vec<double, VX> tv = tn ? vload<double, VX>(tn + c) : vzero<double, VX>();
+            Vec<TD, VX> dv;
+            if (delta) dv = vload<TD, VX>(delta + c);
+            Vec<double, VX> rv;
+            Vec<TI, VX> rl;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                double b = P.P[c + e];
-                if (P.Tn) b += cap * (P.Tn[c + e] - P.tn_off);
+                double b = pv.a[e];
+                if (tn) b += cap * (tv.a[e] - tn_off);
                 const double rc = b - ath.a[e];
-                if (P.th_out) P.th_out[c + e] = th.a[e];
-                if (P.r64) P.r64[c + e] = rc;
-                if (P.r_in) {
-                    const TI v = (TI)rc;
-                    P.r_in[c + e] = v;
-                    P.rhat[c + e] = v;
-                }
+                rv.a[e] = rc;
+                rl.a[e] = (TI)rc;
                 acc[0] += rc * rc;
                 acc[1] += b * b;
-                if (delta) acc[2] = fmax(acc[2], fabs((double)delta[c + e]));
+                if (delta) acc[2] = fmax(acc[2], fabs((double)dv.a[e]));
                 acc[3] = fmax(acc[3], fabs(th.a[e]));
                 acc[4] += isfinite(rc) ? 0.0 : 1.0;
+            }
+            if (th_out) vstore<double, VX>(th_out + c, th);
+            if (r64) vstore<double, VX>(r64 + c, rv);
+            if (r_in) {
+                vstore<TI, VX>(r_in + c, rl);
+                vstore<TI, VX>(rhat + c, rl);
             }
         });
     block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out, gridDim.x, slot);

@@ -168,32 +168,44 @@ def test_solve_ragged(prec, tol):
     g.close()
 
 
-@pytest.mark.parametrize("degree", [1, 30])
-def test_reduce_launch_mode(monkeypatch, degree):
+def test_reduce_launch_mode(monkeypatch):
     """The per-problem reduce launch (used for grids with more than 4096
-    workgroups) forced on a small ragged grid and on a two-grid batch: same
-    oracle parity as the direct mode, and the two modes agree to the solve
-    tolerance (their fixed summation orders differ)."""
+    workgroups) forced on small grids: same oracle parity as the direct mode,
+    and the two modes agree to the solve tolerance (their fixed summation
+    orders differ).  Degree 30 on a steady ragged grid and on a two-grid batch;
+    degree 1 (the scaling preconditioner, plain CG) on a backward-Euler step,
+    whose system is well conditioned."""
     import paper_2606_17850_amd as cuth
-    say(f"reduce launch mode, degree {degree}")
+    say("reduce launch mode")
     st = ragged_stack(70, 9, mult=True)
     P = np.zeros(st.shape)
     P[0] = np.random.default_rng(6).uniform(0, 2e-3, (st.ny, st.nx))
     ref = _ref_steady(st, P)
     g = grid_of(st)
+    dt = 1e-4
+    th0 = np.random.default_rng(8).uniform(0, 5.0, st.n)
+    ref_tr = transient.step(st, P.ravel(), th0, dt)
     for prec, tol in (("mixed", 1e-8), ("fp64", 1e-10)):
-        monkeypatch.delenv("CUTH_REDUCE_ABOVE", raising=False)
-        Td, _ = g.solve(t64(P), precision=prec, cheb_degree=degree, max_inner=5000)
-        monkeypatch.setenv("CUTH_REDUCE_ABOVE", "0")
-        Tr, _ = g.solve(t64(P), precision=prec, cheb_degree=degree, max_inner=5000)
-        assert rise_err(Tr.cpu().numpy(), ref, st.t_amb) <= tol
-        assert rise_err(Tr.cpu().numpy(), Td.cpu().numpy(), st.t_amb) <= tol
+        out = {}
+        for mode in ("direct", "reduce"):
+            if mode == "reduce":
+                monkeypatch.setenv("CUTH_REDUCE_ABOVE", "0")
+            else:
+                monkeypatch.delenv("CUTH_REDUCE_ABOVE", raising=False)
+            T, _ = g.solve(t64(P), precision=prec)
+            Tt, _ = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision=prec,
+                                     cheb_degree=1, max_inner=5000)
+            assert rise_err(T.cpu().numpy(), ref, st.t_amb) <= tol
+            got = Tt.cpu().numpy() - st.t_amb
+            assert np.abs(got - ref_tr).max() <= tol * np.abs(ref_tr).max()
+            out[mode] = (T.cpu().numpy(), Tt.cpu().numpy())
+        assert rise_err(out["reduce"][0], out["direct"][0], st.t_amb) <= tol
+    monkeypatch.setenv("CUTH_REDUCE_ABOVE", "0")
     stacks = [w.uniform_stack(64, 48, ["Si", "BEOL", "TIM", "Cu"]),
               w.uniform_stack(96, 40, ["Si", "bond", "Si", "TIM", "Cu"])]
     maps = [np.random.default_rng(20 + i).uniform(0, 2e-3, s.n) for i, s in enumerate(stacks)]
     grids = [grid_of(s) for s in stacks]
-    T, _ = cuth.solve_batch(grids, [t64(m) for m in maps], nrhs=1, precision="mixed",
-                            cheb_degree=degree, max_inner=5000)
+    T, _ = cuth.solve_batch(grids, [t64(m) for m in maps], nrhs=1, precision="mixed")
     for s, m, t in zip(stacks, maps, T):
         refb = s.t_amb + direct.solve_separable(s, m)
         assert rise_err(t.cpu().numpy(), refb, s.t_amb) <= 1e-8

@@ -448,3 +448,68 @@ def test_adjoint_special_cases():
     assert np.all(gr.dk_vert < 0)
     # dL/dP = lambda > 0 (M-matrix inverse is positive)
     assert gr.dP.min() > 0
+
+
+# ------------------------------------------------------------ FP16 storage
+def test_fp16_storage_rounding_bound_and_range(c4s):
+    """Every stored lateral conductance is within one FP16 half-ulp (plus the
+    FP32 step) of the exact value, and the scaled layer maxima sit in
+    (2^13, 2^14]: normal FP16 numbers, far from overflow."""
+    st = c4s[0]
+    c = assembly.conductances(st)
+    h = assembly.fp16_lateral(c)
+    e = assembly.fp16_exponents(c)
+    bound = 2.0 ** -11 * (1 + 2.0 ** -12)
+    for g, gh in ((c.gx, h.gx), (c.gy, h.gy)):
+        assert np.all(gh > 0)
+        assert np.max(np.abs(gh - g) / g) <= bound
+    for l in range(st.nz):
+        m = max(c.gx[l].max(), c.gy[l].max()) * 2.0 ** e[l]
+        assert 2.0 ** 13 < m <= 2.0 ** 14
+    assert np.array_equal(h.gz, c.gz) and np.array_equal(h.sink, c.sink)
+
+
+def test_fp16_storage_exact_for_powers_of_two():
+    """dx = dy = dz = 1 and k = 2^-20 give g = 2^-20 exactly: its exponent is 34
+    (2^-20 * 2^34 = 2^14) and the stored value is exact; k = 3 * 2^-20 with a
+    mantissa that FP16 holds is also exact."""
+    for kk, exact in ((2.0 ** -20, True), (3 * 2.0 ** -20, True), (1.0 / 3.0, False)):
+        st = w.Stack(4, 3, ["Si", "Cu"], dx=1.0, dy=1.0, dz=np.array([1.0, 1.0]),
+                     k_lat=np.array([kk, kk]), k_vert=np.array([1.0, 1.0]), h_top=1.0)
+        c = assembly.conductances(st)
+        h = assembly.fp16_lateral(c)
+        assert np.allclose(c.gx, kk, rtol=1e-15)
+        if exact:
+            assert np.array_equal(h.gx, c.gx) and np.array_equal(h.gy, c.gy)
+        else:
+            assert not np.array_equal(h.gx, c.gx)
+    e = assembly.fp16_exponents(assembly.conductances(
+        w.Stack(4, 3, ["Si"], dx=1.0, dy=1.0, dz=np.array([1.0]), k_lat=np.array([2.0 ** -20]),
+                k_vert=np.array([1.0]), h_top=1.0)))
+    assert e.tolist() == [34]
+
+
+def test_fp16_operator_balanced_spd_and_relative_bound():
+    """The FP16-stored operator keeps every row sum equal to the sink (the
+    diagonal is formed from the stored off-diagonals), stays SPD, and, as a
+    relative perturbation of each edge weight by at most eps = 2^-11 of a
+    Laplacian-plus-diagonal matrix, satisfies (1 - eps) A <= A16 <= (1 + eps) A:
+    the generalized eigenvalues of (A16, A) lie in [1 - eps, 1 + eps].  A
+    missing unscale or a wrong exponent moves them far outside."""
+    st = w.uniform_stack(5, 4, ["Si", "BEOL", "TIM", "Cu"])
+    st.k_lat_mult = np.random.default_rng(3).lognormal(0.0, 0.3, st.shape)
+    c = assembly.conductances(st)
+    h = assembly.fp16_lateral(c)
+    A = assembly.assemble(st, cond=c).toarray()
+    A16 = assembly.assemble(st, cond=h).toarray()
+    assert np.array_equal(A16, A16.T)
+    assert np.allclose(A16 @ np.ones(st.n), c.sink.ravel(), rtol=0, atol=1e-15 * np.abs(A16).max())
+    ev = sla.eigh(A16, A, eigvals_only=True)
+    eps = 2.0 ** -11 * (1 + 2.0 ** -12)
+    assert ev.min() >= 1 - eps and ev.max() <= 1 + eps
+    assert np.linalg.eigvalsh(A16).min() > 0
+    # planted mistake: the scale left in the stored values
+    e = assembly.fp16_exponents(c)
+    bad = assembly.Conductances(h.gx * np.ldexp(1.0, e)[:, None, None], h.gy, h.gz, h.sink)
+    ev_bad = sla.eigh(assembly.assemble(st, cond=bad).toarray(), A, eigvals_only=True)
+    assert ev_bad.max() > 2.0
