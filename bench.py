@@ -243,7 +243,9 @@ def main() -> int:
     create_ms = (time.perf_counter() - t0) * 1e3
 
     mixed = cuth.options("mixed")
+    mixed16 = cuth.options("mixed16")
     fp64 = cuth.options("fp64")
+    staged = cuth.options("adaptive")
 
     def step(opts):
         g.reset_bounds()
@@ -272,11 +274,21 @@ def main() -> int:
     g.profile_enable(False)
     T_mixed = T.clone()
 
+    # the same solve with the FP16-stored lateral conductances in the Chebyshev
+    # sweeps (not profiled; reported beside the headline)
+    step(mixed16)
+    ms_m16, st_m16 = timed(mixed16, args.steps)
+    T_m16 = T.clone()
+
     k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
     for _ in range(min(args.warmup, 1)):
         step(fp64)
     ms_fp64, st_fp64 = timed(fp64, k64)
     T_fp64 = T.clone()
+    # the paper's stage-switched scheme, to the same FP64 residual tolerance
+    step(staged)
+    ms_st, st_st = timed(staged, k64)
+    T_st = T.clone()
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -287,6 +299,10 @@ def main() -> int:
 
     rise = float((T_fp64 - stack.t_amb).abs().max())
     diff = float((T_mixed - T_fp64).abs().max()) / rise
+    diff16 = float((T_m16 - T_fp64).abs().max()) / rise
+    per16 = ms_m16 / args.steps
+    diff_st = float((T_st - T_fp64).abs().max()) / rise
+    per_st = ms_st / k64
 
     per_step = ms_mixed / args.steps
     bytes_step = sum(s["alg_bytes"] for s in st_mixed) / args.steps
@@ -316,7 +332,11 @@ def main() -> int:
             "cheb_degree": 30,
         },
         "time_to_tol_ms": {"mixed": round(per_step, 3), "fp64": round(per64, 3),
-                           "speedup_mixed_vs_fp64": round(per64 / per_step, 3)},
+                           "speedup_mixed_vs_fp64": round(per64 / per_step, 3),
+                           "mixed16": round(per16, 3),
+                           "speedup_mixed16_vs_fp64": round(per64 / per16, 3),
+                           "stage_switched_to_fp64_tol": round(per_st, 3),
+                           "speedup_stage_switched_vs_fp64": round(per64 / per_st, 3)},
         "solve_detail": {
             "mixed_cg_iters": st_mixed[-1]["cg_iters"],
             "mixed_outer_cycles": st_mixed[-1]["outer_cycles"],
@@ -326,6 +346,14 @@ def main() -> int:
             "fp64_rel_residual": st_fp64[-1]["rel_residual"],
             "fp64_GBps": round(sum(s["alg_bytes"] for s in st_fp64) / k64 / (per64 / 1e3) / 1e9, 2),
             "mixed_vs_fp64_max_rise_rel_diff": diff,
+            "mixed16_cg_iters": st_m16[-1]["cg_iters"],
+            "mixed16_outer_cycles": st_m16[-1]["outer_cycles"],
+            "mixed16_GBps": round(sum(s["alg_bytes"] for s in st_m16) / args.steps / (per16 / 1e3) / 1e9, 2),
+            "mixed16_vs_fp64_max_rise_rel_diff": diff16,
+            "stage_switched_cg_iters": st_st[-1]["cg_iters"],
+            "stage_switched_cycles": st_st[-1]["outer_cycles"],
+            "stage_switched_rel_residual": st_st[-1]["rel_residual"],
+            "stage_switched_vs_fp64_max_rise_rel_diff": diff_st,
             "grid_create_ms": round(create_ms, 3),
             "unknown_stencils_per_s": round(st_mixed[-1]["stencil_applies"] * stack.n
                                             / (per_step / 1e3), 1),

@@ -57,9 +57,39 @@ typedef enum {
 } cuth_status;
 
 typedef enum {
-    CUTH_FP64 = 0,   /* every step in FP64                                          */
-    CUTH_MIXED = 1   /* FP32 inner PCG + FP64 residual and refinement update         */
+    CUTH_FP64 = 0,    /* every step in FP64                                         */
+    CUTH_MIXED = 1,   /* FP32 inner PCG + FP64 residual and refinement update        */
+    CUTH_MIXED16 = 2, /* as CUTH_MIXED, and the Chebyshev sweeps read the lateral
+                         conductances from FP16 copies (Section 4.2, the
+                         half-precision copy of the in-plane diagonals; Section
+                         4.4, component-wise precision in preconditioning).  Each
+                         layer's values are stored as fp16(fp32(g * 2^e_l)),
+                         e_l = 14 - ceil(log2(max g of the layer)), and promoted
+                         to FP32 and scaled by 2^-e_l before use.  CG products,
+                         checks and Lanczos use the FP32 conductances.  Same as
+                         CUTH_MIXED for grids without k_lat_mult.             */
+    CUTH_ADAPTIVE = 3 /* the paper's stage-switched scheme (Section 4.4): CG
+                         vectors, scalars and inner products in FP64; the
+                         Chebyshev preconditioner in FP32 with the FP16-stored
+                         lateral conductances (as CUTH_MIXED16); the CG product
+                         with FP32-stored conductances promoted to FP64 in the
+                         early stage, FP64 ones in the late stage.  The early
+                         stage ends when ||r_low|| <= sqrt(tol) ||b|| (eq.
+                         switching a, relative), or when the FP64 true residual,
+                         checked every check_period iterations, stagnates (b)
+                         or drifts from r_low (c); the switch recomputes
+                         r = b - A T in FP64 and restarts p (hot restart).
+                         Stops at ||b - A T|| <= tol ||b|| (tol as CUTH_FP64). */
 } cuth_precision;
+
+/* Preconditioner of the inner PCG.  The Chebyshev polynomial is the paper's
+ * (Section 4.3); Jacobi and none are the baselines of its Ablation III
+ * (Section 5), here as single element-wise passes. */
+typedef enum {
+    CUTH_PC_CHEBYSHEV = 0,  /* z = q(A) r, degree cheb_degree, Lanczos bounds     */
+    CUTH_PC_JACOBI = 1,     /* z = r / diag(A), diag = sink + face conductances   */
+    CUTH_PC_NONE = 2        /* z = r (plain CG); no Lanczos setup either         */
+} cuth_preconditioner;
 
 /* Grid descriptor.  Conductances follow the series (harmonic) half-cell rule:
  * a lateral face between cells a and b of layer l has
@@ -84,11 +114,11 @@ typedef struct {
 
 typedef struct {
     int32_t precision;           /* cuth_precision                                     */
-    double tol;                  /* 0 selects the default.  CUTH_MIXED: target
+    double tol;                  /* 0 selects the default.  CUTH_MIXED(16): target
                                     relative error of the rise T - T_amb (inf-norm),
-                                    default 1e-8.  CUTH_FP64: relative residual
-                                    ||b - A T|| / ||b||, default 1e-10 for steady and
-                                    1e-12 for transient solves.                       */
+                                    default 1e-8.  CUTH_FP64, CUTH_ADAPTIVE: relative
+                                    residual ||b - A T|| / ||b||, default 1e-10 for
+                                    steady and 1e-12 for transient solves.            */
     int32_t cheb_degree;         /* Chebyshev degree k, 1..256 (default 30)            */
     int32_t lanczos_steps;       /* Lanczos steps m, 2..256 (default 30)               */
     int32_t max_inner;           /* CG iterations per inner solve (default 2000)       */
@@ -96,6 +126,7 @@ typedef struct {
     int32_t use_initial_guess;   /* 1: T holds the initial guess on entry (cuth_solve) */
     int32_t check_period;        /* iterations between true-residual checks, 0 = the
                                     default (20 steady, 5 transient)                   */
+    int32_t preconditioner;      /* cuth_preconditioner (default CUTH_PC_CHEBYSHEV)    */
 } cuth_options;
 
 typedef struct {
@@ -180,7 +211,9 @@ const char *cuth_last_error(void);
 
 /* y = A x for the steady (dt == 0) or transient (dt > 0) operator.
  * precision CUTH_FP64: x, y device double [N]; CUTH_MIXED: the FP32 operator,
- * x, y device float [N].  Paper Algorithm 2 computes the same product. */
+ * x, y device float [N]; CUTH_MIXED16: the FP32 operator with the FP16-stored
+ * lateral conductances (the one the CUTH_MIXED16 Chebyshev sweeps apply), x, y
+ * device float [N].  Paper Algorithm 2 computes the same product. */
 cuth_status cuth_apply(cuth_grid g, double dt, int32_t precision, const void *x, void *y);
 
 /* r = b - A (T - t_amb) in FP64 (the true residual of Section 4.4).
@@ -189,7 +222,8 @@ cuth_status cuth_residual(cuth_grid g, double dt, const double *b, const double 
 
 /* z = q(A) r: one application of the Chebyshev polynomial preconditioner of
  * degree `degree` on [lmin, lmax] (Section 4.3).  precision selects FP64
- * (double vectors) or FP32 (float vectors, FP32 operator). */
+ * (double vectors), FP32 (CUTH_MIXED: float vectors, FP32 operator) or FP32
+ * with the FP16-stored lateral conductances (CUTH_MIXED16, float vectors). */
 cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, double lmin,
                                double lmax, int32_t degree, const void *r, void *z);
 

@@ -19,10 +19,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import CUTH_FP64, CUTH_MIXED, STATUS_NAMES
+from ._lib import CUTH_FP64, CUTH_MIXED, CUTH_MIXED16, PRECISIONS, STATUS_NAMES
 
 __all__ = ["Grid", "CuthError", "solve_batch", "ThermalSolve", "options", "CUTH_FP64",
-           "CUTH_MIXED", "library"]
+           "CUTH_MIXED", "CUTH_MIXED16", "library"]
 
 
 class CuthError(RuntimeError):
@@ -44,10 +44,13 @@ def _check(status: int, stats: Optional[_lib.Stats] = None):
 
 def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: int = 30,
             lanczos_steps: int = 30, max_inner: int = 2000, max_outer: int = 12,
-            use_initial_guess: bool = False, check_period: int = 0) -> _lib.Options:
+            use_initial_guess: bool = False, check_period: int = 0,
+            preconditioner: str = "chebyshev") -> _lib.Options:
     o = _lib.Options()
     library().cuth_default_options(ctypes.byref(o))
-    o.precision = CUTH_MIXED if precision == "mixed" else CUTH_FP64
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
+    o.precision = PRECISIONS[precision]
     o.tol = 0.0 if tol is None else float(tol)
     o.cheb_degree = cheb_degree
     o.lanczos_steps = lanczos_steps
@@ -55,6 +58,10 @@ def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: 
     o.max_outer = max_outer
     o.use_initial_guess = 1 if use_initial_guess else 0
     o.check_period = check_period
+    if preconditioner not in _lib.PRECONDITIONERS:
+        raise ValueError(f"preconditioner must be one of {sorted(_lib.PRECONDITIONERS)}, "
+                         f"got {preconditioner!r}")
+    o.preconditioner = _lib.PRECONDITIONERS[preconditioner]
     return o
 
 
@@ -187,9 +194,10 @@ class Grid:
         return dP, dk, st.as_dict()
 
     # ------------------------------------------------------ step-level calls
-    def apply(self, x: torch.Tensor, dt: float = 0.0) -> torch.Tensor:
-        """y = A x (float64: FP64 operator, float32: FP32 operator)."""
-        prec = CUTH_FP64 if x.dtype == torch.float64 else CUTH_MIXED
+    def apply(self, x: torch.Tensor, dt: float = 0.0, fp16_coef: bool = False) -> torch.Tensor:
+        """y = A x (float64: FP64 operator, float32: FP32 operator; fp16_coef:
+        the FP32 operator with the FP16-stored lateral conductances)."""
+        prec = CUTH_FP64 if x.dtype == torch.float64 else (CUTH_MIXED16 if fp16_coef else CUTH_MIXED)
         y = self._new(x.dtype)
         with torch.cuda.device(self.device):
             _check(library().cuth_apply(self._h, float(dt), prec, self._vec(x, "x", x.dtype),
@@ -204,8 +212,8 @@ class Grid:
         return r
 
     def precond_apply(self, r: torch.Tensor, lmin: float, lmax: float, degree: int,
-                      dt: float = 0.0) -> torch.Tensor:
-        prec = CUTH_FP64 if r.dtype == torch.float64 else CUTH_MIXED
+                      dt: float = 0.0, fp16_coef: bool = False) -> torch.Tensor:
+        prec = CUTH_FP64 if r.dtype == torch.float64 else (CUTH_MIXED16 if fp16_coef else CUTH_MIXED)
         z = self._new(r.dtype)
         with torch.cuda.device(self.device):
             _check(library().cuth_precond_apply(self._h, float(dt), prec, float(lmin), float(lmax),

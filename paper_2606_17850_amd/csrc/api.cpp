@@ -55,8 +55,10 @@ cuth_status check_desc(const cuth_grid_desc *d) {
 }
 
 cuth_status check_opts(const cuth_options &o) {
-    if (o.precision != CUTH_FP64 && o.precision != CUTH_MIXED)
-        return fail(CUTH_E_INVALID, "precision must be CUTH_FP64 or CUTH_MIXED");
+    if (o.precision < CUTH_FP64 || o.precision > CUTH_ADAPTIVE)
+        return fail(CUTH_E_INVALID, "precision must be a cuth_precision value");
+    if (o.preconditioner < CUTH_PC_CHEBYSHEV || o.preconditioner > CUTH_PC_NONE)
+        return fail(CUTH_E_INVALID, "preconditioner must be a cuth_preconditioner value");
     if (!(o.tol == 0.0 || (finite_pos(o.tol) && o.tol < 1.0)))
         return fail(CUTH_E_INVALID, "tol must be 0 (default) or in (0, 1)");
     if (o.cheb_degree < 1 || o.cheb_degree > 256)
@@ -117,6 +119,7 @@ void cuth_default_options(cuth_options *o) {
     o->max_outer = 12;
     o->use_initial_guess = 0;
     o->check_period = 0;
+    o->preconditioner = CUTH_PC_CHEBYSHEV;
 }
 
 const char *cuth_last_error(void) { return g_last_error.c_str(); }
@@ -218,7 +221,8 @@ cuth_status cuth_apply(cuth_grid h, double dt, int32_t precision, const void *x,
         if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
         cuth::Grid &g = *h->g;
         if (!x || !y) return fail(CUTH_E_INVALID, "x and y are required");
-        if (precision != CUTH_FP64 && precision != CUTH_MIXED) return fail(CUTH_E_INVALID, "bad precision");
+        if (precision != CUTH_FP64 && precision != CUTH_MIXED && precision != CUTH_MIXED16)
+            return fail(CUTH_E_INVALID, "bad precision");
         if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
         if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
         return report(cuth::apply_op(g, dt, precision, x, y));
@@ -243,7 +247,8 @@ cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, double
         cuth::Grid &g = *h->g;
         if (!r || !z) return fail(CUTH_E_INVALID, "r and z are required");
         if (r == z) return fail(CUTH_E_INVALID, "r and z must not alias");
-        if (precision != CUTH_FP64 && precision != CUTH_MIXED) return fail(CUTH_E_INVALID, "bad precision");
+        if (precision != CUTH_FP64 && precision != CUTH_MIXED && precision != CUTH_MIXED16)
+            return fail(CUTH_E_INVALID, "bad precision");
         if (!finite_pos(lmin) || !finite_pos(lmax) || !(lmax > lmin))
             return fail(CUTH_E_INVALID, "need 0 < lmin < lmax");
         if (degree < 1 || degree > 256) return fail(CUTH_E_INVALID, "degree must be in 1..256");

@@ -26,12 +26,16 @@ struct LayerCoef {
     T gzd, gzu;   // vertical conductance to the layer below / above (0 at the boundary)
     T sink;       // h*dx*dy on convective layers + C*dx*dy*dz/dt for transient operators
     T cap;        // C*dx*dy*dz/dt (weight of T_n in the transient right-hand side)
+    T hs;         // 2^-e_l: factor of the layer's FP16-stored lateral conductances
 };
 
 // Operator view handed to kernels.  gx/gy are null for per-layer-uniform grids;
 // otherwise gx[c] couples c and c+1 (0 on the last column), gy[c] couples c and
 // c+nx (0 on the last row).  vx, by, zc: launch shape (cells per lane along
 // x, wavefront rows per workgroup, layers per vertical march); vx divides nx.
+// hx/hy (FP16 bit patterns of gx*2^e_l, gy*2^e_l; Section 4.2, the
+// half-precision copy of the in-plane diagonals) are set only where the
+// Chebyshev sweeps use the FP16-stored conductances.
 template <typename T>
 struct OpView {
     int nx, ny, nz;
@@ -39,6 +43,12 @@ struct OpView {
     const T *gy;
     const LayerCoef<T> *lc;   // device [nz]
     int vx, by, zc;
+    const uint16_t *hx = nullptr;
+    const uint16_t *hy = nullptr;
+    // FP32 copies of gx/gy read by FP64 operators that promote them (the
+    // paper's "FP64/32 SpMV"; set where such launches are made)
+    const float *fx = nullptr;
+    const float *fy = nullptr;
 };
 
 // Number of workgroups of a stencil launch (one 64*vx by `by` tile and one
@@ -85,6 +95,12 @@ struct InnerProb {
     CgState<T> *st;
     const T *cheb;            // 1/theta at [0], c1_j at [1 + j], c2_j at [1 + kcap + j]
     int kcap, pad;
+    // FP64 CG with an FP32 preconditioner (the paper's stage-switched scheme):
+    // the update also writes r_lo = (float) r; k_promote_dot reads the
+    // preconditioner's z_lo; k_reduce_conv mirrors the stop flag to *done_lo.
+    float *r_lo = nullptr;
+    const float *z_lo = nullptr;
+    int *done_lo = nullptr;
 };
 
 // One FP64 outer-residual problem of a batched launch:
@@ -121,21 +137,36 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 // goes to z[1 - zin].  last: partials of r^T z_{j+1}.  chk: the first kernel after
 // a CG update reduces the update's partials (part_in) and stops converged
 // problems (rr <= tol2).
+// h16: read the FP16-stored lateral conductances (FP32, per-cell grids only).
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int by,
                    int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
                    T *part_out, hipStream_t s);
 
-// Degree-1 preconditioner z[0] = r/theta (same chk/last behaviour).
+// Single-pass preconditioner into z[0] (same chk/last behaviour as the sweeps):
+// pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r.
 template <typename T>
-void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, bool chk,
-                    const T *part_in, bool red, T *part_out, hipStream_t s);
+void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int pm, int vx, int by,
+                    bool chk, const T *part_in, bool red, T *part_out, hipStream_t s);
 
 // CG iteration of parity par: rz = sum(part_in); p[par] = z[zfin] + (rz / rz_prev) p[1-par];
 // mu = A p[par]; partials of p^T mu.
 template <typename T>
-void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int par,
-                  int zfin, const T *part_in, bool red, T *part_out, hipStream_t s);
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool f32coef, int vx,
+                  int by, int par, int zfin, const T *part_in, bool red, T *part_out,
+                  hipStream_t s);
+
+// f32coef (FP64 only): the product reads the FP32 copies op.fx/op.fy, promoted
+// (the paper's "FP64/32 SpMV" of the early CG stage).
+// z[0] = (T) z_lo with partials of r^T z (FP64 CG with an FP32 preconditioner).
+template <typename T>
+void launch_promote_dot(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, T *part_out,
+                        hipStream_t s);
+
+// One workgroup per problem: r^T r from the update's partials, convergence
+// test against st->tol2, stop flag mirrored to *done_lo.
+template <typename T>
+void launch_reduce_conv(const InnerProb<T> *probs, int nprob, const T *part_in, hipStream_t s);
 
 // x += alpha p[par] (x = alpha p on the first iteration), r -= alpha mu with
 // alpha = rz / p^T mu; partials of r^T r.
@@ -162,15 +193,23 @@ void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool p
 constexpr int kResidualValues = 5;
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s);
+// y = (float) x
+void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 
 // Face conductances of a grid with a per-cell lateral multiplier.  Writes the
-// FP64 and FP32 planes and the per-layer maximum lateral off-diagonal row sum
-// (as the bit pattern of a positive double) for the Gershgorin bound; counts
-// invalid multiplier entries into *bad.
+// FP64 and FP32 planes, the per-layer maximum lateral off-diagonal row sum (as
+// the bit pattern of a positive double) for the Gershgorin bound and the
+// per-layer maximum single lateral conductance (same encoding) for the FP16
+// scale; counts invalid multiplier entries into *bad.
 void launch_build_lateral(int nx, int ny, int nz, double dx, double dy, const double *dz,
                           const double *k_lat, const double *mult, double *gx64, double *gy64,
                           float *gx32, float *gy32, unsigned long long *maxrow,
-                          unsigned int *bad, hipStream_t s);
+                          unsigned long long *maxg, unsigned int *bad, hipStream_t s);
+
+// FP16 planes: hx[c] = fp16(fp32(gx64[c] * scale[l])) (round to nearest even at
+// each step; scale[l] = 2^e_l), hy likewise, as bit patterns.
+void launch_build_fp16(int nx, int ny, int nz, const double *gx64, const double *gy64,
+                       const double *scale, uint16_t *hx, uint16_t *hy, hipStream_t s);
 
 // Lanczos building blocks (FP32).  lz: device scalars, alpha_j at lz[j],
 // beta_j at lz[256 + j].

@@ -79,7 +79,9 @@ struct Grid {
 
     double *gx64 = nullptr, *gy64 = nullptr;
     float *gx32 = nullptr, *gy32 = nullptr;
+    uint16_t *hx = nullptr, *hy = nullptr;   // FP16 planes (per-cell grids)
     std::vector<double> lat_rowmax;    // per layer, per-cell grids only
+    std::vector<int> e16;              // per-layer FP16 scale exponent e_l
 
     std::vector<Setup> setups;
     Work<float> w32;
@@ -124,7 +126,8 @@ void tridiag_extremes(const std::vector<double> &alpha, const std::vector<double
                       double &lo, double &hi);
 
 OpView<double> view64(const Grid &g, const Setup &su);
-OpView<float> view32(const Grid &g, const Setup &su);
+// h16: with the FP16-stored lateral conductances (CUTH_MIXED16 sweeps)
+OpView<float> view32(const Grid &g, const Setup &su, bool h16 = false);
 
 // Solve (dt == 0: G; dt > 0: C/dt + G) theta = P (+ cap*(Tn - t_amb)).  init:
 // optional initial guess given as T (offset init_off).  The result is written as

@@ -60,6 +60,21 @@ __device__ __forceinline__ Vec<T, VX> vzero() {
     return v;
 }
 
+// VX FP16 values (bit patterns) promoted to T and multiplied by the layer's
+// scale factor hs = 2^-e_l (exact: a power of two).
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> h16load(const uint16_t *p, T hs) {
+    const Vec<uint16_t, VX> b = vload<uint16_t, VX>(p);
+    Vec<T, VX> v;
+#pragma unroll
+    for (int e = 0; e < VX; ++e) v.a[e] = (T)(float)__builtin_bit_cast(_Float16, b.a[e]) * hs;
+    return v;
+}
+
+__device__ __forceinline__ float h16one(uint16_t b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+
 __device__ __forceinline__ int tid_lin() { return threadIdx.x + kWave * threadIdx.y; }
 __device__ __forceinline__ int nthreads() { return kWave * blockDim.y; }
 
@@ -193,7 +208,23 @@ __device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
 // gfx950 and are not used: issuing the next layer's loads before computing the
 // current one (more registers, no gain in overlap), and guarding the loads with
 // branches instead of selects (about 15 % slower sweeps).
-template <typename T, bool PC, int VX, typename FV, typename FS, typename FP, typename E>
+// Where a per-cell operator's lateral conductances come from.
+enum CoefSrc : int {
+    CS_OWN = 0,   // op.gx/op.gy in the operator's precision
+    CS_F16 = 1,   // op.hx/op.hy: FP16 copies at the layer's power-of-two scale
+    CS_F32 = 2    // op.fx/op.fy: FP32 copies, promoted (FP64 operators)
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> f32load(const float *p) {
+    const Vec<float, VX> b = vload<float, VX>(p);
+    Vec<T, VX> v;
+#pragma unroll
+    for (int e = 0; e < VX; ++e) v.a[e] = (T)b.a[e];
+    return v;
+}
+
+template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                            FP &&PRE, E &&emit) {
     const int nx = op.nx, ny = op.ny, nz = op.nz;
@@ -216,7 +247,21 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
         Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
-        if constexpr (PC) {
+        if constexpr (PC && CS == CS_F16) {
+            // FP16-stored lateral conductances, promoted to T before use
+            gxp = act ? h16load<T, VX>(op.hx + c, L.hs) : zero;
+            gyp = act ? h16load<T, VX>(op.hy + c, L.hs) : zero;
+            gym = has_s ? h16load<T, VX>(op.hy + c - nx, L.hs) : zero;
+            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+            if (ln.lane == 0) gxl = has_l ? (T)h16one(op.hx[c - 1]) * L.hs : T(0);
+        } else if constexpr (PC && CS == CS_F32) {
+            // FP32-stored lateral conductances, promoted to T before use
+            gxp = act ? f32load<T, VX>(op.fx + c) : zero;
+            gyp = act ? f32load<T, VX>(op.fy + c) : zero;
+            gym = has_s ? f32load<T, VX>(op.fy + c - nx) : zero;
+            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+            if (ln.lane == 0) gxl = has_l ? (T)op.fx[c - 1] : T(0);
+        } else if constexpr (PC) {
             gxp = act ? vload<T, VX>(op.gx + c) : zero;
             gyp = act ? vload<T, VX>(op.gy + c) : zero;
             gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
@@ -260,7 +305,7 @@ struct NoEx {};
 template <typename T, bool PC, int VX, typename FV, typename FS, typename E>
 __device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                        E &&emit) {
-    column_pre<T, PC, VX>(
+    column_pre<T, PC, VX, CS_OWN>(
         op, ln, XV, XS, [](int64_t) { return NoEx{}; },
         [&](int l, int64_t c, const Vec<T, VX> &x, const Vec<T, VX> &ax, const NoEx &) {
             emit(l, c, x, ax);
@@ -277,13 +322,16 @@ __device__ __forceinline__ void cells(const OpView<T> &op, const Lane &ln, E &&e
 }
 
 // ------------------------------------------------------------------ apply
-template <typename T, bool PC, int VX>
+template <typename T, bool PC, int VX, bool H16>
 __global__ __launch_bounds__(512) void k_apply(OpView<T> op, const T *__restrict__ x,
                                                T *__restrict__ y) {
     const Lane ln = lane_of<VX>(op);
-    column<T, PC, VX>(
+    column_pre<T, PC, VX, H16 ? CS_F16 : CS_OWN>(
         op, ln, [&](int64_t q) { return vload<T, VX>(x + q); }, [&](int64_t q) { return x[q]; },
-        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax) { vstore<T, VX>(y + c, ax); });
+        [](int64_t) { return NoEx{}; },
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const NoEx &) {
+            vstore<T, VX>(y + c, ax);
+        });
 }
 
 // Problem pidx's sum of the previous kernel's partials: summed here by every
@@ -311,7 +359,7 @@ __device__ __forceinline__ bool conv_test(CgState<T> *st, const T *part_in, int 
 }
 
 // ---------------------------------------------------- batched Chebyshev sweep
-template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK>
+template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, bool H16>
 __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                 int j, int zin, const T *__restrict__ part_in,
                                                 int red, T *__restrict__ part_out) {
@@ -359,7 +407,7 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
         else e.zm = vzero<T, VX>();
         return e;
     };
-    column_pre<T, PC, VX>(op, ln, XV, XS, PRE,
+    column_pre<T, PC, VX, H16 ? CS_F16 : CS_OWN>(op, ln, XV, XS, PRE,
                       [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az, const Ex &ex) {
                           const Vec<T, VX> &rc = ex.r;
                           const Vec<T, VX> &zm = ex.zm;
@@ -378,8 +426,14 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
-// Degree-1 preconditioner z[0] = r/theta, partials of r^T z.
-template <typename T, int VX, bool CHK>
+// Single-pass preconditioners, partials of r^T z:
+//   PM_SCALE   z = r / theta (the Chebyshev polynomial of degree 1);
+//   PM_JACOBI  z = r / diag(A), diag = sink + the sum of the cell's face
+//              conductances (the Jacobi-PCG baseline of Section 5, Ablation III);
+//   PM_NONE    z = r (plain CG).
+enum PrecMode : int { PM_SCALE = 0, PM_JACOBI = 1, PM_NONE = 2 };
+
+template <typename T, bool PC, int VX, bool CHK, int PM>
 __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                  const T *__restrict__ part_in, int red,
                                                  T *__restrict__ part_out) {
@@ -400,12 +454,30 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
     const T *__restrict__ r = P.r;
     T *__restrict__ z0 = P.z[0];
     T acc[1] = {T(0)};
-    cells<T, VX>(op, ln, [&](int, int64_t c) {
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    cells<T, VX>(op, ln, [&](int l, int64_t c) {
         const Vec<T, VX> rv = vload<T, VX>(r + c);
         Vec<T, VX> zv;
+        [[maybe_unused]] LayerCoef<T> L;
+        if constexpr (PM == PM_JACOBI) L = op.lc[l];
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
-            zv.a[e] = rv.a[e] * inv_th;
+            if constexpr (PM == PM_SCALE) {
+                zv.a[e] = rv.a[e] * inv_th;
+            } else if constexpr (PM == PM_JACOBI) {
+                const int i = ln.i0 + e;
+                T d = L.sink + (l > 0 ? L.gzd : T(0)) + (l < nz - 1 ? L.gzu : T(0));
+                if constexpr (PC) {
+                    const int64_t q = c + e;
+                    d += op.gx[q] + op.gy[q] + (i > 0 ? op.gx[q - 1] : T(0)) +
+                         (ln.j > 0 ? op.gy[q - nx] : T(0));
+                } else {
+                    d += L.gx * (T)((i > 0) + (i < nx - 1)) + L.gy * (T)((ln.j > 0) + (ln.j < ny - 1));
+                }
+                zv.a[e] = rv.a[e] / d;
+            } else {
+                zv.a[e] = rv.a[e];
+            }
             acc[0] += rv.a[e] * zv.a[e];
         }
         vstore<T, VX>(z0 + c, zv);
@@ -414,7 +486,7 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
 }
 
 // ---------------------------------------------- CG: direction + SpMV + p^T A p
-template <typename T, bool PC, int VX>
+template <typename T, bool PC, int VX, int CS>
 __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                int par, int zfin, const T *__restrict__ part_in,
                                                int red, T *__restrict__ part_out) {
@@ -452,8 +524,8 @@ __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ 
         return v;
     };
     auto XS = [&](int64_t q) -> T { return has_p ? z[q] + beta * pold[q] : z[q]; };
-    column<T, PC, VX>(op, ln, XV, XS,
-                      [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap) {
+    column_pre<T, PC, VX, CS>(op, ln, XV, XS, [](int64_t) { return NoEx{}; },
+                      [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap, const NoEx &) {
                           vstore<T, VX>(pnew + c, p);
                           vstore<T, VX>(mu + c, ap);
 #pragma unroll
@@ -487,6 +559,7 @@ __global__ __launch_bounds__(512) void k_update_b(const InnerProb<T> *__restrict
     const T *__restrict__ mu = P.mu;
     T *__restrict__ x = P.x;
     T *__restrict__ r = P.r;
+    float *__restrict__ r_lo = P.r_lo;
     const OpView<T> op = P.op;
     const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     T acc[1] = {T(0)};
@@ -494,16 +567,69 @@ __global__ __launch_bounds__(512) void k_update_b(const InnerProb<T> *__restrict
         const Vec<T, VX> pv = vload<T, VX>(p + c), mv = vload<T, VX>(mu + c);
         Vec<T, VX> rv = vload<T, VX>(r + c);
         Vec<T, VX> xv = first ? vzero<T, VX>() : vload<T, VX>(x + c);
+        Vec<float, VX> rl;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
             xv.a[e] += alpha * pv.a[e];
             rv.a[e] -= alpha * mv.a[e];
             acc[0] += rv.a[e] * rv.a[e];
+            rl.a[e] = (float)rv.a[e];
         }
         vstore<T, VX>(x + c, xv);
         vstore<T, VX>(r + c, rv);
+        if (r_lo) vstore<float, VX>(r_lo + c, rl);
     });
     block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
+}
+
+// z = (T) z_lo (the FP32 preconditioner's result promoted) into z[0], with
+// partials of r^T z in T (the inner products of the FP64 CG stay FP64).
+template <typename T, int VX>
+__global__ __launch_bounds__(512) void k_promote_dot(const InnerProb<T> *__restrict__ probs,
+                                                     int nprob, T *__restrict__ part_out) {
+    const int slot = xcd_slot();
+    const int pidx = find_prob(probs, nprob, slot);
+    const InnerProb<T> &P = probs[pidx];
+    if (P.st->done) return;
+    const float *__restrict__ zl = P.z_lo;
+    const T *__restrict__ r = P.r;
+    T *__restrict__ z = P.z[0];
+    const OpView<T> op = P.op;
+    const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
+    T acc[1] = {T(0)};
+    cells<T, VX>(op, ln, [&](int, int64_t c) {
+        const Vec<T, VX> zv = f32load<T, VX>(zl + c);
+        const Vec<T, VX> rv = vload<T, VX>(r + c);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) acc[0] += rv.a[e] * zv.a[e];
+        vstore<T, VX>(z + c, zv);
+    });
+    block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
+}
+
+// One workgroup per problem: r^T r from the update's partials, the convergence
+// test (rr <= tol2), and the stop flag mirrored to the FP32 preconditioner's
+// state (*done_lo) so its sweeps exit early too.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_conv(const InnerProb<T> *__restrict__ probs,
+                                                     const T *__restrict__ part_in) {
+    const InnerProb<T> &P = probs[blockIdx.x];
+    CgState<T> *st = P.st;
+    const int done = st->done;
+    const T tol2 = st->tol2;
+    const T rr = reduce_prev(part_in + P.tile0, P.ntiles);
+    if (tid_lin() != 0) return;
+    if (done) {
+        if (P.done_lo) *P.done_lo = done;
+        return;
+    }
+    const bool stop = !(rr > tol2) || !finite_val(rr);
+    st->rr = rr;
+    st->iter = st->iter + 1;
+    if (stop) {
+        st->done = finite_val(rr) ? 1 : 4;
+        if (P.done_lo) *P.done_lo = st->done;
+    }
 }
 
 // Per-problem fixed-order sum of the previous kernel's partials (one workgroup
@@ -534,7 +660,7 @@ __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict_
     struct Ex {
         Vec<T, VX> rh, rr;
     };
-    column_pre<T, PC, VX>(
+    column_pre<T, PC, VX, CS_OWN>(
         op, ln,
         [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
         [&](int64_t q) { return have_x ? x[q] : T(0); },
@@ -620,6 +746,13 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out, gridDim.x, slot);
 }
 
+__global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restrict__ x,
+                                                float *__restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * nthreads();
+    for (int64_t q = (int64_t)blockIdx.x * nthreads() + tid_lin(); q < n; q += stride)
+        y[q] = (float)x[q];
+}
+
 __global__ __launch_bounds__(256) void k_add_scalar(int64_t n, const double *__restrict__ x,
                                                     double a, double *__restrict__ y) {
     const int64_t stride = (int64_t)gridDim.x * nthreads();
@@ -654,23 +787,52 @@ __global__ __launch_bounds__(256) void k_build_lateral(
     }
 }
 
-// Per-layer max over cells of the lateral off-diagonal row sum (after the planes exist).
+// Per-layer max over cells of the lateral off-diagonal row sum and of a single
+// lateral conductance (after the planes exist).  Positive doubles order like
+// their bit patterns, so an integer max of the patterns is the max.
 __global__ __launch_bounds__(256) void k_lateral_rowmax(int nx, int ny, int nz,
                                                         const double *__restrict__ gx,
                                                         const double *__restrict__ gy,
-                                                        unsigned long long *maxrow) {
+                                                        unsigned long long *maxrow,
+                                                        unsigned long long *maxg) {
     const int i = blockIdx.x * kWave + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const bool act = (i < nx && j < ny);
     const int64_t plane = (int64_t)nx * ny;
     for (int l = 0; l < nz; ++l) {
-        double s = 0.0;
+        double s = 0.0, m = 0.0;
         if (act) {
             const int64_t c = i + (int64_t)nx * j + plane * l;
             s = gx[c] + gy[c] + (i > 0 ? gx[c - 1] : 0.0) + (j > 0 ? gy[c - nx] : 0.0);
+            m = fmax(gx[c], gy[c]);
         }
         s = wave_max(s);
-        if (threadIdx.x == 0) atomicMax(&maxrow[l], (unsigned long long)__double_as_longlong(s));
+        m = wave_max(m);
+        if (threadIdx.x == 0) {
+            atomicMax(&maxrow[l], (unsigned long long)__double_as_longlong(s));
+            atomicMax(&maxg[l], (unsigned long long)__double_as_longlong(m));
+        }
+    }
+}
+
+// FP16 copies of the lateral planes at the per-layer power-of-two scale.
+__global__ __launch_bounds__(256) void k_build_fp16(int nx, int ny, int nz,
+                                                    const double *__restrict__ gx,
+                                                    const double *__restrict__ gy,
+                                                    const double *__restrict__ scale,
+                                                    uint16_t *__restrict__ hx,
+                                                    uint16_t *__restrict__ hy) {
+    const int i = blockIdx.x * kWave + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int64_t plane = (int64_t)nx * ny;
+    int64_t c = i + (int64_t)nx * j;
+    for (int l = 0; l < nz; ++l, c += plane) {
+        const double sc = scale[l];
+        const _Float16 a = (_Float16)(float)(gx[c] * sc);
+        const _Float16 b = (_Float16)(float)(gy[c] * sc);
+        hx[c] = __builtin_bit_cast(uint16_t, a);
+        hy[c] = __builtin_bit_cast(uint16_t, b);
     }
 }
 
@@ -861,17 +1023,24 @@ __global__ __launch_bounds__(256) void k_adjoint_finish(int nz, int np,
 template <typename T>
 void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s) {
     const dim3 g(stencil_blocks(op)), b(kWave, op.by);
+    if constexpr (sizeof(T) == 4) {
+        if (op.gx != nullptr && op.hx != nullptr) {
+            CUTH_VX_DISPATCH(T, op.vx, (hipLaunchKernelGGL((k_apply<T, true, VX, true>), g, b, 0, s,
+                                                           op, x, y)));
+            return;
+        }
+    }
     CUTH_PC_VX_DISPATCH(T, op.gx != nullptr, op.vx,
-                        (hipLaunchKernelGGL((k_apply<T, PC, VX>), g, b, 0, s, op, x, y)));
+                        (hipLaunchKernelGGL((k_apply<T, PC, VX, false>), g, b, 0, s, op, x, y)));
 }
 
-template <typename T, bool PC, int VX>
+template <typename T, bool PC, int VX, bool H16>
 static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int mode, bool last,
                        bool chk, int j, int zin, const T *pin, bool red, T *pout, hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
 #define CUTH_CHEB(M, LST, CK)                                                                      \
-    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK>), g, b, 0, s, probs, nprob, j, zin, pin, \
-                       (int)red, pout)
+    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK, H16>), g, b, 0, s, probs, nprob, j, zin, \
+                       pin, (int)red, pout)
     if (mode == 1) {
         if (chk) {
             if (last) CUTH_CHEB(1, true, true); else CUTH_CHEB(1, false, true);
@@ -887,31 +1056,78 @@ static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int
 }
 
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int mode,
-                   bool last, bool chk, int j, int zin, const T *part_in, bool red, T *part_out,
-                   hipStream_t s) {
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX>(probs, nprob, nb, by, mode, last, chk, j,
-                                                          zin, part_in, red, part_out, s)));
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int by,
+                   int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
+                   T *part_out, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (pc && h16) {
+            CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, true, VX, true>(probs, nprob, nb, by, mode, last,
+                                                                   chk, j, zin, part_in, red,
+                                                                   part_out, s)));
+            return;
+        }
+    }
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX, false>(probs, nprob, nb, by, mode, last,
+                                                                 chk, j, zin, part_in, red,
+                                                                 part_out, s)));
 }
 
-template <typename T>
-void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, bool chk,
-                    const T *part_in, bool red, T *part_out, hipStream_t s) {
+template <typename T, bool PC, int VX, int PM>
+static void scale_chk(const InnerProb<T> *probs, int nprob, int nb, int by, bool chk,
+                      const T *part_in, bool red, T *part_out, hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
     if (chk)
-        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_scale_b<T, VX, true>), g, b, 0, s, probs, nprob,
-                                                    part_in, (int)red, part_out)));
+        hipLaunchKernelGGL((k_scale_b<T, PC, VX, true, PM>), g, b, 0, s, probs, nprob, part_in,
+                           (int)red, part_out);
     else
-        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_scale_b<T, VX, false>), g, b, 0, s, probs, nprob,
-                                                    part_in, (int)red, part_out)));
+        hipLaunchKernelGGL((k_scale_b<T, PC, VX, false, PM>), g, b, 0, s, probs, nprob, part_in,
+                           (int)red, part_out);
 }
 
 template <typename T>
-void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by, int par,
-                  int zfin, const T *part_in, bool red, T *part_out, hipStream_t s) {
+void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int pm, int vx, int by,
+                    bool chk, const T *part_in, bool red, T *part_out, hipStream_t s) {
+    if (pm == PM_JACOBI) {
+        CUTH_PC_VX_DISPATCH(T, pc, vx, (scale_chk<T, PC, VX, PM_JACOBI>(probs, nprob, nb, by, chk,
+                                                                        part_in, red, part_out, s)));
+    } else if (pm == PM_NONE) {
+        CUTH_VX_DISPATCH(T, vx, (scale_chk<T, false, VX, PM_NONE>(probs, nprob, nb, by, chk, part_in,
+                                                                  red, part_out, s)));
+    } else {
+        CUTH_VX_DISPATCH(T, vx, (scale_chk<T, false, VX, PM_SCALE>(probs, nprob, nb, by, chk, part_in,
+                                                                   red, part_out, s)));
+    }
+}
+
+template <typename T>
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool f32coef, int vx,
+                  int by, int par, int zfin, const T *part_in, bool red, T *part_out,
+                  hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_dir_b<T, PC, VX>), g, b, 0, s, probs, nprob,
-                                                       par, zfin, part_in, (int)red, part_out)));
+    if constexpr (sizeof(T) == 8) {
+        if (pc && f32coef) {
+            CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_dir_b<T, true, VX, CS_F32>), g, b, 0, s,
+                                                        probs, nprob, par, zfin, part_in, (int)red,
+                                                        part_out)));
+            return;
+        }
+    }
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_dir_b<T, PC, VX, CS_OWN>), g, b, 0, s,
+                                                       probs, nprob, par, zfin, part_in, (int)red,
+                                                       part_out)));
+}
+
+template <typename T>
+void launch_promote_dot(const InnerProb<T> *probs, int nprob, int nb, int vx, int by, T *part_out,
+                        hipStream_t s) {
+    const dim3 g(nb), b(kWave, by);
+    CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_promote_dot<T, VX>), g, b, 0, s, probs, nprob,
+                                                part_out)));
+}
+
+template <typename T>
+void launch_reduce_conv(const InnerProb<T> *probs, int nprob, const T *part_in, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_conv<T>), dim3(nprob), dim3(kWave, 4), 0, s, probs, part_in);
 }
 
 template <typename T>
@@ -944,19 +1160,29 @@ void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool p
                                                             s, probs, nprob, part_out)));
 }
 
+void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, x, y);
+}
+
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_add_scalar, dim3(red_blocks(n)), dim3(kWave, 4), 0, s, n, x, a, y);
 }
 
 void launch_build_lateral(int nx, int ny, int nz, double dx, double dy, const double *dz,
                           const double *k_lat, const double *mult, double *gx64, double *gy64,
-                          float *gx32, float *gy32, unsigned long long *maxrow, unsigned int *bad,
-                          hipStream_t s) {
+                          float *gx32, float *gy32, unsigned long long *maxrow,
+                          unsigned long long *maxg, unsigned int *bad, hipStream_t s) {
     const dim3 g((nx + kWave - 1) / kWave, (ny + 3) / 4), b(kWave, 4);
     hipLaunchKernelGGL(k_build_lateral, g, b, 0, s, nx, ny, nz, dx, dy, dz, k_lat, mult, gx64,
                        gy64, gx32, gy32, bad);
     hipLaunchKernelGGL(k_lateral_rowmax, g, b, 0, s, nx, ny, nz, (const double *)gx64,
-                       (const double *)gy64, maxrow);
+                       (const double *)gy64, maxrow, maxg);
+}
+
+void launch_build_fp16(int nx, int ny, int nz, const double *gx64, const double *gy64,
+                       const double *scale, uint16_t *hx, uint16_t *hy, hipStream_t s) {
+    const dim3 g((nx + kWave - 1) / kWave, (ny + 3) / 4), b(kWave, 4);
+    hipLaunchKernelGGL(k_build_fp16, g, b, 0, s, nx, ny, nz, gx64, gy64, scale, hx, hy);
 }
 
 void launch_fill_random(int64_t n, uint64_t seed, float *v, hipStream_t s) {
@@ -1008,11 +1234,11 @@ void launch_adjoint(const OpView<double> &op, const double *lam, const double *T
 
 #define CUTH_INST(T)                                                                              \
     template void launch_apply<T>(const OpView<T> &, const T *, T *, hipStream_t);                \
-    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, bool,     \
-                                   bool, int, int, const T *, bool, T *, hipStream_t);            \
-    template void launch_scale_b<T>(const InnerProb<T> *, int, int, int, int, bool, const T *,    \
-                                    bool, T *, hipStream_t);                                      \
-    template void launch_dir_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, int,       \
+    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, bool, int, int, int,     \
+                                   bool, bool, int, int, const T *, bool, T *, hipStream_t);      \
+    template void launch_scale_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, bool,    \
+                                    const T *, bool, T *, hipStream_t);                           \
+    template void launch_dir_b<T>(const InnerProb<T> *, int, int, bool, bool, int, int, int, int, \
                                   const T *, bool, T *, hipStream_t);                             \
     template void launch_update_b<T>(const InnerProb<T> *, int, int, int, int, int, const T *,    \
                                      bool, T *, hipStream_t);                                     \
@@ -1022,6 +1248,11 @@ void launch_adjoint(const OpView<double> &op, const double *lam, const double *T
 CUTH_INST(float)
 CUTH_INST(double)
 #undef CUTH_INST
+
+template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
+                                         hipStream_t);
+template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,
+                                         hipStream_t);
 
 template void launch_residual_b<float, float>(const OuterProb<float, float> *, int, int, bool, int,
                                               int, double *, hipStream_t);

@@ -171,15 +171,19 @@ ChebConsts make_cheb(double lmin, double lmax, int k) {
 // Algorithmic bytes per unknown of each kernel (what the method must move).
 template <typename T>
 struct Bytes {
-    double coef;   // per-cell lateral conductances read by one stencil sweep
-    explicit Bytes(bool per_cell) : coef(per_cell ? 2.0 * sizeof(T) : 0.0) {}
-    double cheb(int mode) const { return (mode == 1 ? 2 : mode == 2 ? 3 : 4) * sizeof(T) + coef; }
+    double coef;     // per-cell lateral conductances read by one CG stencil pass
+    double coef_sw;  // ... by one Chebyshev sweep (FP16-stored: 2 x 2 B)
+    explicit Bytes(bool per_cell, bool h16 = false)
+        : coef(per_cell ? 2.0 * sizeof(T) : 0.0),
+          coef_sw(per_cell ? (h16 ? 4.0 : 2.0 * sizeof(T)) : 0.0) {}
+    double cheb(int mode) const { return (mode == 1 ? 2 : mode == 2 ? 3 : 4) * sizeof(T) + coef_sw; }
     double dir() const { return 4.0 * sizeof(T) + coef; }
     double update() const { return 6.0 * sizeof(T); }
     double check() const { return 3.0 * sizeof(T) + coef; }
     double scale() const { return 2.0 * sizeof(T); }
-    double precond(int k) const {
-        if (k == 1) return scale();
+    double precond(int k, int pm = 0) const {
+        if (pm == 1) return scale() + coef;   // Jacobi: also the lateral conductances
+        if (k == 1 || pm == 2) return scale();
         double b = cheb(1);
         for (int j = 2; j < k; ++j) b += cheb(j == 2 ? 2 : 0);
         return b;
@@ -206,6 +210,13 @@ struct Problem {
     bool have_delta = false;
     double *th_out = nullptr, *th_final = nullptr;
     double last_red = 1.0, d_prev = 1.0, est = 1.0, prev_relres = INFINITY;
+    // the Chebyshev sweeps read the FP16-stored lateral conductances
+    bool h16 = false;
+    // preconditioner: 0 Chebyshev, 1 Jacobi, 2 none (cuth_options.preconditioner)
+    int pm = 0;
+    // stage-switched scheme: still in the early stage (FP32-stored coefficients
+    // in the CG product, switch test (a) as the inner tolerance)
+    bool early = false;
     // per inner solve
     bool inner = false;
     double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, true_rr = 0.0;
@@ -230,8 +241,13 @@ template <> struct Sel<float> {
     static Work<float> &w(Problem &p) { return p.w32; }
     static OpView<float> view(const Problem &p, const Shape &sh) {
         const Grid &g = *p.g;
-        return OpView<float>{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr,
-                             g.per_cell ? g.gy32 : nullptr, p.su->lc32, sh.vx, sh.by, sh.zc};
+        OpView<float> v{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr,
+                        g.per_cell ? g.gy32 : nullptr, p.su->lc32, sh.vx, sh.by, sh.zc};
+        if (p.h16 && g.per_cell) {
+            v.hx = g.hx;
+            v.hy = g.hy;
+        }
+        return v;
     }
 };
 template <> struct Sel<double> {
@@ -395,29 +411,29 @@ T *red_rr(Engine &E) { return eslot<T>(E, P_RED) + 2 * E.cap; }
 // z = q(A) r for every problem of the launch; returns the buffer index of z.
 // chk: the first kernel also runs the convergence test on the update's r^T r.
 template <typename T>
-int enqueue_precond(Engine &E, int nprob, int nb, bool pc, const Shape &sh, int k, bool chk,
-                    bool red, hipStream_t s, Grid *prof, int tag = -1) {
+int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, const Shape &sh, int k,
+                    bool chk, bool red, hipStream_t s, Grid *prof, int tag = -1) {
     InnerProb<T> *d = Sel<T>::d(E);
     const T *rr_in = red ? red_rr<T>(E) : eslot<T>(E, P_UPD);
-    if (k == 1) {
-        launch_scale_b<T>(d, nprob, nb, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
+    if (k == 1 || pm != 0) {
+        launch_scale_b<T>(d, nprob, nb, pc, pm, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
         return 0;
     }
-    launch_cheb_b<T>(d, nprob, nb, pc, sh.vx, sh.by, 1, k == 2, chk, 1, 0, rr_in, red,
+    launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, 1, k == 2, chk, 1, 0, rr_in, red,
                      eslot<T>(E, P_CHEB), s);
     for (int j = 2; j < k; ++j) {
         const int mode = (j == 2) ? 2 : 0;
         const bool timed = prof && prof->prof && j == 3 && prof->pev_used + 2 <= prof->pev.size();
         if (timed) (void)hipEventRecord(prof->pev[prof->pev_used], s);
-        launch_cheb_b<T>(d, nprob, nb, pc, sh.vx, sh.by, mode, j == k - 1, false, j, (j - 1) & 1,
+        launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, mode, j == k - 1, false, j, (j - 1) & 1,
                          rr_in, red, eslot<T>(E, P_CHEB), s);
         if (timed) {
             (void)hipEventRecord(prof->pev[prof->pev_used + 1], s);
             if (prof->pev_tag.size() < prof->pev.size() / 2) prof->pev_tag.resize(prof->pev.size() / 2);
             prof->pev_tag[prof->pev_used / 2] = tag;
             prof->pev_used += 2;
-            prof->prof_bytes = Bytes<T>(pc).cheb(0) * (double)prof->N;
+            prof->prof_bytes = Bytes<T>(pc, h16).cheb(0) * (double)prof->N;
         }
     }
     if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
@@ -425,18 +441,18 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, const Shape &sh, int 
 }
 
 template <typename T>
-void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, const Shape &sh, int k, int first_k,
-                        int count, int zfin, bool red, hipStream_t s, Grid *prof) {
+void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, const Shape &sh, int k,
+                        int first_k, int count, int zfin, bool red, hipStream_t s, Grid *prof) {
     InnerProb<T> *d = Sel<T>::d(E);
     for (int q = 0; q < count; ++q) {
         const int par = (first_k + q) & 1;
-        launch_dir_b<T>(d, nprob, nb, pc, sh.vx, sh.by, par, zfin,
+        launch_dir_b<T>(d, nprob, nb, pc, false, sh.vx, sh.by, par, zfin,
                         red ? red_rz<T>(E) : eslot<T>(E, P_CHEB), red, eslot<T>(E, P_DIR), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_DIR), red_pmu<T>(E), s);
         launch_update_b<T>(d, nprob, nb, sh.vx, sh.by, par, red ? red_pmu<T>(E) : eslot<T>(E, P_DIR),
                            red, eslot<T>(E, P_UPD), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_UPD), red_rr<T>(E), s);
-        enqueue_precond<T>(E, nprob, nb, pc, sh, k, true, red, s, prof, first_k + q);
+        enqueue_precond<T>(E, nprob, nb, pc, h16, pm, sh, k, true, red, s, prof, first_k + q);
     }
 }
 
@@ -455,6 +471,8 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     const int nprob = (int)which.size();
     if (nprob == 0) return Status::ok();
     const bool pc = ps[which[0]]->g->per_cell;
+    const bool h16 = pc && ps[which[0]]->h16;
+    const int pm = ps[which[0]]->pm;
     bool red = false;
     const int above = reduce_above();
     for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
@@ -474,13 +492,13 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         p.stop = 0;
     }
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>) * nprob, hipMemcpyHostToDevice, s));
-    const int zfin = enqueue_precond<T>(E, nprob, nb, pc, sh, k, false, red, s, prof);
+    const int zfin = enqueue_precond<T>(E, nprob, nb, pc, h16, pm, sh, k, false, red, s, prof);
     const bool graph = use_graph && period % 2 == 0;
     hipGraphExec_t exec = nullptr;
     if (graph) {
         hipGraph_t gr = nullptr;
         CUTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_iterations<T>(E, nprob, nb, pc, sh, k, 0, period, zfin, red, s, nullptr);
+        enqueue_iterations<T>(E, nprob, nb, pc, h16, pm, sh, k, 0, period, zfin, red, s, nullptr);
         CUTH_HIP(hipStreamEndCapture(s, &gr));
         const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
@@ -498,7 +516,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
                 break;
             }
         } else {
-            enqueue_iterations<T>(E, nprob, nb, pc, sh, k, it, cnt, zfin, red, s, prof);
+            enqueue_iterations<T>(E, nprob, nb, pc, h16, pm, sh, k, it, cnt, zfin, red, s, prof);
         }
         it += cnt;
         launch_check_b<T>(Sel<T>::d(E), nprob, nb, pc, sh.vx, sh.by, eslot<T>(E, P_CHK), s);
@@ -552,14 +570,14 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     // exit early and move no data)
     for (int n = 0; n < nprob; ++n) {
         Problem &p = *ps[which[n]];
-        const Bytes<T> by(p.g->per_cell);
+        const Bytes<T> by(p.g->per_cell, p.h16);
         const double N = (double)p.g->N;
         const int iters = hs[n].iter;
         const int reason = p.stop ? p.stop : 5;
         const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
         p.cg_iters += iters;
         p.reason = reason;
-        p.bytes += precs_run * by.precond(k) * N + iters * (by.dir() + by.update()) * N +
+        p.bytes += precs_run * by.precond(k, p.pm) * N + iters * (by.dir() + by.update()) * N +
                    nchecks * by.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
         p.last_red = p.rr0 > 0 ? std::sqrt(p.true_rr / p.rr0) : 0.0;
@@ -757,6 +775,229 @@ Status run_refinement(Engine &E, std::vector<Problem *> &ps, const Shape &sh_in,
     return Status::ok();
 }
 
+// ---------------------------------------------------------------------------
+// The paper's stage-switched scheme (Section 4.4): CG vectors, scalars and inner
+// products in FP64; the Chebyshev preconditioner in FP32 with FP16-stored
+// lateral conductances; the CG product with FP32-stored conductances promoted
+// to FP64 in the early stage and FP64 ones in the late stage.  The early stage
+// ends at the first of: ||r_low|| <= sqrt(tol) ||b|| (eq. switching a, with the
+// relative tolerance in place of the absolute one), stagnation (b) or drift (c)
+// of the FP64 true residual checked every `period` iterations; the switch is a
+// hot restart: r recomputed as b - A x in FP64 (x kept), p restarted.
+
+// One FP64 inner CG with the FP32 preconditioner on the problems with
+// p->inner set: A x = rhat from x = 0, r = rhat (FP64) and r_lo = (float) r
+// already written.
+Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh32,
+                          const Shape &sh64, int k, int maxit, int period, hipStream_t s) {
+    std::vector<int> which32, which;
+    const int nb32 = build_inner<float>(E, ps, sh32, which32);
+    const int nb = build_inner<double>(E, ps, sh64, which);   // p->tile0/ntiles: FP64 tiling
+    if (nb32 < 0 || nb < 0) return Status::err(CUTH_E_DEVICE, "internal: staged solve does not fit the engine");
+    const int nprob = (int)which.size();
+    if (nprob == 0) return Status::ok();
+    const bool pc = ps[which[0]]->g->per_cell;
+    const bool h16 = pc && ps[which[0]]->h16;
+    const int pm = ps[which[0]]->pm;
+    const bool early = ps[which[0]]->early;
+    bool red = false;
+    const int above = reduce_above();
+    for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
+    const int zfin32 = (k == 1 || pm != 0) ? 0 : (k - 1) & 1;
+    InnerProb<double> *h64 = E.h_in64;
+    for (int n = 0; n < nprob; ++n) {
+        Problem &p = *ps[which[n]];
+        h64[n].op.fx = p.g->per_cell ? p.g->gx32 : nullptr;
+        h64[n].op.fy = p.g->per_cell ? p.g->gy32 : nullptr;
+        h64[n].r_lo = p.w32.r;
+        h64[n].z_lo = zfin32 == 0 ? p.w32.zA : p.w32.zB;
+        h64[n].done_lo = &E.st32[n].done;
+    }
+    CUTH_HIP(hipMemcpyAsync(E.in32, E.h_in32, sizeof(InnerProb<float>) * nprob, hipMemcpyHostToDevice, s));
+    CUTH_HIP(hipMemcpyAsync(E.in64, E.h_in64, sizeof(InnerProb<double>) * nprob, hipMemcpyHostToDevice, s));
+    CgState<double> *hs = E.h_st64;
+    CgState<float> *hs32 = E.h_st32;
+    for (int n = 0; n < nprob; ++n) {
+        Problem &p = *ps[which[n]];
+        std::memset(&hs[n], 0, sizeof(hs[n]));
+        std::memset(&hs32[n], 0, sizeof(hs32[n]));
+        hs[n].rz[1] = std::numeric_limits<double>::infinity();
+        hs[n].rr = p.rr0;
+        hs[n].rr0 = p.rr0;
+        hs[n].tol2 = p.tol2;
+        hs[n].done = p.rr0 > 0.0 ? 0 : 1;
+        hs32[n].done = hs[n].done;
+        p.true_prev = -1.0;
+        p.stop = 0;
+    }
+    CUTH_HIP(hipMemcpyAsync(E.st64, hs, sizeof(CgState<double>) * nprob, hipMemcpyHostToDevice, s));
+    CUTH_HIP(hipMemcpyAsync(E.st32, hs32, sizeof(CgState<float>) * nprob, hipMemcpyHostToDevice, s));
+    InnerProb<double> *d = E.in64;
+    auto precond = [&]() {
+        (void)enqueue_precond<float>(E, nprob, nb32, pc, h16, pm, sh32, k, false, false, s, nullptr);
+        launch_promote_dot<double>(d, nprob, nb, sh64.vx, sh64.by, eslot<double>(E, P_CHEB), s);
+        if (red) launch_reduce_b<double>(d, nprob, eslot<double>(E, P_CHEB), red_rz<double>(E), s);
+    };
+    precond();
+    int it = 0, nchecks = 0;
+    while (it < maxit) {
+        const int cnt = std::min(period, maxit - it);
+        for (int q = 0; q < cnt; ++q) {
+            const int par = (it + q) & 1;
+            launch_dir_b<double>(d, nprob, nb, pc, early, sh64.vx, sh64.by, par, 0,
+                                 red ? red_rz<double>(E) : eslot<double>(E, P_CHEB), red,
+                                 eslot<double>(E, P_DIR), s);
+            if (red) launch_reduce_b<double>(d, nprob, eslot<double>(E, P_DIR), red_pmu<double>(E), s);
+            launch_update_b<double>(d, nprob, nb, sh64.vx, sh64.by, par,
+                                    red ? red_pmu<double>(E) : eslot<double>(E, P_DIR), red,
+                                    eslot<double>(E, P_UPD), s);
+            launch_reduce_conv<double>(d, nprob, eslot<double>(E, P_UPD), s);
+            precond();
+        }
+        it += cnt;
+        // FP64 true residual with the FP64 operator (switch tests b and c)
+        launch_check_b<double>(d, nprob, nb, pc, sh64.vx, sh64.by, eslot<double>(E, P_CHK), s);
+        ++nchecks;
+        CUTH_HIP(hipMemcpyAsync(hs, E.st64, sizeof(CgState<double>) * nprob, hipMemcpyDeviceToHost, s));
+        CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<double>(E, P_CHK), sizeof(double) * 2 * (size_t)nb,
+                                hipMemcpyDeviceToHost, s));
+        CUTH_TRY(sync_stream(s));
+        bool all_done = true;
+        for (int n = 0; n < nprob; ++n) {
+            Problem &p = *ps[which[n]];
+            if (p.stop) continue;
+            double a = 0.0, b = 0.0;
+            for (int q = p.tile0; q < p.tile0 + p.ntiles; ++q) {
+                a += E.h_part[q];
+                b += E.h_part[nb + q];
+            }
+            p.true_rr = a;
+            const double tn = std::sqrt(a);
+            int why = hs[n].done;
+            if (!why) {
+                if (!std::isfinite(tn)) why = 4;
+                else if (std::sqrt(b) >= 0.5 * tn) why = 2;
+                else if (p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
+                else if (it >= maxit) why = 5;
+                if (why) {
+                    hs[n].done = why;
+                    CUTH_HIP(hipMemcpyAsync(&E.st64[n].done, &hs[n].done, sizeof(int),
+                                            hipMemcpyHostToDevice, s));
+                    CUTH_HIP(hipMemcpyAsync(&E.st32[n].done, &hs[n].done, sizeof(int),
+                                            hipMemcpyHostToDevice, s));
+                }
+            }
+            p.true_prev = tn;
+            if (why) p.stop = why;
+            else all_done = false;
+        }
+        if (all_done) break;
+    }
+    CUTH_TRY(sync_stream(s));
+    for (int n = 0; n < nprob; ++n) {
+        Problem &p = *ps[which[n]];
+        const double N = (double)p.g->N;
+        const Bytes<float> b32(p.g->per_cell, p.h16);
+        const Bytes<double> b64(p.g->per_cell);
+        const int iters = hs[n].iter;
+        const int reason = p.stop ? p.stop : 5;
+        const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
+        const double dir64 = 32.0 + (p.g->per_cell ? (p.early ? 8.0 : 16.0) : 0.0);
+        p.cg_iters += iters;
+        p.reason = reason;
+        p.bytes += precs_run * (b32.precond(k, p.pm) + 20.0) * N + iters * (dir64 + b64.update() + 4.0) * N +
+                   nchecks * b64.check() * N;
+        p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
+        p.last_red = p.rr0 > 0 ? std::sqrt(p.true_rr / p.rr0) : 0.0;
+        p.cycles += 1;
+        p.inner = false;
+        if (iters == 0 && reason != 1) {
+            p.status = Status::err(CUTH_E_BREAKDOWN, "inner solve made no progress");
+            p.finished = true;
+        } else if (reason == 4) {
+            p.status = Status::err(CUTH_E_BREAKDOWN, "CG breakdown (p^T A p <= 0 or non-finite value)");
+        }
+    }
+    return Status::ok();
+}
+
+// Decisions of the stage-switched scheme after an FP64 residual: finished at
+// ||b - A T|| <= tol ||b||; otherwise an inner solve to tol2 = tol ||b||^2 (early
+// stage, switch test a) or tol^2 ||b||^2 (late stage).
+void decide_staged(Problem &p, const double *o, int max_outer) {
+    const double rr = o[0], bb = o[1], dinf = o[2], thinf = o[3], bad = o[4];
+    p.relres = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    p.inner = false;
+    if (bad > 0) {
+        p.status = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
+        p.finished = true;
+        return;
+    }
+    if (p.cycles >= 1 && thinf > 0) p.err_est = dinf / thinf;
+    if (!p.status.bad() && p.relres <= p.tol) {
+        p.finished = true;
+        return;
+    }
+    if (!p.status.bad() && !p.early && p.cycles >= 2 && p.relres > 0.5 * p.prev_relres) {
+        p.status = Status::err(CUTH_E_NOT_CONVERGED,
+                               "true residual stagnated above tol (attainable accuracy)");
+        p.finished = true;
+        return;
+    }
+    p.prev_relres = p.relres;
+    if (rr == 0.0 || p.status.bad()) {
+        p.finished = true;
+        return;
+    }
+    if (p.cycles >= max_outer) {
+        p.status = Status::err(CUTH_E_NOT_CONVERGED, "refinement cycle limit reached");
+        p.finished = true;
+        return;
+    }
+    p.inner = true;
+    p.rr0 = rr;
+    p.tol2 = p.early ? p.tol * bb : p.tol * p.tol * bb;
+}
+
+Status run_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh32, const Shape &sh64,
+                  int k, const cuth_options &o, int period, hipStream_t s) {
+    std::vector<double> st5;
+    CUTH_TRY(upload_cheb<float>(E, ps, s));
+    for (Problem *p : ps) p->early = true;
+    for (;;) {
+        CUTH_TRY(outer_step<double>(E, ps, sh64, s, st5));
+        bool any = false;
+        for (size_t i = 0; i < ps.size(); ++i) {
+            Problem &p = *ps[i];
+            if (p.finished) continue;
+            decide_staged(p, &st5[i * kResidualValues], o.max_outer);
+            if (log_on() && p.inner)
+                std::fprintf(stderr, "cuth: problem %zu cycle %d %s stage relres %.3e\n", i, p.cycles,
+                             p.early ? "early" : "late", p.relres);
+            any = any || p.inner;
+        }
+        if (!any) break;
+        std::vector<Problem *> ran;
+        for (Problem *p : ps)
+            if (p->inner) {
+                ran.push_back(p);
+                launch_to_f32(p->g->N, p->w64.r, p->w32.r, s);
+            }
+        // every problem of a launch is in the same stage (they start together
+        // and each switches after its first inner solve)
+        CUTH_TRY(inner_solve_staged(E, ps, sh32, sh64, k, o.max_inner, period, s));
+        for (Problem *p : ran) {
+            p->early = false;
+            if (p->finished) continue;
+            p->th_in = p->th_out;
+            p->in_off = 0.0;
+            p->have_delta = true;
+            p->th_out = (p->th_out == p->thA) ? p->thB : p->thA;
+        }
+    }
+    return Status::ok();
+}
+
 int sturm_count(const std::vector<double> &a, const std::vector<double> &b, double x) {
     int cnt = 0;
     double d = 1.0;
@@ -893,36 +1134,63 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
         if ((st = dev_alloc(&g->gy64, (size_t)N)).bad()) return fail(st);
         if ((st = dev_alloc(&g->gx32, (size_t)N)).bad()) return fail(st);
         if ((st = dev_alloc(&g->gy32, (size_t)N)).bad()) return fail(st);
-        double *ddz = nullptr, *dkl = nullptr;
+        if ((st = dev_alloc(&g->hx, (size_t)N)).bad()) return fail(st);
+        if ((st = dev_alloc(&g->hy, (size_t)N)).bad()) return fail(st);
+        const int nz = g->nz;
+        double *ddz = nullptr, *dkl = nullptr, *dscale = nullptr;
         unsigned long long *dmax = nullptr;
         unsigned int *dbad = nullptr;
-        if ((st = dev_alloc(&ddz, (size_t)g->nz)).bad() || (st = dev_alloc(&dkl, (size_t)g->nz)).bad() ||
-            (st = dev_alloc(&dmax, (size_t)g->nz)).bad() || (st = dev_alloc(&dbad, 1)).bad()) {
-            dev_free(ddz); dev_free(dkl); dev_free(dmax); dev_free(dbad);
+        auto free_tmp = [&] {
+            dev_free(ddz); dev_free(dkl); dev_free(dscale); dev_free(dmax); dev_free(dbad);
+        };
+        if ((st = dev_alloc(&ddz, (size_t)nz)).bad() || (st = dev_alloc(&dkl, (size_t)nz)).bad() ||
+            (st = dev_alloc(&dscale, (size_t)nz)).bad() || (st = dev_alloc(&dmax, (size_t)2 * nz)).bad() ||
+            (st = dev_alloc(&dbad, 1)).bad()) {
+            free_tmp();
             return fail(st);
         }
-        std::vector<unsigned long long> hmax(g->nz, 0ull);
+        // dmax[0, nz): max lateral row sum per layer; dmax[nz, 2 nz): max single g
+        std::vector<unsigned long long> hmax(2 * (size_t)nz, 0ull);
         unsigned int hbad = 0;
-        bool ok = hipMemcpy(ddz, g->dz.data(), g->nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemcpy(dkl, g->k_lat.data(), g->nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemset(dmax, 0, g->nz * sizeof(unsigned long long)) == hipSuccess &&
+        bool ok = hipMemcpy(ddz, g->dz.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(dkl, g->k_lat.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemset(dmax, 0, 2 * nz * sizeof(unsigned long long)) == hipSuccess &&
                   hipMemset(dbad, 0, sizeof(unsigned int)) == hipSuccess;
         if (ok) {
-            launch_build_lateral(g->nx, g->ny, g->nz, g->dx, g->dy, ddz, dkl, d.k_lat_mult, g->gx64,
-                                 g->gy64, g->gx32, g->gy32, dmax, dbad, g->stream);
+            launch_build_lateral(g->nx, g->ny, nz, g->dx, g->dy, ddz, dkl, d.k_lat_mult, g->gx64,
+                                 g->gy64, g->gx32, g->gy32, dmax, dmax + nz, dbad, g->stream);
             ok = hipStreamSynchronize(g->stream) == hipSuccess &&
-                 hipMemcpy(hmax.data(), dmax, g->nz * sizeof(unsigned long long), hipMemcpyDeviceToHost) == hipSuccess &&
+                 hipMemcpy(hmax.data(), dmax, 2 * nz * sizeof(unsigned long long), hipMemcpyDeviceToHost) == hipSuccess &&
                  hipMemcpy(&hbad, dbad, sizeof(unsigned int), hipMemcpyDeviceToHost) == hipSuccess;
         }
-        dev_free(ddz); dev_free(dkl); dev_free(dmax); dev_free(dbad);
+        if (ok && !hbad) {
+            g->lat_rowmax.resize(nz);
+            g->e16.assign(nz, 0);
+            std::vector<double> scale(nz, 1.0);
+            for (int l = 0; l < nz; ++l) {
+                double v, m;
+                std::memcpy(&v, &hmax[l], sizeof(double));
+                std::memcpy(&m, &hmax[nz + l], sizeof(double));
+                g->lat_rowmax[l] = v;
+                // FP16 storage scale 2^e_l with e_l = 14 - ceil(log2(max g)):
+                // frexp gives m = f 2^x with f in [0.5, 1), so ceil(log2 m) is
+                // x, or x - 1 when f is exactly 0.5
+                if (m > 0.0) {
+                    int x = 0;
+                    const double f = std::frexp(m, &x);
+                    g->e16[l] = 14 - (f == 0.5 ? x - 1 : x);
+                }
+                scale[l] = std::ldexp(1.0, g->e16[l]);
+            }
+            ok = hipMemcpy(dscale, scale.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+            if (ok) {
+                launch_build_fp16(g->nx, g->ny, nz, g->gx64, g->gy64, dscale, g->hx, g->hy, g->stream);
+                ok = hipStreamSynchronize(g->stream) == hipSuccess;
+            }
+        }
+        free_tmp();
         if (!ok) return fail(Status::err(CUTH_E_DEVICE, "coefficient build failed"));
         if (hbad) return fail(Status::err(CUTH_E_INVALID, "k_lat_mult has entries <= 0 or non-finite"));
-        g->lat_rowmax.resize(g->nz);
-        for (int l = 0; l < g->nz; ++l) {
-            double v;
-            std::memcpy(&v, &hmax[l], sizeof(double));
-            g->lat_rowmax[l] = v;
-        }
     }
     *out = g;
     return Status::ok();
@@ -940,6 +1208,8 @@ void grid_destroy(Grid *g) {
     dev_free(g->gy64);
     dev_free(g->gx32);
     dev_free(g->gy32);
+    dev_free(g->hx);
+    dev_free(g->hy);
     free_work(g->w32);
     free_work(g->w64);
     dev_free(g->thA);
@@ -961,10 +1231,14 @@ OpView<double> view64(const Grid &g, const Setup &su) {
                           g.sh64.zc};
 }
 
-OpView<float> view32(const Grid &g, const Setup &su) {
-    return OpView<float>{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr,
-                         g.per_cell ? g.gy32 : nullptr, su.lc32, g.sh32.vx, g.sh32.by,
-                         g.sh32.zc};
+OpView<float> view32(const Grid &g, const Setup &su, bool h16) {
+    OpView<float> v{g.nx, g.ny, g.nz, g.per_cell ? g.gx32 : nullptr, g.per_cell ? g.gy32 : nullptr,
+                    su.lc32, g.sh32.vx, g.sh32.by, g.sh32.zc};
+    if (h16 && g.per_cell) {
+        v.hx = g.hx;
+        v.hy = g.hy;
+    }
+    return v;
 }
 
 Setup *get_setup(Grid &g, double dt, Status &status) {
@@ -989,6 +1263,7 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
         L.gzd = (l > 0) ? su.hlc[l - 1].gzu : 0.0;
         L.cap = (dt > 0.0) ? g.cap[l] * dxdy * d / dt : 0.0;
         L.sink = L.cap + (l == nz - 1 ? g.h_top * dxdy : 0.0) + (l == 0 ? g.h_bot * dxdy : 0.0);
+        L.hs = g.e16.empty() ? 1.0 : std::ldexp(1.0, -g.e16[l]);
         const double lat = g.per_cell ? g.lat_rowmax[l]
                                       : std::min(2, g.nx - 1) * L.gx + std::min(2, g.ny - 1) * L.gy;
         gersh = std::max(gersh, 2.0 * (lat + L.gzu + L.gzd) + L.sink);
@@ -998,7 +1273,7 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
     for (int l = 0; l < nz; ++l) {
         const LayerCoef<double> &L = su.hlc[l];
         h32[l] = LayerCoef<float>{(float)L.gx, (float)L.gy, (float)L.gzd, (float)L.gzu,
-                                  (float)L.sink, (float)L.cap};
+                                  (float)L.sink, (float)L.cap, (float)L.hs};
     }
     status = dev_alloc(&su.lc64, (size_t)nz);
     if (!status.bad()) status = dev_alloc(&su.lc32, (size_t)nz);
@@ -1095,7 +1370,8 @@ double default_tol(const cuth_options &o, double dt) {
     // 1e-8; FP64, relative residual 1e-10 (steady) or 1e-12 (transient, where
     // ||b|| is dominated by the C/dt T_n term and the residual bound is looser)
     if (o.tol > 0.0) return o.tol;
-    return o.precision == CUTH_MIXED ? 1e-8 : (dt > 0.0 ? 1e-12 : 1e-10);
+    const bool mixed = o.precision == CUTH_MIXED || o.precision == CUTH_MIXED16;
+    return mixed ? 1e-8 : (dt > 0.0 ? 1e-12 : 1e-10);
 }
 
 void fill_stats(const Problem &p, cuth_stats *stats, float ms_setup, float ms_solve) {
@@ -1121,10 +1397,14 @@ Status run_set(Engine &E, std::vector<Problem *> &ps, hipStream_t user, const Sh
     CUTH_HIP(hipEventRecord(E.ev_in, user));
     CUTH_HIP(hipStreamWaitEvent(s, E.ev_in, 0));
     Status st;
-    if (o.precision == CUTH_MIXED)
-        st = run_refinement<float>(E, ps, sh32, sh64, o.cheb_degree, o, period, use_graph, s, prof);
+    // Jacobi and no preconditioning are single passes (degree-1 path)
+    const int k = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+    if (o.precision == CUTH_ADAPTIVE)
+        st = run_staged(E, ps, sh32, sh64, k, o, period, s);
+    else if (o.precision != CUTH_FP64)
+        st = run_refinement<float>(E, ps, sh32, sh64, k, o, period, use_graph, s, prof);
     else
-        st = run_refinement<double>(E, ps, sh64, sh64, o.cheb_degree, o, period, use_graph, s, prof);
+        st = run_refinement<double>(E, ps, sh64, sh64, k, o, period, use_graph, s, prof);
     if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_NOMEM) return st;
     for (Problem *p : ps)
         if (p->th_final) {
@@ -1148,13 +1428,15 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     CUTH_HIP(hipEventRecord(g.ev0, g.stream));
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps));
+    const bool cheb = o.preconditioner == CUTH_PC_CHEBYSHEV;
+    if (cheb) CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps));
     CUTH_HIP(hipEventRecord(g.ev1, g.stream));
-    if (o.precision != CUTH_MIXED) CUTH_TRY(alloc_work(g.w64, g.N));
+    if (o.precision == CUTH_FP64 || o.precision == CUTH_ADAPTIVE) CUTH_TRY(alloc_work(g.w64, g.N));
     Problem p;
     p.g = &g;
     p.su = su;
-    p.cc = make_cheb(su->lmin, su->lmax, o.cheb_degree);
+    p.cc = cheb ? make_cheb(su->lmin, su->lmax, o.cheb_degree) : ChebConsts{};
+    p.pm = o.preconditioner;
     p.P = P;
     p.Tn = Tn;
     p.init = init;
@@ -1163,6 +1445,8 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     p.out_off = out_off;
     p.w32 = g.w32;
     p.w64 = g.w64;
+    // the stage-switched scheme's preconditioner reads FP16 conductances too
+    p.h16 = o.precision == CUTH_MIXED16 || o.precision == CUTH_ADAPTIVE;
     p.thA = g.thA;
     p.thB = g.thB;
     p.tol = default_tol(o, dt);
@@ -1261,13 +1545,13 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
         CUTH_HIP(hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * n,
                                 hipMemcpyHostToDevice, s));
         CUTH_HIP(hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s));
-        const bool pc = ps[0]->g->per_cell;
+        const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
         for (int rep = 0; rep < 2; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, sh.vx, sh.by, 0, false, false, 2, 1,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, 1,
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 6; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, sh.vx, sh.by, 0, false, false, 2, rep & 1,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, rep & 1,
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e1, s));
         CUTH_TRY(sync_stream(s));
@@ -1298,7 +1582,8 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
 Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
                    double *const *T, const cuth_options &o, cuth_stats *stats) {
     if (o.cheb_degree > 256) return Status::err(CUTH_E_INVALID, "cheb_degree above 256");
-    const bool mixed = o.precision == CUTH_MIXED;
+    const bool mixed = o.precision == CUTH_MIXED || o.precision == CUTH_MIXED16;
+    const bool staged = o.precision == CUTH_ADAPTIVE;
     const hipStream_t user = grids[0]->stream;
     // per-system setup (Lanczos bounds cached in each grid)
     std::vector<Setup *> sus(nsys);
@@ -1306,7 +1591,8 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         Status st;
         sus[s] = get_setup(*grids[s], 0.0, st);
         if (!sus[s]) return st;
-        CUTH_TRY(ensure_bounds(*grids[s], *sus[s], o.lanczos_steps));
+        if (o.preconditioner == CUTH_PC_CHEBYSHEV)
+            CUTH_TRY(ensure_bounds(*grids[s], *sus[s], o.lanczos_steps));
     }
     // problems grouped by coefficient storage (one launch family per group)
     Status result = Status::ok();
@@ -1326,9 +1612,10 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         const int nvec = 8;
         Status st;
         if ((st = dev_alloc(&poolth, (size_t)ntot * 2)).bad()) return st;
-        if (mixed) st = dev_alloc(&pool32, (size_t)ntot * nvec);
-        else st = dev_alloc(&pool64, (size_t)ntot * nvec);
+        if (mixed || staged) st = dev_alloc(&pool32, (size_t)ntot * nvec);
+        if (!st.bad() && !mixed) st = dev_alloc(&pool64, (size_t)ntot * nvec);
         if (st.bad()) {
+            dev_free(pool32);
             dev_free(poolth);
             return st;
         }
@@ -1336,7 +1623,8 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         int n = 0;
         size_t nb_max = kRedBlocks;
         std::ostringstream sig;
-        sig << (mixed ? "f32" : "f64") << (group ? "pc" : "mf");
+        const bool h16 = group == 1 && (o.precision == CUTH_MIXED16 || staged);
+        sig << (mixed ? "f32" : staged ? "f64s" : "f64") << (group ? (h16 ? "pc16" : "pc") : "mf");
         for (int s : sys) {
             Grid &g = *grids[s];
             sig << ' ' << g.nx << 'x' << g.ny << 'x' << g.nz;
@@ -1344,7 +1632,10 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                 Problem &p = probs[n];
                 p.g = &g;
                 p.su = sus[s];
-                p.cc = make_cheb(sus[s]->lmin, sus[s]->lmax, o.cheb_degree);
+                p.cc = o.preconditioner == CUTH_PC_CHEBYSHEV
+                           ? make_cheb(sus[s]->lmin, sus[s]->lmax, o.cheb_degree)
+                           : ChebConsts{};
+                p.pm = o.preconditioner;
                 p.P = P[s] + (int64_t)q * g.N;
                 p.out = T[s] + (int64_t)q * g.N;
                 p.out_off = g.t_amb;
@@ -1361,12 +1652,13 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                     double **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
                     for (int i = 0; i < nvec; ++i) *v[i] = b + (int64_t)i * N;
                 };
-                if (mixed) carve32(p.w32);
-                else carve64(p.w64);
+                if (mixed || staged) carve32(p.w32);
+                if (!mixed) carve64(p.w64);
                 p.thA = poolth + off * 2;
                 p.thB = p.thA + N;
                 off += N;
                 p.tol = default_tol(o, 0.0);
+                p.h16 = h16;
                 p.th_in = p.init;
                 p.in_off = p.init_off;
                 p.th_out = p.thA;
@@ -1393,9 +1685,11 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         Shape sh_in, sh64{2, 1, 8};
         for (Problem *p : ps)
             while (sh64.vx > 1 && p->g->nx % sh64.vx != 0) sh64.vx /= 2;
-        Status ts = mixed ? autotune<float>(E, ps, o.cheb_degree, sig.str() + " in", sh_in)
-                          : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
-        if (!mixed) sh64 = sh_in;
+        // (the stage-switched scheme tunes its FP32 preconditioner's shape)
+        Status ts = (mixed || staged)
+                        ? autotune<float>(E, ps, o.cheb_degree, sig.str() + " in", sh_in)
+                        : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
+        if (!mixed && !staged) sh64 = sh_in;
         if (!ts.bad()) {
             const int period = o.check_period > 0 ? o.check_period : 20;
             const bool use_graph = graph_env() != 0;
@@ -1421,7 +1715,9 @@ Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
     Status st;
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    if (precision == CUTH_MIXED) launch_apply<float>(view32(g, *su), (const float *)x, (float *)y, g.stream);
+    if (precision != CUTH_FP64)
+        launch_apply<float>(view32(g, *su, precision == CUTH_MIXED16), (const float *)x, (float *)y,
+                            g.stream);
     else launch_apply<double>(view64(g, *su), (const double *)x, (double *)y, g.stream);
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
@@ -1458,7 +1754,7 @@ Status residual(Grid &g, double dt, const double *b, const double *T, double *r)
 
 template <typename T>
 static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, const ChebConsts &cc,
-                            const T *r, T *z) {
+                            bool h16, const T *r, T *z) {
     // the result lands in z[0] for k == 1 or odd k, in z[1] for even k >= 2
     Engine &E = g.eng;
     const int zfin = cc.k == 1 ? 0 : (cc.k - 1) & 1;
@@ -1466,6 +1762,7 @@ static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, con
     p.g = &g;
     p.su = &su;
     p.cc = cc;
+    p.h16 = h16 && g.per_cell;
     Work<T> &pw = Sel<T>::w(p);
     pw = w;
     pw.r = const_cast<T *>(r);
@@ -1482,7 +1779,8 @@ static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, con
     CgState<T> *hs = Sel<T>::hs(E);
     std::memset(hs, 0, sizeof(CgState<T>));
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
-    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, sh, cc.k, false, false, g.stream, nullptr);
+    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, p.h16, 0, sh, cc.k, false, false, g.stream,
+                                       nullptr);
     if (got != zfin) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
@@ -1495,10 +1793,11 @@ Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
     const ChebConsts cc = make_cheb(lmin, lmax, degree);
-    if (precision == CUTH_MIXED)
-        return precond_typed<float>(g, *su, g.w32, g.sh32, cc, (const float *)r, (float *)z);
+    if (precision != CUTH_FP64)
+        return precond_typed<float>(g, *su, g.w32, g.sh32, cc, precision == CUTH_MIXED16,
+                                    (const float *)r, (float *)z);
     CUTH_TRY(alloc_work(g.w64, g.N));
-    return precond_typed<double>(g, *su, g.w64, g.sh64, cc, (const double *)r, (double *)z);
+    return precond_typed<double>(g, *su, g.w64, g.sh64, cc, false, (const double *)r, (double *)z);
 }
 
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,

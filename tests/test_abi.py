@@ -40,6 +40,9 @@ def test_default_options(lib):
     lib.cuth_default_options(ctypes.byref(o))
     assert o.precision == _lib.CUTH_MIXED and o.tol == 0.0
     assert o.cheb_degree == 30 and o.lanczos_steps == 30
+    assert o.preconditioner == 0
+    # the ctypes mirror has the header's size (no field missing or misplaced)
+    assert ctypes.sizeof(_lib.Options) == 48
 
 
 def _desc(nx=4, ny=3, nz=2, dx=1e-3, dy=1e-3, dz=(1e-3, 1e-3), kl=(1.0, 2.0), kv=(1.0, 2.0),
@@ -99,3 +102,21 @@ def test_package_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_precision_names_match_header(lib):
+    """The binding's precision table equals the header's enum, and an unknown
+    name is refused instead of falling back to another precision."""
+    import re
+
+    import paper_2606_17850_amd as cuth
+    from paper_2606_17850_amd import _lib
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "cuth.h")).read()
+    enum = dict((k, int(v)) for k, v in
+                re.findall(r"(CUTH_FP64|CUTH_MIXED16|CUTH_MIXED|CUTH_ADAPTIVE)\s*=\s*(\d+)", hdr))
+    assert enum == {"CUTH_FP64": _lib.CUTH_FP64, "CUTH_MIXED": _lib.CUTH_MIXED,
+                    "CUTH_MIXED16": _lib.CUTH_MIXED16, "CUTH_ADAPTIVE": _lib.CUTH_ADAPTIVE}
+    assert cuth.options("mixed16").precision == enum["CUTH_MIXED16"]
+    assert cuth.options("fp64").precision == enum["CUTH_FP64"]
+    with pytest.raises(ValueError):
+        cuth.options("fp16")
