@@ -279,6 +279,16 @@ def main() -> int:
     step(mixed16)
     ms_m16, st_m16 = timed(mixed16, args.steps)
     T_m16 = T.clone()
+    # and with the general sweeps fused in pairs (two sweeps per HBM pass)
+    fuse_prev = os.environ.get("CUTH_FUSE")
+    os.environ["CUTH_FUSE"] = "1"
+    step(mixed)
+    ms_fu, st_fu = timed(mixed, args.steps)
+    T_fu = T.clone()
+    if fuse_prev is None:
+        del os.environ["CUTH_FUSE"]
+    else:
+        os.environ["CUTH_FUSE"] = fuse_prev
 
     k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
     for _ in range(min(args.warmup, 1)):
@@ -302,6 +312,8 @@ def main() -> int:
     diff16 = float((T_m16 - T_fp64).abs().max()) / rise
     per16 = ms_m16 / args.steps
     diff_st = float((T_st - T_fp64).abs().max()) / rise
+    diff_fu = float((T_fu - T_fp64).abs().max()) / rise
+    per_fu = ms_fu / args.steps
     per_st = ms_st / k64
 
     per_step = ms_mixed / args.steps
@@ -335,6 +347,8 @@ def main() -> int:
                            "speedup_mixed_vs_fp64": round(per64 / per_step, 3),
                            "mixed16": round(per16, 3),
                            "speedup_mixed16_vs_fp64": round(per64 / per16, 3),
+                           "mixed_fused_pairs": round(per_fu, 3),
+                           "speedup_mixed_fused_vs_fp64": round(per64 / per_fu, 3),
                            "stage_switched_to_fp64_tol": round(per_st, 3),
                            "speedup_stage_switched_vs_fp64": round(per64 / per_st, 3)},
         "solve_detail": {
@@ -350,6 +364,9 @@ def main() -> int:
             "mixed16_outer_cycles": st_m16[-1]["outer_cycles"],
             "mixed16_GBps": round(sum(s["alg_bytes"] for s in st_m16) / args.steps / (per16 / 1e3) / 1e9, 2),
             "mixed16_vs_fp64_max_rise_rel_diff": diff16,
+            "mixed_fused_cg_iters": st_fu[-1]["cg_iters"],
+            "mixed_fused_GBps": round(sum(s["alg_bytes"] for s in st_fu) / args.steps / (per_fu / 1e3) / 1e9, 2),
+            "mixed_fused_vs_fp64_max_rise_rel_diff": diff_fu,
             "stage_switched_cg_iters": st_st[-1]["cg_iters"],
             "stage_switched_cycles": st_st[-1]["outer_cycles"],
             "stage_switched_rel_residual": st_st[-1]["rel_residual"],

@@ -91,10 +91,11 @@ struct InnerProb {
     int tile0, ntiles;
     T *x, *r, *rhat, *mu;
     T *p[2];
-    T *z[2];
+    T *z[4];                  // Chebyshev iterates; z[2], z[3] only for fused sweep pairs
     CgState<T> *st;
     const T *cheb;            // 1/theta at [0], c1_j at [1 + j], c2_j at [1 + kcap + j]
     int kcap, pad;
+    int f_tile0 = 0, f_ntiles = 0;   // workgroup slots of fused sweep pairs (launch_cheb2_b)
     // FP64 CG with an FP32 preconditioner (the paper's stage-switched scheme):
     // the update also writes r_lo = (float) r; k_promote_dot reads the
     // preconditioner's z_lo; k_reduce_conv mirrors the stop flag to *done_lo.
@@ -133,15 +134,26 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 // Chebyshev sweep j (Section 4.3, two-term form):
 //   z_{j+1} = z_j + c1_j (z_j - z_{j-1}) + c2_j (r - A z_j).
 // mode 1 (j = 1): z_1 = r/theta and z_0 = 0 are implicit; mode 2 (j = 2):
-// z_{j-1} = r/theta implicit; mode 0: z_{j-1} read.  z_j is in z[zin]; the result
-// goes to z[1 - zin].  last: partials of r^T z_{j+1}.  chk: the first kernel after
+// z_{j-1} = r/theta implicit; mode 0: z_{j-1} read.  zsel = in + 4*out: z_j is in
+// z[in], z_{j-1} in z[out] (read at the cell only) and the result overwrites z[out].  last: partials of r^T z_{j+1}.  chk: the first kernel after
 // a CG update reduces the update's partials (part_in) and stops converged
 // problems (rr <= tol2).
 // h16: read the FP16-stored lateral conductances (FP32, per-cell grids only).
 template <typename T>
 void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int by,
-                   int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
+                   int mode, bool last, bool chk, int j, int zsel, const T *part_in, bool red,
                    T *part_out, hipStream_t s);
+
+// Two consecutive general sweeps j, j+1 in one pass (temporal blocking):
+// zsel = N + 4 P + 16 X + 64 Y with z_j in z[N], z_{j-1} in z[P]; z_{j+1} is
+// written to z[X] and z_{j+2} to z[Y] (four distinct buffers).  A workgroup is
+// R + 2 rows of wpr wavefronts (whole rows of 64*vx*wpr >= nx cells) and a chunk
+// of zc layers; the launch covers the problems' slots [f_tile0, f_tile0 +
+// f_ntiles) with f_ntiles = ceil(ny / R) * ceil(nz / zc).  FP32, coefficients
+// in the operator's own precision.
+template <typename T>
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int R, int zc,
+                    int wpr, int j, int zsel, hipStream_t s);
 
 // Single-pass preconditioner into z[0] (same chk/last behaviour as the sweeps):
 // pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r.

@@ -14,6 +14,7 @@ template <typename T>
 struct Work {
     T *x = nullptr, *r = nullptr, *rhat = nullptr, *pA = nullptr, *pB = nullptr, *mu = nullptr,
       *zA = nullptr, *zB = nullptr;
+    T *zC = nullptr, *zD = nullptr;   // the fused sweep pairs' extra iterates (FP32)
     bool ready() const { return x != nullptr; }
 };
 
@@ -41,9 +42,12 @@ struct Status {
     bool bad() const { return code != CUTH_OK; }
 };
 
-// Launch shape of the stencil kernels of one precision.
+// Launch shape of the stencil kernels of one precision.  fr > 0: general
+// Chebyshev sweeps run as fused pairs with fr rows and fzc layers per workgroup
+// and fwpr wavefronts per row (FP32 only).
 struct Shape {
     int vx = 1, by = 1, zc = 8;
+    int fr = 0, fzc = 8, fwpr = 1;
 };
 
 // Device descriptors, states and reduction partials for up to `cap` problems
@@ -105,6 +109,7 @@ struct Grid {
     std::vector<int> pev_tag;   // CG iteration of each recorded pair (-1: initial)
     size_t pev_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
+    bool prof_fused = false;   // the timed launch was a fused sweep pair
     int64_t prof_count = 0;
 
     template <typename T>

@@ -44,7 +44,8 @@ struct alignas(sizeof(T) * VX) Vec {
 
 template <typename T, int VX>
 __device__ __forceinline__ Vec<T, VX> vload(const T *p) {
-    return *reinterpret_cast<const Vec<T, VX> *>(p);
+    // callers pass cells whose index is a multiple of VX (VX divides nx)
+    return *reinterpret_cast<const Vec<T, VX> *>(__builtin_assume_aligned(p, sizeof(T) * VX));
 }
 
 template <typename T, int VX>
@@ -248,19 +249,41 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
         if constexpr (PC && CS == CS_F16) {
-            // FP16-stored lateral conductances, promoted to T before use
-            gxp = act ? h16load<T, VX>(op.hx + c, L.hs) : zero;
-            gyp = act ? h16load<T, VX>(op.hy + c, L.hs) : zero;
-            gym = has_s ? h16load<T, VX>(op.hy + c - nx, L.hs) : zero;
+            // FP16-stored lateral conductances.  Every lane loads from an
+            // in-bounds cell (inactive lanes sit at cell 0, a missing south or
+            // west neighbour falls back to the cell itself), promotes, then
+            // selects: a guarded load with the promotion inside made the
+            // compiler wait for each load in turn.
+            const Vec<uint16_t, VX> bxp = vload<uint16_t, VX>(op.hx + c);
+            const Vec<uint16_t, VX> byp = vload<uint16_t, VX>(op.hy + c);
+            const Vec<uint16_t, VX> bym = vload<uint16_t, VX>(op.hy + (has_s ? c - nx : c));
+            const uint16_t bxl = op.hx[has_l ? c - 1 : c];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                gxp.a[e] = act ? (T)h16one(bxp.a[e]) * L.hs : T(0);
+                gyp.a[e] = act ? (T)h16one(byp.a[e]) * L.hs : T(0);
+                gym.a[e] = has_s ? (T)h16one(bym.a[e]) * L.hs : T(0);
+            }
+            // every lane promotes its west value; lane 0 selects it (a branch
+            // around the promotion would wait for the load)
+            const T west = has_l ? (T)h16one(bxl) * L.hs : T(0);
             gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-            if (ln.lane == 0) gxl = has_l ? (T)h16one(op.hx[c - 1]) * L.hs : T(0);
+            gxl = ln.lane == 0 ? west : gxl;
         } else if constexpr (PC && CS == CS_F32) {
-            // FP32-stored lateral conductances, promoted to T before use
-            gxp = act ? f32load<T, VX>(op.fx + c) : zero;
-            gyp = act ? f32load<T, VX>(op.fy + c) : zero;
-            gym = has_s ? f32load<T, VX>(op.fy + c - nx) : zero;
+            // FP32-stored lateral conductances, promoted (loads as above)
+            const Vec<float, VX> fxp = vload<float, VX>(op.fx + c);
+            const Vec<float, VX> fyp = vload<float, VX>(op.fy + c);
+            const Vec<float, VX> fym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
+            const float fxl = op.fx[has_l ? c - 1 : c];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                gxp.a[e] = act ? (T)fxp.a[e] : T(0);
+                gyp.a[e] = act ? (T)fyp.a[e] : T(0);
+                gym.a[e] = has_s ? (T)fym.a[e] : T(0);
+            }
+            const T west = has_l ? (T)fxl : T(0);
             gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-            if (ln.lane == 0) gxl = has_l ? (T)op.fx[c - 1] : T(0);
+            gxl = ln.lane == 0 ? west : gxl;
         } else if constexpr (PC) {
             gxp = act ? vload<T, VX>(op.gx + c) : zero;
             gyp = act ? vload<T, VX>(op.gy + c) : zero;
@@ -361,7 +384,7 @@ __device__ __forceinline__ bool conv_test(CgState<T> *st, const T *part_in, int 
 // ---------------------------------------------------- batched Chebyshev sweep
 template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, bool H16>
 __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__ probs, int nprob,
-                                                int j, int zin, const T *__restrict__ part_in,
+                                                int j, int zsel, const T *__restrict__ part_in,
                                                 int red, T *__restrict__ part_out) {
     const int slot = xcd_slot();
     const int pidx = find_prob(probs, nprob, slot);
@@ -380,8 +403,8 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
     const OpView<T> op = P.op;
     const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     const T *__restrict__ r = P.r;
-    const T *__restrict__ z = P.z[zin];
-    T *zo = P.z[1 - zin];
+    const T *__restrict__ z = P.z[zsel & 3];
+    T *zo = P.z[zsel >> 2];
     T acc[1] = {T(0)};
     auto XV = [&](int64_t q) -> Vec<T, VX> {
         if constexpr (MODE == 1) {
@@ -424,6 +447,175 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
                           vstore<T, VX>(zo + c, zn);
                       });
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
+}
+
+// ------------------------------------------- fused pair of Chebyshev sweeps
+// Sweeps j and j+1 of the two-term recurrence in one pass over HBM (temporal
+// blocking, possible because every sweep's constants are fixed in advance):
+//   z_{j+1} = z_j + c1_j (z_j - z_{j-1}) + c2_j (r - A z_j)
+//   z_{j+2} = z_{j+1} + c1_{j+1} (z_{j+1} - z_j) + c2_{j+1} (r - A z_{j+1})
+// A workgroup owns R whole grid rows (wavefront w holds row slot w / wpr and x
+// segment w % wpr) and a chunk of layers.  Stage A marches up through the chunk
+// plus one halo layer below and above, computing z_{j+1} on the R rows plus one
+// halo row on each side into a ring of three layers in LDS; stage B, one layer
+// behind, computes z_{j+2} on the R rows with every neighbour of z_{j+1} from the
+// ring (x and y) or from registers (z).  Halo rows and layers are recomputed by
+// the neighbouring workgroups with the same arithmetic.  One barrier per layer:
+// stage A of layer l writes ring slot l % 3 while stage B of layer l - 1 (other
+// wavefronts) reads slot (l - 1) % 3, and slot (l + 1) % 3 was last read before
+// the previous barrier.
+template <typename T, bool PC, int VX>
+__global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                                  int j, int zsel, int R, int zcf, int wpr) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *ring = reinterpret_cast<T *>(lds_raw);
+    const int slot = xcd_slot();
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].f_tile0 <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    const InnerProb<T> &P = probs[lo];
+    if (P.st->done) return;   // the same for every wavefront of the workgroup
+    const OpView<T> op = P.op;
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const int ntzf = (nz + zcf - 1) / zcf;
+    const int local = slot - P.f_tile0;
+    const int tz = local % ntzf, ty = local / ntzf;
+    const int lane = threadIdx.x, w = threadIdx.y, rs = w / wpr, sg = w % wpr;
+    const int W = wpr * kWave * VX;            // ring row length (cells)
+    const int RR = R + 2;                      // ring rows
+    const int xo = (sg * kWave + lane) * VX;   // x of this lane's first cell
+    const int jr = ty * R - 1 + rs;            // grid row of this wavefront
+    const bool act = jr >= 0 && jr < ny && xo < nx;
+    const bool inner = act && rs >= 1 && rs <= R;
+    const int l0 = tz * zcf, l1 = min(nz, l0 + zcf);
+    const int la0 = max(0, l0 - 1), la1 = min(nz, l1 + 1);
+    const bool has_l = act && xo > 0, has_r = act && xo + VX < nx;
+    const bool has_s = act && jr > 0, has_n = act && jr < ny - 1;
+    const T c1a = P.cheb[1 + j], c2a = P.cheb[1 + P.kcap + j];
+    const T c1b = P.cheb[2 + j], c2b = P.cheb[2 + P.kcap + j];
+    const T *__restrict__ zN = P.z[zsel & 3];
+    const T *__restrict__ zP = P.z[(zsel >> 2) & 3];
+    T *__restrict__ zX = P.z[(zsel >> 4) & 3];
+    T *__restrict__ zY = P.z[(zsel >> 6) & 3];
+    const T *__restrict__ r = P.r;
+    const Vec<T, VX> zero = vzero<T, VX>();
+    auto ring_at = [&](int l, int row) -> T * { return ring + ((size_t)((l % 3) * RR + row)) * W; };
+
+    int64_t c = act ? xo + (int64_t)nx * jr + plane * la0 : 0;
+    Vec<T, VX> xdn = (act && la0 > 0) ? vload<T, VX>(zN + c - plane) : zero;
+    Vec<T, VX> xc = act ? vload<T, VX>(zN + c) : zero;
+    // previous layer's values kept for stage B
+    Vec<T, VX> zA_m1 = zero, zA_m2 = zero, r_m1 = zero, zj_m1 = zero, gxp_m1 = zero,
+               gyp_m1 = zero, gym_m1 = zero;
+    T gxl_m1 = T(0);
+    for (int l = la0; l <= la1; ++l, c += plane) {
+        const bool doA = l < la1;
+        Vec<T, VX> zn = zero, rv = zero, gxp = zero, gyp = zero, gym = zero, xup = zero;
+        T gxl = T(0);
+        if (doA) {
+            // ---- stage A: z_{j+1} at layer l
+            const LayerCoef<T> L = op.lc[l];
+            xup = (act && l + 1 < nz) ? vload<T, VX>(zN + c + plane) : zero;
+            const Vec<T, VX> xso = has_s ? vload<T, VX>(zN + c - nx) : zero;
+            const Vec<T, VX> xno = has_n ? vload<T, VX>(zN + c + nx) : zero;
+            T left = __shfl_up(xc.a[VX - 1], 1, 64);
+            T right = __shfl_down(xc.a[0], 1, 64);
+            if (lane == 0) left = has_l ? zN[c - 1] : T(0);
+            if (lane == kWave - 1) right = has_r ? zN[c + VX] : T(0);
+            if constexpr (PC) {
+                gxp = act ? vload<T, VX>(op.gx + c) : zero;
+                gyp = act ? vload<T, VX>(op.gy + c) : zero;
+                gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+                gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+                if (lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
+            }
+            rv = act ? vload<T, VX>(r + c) : zero;
+            const Vec<T, VX> zm = act ? vload<T, VX>(zP + c) : zero;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const int i = xo + e;
+                const T x = xc.a[e];
+                const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
+                const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
+                T gm, gp, gs, gn;
+                if constexpr (PC) {
+                    gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                    gp = gxp.a[e];
+                    gs = gym.a[e];
+                    gn = gyp.a[e];
+                } else {
+                    gm = gp = L.gx;
+                    gs = gn = L.gy;
+                }
+                T a = L.sink * x;
+                if (i > 0) a += gm * (x - xl);
+                if (i < nx - 1) a += gp * (x - xr);
+                if (jr > 0) a += gs * (x - xso.a[e]);
+                if (jr < ny - 1) a += gn * (x - xno.a[e]);
+                if (l > 0) a += L.gzd * (x - xdn.a[e]);
+                if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
+                zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * (rv.a[e] - a) : T(0);
+            }
+            if (xo < W) vstore<T, VX>(ring_at(l, rs) + xo, zn);
+            if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
+        }
+        __syncthreads();
+        // ---- stage B: z_{j+2} at layer lb = l - 1
+        const int lb = l - 1;
+        if (inner && lb >= l0 && lb < l1) {
+            const LayerCoef<T> L = op.lc[lb];
+            const T *rowc = ring_at(lb, rs);
+            const Vec<T, VX> so = vload<T, VX>(ring_at(lb, rs - 1) + xo);
+            const Vec<T, VX> no = vload<T, VX>(ring_at(lb, rs + 1) + xo);
+            const T left = has_l ? rowc[xo - 1] : T(0);
+            const T right = has_r ? rowc[xo + VX] : T(0);
+            const Vec<T, VX> &y = zA_m1;
+            Vec<T, VX> z2;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const int i = xo + e;
+                const T x = y.a[e];
+                const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
+                const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
+                T gm, gp, gs, gn;
+                if constexpr (PC) {
+                    gm = (e == 0) ? gxl_m1 : gxp_m1.a[e > 0 ? e - 1 : 0];
+                    gp = gxp_m1.a[e];
+                    gs = gym_m1.a[e];
+                    gn = gyp_m1.a[e];
+                } else {
+                    gm = gp = L.gx;
+                    gs = gn = L.gy;
+                }
+                T a = L.sink * x;
+                if (i > 0) a += gm * (x - xl);
+                if (i < nx - 1) a += gp * (x - xr);
+                if (jr > 0) a += gs * (x - so.a[e]);
+                if (jr < ny - 1) a += gn * (x - no.a[e]);
+                if (lb > 0) a += L.gzd * (x - zA_m2.a[e]);
+                if (lb < nz - 1) a += L.gzu * (x - zn.a[e]);
+                z2.a[e] = x + c1b * (x - zj_m1.a[e]) + c2b * (r_m1.a[e] - a);
+            }
+            vstore<T, VX>(zY + c - plane, z2);
+        }
+        // shift the layer registers
+        zA_m2 = zA_m1;
+        zA_m1 = zn;
+        r_m1 = rv;
+        zj_m1 = xc;
+        gxp_m1 = gxp;
+        gyp_m1 = gyp;
+        gym_m1 = gym;
+        gxl_m1 = gxl;
+        if (doA) {
+            xdn = xc;
+            xc = xup;
+        }
+    }
 }
 
 // Single-pass preconditioners, partials of r^T z:
@@ -1072,6 +1264,15 @@ void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h
                                                                  part_out, s)));
 }
 
+template <typename T>
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int R, int zc,
+                    int wpr, int j, int zsel, hipStream_t s) {
+    const dim3 g(nb), b(kWave, wpr * (R + 2));
+    const size_t lds = (size_t)3 * (R + 2) * wpr * kWave * vx * sizeof(T);
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb2_b<T, PC, VX>), g, b, lds, s, probs,
+                                                       nprob, j, zsel, R, zc, wpr)));
+}
+
 template <typename T, bool PC, int VX, int PM>
 static void scale_chk(const InnerProb<T> *probs, int nprob, int nb, int by, bool chk,
                       const T *part_in, bool red, T *part_out, hipStream_t s) {
@@ -1249,6 +1450,8 @@ CUTH_INST(float)
 CUTH_INST(double)
 #undef CUTH_INST
 
+template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, int, int, int, int,
+                                    int, int, hipStream_t);
 template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
                                          hipStream_t);
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,

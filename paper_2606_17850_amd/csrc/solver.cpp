@@ -106,16 +106,21 @@ Status sync_stream(hipStream_t s) {
 }
 
 template <typename T>
-Status alloc_work(Work<T> &w, int64_t N) {
-    if (w.ready()) return Status::ok();
-    T **ps[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
-    for (T **p : ps) CUTH_TRY(dev_alloc(p, (size_t)N));
+Status alloc_work(Work<T> &w, int64_t N, bool extra_z = false) {
+    if (!w.ready()) {
+        T **ps[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
+        for (T **p : ps) CUTH_TRY(dev_alloc(p, (size_t)N));
+    }
+    if (extra_z && !w.zC) {
+        CUTH_TRY(dev_alloc(&w.zC, (size_t)N));
+        CUTH_TRY(dev_alloc(&w.zD, (size_t)N));
+    }
     return Status::ok();
 }
 
 template <typename T>
 void free_work(Work<T> &w) {
-    T **ps[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
+    T **ps[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB, &w.zC, &w.zD};
     for (T **p : ps) dev_free(*p);
 }
 
@@ -181,11 +186,22 @@ struct Bytes {
     double update() const { return 6.0 * sizeof(T); }
     double check() const { return 3.0 * sizeof(T) + coef; }
     double scale() const { return 2.0 * sizeof(T); }
-    double precond(int k, int pm = 0) const {
+    // a fused pair of general sweeps: z_j, z_{j-1}, r (+ conductances) read once,
+    // z_{j+1} and z_{j+2} written
+    double pair() const { return 5.0 * sizeof(T) + coef_sw; }
+    double precond(int k, int pm = 0, bool fuse = false) const {
         if (pm == 1) return scale() + coef;   // Jacobi: also the lateral conductances
         if (k == 1 || pm == 2) return scale();
         double b = cheb(1);
-        for (int j = 2; j < k; ++j) b += cheb(j == 2 ? 2 : 0);
+        for (int j = 2; j < k;) {
+            if (fuse && j >= 3 && j + 1 < k - 1) {
+                b += pair();
+                j += 2;
+            } else {
+                b += cheb(j == 2 ? 2 : 0);
+                j += 1;
+            }
+        }
         return b;
     }
 };
@@ -362,7 +378,7 @@ Status upload_cheb(Engine &E, std::vector<Problem *> &ps, hipStream_t s) {
 template <typename T>
 int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vector<int> &which) {
     InnerProb<T> *h = Sel<T>::h(E);
-    int tile = 0, n = 0;
+    int tile = 0, ftile = 0, n = 0;
     which.clear();
     for (size_t i = 0; i < ps.size(); ++i) {
         Problem &p = *ps[i];
@@ -384,6 +400,15 @@ int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vec
         d.p[1] = w.pB;
         d.z[0] = w.zA;
         d.z[1] = w.zB;
+        d.z[2] = w.zC;
+        d.z[3] = w.zD;
+        d.f_tile0 = d.f_ntiles = 0;
+        if (sh.fr > 0) {
+            if (!w.zC || !w.zD) return -1;
+            d.f_tile0 = ftile;
+            d.f_ntiles = tiles_y(p.g->ny, sh.fr) * tiles_z(p.g->nz, sh.fzc);
+            ftile += d.f_ntiles;
+        }
         d.st = Sel<T>::ds(E) + n;
         d.cheb = Sel<T>::dc(E) + i * (1 + 2 * E.kcap);
         d.kcap = E.kcap;
@@ -398,6 +423,41 @@ int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vec
     // the check kernel writes two partials per workgroup into one slot
     if ((size_t)tile * 2 > E.slot_doubles) return -1;
     return tile;
+}
+
+// Packed buffer selection of a sweep: z_j in z[in], result over z[out].
+inline int zsel(int in, int out) { return in + 4 * out; }
+
+// The two of the four z buffers that are neither n nor p.
+inline void free_pair(int n, int p, int &x, int &y) {
+    x = y = -1;
+    for (int b = 0; b < 4; ++b)
+        if (b != n && b != p) {
+            if (x < 0) x = b;
+            else y = b;
+        }
+}
+
+// Buffer that holds z = q(A) r after enqueue_precond (same rotation): mode 1
+// writes z[1]; every single sweep writes over the older of (newest, older);
+// a fused pair writes the two other buffers.
+int precond_final(int k, int pm, bool fuse) {
+    if (k == 1 || pm != 0) return 0;
+    if (k == 2) return 1;
+    int n = 0, p = 1;   // after mode 2
+    for (int j = 3; j < k;) {
+        if (fuse && j + 1 < k - 1) {
+            int x, y;
+            free_pair(n, p, x, y);
+            p = x;
+            n = y;
+            j += 2;
+        } else {
+            std::swap(n, p);
+            j += 1;
+        }
+    }
+    return n;
 }
 
 // Per-problem sums written by launch_reduce_b (red mode): r^T z, p^T A p, r^T r.
@@ -420,24 +480,48 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, con
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
         return 0;
     }
-    launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, 1, k == 2, chk, 1, 0, rr_in, red,
+    launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1), rr_in, red,
                      eslot<T>(E, P_CHEB), s);
-    for (int j = 2; j < k; ++j) {
-        const int mode = (j == 2) ? 2 : 0;
+    // fused pairs: FP32 sweeps reading the operator's own conductances
+    const bool fuse = sizeof(T) == 4 && sh.fr > 0 && !h16;
+    int nbf = 0;
+    if (fuse) {
+        const InnerProb<T> &last = Sel<T>::h(E)[nprob - 1];
+        nbf = last.f_tile0 + last.f_ntiles;
+    }
+    int n = 1, p = 0;   // newest and older iterate after mode 1
+    for (int j = 2; j < k;) {
+        const bool pair = fuse && j >= 3 && j + 1 < k - 1;
         const bool timed = prof && prof->prof && j == 3 && prof->pev_used + 2 <= prof->pev.size();
         if (timed) (void)hipEventRecord(prof->pev[prof->pev_used], s);
-        launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, mode, j == k - 1, false, j, (j - 1) & 1,
-                         rr_in, red, eslot<T>(E, P_CHEB), s);
+        if (pair) {
+            int x, y;
+            free_pair(n, p, x, y);
+            if constexpr (sizeof(T) == 4)
+                launch_cheb2_b<T>(d, nprob, nbf, pc, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
+                                  n + 4 * p + 16 * x + 64 * y, s);
+            p = x;
+            n = y;
+        } else {
+            const int mode = (j == 2) ? 2 : 0;
+            launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, mode, j == k - 1, false, j,
+                             zsel(n, p), rr_in, red, eslot<T>(E, P_CHEB), s);
+            std::swap(n, p);
+        }
         if (timed) {
             (void)hipEventRecord(prof->pev[prof->pev_used + 1], s);
             if (prof->pev_tag.size() < prof->pev.size() / 2) prof->pev_tag.resize(prof->pev.size() / 2);
             prof->pev_tag[prof->pev_used / 2] = tag;
             prof->pev_used += 2;
-            prof->prof_bytes = Bytes<T>(pc, h16).cheb(0) * (double)prof->N;
+            // a fused pair reads z_j, z_{j-1}, r (+ gx, gy) once and writes two iterates
+            const Bytes<T> by(pc, h16);
+            prof->prof_bytes = (pair ? by.pair() : by.cheb(0)) * (double)prof->N;
+            prof->prof_fused = pair;
         }
+        j += pair ? 2 : 1;
     }
     if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
-    return (k - 1) & 1;
+    return n;
 }
 
 template <typename T>
@@ -577,7 +661,8 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
         p.cg_iters += iters;
         p.reason = reason;
-        p.bytes += precs_run * by.precond(k, p.pm) * N + iters * (by.dir() + by.update()) * N +
+        const bool fused = sizeof(T) == 4 && sh.fr > 0 && !p.h16;
+        p.bytes += precs_run * by.precond(k, p.pm, fused) * N + iters * (by.dir() + by.update()) * N +
                    nchecks * by.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
         p.last_red = p.rr0 > 0 ? std::sqrt(p.true_rr / p.rr0) : 0.0;
@@ -803,7 +888,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
     bool red = false;
     const int above = reduce_above();
     for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
-    const int zfin32 = (k == 1 || pm != 0) ? 0 : (k - 1) & 1;
+    const int zfin32 = precond_final(k, pm, sh32.fr > 0 && !h16);
     InnerProb<double> *h64 = E.h_in64;
     for (int n = 0; n < nprob; ++n) {
         Problem &p = *ps[which[n]];
@@ -1020,6 +1105,32 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
         else lo = mid;
     }
     return 0.5 * (lo + hi);
+}
+
+// CUTH_FUSE=1: run the general FP32 Chebyshev sweeps as fused pairs;
+// CUTH_FUSE_SHAPE="R,zc" rows and layers per workgroup (default 2,8).  A
+// workgroup holds R + 2 rows of whole-row wavefronts (at most 16) and a ring of
+// three layers of them in LDS (at most 64 KB); grids too wide for that keep
+// single sweeps.
+void set_fuse(Shape &sh, int max_nx) {
+    sh.fr = 0;
+    const char *e = std::getenv("CUTH_FUSE");
+    if (!e || e[0] != '1') return;
+    int R = 2, zc = 8;
+    if (const char *f = std::getenv("CUTH_FUSE_SHAPE")) {
+        int a = 0, b = 0;
+        if (std::sscanf(f, "%d,%d", &a, &b) == 2 && a >= 1 && a <= 14 && b >= 1) {
+            R = a;
+            zc = b;
+        }
+    }
+    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
+    auto lds = [&](int r) { return (size_t)3 * (r + 2) * wpr * kWave * sh.vx * sizeof(float); };
+    while (R > 1 && (wpr * (R + 2) > 16 || lds(R) > 65536)) --R;
+    if (wpr * (R + 2) > 16 || lds(R) > 65536) return;
+    sh.fr = R;
+    sh.fzc = zc;
+    sh.fwpr = wpr;
 }
 
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
@@ -1456,7 +1567,13 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     std::vector<Problem *> ps{&p};
     const int period = o.check_period > 0 ? o.check_period : (transient_defaults ? 5 : 20);
     const bool use_graph = graph_env() == 1 && !g.prof;
-    Status rs = run_set(g.eng, ps, g.stream, g.sh32, g.sh64, o, period, use_graph, &g);
+    Shape sh32 = g.sh32;
+    set_fuse(sh32, g.nx);
+    if (sh32.fr > 0) {
+        CUTH_TRY(alloc_work(g.w32, g.N, true));
+        p.w32 = g.w32;
+    }
+    Status rs = run_set(g.eng, ps, g.stream, sh32, g.sh64, o, period, use_graph, &g);
     if (rs.code == CUTH_E_DEVICE || rs.code == CUTH_E_NOMEM) return rs;
     CUTH_HIP(hipEventRecord(g.ev2, g.stream));
     CUTH_TRY(sync_stream(g.stream));
@@ -1547,11 +1664,12 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
         CUTH_HIP(hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s));
         const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
         for (int rep = 0; rep < 2; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, 1,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, zsel(1, 0),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 6; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, rep & 1,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2,
+                             zsel(rep & 1, 1 - (rep & 1)),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e1, s));
         CUTH_TRY(sync_stream(s));
@@ -1609,7 +1727,10 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         for (int s : sys) ntot += grids[s]->N * nrhs;
         float *pool32 = nullptr;
         double *pool64 = nullptr, *poolth = nullptr;
-        const int nvec = 8;
+        // FP32 pools hold two more iterates when general sweeps run as fused pairs
+        const bool fuse32 = (mixed || staged) && std::getenv("CUTH_FUSE") &&
+                            std::getenv("CUTH_FUSE")[0] == '1';
+        const int nvec = fuse32 ? 10 : 8;
         Status st;
         if ((st = dev_alloc(&poolth, (size_t)ntot * 2)).bad()) return st;
         if (mixed || staged) st = dev_alloc(&pool32, (size_t)ntot * nvec);
@@ -1644,13 +1765,13 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                 const int64_t N = g.N;
                 auto carve32 = [&](Work<float> &w) {
                     float *b = pool32 + off * nvec;
-                    float **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
+                    float **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB, &w.zC, &w.zD};
                     for (int i = 0; i < nvec; ++i) *v[i] = b + (int64_t)i * N;
                 };
                 auto carve64 = [&](Work<double> &w) {
                     double *b = pool64 + off * nvec;
                     double **v[] = {&w.x, &w.r, &w.rhat, &w.pA, &w.pB, &w.mu, &w.zA, &w.zB};
-                    for (int i = 0; i < nvec; ++i) *v[i] = b + (int64_t)i * N;
+                    for (int i = 0; i < 8; ++i) *v[i] = b + (int64_t)i * N;
                 };
                 if (mixed || staged) carve32(p.w32);
                 if (!mixed) carve64(p.w64);
@@ -1690,6 +1811,11 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                         ? autotune<float>(E, ps, o.cheb_degree, sig.str() + " in", sh_in)
                         : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
         if (!mixed && !staged) sh64 = sh_in;
+        if (fuse32) {
+            int max_nx = 1;
+            for (Problem *p : ps) max_nx = std::max(max_nx, p->g->nx);
+            set_fuse(sh_in, max_nx);
+        }
         if (!ts.bad()) {
             const int period = o.check_period > 0 ? o.check_period : 20;
             const bool use_graph = graph_env() != 0;
@@ -1755,19 +1881,22 @@ Status residual(Grid &g, double dt, const double *b, const double *T, double *r)
 template <typename T>
 static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, const ChebConsts &cc,
                             bool h16, const T *r, T *z) {
-    // the result lands in z[0] for k == 1 or odd k, in z[1] for even k >= 2
+    // the result lands in the buffer the sweep rotation ends in (fused pairs
+    // exactly where enqueue_precond uses them: FP32, no FP16 planes in use)
     Engine &E = g.eng;
-    const int zfin = cc.k == 1 ? 0 : (cc.k - 1) & 1;
+    const bool h16e = h16 && g.per_cell;
+    const bool fuse = sizeof(T) == 4 && sh.fr > 0 && !h16e;
+    const int zfin = precond_final(cc.k, 0, fuse);
     Problem p;
     p.g = &g;
     p.su = &su;
     p.cc = cc;
-    p.h16 = h16 && g.per_cell;
+    p.h16 = h16e;
     Work<T> &pw = Sel<T>::w(p);
     pw = w;
     pw.r = const_cast<T *>(r);
-    if (zfin == 0) pw.zA = z;
-    else pw.zB = z;
+    T **zs[4] = {&pw.zA, &pw.zB, &pw.zC, &pw.zD};
+    *zs[zfin] = z;
     p.inner = true;
     std::vector<Problem *> ps{&p};
     std::vector<int> which;
@@ -1793,9 +1922,13 @@ Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
     const ChebConsts cc = make_cheb(lmin, lmax, degree);
-    if (precision != CUTH_FP64)
-        return precond_typed<float>(g, *su, g.w32, g.sh32, cc, precision == CUTH_MIXED16,
+    if (precision != CUTH_FP64) {
+        Shape sh32 = g.sh32;
+        set_fuse(sh32, g.nx);
+        if (sh32.fr > 0) CUTH_TRY(alloc_work(g.w32, g.N, true));
+        return precond_typed<float>(g, *su, g.w32, sh32, cc, precision == CUTH_MIXED16,
                                     (const float *)r, (float *)z);
+    }
     CUTH_TRY(alloc_work(g.w64, g.N));
     return precond_typed<double>(g, *su, g.w64, g.sh64, cc, false, (const double *)r, (double *)z);
 }
