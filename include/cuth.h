@@ -244,14 +244,16 @@ cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t steps, const fl
 cuth_status cuth_grid_reset_bounds(cuth_grid g);
 
 /* Kernel timing for measurement.  When on, each preconditioner application
- * brackets its first general Chebyshev sweep with HIP events on the handle's
- * stream; cuth_profile_read returns the summed duration (ms), the number of
- * timed launches and the algorithmic bytes of one such launch (N times the
- * bytes per unknown of the sweep).  Enabling resets the counters and
+ * brackets its first launch of general Chebyshev sweeps (one sweep, or a fused
+ * pair of sweeps) with HIP events on the handle's stream; cuth_profile_read
+ * returns the summed duration (ms), the number of timed launches, the
+ * algorithmic bytes of one such launch (N times the bytes per unknown) and
+ * whether the timed launches were fused pairs (*fused 1) or single sweeps (0).
+ * Any output pointer may be NULL.  Enabling resets the counters and
  * synchronises the stream. */
 cuth_status cuth_profile_enable(cuth_grid g, int32_t on);
 cuth_status cuth_profile_read(cuth_grid g, double *total_ms, int64_t *launches,
-                              double *bytes_per_launch);
+                              double *bytes_per_launch, int32_t *fused);
 
 #ifdef __cplusplus
 }

@@ -228,10 +228,11 @@ class Grid:
         _check(library().cuth_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self) -> dict:
-        ms, cnt, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        ms, cnt, by, fu = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
         _check(library().cuth_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
-                                           ctypes.byref(by)))
-        return {"total_ms": ms.value, "launches": cnt.value, "bytes_per_launch": by.value}
+                                           ctypes.byref(by), ctypes.byref(fu)))
+        return {"total_ms": ms.value, "launches": cnt.value, "bytes_per_launch": by.value,
+                "fused": bool(fu.value)}
 
     def spectral_bounds(self, dt: float = 0.0, steps: int = 30,
                         v0: Optional[torch.Tensor] = None) -> dict:

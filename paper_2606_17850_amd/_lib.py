@@ -103,7 +103,7 @@ def load() -> ctypes.CDLL:
         "cuth_grid_reset_bounds": (ctypes.c_int, [vp]),
         "cuth_profile_enable": (ctypes.c_int, [vp, i32]),
         "cuth_profile_read": (ctypes.c_int, [vp, c_double_p, ctypes.POINTER(ctypes.c_int64),
-                                             c_double_p]),
+                                             c_double_p, ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -317,7 +317,7 @@ cuth_status cuth_profile_enable(cuth_grid h, int32_t on) {
 }
 
 cuth_status cuth_profile_read(cuth_grid h, double *total_ms, int64_t *launches,
-                              double *bytes_per_launch) {
+                              double *bytes_per_launch, int32_t *fused) {
     return guarded([&]() -> cuth_status {
         if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
         cuth::Grid &g = *h->g;
@@ -327,6 +327,7 @@ cuth_status cuth_profile_read(cuth_grid h, double *total_ms, int64_t *launches,
         if (total_ms) *total_ms = g.prof_ms;
         if (launches) *launches = g.prof_count;
         if (bytes_per_launch) *bytes_per_launch = g.prof_bytes;
+        if (fused) *fused = g.prof_fused ? 1 : 0;
         return CUTH_OK;
     });
 }

@@ -149,11 +149,11 @@ void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h
 // written to z[X] and z_{j+2} to z[Y] (four distinct buffers).  A workgroup is
 // R + 2 rows of wpr wavefronts (whole rows of 64*vx*wpr >= nx cells) and a chunk
 // of zc layers; the launch covers the problems' slots [f_tile0, f_tile0 +
-// f_ntiles) with f_ntiles = ceil(ny / R) * ceil(nz / zc).  FP32, coefficients
-// in the operator's own precision.
+// f_ntiles) with f_ntiles = ceil(ny / R) * ceil(nz / zc).  FP32; h16: the
+// FP16-stored lateral conductances (per-cell grids).
 template <typename T>
-void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int R, int zc,
-                    int wpr, int j, int zsel, hipStream_t s);
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                    int zc, int wpr, int j, int zsel, hipStream_t s);
 
 // Single-pass preconditioner into z[0] (same chk/last behaviour as the sweeps):
 // pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r.

@@ -225,6 +225,61 @@ __device__ __forceinline__ Vec<T, VX> f32load(const float *p) {
     return v;
 }
 
+// Lateral conductances of a per-cell operator at cell c of layer L for one
+// lane: gxp, gyp (to +x, +y), gym (from -y) and gxl (from -x, via the lane to the
+// left or a load on lane 0), from the source CS.
+template <typename T, int VX, int CS>
+__device__ __forceinline__ void lateral_coefs(const OpView<T> &op, const LayerCoef<T> &L, int64_t c,
+                                              int lane, bool act, bool has_l, bool has_s,
+                                              Vec<T, VX> &gxp, Vec<T, VX> &gyp, Vec<T, VX> &gym,
+                                              T &gxl) {
+    const int nx = op.nx;
+    const Vec<T, VX> zero = vzero<T, VX>();
+    if constexpr (CS == CS_F16) {
+        // FP16-stored lateral conductances.  Every lane loads from an
+        // in-bounds cell (inactive lanes sit at cell 0, a missing south or
+        // west neighbour falls back to the cell itself), promotes, then
+        // selects: a guarded load with the promotion inside made the
+        // compiler wait for each load in turn.
+        const Vec<uint16_t, VX> bxp = vload<uint16_t, VX>(op.hx + c);
+        const Vec<uint16_t, VX> byp = vload<uint16_t, VX>(op.hy + c);
+        const Vec<uint16_t, VX> bym = vload<uint16_t, VX>(op.hy + (has_s ? c - nx : c));
+        const uint16_t bxl = op.hx[has_l ? c - 1 : c];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            gxp.a[e] = act ? (T)h16one(bxp.a[e]) * L.hs : T(0);
+            gyp.a[e] = act ? (T)h16one(byp.a[e]) * L.hs : T(0);
+            gym.a[e] = has_s ? (T)h16one(bym.a[e]) * L.hs : T(0);
+        }
+        // every lane promotes its west value; lane 0 selects it (a branch
+        // around the promotion would wait for the load)
+        const T west = has_l ? (T)h16one(bxl) * L.hs : T(0);
+        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+        gxl = lane == 0 ? west : gxl;
+    } else if constexpr (CS == CS_F32) {
+        // FP32-stored lateral conductances, promoted (loads as above)
+        const Vec<float, VX> fxp = vload<float, VX>(op.fx + c);
+        const Vec<float, VX> fyp = vload<float, VX>(op.fy + c);
+        const Vec<float, VX> fym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
+        const float fxl = op.fx[has_l ? c - 1 : c];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            gxp.a[e] = act ? (T)fxp.a[e] : T(0);
+            gyp.a[e] = act ? (T)fyp.a[e] : T(0);
+            gym.a[e] = has_s ? (T)fym.a[e] : T(0);
+        }
+        const T west = has_l ? (T)fxl : T(0);
+        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+        gxl = lane == 0 ? west : gxl;
+    } else {
+        gxp = act ? vload<T, VX>(op.gx + c) : zero;
+        gyp = act ? vload<T, VX>(op.gy + c) : zero;
+        gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
+        if (lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
+    }
+}
+
 template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                            FP &&PRE, E &&emit) {
@@ -248,49 +303,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
         Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
-        if constexpr (PC && CS == CS_F16) {
-            // FP16-stored lateral conductances.  Every lane loads from an
-            // in-bounds cell (inactive lanes sit at cell 0, a missing south or
-            // west neighbour falls back to the cell itself), promotes, then
-            // selects: a guarded load with the promotion inside made the
-            // compiler wait for each load in turn.
-            const Vec<uint16_t, VX> bxp = vload<uint16_t, VX>(op.hx + c);
-            const Vec<uint16_t, VX> byp = vload<uint16_t, VX>(op.hy + c);
-            const Vec<uint16_t, VX> bym = vload<uint16_t, VX>(op.hy + (has_s ? c - nx : c));
-            const uint16_t bxl = op.hx[has_l ? c - 1 : c];
-#pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                gxp.a[e] = act ? (T)h16one(bxp.a[e]) * L.hs : T(0);
-                gyp.a[e] = act ? (T)h16one(byp.a[e]) * L.hs : T(0);
-                gym.a[e] = has_s ? (T)h16one(bym.a[e]) * L.hs : T(0);
-            }
-            // every lane promotes its west value; lane 0 selects it (a branch
-            // around the promotion would wait for the load)
-            const T west = has_l ? (T)h16one(bxl) * L.hs : T(0);
-            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-            gxl = ln.lane == 0 ? west : gxl;
-        } else if constexpr (PC && CS == CS_F32) {
-            // FP32-stored lateral conductances, promoted (loads as above)
-            const Vec<float, VX> fxp = vload<float, VX>(op.fx + c);
-            const Vec<float, VX> fyp = vload<float, VX>(op.fy + c);
-            const Vec<float, VX> fym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
-            const float fxl = op.fx[has_l ? c - 1 : c];
-#pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                gxp.a[e] = act ? (T)fxp.a[e] : T(0);
-                gyp.a[e] = act ? (T)fyp.a[e] : T(0);
-                gym.a[e] = has_s ? (T)fym.a[e] : T(0);
-            }
-            const T west = has_l ? (T)fxl : T(0);
-            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-            gxl = ln.lane == 0 ? west : gxl;
-        } else if constexpr (PC) {
-            gxp = act ? vload<T, VX>(op.gx + c) : zero;
-            gyp = act ? vload<T, VX>(op.gy + c) : zero;
-            gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
-            gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-            if (ln.lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
-        }
+        if constexpr (PC) lateral_coefs<T, VX, CS>(op, L, c, ln.lane, act, has_l, has_s, gxp, gyp, gym, gxl);
         Vec<T, VX> ax;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
@@ -464,7 +477,7 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
 // stage A of layer l writes ring slot l % 3 while stage B of layer l - 1 (other
 // wavefronts) reads slot (l - 1) % 3, and slot (l + 1) % 3 was last read before
 // the previous barrier.
-template <typename T, bool PC, int VX>
+template <typename T, bool PC, int VX, int CS>
 __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                   int j, int zsel, int R, int zcf, int wpr) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -526,13 +539,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             T right = __shfl_down(xc.a[0], 1, 64);
             if (lane == 0) left = has_l ? zN[c - 1] : T(0);
             if (lane == kWave - 1) right = has_r ? zN[c + VX] : T(0);
-            if constexpr (PC) {
-                gxp = act ? vload<T, VX>(op.gx + c) : zero;
-                gyp = act ? vload<T, VX>(op.gy + c) : zero;
-                gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
-                gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-                if (lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
-            }
+            if constexpr (PC)
+                lateral_coefs<T, VX, CS>(op, L, c, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
             rv = act ? vload<T, VX>(r + c) : zero;
             const Vec<T, VX> zm = act ? vload<T, VX>(zP + c) : zero;
 #pragma unroll
@@ -1265,12 +1273,17 @@ void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h
 }
 
 template <typename T>
-void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int R, int zc,
-                    int wpr, int j, int zsel, hipStream_t s) {
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                    int zc, int wpr, int j, int zsel, hipStream_t s) {
     const dim3 g(nb), b(kWave, wpr * (R + 2));
     const size_t lds = (size_t)3 * (R + 2) * wpr * kWave * vx * sizeof(T);
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb2_b<T, PC, VX>), g, b, lds, s, probs,
-                                                       nprob, j, zsel, R, zc, wpr)));
+    if (pc && h16) {
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb2_b<T, true, VX, CS_F16>), g, b, lds, s,
+                                                    probs, nprob, j, zsel, R, zc, wpr)));
+        return;
+    }
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb2_b<T, PC, VX, CS_OWN>), g, b, lds, s,
+                                                       probs, nprob, j, zsel, R, zc, wpr)));
 }
 
 template <typename T, bool PC, int VX, int PM>
@@ -1450,8 +1463,8 @@ CUTH_INST(float)
 CUTH_INST(double)
 #undef CUTH_INST
 
-template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, int, int, int, int,
-                                    int, int, hipStream_t);
+template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, bool, int, int, int,
+                                    int, int, int, hipStream_t);
 template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
                                          hipStream_t);
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,

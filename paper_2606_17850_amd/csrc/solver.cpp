@@ -482,8 +482,8 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, con
     }
     launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1), rr_in, red,
                      eslot<T>(E, P_CHEB), s);
-    // fused pairs: FP32 sweeps reading the operator's own conductances
-    const bool fuse = sizeof(T) == 4 && sh.fr > 0 && !h16;
+    // fused pairs of general sweeps (FP32)
+    const bool fuse = sizeof(T) == 4 && sh.fr > 0;
     int nbf = 0;
     if (fuse) {
         const InnerProb<T> &last = Sel<T>::h(E)[nprob - 1];
@@ -498,7 +498,7 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, con
             int x, y;
             free_pair(n, p, x, y);
             if constexpr (sizeof(T) == 4)
-                launch_cheb2_b<T>(d, nprob, nbf, pc, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
+                launch_cheb2_b<T>(d, nprob, nbf, pc, h16, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
                                   n + 4 * p + 16 * x + 64 * y, s);
             p = x;
             n = y;
@@ -661,7 +661,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
         p.cg_iters += iters;
         p.reason = reason;
-        const bool fused = sizeof(T) == 4 && sh.fr > 0 && !p.h16;
+        const bool fused = sizeof(T) == 4 && sh.fr > 0;
         p.bytes += precs_run * by.precond(k, p.pm, fused) * N + iters * (by.dir() + by.update()) * N +
                    nchecks * by.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
@@ -888,7 +888,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
     bool red = false;
     const int above = reduce_above();
     for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
-    const int zfin32 = precond_final(k, pm, sh32.fr > 0 && !h16);
+    const int zfin32 = precond_final(k, pm, sh32.fr > 0);
     InnerProb<double> *h64 = E.h_in64;
     for (int n = 0; n < nprob; ++n) {
         Problem &p = *ps[which[n]];
@@ -1107,15 +1107,34 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
     return 0.5 * (lo + hi);
 }
 
-// CUTH_FUSE=1: run the general FP32 Chebyshev sweeps as fused pairs;
-// CUTH_FUSE_SHAPE="R,zc" rows and layers per workgroup (default 2,8).  A
-// workgroup holds R + 2 rows of whole-row wavefronts (at most 16) and a ring of
-// three layers of them in LDS (at most 64 KB); grids too wide for that keep
-// single sweeps.
+// Fused pairs of general FP32 Chebyshev sweeps: CUTH_FUSE=0 never, CUTH_FUSE=1
+// always (shape CUTH_FUSE_SHAPE="R,zc", default 2,8), unset: chosen per grid by
+// timing (tune_fuse).  A workgroup holds R + 2 rows of whole-row wavefronts (at
+// most 16) and a ring of three layers of them in LDS (at most 64 KB); grids too
+// wide for that keep single sweeps.
+int fuse_env() {
+    const char *e = std::getenv("CUTH_FUSE");
+    if (!e) return -1;
+    return e[0] == '0' ? 0 : 1;
+}
+
+// Fit fused shape (R, zc) to rows of max_nx cells; false when it cannot fit.
+bool fuse_fit(Shape &sh, int max_nx, int R, int zc) {
+    sh.fr = 0;
+    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
+    auto lds = [&](int r) { return (size_t)3 * (r + 2) * wpr * kWave * sh.vx * sizeof(float); };
+    while (R > 1 && (wpr * (R + 2) > 16 || lds(R) > 65536)) --R;
+    if (R < 1 || wpr * (R + 2) > 16 || lds(R) > 65536) return false;
+    sh.fr = R;
+    sh.fzc = zc;
+    sh.fwpr = wpr;
+    return true;
+}
+
+// Shape forced from the environment (CUTH_FUSE=1), or no fusion.
 void set_fuse(Shape &sh, int max_nx) {
     sh.fr = 0;
-    const char *e = std::getenv("CUTH_FUSE");
-    if (!e || e[0] != '1') return;
+    if (fuse_env() != 1) return;
     int R = 2, zc = 8;
     if (const char *f = std::getenv("CUTH_FUSE_SHAPE")) {
         int a = 0, b = 0;
@@ -1124,13 +1143,7 @@ void set_fuse(Shape &sh, int max_nx) {
             zc = b;
         }
     }
-    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
-    auto lds = [&](int r) { return (size_t)3 * (r + 2) * wpr * kWave * sh.vx * sizeof(float); };
-    while (R > 1 && (wpr * (R + 2) > 16 || lds(R) > 65536)) --R;
-    if (wpr * (R + 2) > 16 || lds(R) > 65536) return;
-    sh.fr = R;
-    sh.fzc = zc;
-    sh.fwpr = wpr;
+    (void)fuse_fit(sh, max_nx, R, zc);
 }
 
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
@@ -1476,6 +1489,9 @@ Status ensure_bounds(Grid &g, Setup &su, int steps) {
 
 namespace {
 
+template <typename T>
+Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const std::string &sig);
+
 double default_tol(const cuth_options &o, double dt) {
     // tol == 0 selects the default of the precision: mixed, relative rise error
     // 1e-8; FP64, relative residual 1e-10 (steady) or 1e-12 (transient, where
@@ -1568,10 +1584,16 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     const int period = o.check_period > 0 ? o.check_period : (transient_defaults ? 5 : 20);
     const bool use_graph = graph_env() == 1 && !g.prof;
     Shape sh32 = g.sh32;
-    set_fuse(sh32, g.nx);
-    if (sh32.fr > 0) {
+    if (o.precision != CUTH_FP64 && fuse_env() != 0) {
+        // fused pairs of general sweeps where they are faster on this grid
         CUTH_TRY(alloc_work(g.w32, g.N, true));
         p.w32 = g.w32;
+        std::ostringstream sig;
+        sig << "single " << g.nx << 'x' << g.ny << 'x' << g.nz << (g.per_cell ? " pc" : " mf")
+            << (p.h16 && g.per_cell ? "16" : "") << ' ' << g.sh32.vx << ',' << g.sh32.by << ','
+            << g.sh32.zc;
+        const int kk = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+        CUTH_TRY(tune_fuse<float>(g.eng, ps, kk, sh32, sig.str()));
     }
     Status rs = run_set(g.eng, ps, g.stream, sh32, g.sh64, o, period, use_graph, &g);
     if (rs.code == CUTH_E_DEVICE || rs.code == CUTH_E_NOMEM) return rs;
@@ -1695,6 +1717,103 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
     return Status::ok();
 }
 
+// Fused pairs or single sweeps for these problems (FP32 general sweeps): the
+// environment decides if it says so (fuse_env), else the faster of four single
+// sweeps and two fused pairs per candidate shape, timed on the problems
+// themselves and cached per signature.  Needs the four iterate buffers.
+template <typename T>
+Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const std::string &sig) {
+    sh.fr = 0;
+    if (sizeof(T) != 4 || ps.empty()) return Status::ok();
+    const int fe = fuse_env();
+    int max_nx = 1;
+    for (Problem *p : ps) max_nx = std::max(max_nx, p->g->nx);
+    if (fe == 0) return Status::ok();
+    if (fe == 1) {
+        set_fuse(sh, max_nx);
+        return Status::ok();
+    }
+    if (k < 6 || ps[0]->pm != 0) return Status::ok();   // no pair of general sweeps
+    for (Problem *p : ps)
+        if (!Sel<T>::w(*p).zC || !Sel<T>::w(*p).zD) return Status::ok();
+    const std::string key = sig + " fuse";
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            if (it->second.fr > 0) (void)fuse_fit(sh, max_nx, it->second.fr, it->second.fzc);
+            return Status::ok();
+        }
+    }
+    const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
+    const int cand[][2] = {{0, 0}, {2, 8}, {4, 8}, {2, 16}, {4, 4}, {1, 16}};
+    const hipStream_t s = E.own;
+    hipEvent_t e0, e1;
+    CUTH_HIP(hipEventCreate(&e0));
+    CUTH_HIP(hipEventCreate(&e1));
+    for (Problem *p : ps) p->inner = true;
+    float best_ms = INFINITY;
+    Shape best = sh;
+    best.fr = 0;
+    Status st = Status::ok();
+    for (const auto &cd : cand) {
+        Shape c = sh;
+        c.fr = 0;
+        if (cd[0] > 0 && !fuse_fit(c, max_nx, cd[0], cd[1])) continue;
+        std::vector<int> which;
+        const int nb = build_inner<T>(E, ps, c, which);
+        if (nb < 0) continue;
+        const int n = (int)which.size();
+        const InnerProb<T> &last = Sel<T>::h(E)[n - 1];
+        const int nbf = last.f_tile0 + last.f_ntiles;
+        if (hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * n,
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s) != hipSuccess) {
+            st = Status::err(CUTH_E_DEVICE, "tune_fuse: upload failed");
+            break;
+        }
+        auto round = [&]() {
+            if (c.fr == 0) {
+                for (int q = 0; q < 4; ++q)
+                    launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, c.vx, c.by, 0, false, false, 3,
+                                     zsel(q & 1, 1 - (q & 1)), eslot<T>(E, P_UPD), false,
+                                     eslot<T>(E, P_CHEB), s);
+            } else {
+                if constexpr (sizeof(T) == 4) {
+                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, c.vx, c.fr, c.fzc, c.fwpr, 3,
+                                      0 + 4 * 1 + 16 * 2 + 64 * 3, s);
+                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, c.vx, c.fr, c.fzc, c.fwpr, 3,
+                                      3 + 4 * 2 + 16 * 0 + 64 * 1, s);
+                }
+            }
+        };
+        round();
+        (void)hipEventRecord(e0, s);
+        for (int rep = 0; rep < 3; ++rep) round();
+        (void)hipEventRecord(e1, s);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            st = Status::err(CUTH_E_DEVICE, "tune_fuse: timing launch failed");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (log_on())
+            std::fprintf(stderr, "cuth: fuse %d,%d %.3f ms per 4 sweeps\n", c.fr, c.fzc, ms / 3);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    for (Problem *p : ps) p->inner = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st.bad()) return st;
+    sh = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    return Status::ok();
+}
+
 }  // namespace
 
 Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
@@ -1728,8 +1847,7 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         float *pool32 = nullptr;
         double *pool64 = nullptr, *poolth = nullptr;
         // FP32 pools hold two more iterates when general sweeps run as fused pairs
-        const bool fuse32 = (mixed || staged) && std::getenv("CUTH_FUSE") &&
-                            std::getenv("CUTH_FUSE")[0] == '1';
+        const bool fuse32 = (mixed || staged) && fuse_env() != 0;
         const int nvec = fuse32 ? 10 : 8;
         Status st;
         if ((st = dev_alloc(&poolth, (size_t)ntot * 2)).bad()) return st;
@@ -1791,9 +1909,9 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         for (Problem *p : ps)
             nb_max += (size_t)tiles_x(p->g->nx, 1) * p->g->ny * tiles_z(p->g->nz, 4);
         Engine E;
-        // the autotuner's timed sweep reads the constants of sweep j = 2, so the
-        // constant rows hold at least 3 sweeps whatever the degree
-        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 3), nb_max)).bad()) {
+        // the tuners' timed sweeps read the constants of sweeps up to j = 4, so
+        // the constant rows hold at least 5 sweeps whatever the degree
+        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 5), nb_max)).bad()) {
             engine_free(E);
             dev_free(pool32);
             dev_free(pool64);
@@ -1811,10 +1929,10 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                         ? autotune<float>(E, ps, o.cheb_degree, sig.str() + " in", sh_in)
                         : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
         if (!mixed && !staged) sh64 = sh_in;
-        if (fuse32) {
-            int max_nx = 1;
-            for (Problem *p : ps) max_nx = std::max(max_nx, p->g->nx);
-            set_fuse(sh_in, max_nx);
+        if (fuse32 && !ts.bad()) {
+            const int kk = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+            for (Problem *p : ps) p->pm = o.preconditioner;
+            ts = tune_fuse<float>(E, ps, kk, sh_in, sig.str());
         }
         if (!ts.bad()) {
             const int period = o.check_period > 0 ? o.check_period : 20;
@@ -1882,10 +2000,10 @@ template <typename T>
 static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, const ChebConsts &cc,
                             bool h16, const T *r, T *z) {
     // the result lands in the buffer the sweep rotation ends in (fused pairs
-    // exactly where enqueue_precond uses them: FP32, no FP16 planes in use)
+    // exactly where enqueue_precond uses them: FP32)
     Engine &E = g.eng;
     const bool h16e = h16 && g.per_cell;
-    const bool fuse = sizeof(T) == 4 && sh.fr > 0 && !h16e;
+    const bool fuse = sizeof(T) == 4 && sh.fr > 0;
     const int zfin = precond_final(cc.k, 0, fuse);
     Problem p;
     p.g = &g;

@@ -374,9 +374,12 @@ def test_fused_sweep_pairs(monkeypatch, case, shape):
     lmin, lmax = krylov.spectral_bounds(A, w.lanczos_start(st.n))
     r = np.random.default_rng(11).standard_normal(st.n)
     g = grid_of(st)
+    A16 = None
+    if st.k_lat_mult is not None:
+        A16 = assembly.assemble(st, cond=assembly.fp16_lateral(assembly.conductances(st)))
     for degree in (5, 6, 30):
         ref = krylov.chebyshev_precondition(lambda v: A @ v, r, lmin, lmax, degree)
-        monkeypatch.delenv("CUTH_FUSE", raising=False)
+        monkeypatch.setenv("CUTH_FUSE", "0")
         z1 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
         monkeypatch.setenv("CUTH_FUSE", "1")
         monkeypatch.setenv("CUTH_FUSE_SHAPE", shape)
@@ -384,6 +387,11 @@ def test_fused_sweep_pairs(monkeypatch, case, shape):
         assert np.abs(z2 - ref).max() <= 2e-3 * np.abs(ref).max()
         # same arithmetic in the same order as two single sweeps
         assert np.abs(z2 - z1).max() <= 1e-6 * np.abs(z1).max()
+        if A16 is not None:
+            # and with the FP16-stored conductances
+            ref16 = krylov.chebyshev_precondition(lambda v: A16 @ v, r, lmin, lmax, degree)
+            z3 = g.precond_apply(t32(r), lmin, lmax, degree, fp16_coef=True).cpu().numpy()
+            assert np.abs(z3.astype(np.float64) - ref16).max() <= 2e-3 * np.abs(ref16).max()
     g.close()
 
 
