@@ -27,6 +27,9 @@ struct Setup {
     bool have_bounds = false;
     int bounds_steps = 0;
     double lmin = 0, lmax = 0, ritz_min = 0, ritz_max = 0, gersh = 0;
+    // CG iterations at which the last inner solve of refinement cycle c stopped
+    // on its tolerance ([0]: FP64 inner, [1]: FP32 inner; 0 = unknown)
+    int stop_iter[2][16] = {};
 };
 
 struct Status {

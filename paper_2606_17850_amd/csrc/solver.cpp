@@ -591,8 +591,15 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     std::vector<double> sums(2 * (size_t)nprob, 0.0);
     int it = 0, nchecks = 0;
     Status result = Status::ok();
+    // one more host check where the last inner solve of this cycle on this
+    // operator stopped: a stop found on the device is only seen at the next
+    // check, and every iteration launched before that runs empty
+    const int pi = sizeof(T) == 4 ? 1 : 0;
+    Problem &p0 = *ps[which[0]];
+    const int pred = (nprob == 1 && !graph) ? p0.su->stop_iter[pi][std::min(p0.cycles, 15)] : 0;
     while (it < maxit) {
-        const int cnt = graph ? period : std::min(period, maxit - it);
+        int cnt = graph ? period : std::min(period, maxit - it);
+        if (pred > it && pred - it < cnt) cnt = pred - it;
         if (graph) {
             const hipError_t le = hipGraphLaunch(exec, s);
             if (le != hipSuccess) {
@@ -650,6 +657,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     if (exec) (void)hipGraphExecDestroy(exec);
     CUTH_TRY(sync_stream(s));
     CUTH_TRY(result);
+    if (nprob == 1 && p0.stop == 1) p0.su->stop_iter[pi][std::min(p0.cycles, 15)] = hs[0].iter;
     // per-problem results and byte accounting (launches after a problem's stop
     // exit early and move no data)
     for (int n = 0; n < nprob; ++n) {
