@@ -168,6 +168,66 @@ def bench_transient(args) -> int:
     return 0
 
 
+def bench_ablation(args) -> int:
+    """The paper's ablations (Section 5) on the 512x512x16 system: Ablation I,
+    the FP64 product with the matrix-free stencil against a row-wise CSR copy
+    of the same operator (and the FP32 stencil); Ablation III, FP64 PCG to
+    relative residual 1e-10 with no preconditioner, Jacobi and Chebyshev
+    (k = 30).  Product times are per call and include the launch and the
+    synchronisation of each call; kernel-only times come from a kernel trace."""
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stack, P = w.config1()
+    g = cuth.Grid.from_stack(stack, device=dev)
+    x64 = torch.rand(stack.n, dtype=torch.float64, device=dev)
+    x32 = x64.float()
+    reps = max(args.steps, 10)
+
+    def per_call(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e6 / reps
+
+    spmv = {"stencil_fp64_us": per_call(lambda: g.apply(x64)),
+            "csr_fp64_us": per_call(lambda: g.apply_csr(x64)),
+            "stencil_fp32_us": per_call(lambda: g.apply(x32))}
+    nnz = 7 * stack.n - 2 * (stack.ny * stack.nz + stack.nx * stack.nz + stack.nx * stack.ny)
+    Pt = torch.as_tensor(P.ravel(), device=dev)
+    T = torch.empty_like(Pt)
+    pre = {}
+    for name in ("none", "jacobi", "chebyshev"):
+        o = cuth.options("fp64", preconditioner=name, max_inner=50000,
+                         check_period=0 if name == "chebyshev" else 50000)
+        g.reset_bounds()
+        g.solve(Pt, T, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = g.solve(Pt, T, opts=o)
+        torch.cuda.synchronize()
+        pre[name] = {"cg_iters": st["cg_iters"], "stencil_applies": st["stencil_applies"],
+                     "time_ms": round((time.perf_counter() - t0) * 1e3, 3),
+                     "rel_residual": st["rel_residual"]}
+    g.close()
+    out = {"metric": "ablations (Section 5): product time by storage, PCG by preconditioner",
+           "unit": "us per call / ms per solve", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "steady 512x512x16 layered stack, lognormal(0.3) lateral k",
+                      "unknowns": stack.n, "nonzeros": nnz},
+           "ablation_I_product": {k: round(v, 2) for k, v in spmv.items()},
+           "ablation_III_fp64_pcg_to_1e-10": pre}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_batch(args) -> int:
     """64 uneven stacks x 4 power maps in one batched mixed solve per step."""
     import numpy as np
@@ -216,7 +276,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
-    ap.add_argument("--workload", choices=("c1", "c2", "c3"), default="c1",
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "ablation"), default="c1",
                     help="c1: 512x512x16 steady (default, the headline); c2: 1024x1024x20 "
                          "transient steps; c3: 64-stack batch")
     args = ap.parse_args()
@@ -230,6 +290,8 @@ def main() -> int:
         return bench_transient(args)
     if args.workload == "c3":
         return bench_batch(args)
+    if args.workload == "ablation":
+        return bench_ablation(args)
 
     import numpy as np
     import torch

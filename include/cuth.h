@@ -216,6 +216,16 @@ const char *cuth_last_error(void);
  * device float [N].  Paper Algorithm 2 computes the same product. */
 cuth_status cuth_apply(cuth_grid g, double dt, int32_t precision, const void *x, void *y);
 
+/* y = A x with the operator stored as a CSR matrix (FP64 values, 32-bit column
+ * indices, rows in cell order, columns ascending, the diagonal formed from the
+ * face conductances as in the stencil) and one thread per row: the storage
+ * baseline of the paper's Ablation I (Section 5, Quad-Diag against CSR),
+ * compared with the matrix-free stencil of cuth_apply.  The matrix of (grid,
+ * dt) is built on first use (host row pointers, device fill) and kept by the
+ * handle.  x, y: device double [N].  CUTH_E_INVALID if the grid has 2^31 or
+ * more nonzeros. */
+cuth_status cuth_apply_csr(cuth_grid g, double dt, const double *x, double *y);
+
 /* r = b - A (T - t_amb) in FP64 (the true residual of Section 4.4).
  * b, T, r: device double [N]. */
 cuth_status cuth_residual(cuth_grid g, double dt, const double *b, const double *T, double *r);

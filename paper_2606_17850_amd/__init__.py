@@ -211,6 +211,13 @@ class Grid:
                                            r.data_ptr()))
         return r
 
+    def apply_csr(self, x: torch.Tensor, dt: float = 0.0) -> torch.Tensor:
+        """y = A x through the CSR copy of the FP64 operator (Ablation I baseline)."""
+        y = self._new(torch.float64)
+        with torch.cuda.device(self.device):
+            _check(library().cuth_apply_csr(self._h, float(dt), self._vec(x, "x"), self._vec(y, "y")))
+        return y
+
     def precond_apply(self, r: torch.Tensor, lmin: float, lmax: float, degree: int,
                       dt: float = 0.0, fp16_coef: bool = False) -> torch.Tensor:
         prec = CUTH_FP64 if r.dtype == torch.float64 else (CUTH_MIXED16 if fp16_coef else CUTH_MIXED)

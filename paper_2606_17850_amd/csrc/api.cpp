@@ -240,6 +240,17 @@ cuth_status cuth_residual(cuth_grid h, double dt, const double *b, const double 
     });
 }
 
+cuth_status cuth_apply_csr(cuth_grid h, double dt, const double *x, double *y) {
+    return guarded([&]() -> cuth_status {
+        if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
+        cuth::Grid &g = *h->g;
+        if (!x || !y) return fail(CUTH_E_INVALID, "x and y are required");
+        if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
+        if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
+        return report(cuth::apply_csr(g, dt, x, y));
+    });
+}
+
 cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, double lmin, double lmax,
                                int32_t degree, const void *r, void *z) {
     return guarded([&]() -> cuth_status {

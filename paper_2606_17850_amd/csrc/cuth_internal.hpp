@@ -208,6 +208,13 @@ void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStrea
 // y = (float) x
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s);
 
+// CSR copy of the FP64 operator: row r's entries at [ptr[r], ptr[r+1]) in
+// ascending column order; and y = A x with one thread per row.
+void launch_csr_fill(const OpView<double> &op, const int *ptr, int *col, double *val,
+                     hipStream_t s);
+void launch_csr_spmv(int64_t n, const int *ptr, const int *col, const double *val,
+                     const double *x, double *y, hipStream_t s);
+
 // Face conductances of a grid with a per-cell lateral multiplier.  Writes the
 // FP64 and FP32 planes, the per-layer maximum lateral off-diagonal row sum (as
 // the bit pattern of a positive double) for the Gershgorin bound and the

@@ -27,6 +27,10 @@ struct Setup {
     bool have_bounds = false;
     int bounds_steps = 0;
     double lmin = 0, lmax = 0, ritz_min = 0, ritz_max = 0, gersh = 0;
+    // CSR copy of the FP64 operator (cuth_apply_csr), built on first use
+    int *csr_ptr = nullptr, *csr_col = nullptr;
+    double *csr_val = nullptr;
+    int64_t csr_nnz = 0;
     // CG iterations at which the last inner solve of refinement cycle c stopped
     // on its tolerance ([0]: FP64 inner, [1]: FP32 inner; 0 = unknown)
     int stop_iter[2][16] = {};
@@ -153,6 +157,7 @@ Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax
                      const void *r, void *z);
 Status apply_op(Grid &g, double dt, int precision, const void *x, void *y);
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r);
+Status apply_csr(Grid &g, double dt, const double *x, double *y);
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,
                const cuth_options &o, cuth_stats *stats);
 

@@ -32,6 +32,7 @@
 // run-to-run deterministic.
 #include "cuth_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace cuth {
@@ -946,6 +947,48 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out, gridDim.x, slot);
 }
 
+// CSR fill: one thread per cell writes its row (neighbours below, south, west,
+// the cell, east, north, above: ascending columns); off-diagonals -g, the
+// diagonal sink + the sum of the face conductances (as the stencil's rows).
+__global__ __launch_bounds__(256) void k_csr_fill(OpView<double> op, const int *__restrict__ ptr,
+                                                  int *__restrict__ col, double *__restrict__ val) {
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    const int64_t plane = (int64_t)nx * ny, n = plane * nz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), l = (int)(c / plane);
+        const LayerCoef<double> L = op.lc[l];
+        const bool pc = op.gx != nullptr;
+        const double gw = i > 0 ? (pc ? op.gx[c - 1] : L.gx) : 0.0;
+        const double ge = i < nx - 1 ? (pc ? op.gx[c] : L.gx) : 0.0;
+        const double gs = j > 0 ? (pc ? op.gy[c - nx] : L.gy) : 0.0;
+        const double gn = j < ny - 1 ? (pc ? op.gy[c] : L.gy) : 0.0;
+        const double gd = l > 0 ? L.gzd : 0.0, gu = l < nz - 1 ? L.gzu : 0.0;
+        int k = ptr[c];
+        if (l > 0) { col[k] = (int)(c - plane); val[k++] = -gd; }
+        if (j > 0) { col[k] = (int)(c - nx); val[k++] = -gs; }
+        if (i > 0) { col[k] = (int)(c - 1); val[k++] = -gw; }
+        col[k] = (int)c;
+        val[k++] = L.sink + gd + gs + gw + ge + gn + gu;
+        if (i < nx - 1) { col[k] = (int)(c + 1); val[k++] = -ge; }
+        if (j < ny - 1) { col[k] = (int)(c + nx); val[k++] = -gn; }
+        if (l < nz - 1) { col[k] = (int)(c + plane); val[k++] = -gu; }
+    }
+}
+
+// Row-wise CSR product, one thread per row (the Ablation I baseline).
+__global__ __launch_bounds__(256) void k_csr_spmv(int64_t n, const int *__restrict__ ptr,
+                                                  const int *__restrict__ col,
+                                                  const double *__restrict__ val,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double a = 0.0;
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) a += val[k] * x[col[k]];
+    y[r] = a;
+}
+
 __global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restrict__ x,
                                                 float *__restrict__ y) {
     const int64_t stride = (int64_t)gridDim.x * nthreads();
@@ -1372,6 +1415,19 @@ void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool p
     const dim3 g(nb), b(kWave, by);
     CUTH_PC_VX_DISPATCH(double, pc, vx, (hipLaunchKernelGGL((k_residual_b<PC, VX, TD, TI>), g, b, 0,
                                                             s, probs, nprob, part_out)));
+}
+
+void launch_csr_fill(const OpView<double> &op, const int *ptr, int *col, double *val,
+                     hipStream_t s) {
+    const int64_t n = (int64_t)op.nx * op.ny * op.nz;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)blocks), dim3(256), 0, s, op, ptr, col, val);
+}
+
+void launch_csr_spmv(int64_t n, const int *ptr, const int *col, const double *val,
+                     const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_spmv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ptr, col,
+                       val, x, y);
 }
 
 void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t s) {

@@ -1335,6 +1335,9 @@ void grid_destroy(Grid *g) {
     for (Setup &su : g->setups) {
         dev_free(su.lc64);
         dev_free(su.lc32);
+        dev_free(su.csr_ptr);
+        dev_free(su.csr_col);
+        dev_free(su.csr_val);
     }
     dev_free(g->gx64);
     dev_free(g->gy64);
@@ -1971,6 +1974,38 @@ Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
         launch_apply<float>(view32(g, *su, precision == CUTH_MIXED16), (const float *)x, (float *)y,
                             g.stream);
     else launch_apply<double>(view64(g, *su), (const double *)x, (double *)y, g.stream);
+    CUTH_HIP(hipGetLastError());
+    return sync_stream(g.stream);
+}
+
+Status apply_csr(Grid &g, double dt, const double *x, double *y) {
+    Status st;
+    Setup *su = get_setup(g, dt, st);
+    if (!su) return st;
+    if (!su->csr_ptr) {
+        // row pointers on the host: 1 + one entry per existing face neighbour
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        std::vector<int> ptr((size_t)g.N + 1);
+        int64_t k = 0;
+        size_t r = 0;
+        for (int l = 0; l < nz; ++l)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    ptr[r++] = (int)k;
+                    k += 1 + (i > 0) + (i < nx - 1) + (j > 0) + (j < ny - 1) + (l > 0) + (l < nz - 1);
+                    if (k >= ((int64_t)1 << 31) - 1)
+                        return Status::err(CUTH_E_INVALID, "CSR needs fewer than 2^31 nonzeros");
+                }
+        ptr[r] = (int)k;
+        CUTH_TRY(dev_alloc(&su->csr_ptr, ptr.size()));
+        CUTH_TRY(dev_alloc(&su->csr_col, (size_t)k));
+        CUTH_TRY(dev_alloc(&su->csr_val, (size_t)k));
+        su->csr_nnz = k;
+        CUTH_HIP(hipMemcpy(su->csr_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+        launch_csr_fill(view64(g, *su), su->csr_ptr, su->csr_col, su->csr_val, g.stream);
+        CUTH_HIP(hipGetLastError());
+    }
+    launch_csr_spmv(g.N, su->csr_ptr, su->csr_col, su->csr_val, x, y, g.stream);
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
 }

@@ -50,6 +50,9 @@ def test_apply_matches_csr(case, dt):
     ref = A @ x
     scale = Aabs @ np.abs(x)
     assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+    # the CSR copy of the operator (storage baseline) gives the same product
+    yc = g.apply_csr(t64(x), dt=dt or 0.0).cpu().numpy()
+    assert np.all(np.abs(yc - ref) <= 1e-14 * scale)
     x32 = x.astype(np.float32)
     y32 = g.apply(t32(x32), dt=dt or 0.0).cpu().numpy().astype(np.float64)
     ref32 = A @ x32.astype(np.float64)
