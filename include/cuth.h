@@ -68,7 +68,7 @@ typedef enum {
                          to FP32 and scaled by 2^-e_l before use.  CG products,
                          checks and Lanczos use the FP32 conductances.  Same as
                          CUTH_MIXED for grids without k_lat_mult.             */
-    CUTH_ADAPTIVE = 3 /* the paper's stage-switched scheme (Section 4.4): CG
+    CUTH_ADAPTIVE = 3, /* the paper's stage-switched scheme (Section 4.4): CG
                          vectors, scalars and inner products in FP64; the
                          Chebyshev preconditioner in FP32 with the FP16-stored
                          lateral conductances (as CUTH_MIXED16); the CG product
@@ -80,6 +80,15 @@ typedef enum {
                          or drifts from r_low (c); the switch recomputes
                          r = b - A T in FP64 and restarts p (hot restart).
                          Stops at ||b - A T|| <= tol ||b|| (tol as CUTH_FP64). */
+    CUTH_FP32 = 4     /* ablation baseline (Section 5, Ablation II, fixed FP32): one
+                         PCG entirely in FP32 (vectors, scalars, operator,
+                         preconditioner) that stops when its own recursive FP32
+                         residual meets ||r|| <= tol ||b|| (tol as CUTH_FP64), with
+                         no FP64 refinement and no drift or stagnation test.  The
+                         result is the FP32 iterate; stats.rel_residual is its
+                         FP64 true residual, which may be far above tol (the
+                         drift this baseline exists to show).  CUTH_OK unless a
+                         breakdown or max_inner ends the iteration.           */
 } cuth_precision;
 
 /* Preconditioner of the inner PCG.  The Chebyshev polynomial is the paper's
@@ -90,6 +99,21 @@ typedef enum {
     CUTH_PC_JACOBI = 1,     /* z = r / diag(A), diag = sink + face conductances   */
     CUTH_PC_NONE = 2        /* z = r (plain CG); no Lanczos setup either         */
 } cuth_preconditioner;
+
+/* Storage of the operator in the CG and Chebyshev products.  The matrix-free
+ * layered stencil is the paper's (Section 4.2: direct addressing, coalesced
+ * loads); CSR with one thread per row is the baseline of its Ablation I (and of
+ * the optimisation-off columns of Ablation III), Section 5.  CSR runs the same
+ * PCG kernels with only the product changed; it needs precision CUTH_FP64 and
+ * fewer than 2^31 nonzeros (7 per cell at most), builds the CSR copy of each
+ * operator (steady, and per dt) on first use and keeps it with the grid; the
+ * Lanczos bounds and the once-per-restart FP64 residual still use the stencil,
+ * and stats.alg_bytes still counts the stencil's bytes.  Single solves and
+ * transient steps only (cuth_solve_batch returns CUTH_E_INVALID). */
+typedef enum {
+    CUTH_STORAGE_STENCIL = 0,  /* matrix-free stencil (default)                   */
+    CUTH_STORAGE_CSR = 1       /* CSR copy of the FP64 operator, row-wise products */
+} cuth_storage;
 
 /* Grid descriptor.  Conductances follow the series (harmonic) half-cell rule:
  * a lateral face between cells a and b of layer l has
@@ -127,6 +151,7 @@ typedef struct {
     int32_t check_period;        /* iterations between true-residual checks, 0 = the
                                     default (20 steady, 5 transient)                   */
     int32_t preconditioner;      /* cuth_preconditioner (default CUTH_PC_CHEBYSHEV)    */
+    int32_t storage;             /* cuth_storage (default CUTH_STORAGE_STENCIL)        */
 } cuth_options;
 
 typedef struct {

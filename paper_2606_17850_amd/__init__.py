@@ -45,7 +45,7 @@ def _check(status: int, stats: Optional[_lib.Stats] = None):
 def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: int = 30,
             lanczos_steps: int = 30, max_inner: int = 2000, max_outer: int = 12,
             use_initial_guess: bool = False, check_period: int = 0,
-            preconditioner: str = "chebyshev") -> _lib.Options:
+            preconditioner: str = "chebyshev", storage: str = "stencil") -> _lib.Options:
     o = _lib.Options()
     library().cuth_default_options(ctypes.byref(o))
     if precision not in PRECISIONS:
@@ -62,6 +62,9 @@ def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: 
         raise ValueError(f"preconditioner must be one of {sorted(_lib.PRECONDITIONERS)}, "
                          f"got {preconditioner!r}")
     o.preconditioner = _lib.PRECONDITIONERS[preconditioner]
+    if storage not in _lib.STORAGES:
+        raise ValueError(f"storage must be one of {sorted(_lib.STORAGES)}, got {storage!r}")
+    o.storage = _lib.STORAGES[storage]
     return o
 
 

@@ -18,9 +18,11 @@ CUTH_FP64 = 0
 CUTH_MIXED = 1
 CUTH_MIXED16 = 2
 CUTH_ADAPTIVE = 3
+CUTH_FP32 = 4
 PRECISIONS = {"fp64": CUTH_FP64, "mixed": CUTH_MIXED, "mixed16": CUTH_MIXED16,
-              "adaptive": CUTH_ADAPTIVE}
+              "adaptive": CUTH_ADAPTIVE, "fp32": CUTH_FP32}
 PRECONDITIONERS = {"chebyshev": 0, "jacobi": 1, "none": 2}
+STORAGES = {"stencil": 0, "csr": 1}
 
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BREAKDOWN"}
 
@@ -50,7 +52,7 @@ class Options(ctypes.Structure):
         ("cheb_degree", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
         ("max_inner", ctypes.c_int32), ("max_outer", ctypes.c_int32),
         ("use_initial_guess", ctypes.c_int32), ("check_period", ctypes.c_int32),
-        ("preconditioner", ctypes.c_int32),
+        ("preconditioner", ctypes.c_int32), ("storage", ctypes.c_int32),
     ]
 
 

@@ -55,10 +55,14 @@ cuth_status check_desc(const cuth_grid_desc *d) {
 }
 
 cuth_status check_opts(const cuth_options &o) {
-    if (o.precision < CUTH_FP64 || o.precision > CUTH_ADAPTIVE)
+    if (o.precision < CUTH_FP64 || o.precision > CUTH_FP32)
         return fail(CUTH_E_INVALID, "precision must be a cuth_precision value");
     if (o.preconditioner < CUTH_PC_CHEBYSHEV || o.preconditioner > CUTH_PC_NONE)
         return fail(CUTH_E_INVALID, "preconditioner must be a cuth_preconditioner value");
+    if (o.storage != CUTH_STORAGE_STENCIL && o.storage != CUTH_STORAGE_CSR)
+        return fail(CUTH_E_INVALID, "storage must be a cuth_storage value");
+    if (o.storage == CUTH_STORAGE_CSR && o.precision != CUTH_FP64)
+        return fail(CUTH_E_INVALID, "CSR storage needs precision CUTH_FP64");
     if (!(o.tol == 0.0 || (finite_pos(o.tol) && o.tol < 1.0)))
         return fail(CUTH_E_INVALID, "tol must be 0 (default) or in (0, 1)");
     if (o.cheb_degree < 1 || o.cheb_degree > 256)
@@ -120,6 +124,7 @@ void cuth_default_options(cuth_options *o) {
     o->use_initial_guess = 0;
     o->check_period = 0;
     o->preconditioner = CUTH_PC_CHEBYSHEV;
+    o->storage = CUTH_STORAGE_STENCIL;
 }
 
 const char *cuth_last_error(void) { return g_last_error.c_str(); }
@@ -186,6 +191,8 @@ cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
         bool ok;
         cuth_options o = resolve(opt, ok);
         if (!ok) return check_opts(o);
+        if (o.storage != CUTH_STORAGE_STENCIL)
+            return fail(CUTH_E_INVALID, "batched solves use the stencil storage only");
         for (int s = 0; s < nsys; ++s) {
             if (check_handle(grids[s]) != CUTH_OK) return CUTH_E_INVALID;
             if (!P[s] || !T[s]) return fail(CUTH_E_INVALID, "P[s] and T[s] are required");

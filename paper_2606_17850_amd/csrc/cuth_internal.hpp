@@ -49,6 +49,20 @@ struct OpView {
     // paper's "FP64/32 SpMV"; set where such launches are made)
     const float *fx = nullptr;
     const float *fy = nullptr;
+    // CSR copy of the FP64 operator (row r's entries at [csr_ptr[r],
+    // csr_ptr[r+1])); set only where a solve runs on CSR storage
+    const int *csr_ptr = nullptr;
+    const int *csr_col = nullptr;
+    const double *csr_val = nullptr;
+};
+
+// Where a stencil kernel's operator comes from.
+enum CoefSrc : int {
+    CS_OWN = 0,   // per-cell op.gx/op.gy in the operator's precision, or the per-layer constants
+    CS_F16 = 1,   // op.hx/op.hy: FP16 copies at the layer's power-of-two scale (FP32 sweeps)
+    CS_F32 = 2,   // op.fx/op.fy: FP32 copies, promoted (FP64 operators)
+    CS_CSR = 3    // op.csr_*: every row's entries from the CSR copy, one lane per row
+                  // (Section 5, Ablation I's baseline storage; FP64 operators)
 };
 
 // Number of workgroups of a stencil launch (one 64*vx by `by` tile and one
@@ -138,9 +152,10 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 // z[in], z_{j-1} in z[out] (read at the cell only) and the result overwrites z[out].  last: partials of r^T z_{j+1}.  chk: the first kernel after
 // a CG update reduces the update's partials (part_in) and stops converged
 // problems (rr <= tol2).
-// h16: read the FP16-stored lateral conductances (FP32, per-cell grids only).
+// cs (CoefSrc): CS_F16 reads the FP16-stored lateral conductances (FP32,
+// per-cell grids only), CS_CSR the CSR copy (FP64); otherwise CS_OWN.
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int by,
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
                    int mode, bool last, bool chk, int j, int zsel, const T *part_in, bool red,
                    T *part_out, hipStream_t s);
 
@@ -162,9 +177,10 @@ void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int p
                     bool chk, const T *part_in, bool red, T *part_out, hipStream_t s);
 
 // CG iteration of parity par: rz = sum(part_in); p[par] = z[zfin] + (rz / rz_prev) p[1-par];
-// mu = A p[par]; partials of p^T mu.
+// mu = A p[par]; partials of p^T mu.  cs: CS_F32 (FP64, per-cell grids) promotes
+// the FP32-stored conductances, CS_CSR (FP64) reads the CSR copy; else CS_OWN.
 template <typename T>
-void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool f32coef, int vx,
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx,
                   int by, int par, int zfin, const T *part_in, bool red, T *part_out,
                   hipStream_t s);
 
@@ -192,9 +208,10 @@ template <typename T>
 void launch_reduce_b(const InnerProb<T> *probs, int nprob, const T *part_in, T *red_out,
                      hipStream_t s);
 
-// True residual rt = rhat - A x: partials of ||rt||^2 and ||rt - r||^2.
+// True residual rt = rhat - A x: partials of ||rt||^2 and ||rt - r||^2 (cs:
+// CS_CSR for the CSR copy, FP64; else CS_OWN).
 template <typename T>
-void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
                     T *part_out, hipStream_t s);
 
 // FP64 outer residual; partials of ||r||^2, ||b||^2, max|delta|, max|theta_out|,

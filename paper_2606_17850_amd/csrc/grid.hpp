@@ -32,8 +32,9 @@ struct Setup {
     double *csr_val = nullptr;
     int64_t csr_nnz = 0;
     // CG iterations at which the last inner solve of refinement cycle c stopped
-    // on its tolerance ([0]: FP64 inner, [1]: FP32 inner; 0 = unknown)
-    int stop_iter[2][16] = {};
+    // on its tolerance, per inner precision ([0]: FP64, [1]: FP32) and
+    // preconditioner (cuth_preconditioner); 0 = unknown
+    int stop_iter[2][3][16] = {};
 };
 
 struct Status {
@@ -158,6 +159,8 @@ Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax
 Status apply_op(Grid &g, double dt, int precision, const void *x, void *y);
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r);
 Status apply_csr(Grid &g, double dt, const double *x, double *y);
+// Builds the setup's CSR copy of the FP64 operator if it has none.
+Status ensure_csr(Grid &g, Setup &su);
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,
                const cuth_options &o, cuth_stats *stats);
 

@@ -202,21 +202,6 @@ __device__ __forceinline__ Lane lane_of(const OpView<T> &op) {
                        (op.nz + op.zc - 1) / op.zc);
 }
 
-// March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
-// layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
-// starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
-// (fetched right before emit).  Every lane of the wavefront must call this (the
-// x halo comes through cross-lane shuffles).  Two variants measured slower on
-// gfx950 and are not used: issuing the next layer's loads before computing the
-// current one (more registers, no gain in overlap), and guarding the loads with
-// branches instead of selects (about 15 % slower sweeps).
-// Where a per-cell operator's lateral conductances come from.
-enum CoefSrc : int {
-    CS_OWN = 0,   // op.gx/op.gy in the operator's precision
-    CS_F16 = 1,   // op.hx/op.hy: FP16 copies at the layer's power-of-two scale
-    CS_F32 = 2    // op.fx/op.fy: FP32 copies, promoted (FP64 operators)
-};
-
 template <typename T, int VX>
 __device__ __forceinline__ Vec<T, VX> f32load(const float *p) {
     const Vec<float, VX> b = vload<float, VX>(p);
@@ -281,12 +266,40 @@ __device__ __forceinline__ void lateral_coefs(const OpView<T> &op, const LayerCo
     }
 }
 
+// March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
+// layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
+// starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
+// (fetched right before emit).  Every lane of the wavefront must call this (the
+// x halo comes through cross-lane shuffles), except with CS_CSR.  Two variants
+// measured slower on gfx950 and are not used: issuing the next layer's loads
+// before computing the current one (more registers, no gain in overlap), and
+// guarding the loads with branches instead of selects (about 15 % slower sweeps).
 template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                            FP &&PRE, E &&emit) {
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const bool act = ln.act;
+    if constexpr (CS == CS_CSR) {
+        // the CSR baseline: each of the lane's rows walks its own entries and
+        // gathers the operand at their columns (no neighbour exchange between
+        // lanes, so inactive lanes may leave at once)
+        if (!act) return;
+        int64_t c = ln.i0 + (int64_t)nx * ln.j + plane * ln.l0;
+        for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
+            const Vec<T, VX> xc = XV(c);
+            Vec<T, VX> ax;
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const int k1 = op.csr_ptr[c + e + 1];
+                T a = T(0);
+                for (int k = op.csr_ptr[c + e]; k < k1; ++k) a += (T)op.csr_val[k] * XS(op.csr_col[k]);
+                ax.a[e] = a;
+            }
+            emit(l, c, xc, ax, PRE(c));
+        }
+        return;
+    }
     const bool has_l = act && ln.i0 > 0, has_r = act && ln.i0 + VX < nx;
     const bool has_s = act && ln.j > 0, has_n = act && ln.j < ny - 1;
     int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
@@ -396,7 +409,7 @@ __device__ __forceinline__ bool conv_test(CgState<T> *st, const T *part_in, int 
 }
 
 // ---------------------------------------------------- batched Chebyshev sweep
-template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, bool H16>
+template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, int CS>
 __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                 int j, int zsel, const T *__restrict__ part_in,
                                                 int red, T *__restrict__ part_out) {
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
         else e.zm = vzero<T, VX>();
         return e;
     };
-    column_pre<T, PC, VX, H16 ? CS_F16 : CS_OWN>(op, ln, XV, XS, PRE,
+    column_pre<T, PC, VX, CS>(op, ln, XV, XS, PRE,
                       [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az, const Ex &ex) {
                           const Vec<T, VX> &rc = ex.r;
                           const Vec<T, VX> &zm = ex.zm;
@@ -846,7 +859,7 @@ __global__ __launch_bounds__(256) void k_reduce_b(const InnerProb<T> *__restrict
 }
 
 // ----------------------------------------------------- CG: true residual check
-template <typename T, bool PC, int VX>
+template <typename T, bool PC, int VX, int CS>
 __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                  T *__restrict__ part_out) {
     const int slot = xcd_slot();
@@ -861,7 +874,7 @@ __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict_
     struct Ex {
         Vec<T, VX> rh, rr;
     };
-    column_pre<T, PC, VX, CS_OWN>(
+    column_pre<T, PC, VX, CS>(
         op, ln,
         [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
         [&](int64_t q) { return have_x ? x[q] : T(0); },
@@ -1277,12 +1290,12 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s) {
                         (hipLaunchKernelGGL((k_apply<T, PC, VX, false>), g, b, 0, s, op, x, y)));
 }
 
-template <typename T, bool PC, int VX, bool H16>
+template <typename T, bool PC, int VX, int CS>
 static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int mode, bool last,
                        bool chk, int j, int zin, const T *pin, bool red, T *pout, hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
 #define CUTH_CHEB(M, LST, CK)                                                                      \
-    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK, H16>), g, b, 0, s, probs, nprob, j, zin, \
+    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK, CS>), g, b, 0, s, probs, nprob, j, zin,  \
                        pin, (int)red, pout)
     if (mode == 1) {
         if (chk) {
@@ -1299,20 +1312,27 @@ static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int
 }
 
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int by,
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
                    int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
                    T *part_out, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
-        if (pc && h16) {
-            CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, true, VX, true>(probs, nprob, nb, by, mode, last,
-                                                                   chk, j, zin, part_in, red,
-                                                                   part_out, s)));
+        if (pc && cs == CS_F16) {
+            CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, true, VX, CS_F16>(probs, nprob, nb, by, mode,
+                                                                     last, chk, j, zin, part_in,
+                                                                     red, part_out, s)));
+            return;
+        }
+    } else {
+        if (cs == CS_CSR) {
+            CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, false, VX, CS_CSR>(probs, nprob, nb, by, mode,
+                                                                      last, chk, j, zin, part_in,
+                                                                      red, part_out, s)));
             return;
         }
     }
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX, false>(probs, nprob, nb, by, mode, last,
-                                                                 chk, j, zin, part_in, red,
-                                                                 part_out, s)));
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX, CS_OWN>(probs, nprob, nb, by, mode, last,
+                                                                  chk, j, zin, part_in, red,
+                                                                  part_out, s)));
 }
 
 template <typename T>
@@ -1357,12 +1377,18 @@ void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int p
 }
 
 template <typename T>
-void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool f32coef, int vx,
+void launch_dir_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx,
                   int by, int par, int zfin, const T *part_in, bool red, T *part_out,
                   hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
     if constexpr (sizeof(T) == 8) {
-        if (pc && f32coef) {
+        if (cs == CS_CSR) {
+            CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_dir_b<T, false, VX, CS_CSR>), g, b, 0, s,
+                                                        probs, nprob, par, zfin, part_in, (int)red,
+                                                        part_out)));
+            return;
+        }
+        if (pc && cs == CS_F32) {
             CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_dir_b<T, true, VX, CS_F32>), g, b, 0, s,
                                                         probs, nprob, par, zfin, part_in, (int)red,
                                                         part_out)));
@@ -1402,11 +1428,18 @@ void launch_reduce_b(const InnerProb<T> *probs, int nprob, const T *part_in, T *
 }
 
 template <typename T>
-void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int vx, int by,
+void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
                     T *part_out, hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_check_b<T, PC, VX>), g, b, 0, s, probs,
-                                                       nprob, part_out)));
+    if constexpr (sizeof(T) == 8) {
+        if (cs == CS_CSR) {
+            CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_check_b<T, false, VX, CS_CSR>), g, b, 0,
+                                                        s, probs, nprob, part_out)));
+            return;
+        }
+    }
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_check_b<T, PC, VX, CS_OWN>), g, b, 0, s,
+                                                       probs, nprob, part_out)));
 }
 
 template <typename TD, typename TI>
@@ -1504,16 +1537,16 @@ void launch_adjoint(const OpView<double> &op, const double *lam, const double *T
 
 #define CUTH_INST(T)                                                                              \
     template void launch_apply<T>(const OpView<T> &, const T *, T *, hipStream_t);                \
-    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, bool, int, int, int,     \
+    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, int,      \
                                    bool, bool, int, int, const T *, bool, T *, hipStream_t);      \
     template void launch_scale_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, bool,    \
                                     const T *, bool, T *, hipStream_t);                           \
-    template void launch_dir_b<T>(const InnerProb<T> *, int, int, bool, bool, int, int, int, int, \
+    template void launch_dir_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, int, int,  \
                                   const T *, bool, T *, hipStream_t);                             \
     template void launch_update_b<T>(const InnerProb<T> *, int, int, int, int, int, const T *,    \
                                      bool, T *, hipStream_t);                                     \
     template void launch_reduce_b<T>(const InnerProb<T> *, int, const T *, T *, hipStream_t);     \
-    template void launch_check_b<T>(const InnerProb<T> *, int, int, bool, int, int, T *,          \
+    template void launch_check_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, T *,     \
                                     hipStream_t);
 CUTH_INST(float)
 CUTH_INST(double)

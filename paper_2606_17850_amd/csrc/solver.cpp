@@ -233,6 +233,11 @@ struct Problem {
     // stage-switched scheme: still in the early stage (FP32-stored coefficients
     // in the CG product, switch test (a) as the inner tolerance)
     bool early = false;
+    // fixed-FP32 ablation baseline: one FP32 inner solve to tol on its own
+    // recursive residual, no drift or stagnation stop, no refinement
+    bool fixed32 = false;
+    // FP64 products from the CSR copy of the operator (Ablation I's storage)
+    bool csr = false;
     // per inner solve
     bool inner = false;
     double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, true_rr = 0.0;
@@ -276,8 +281,14 @@ template <> struct Sel<double> {
     static Work<double> &w(Problem &p) { return p.w64; }
     static OpView<double> view(const Problem &p, const Shape &sh) {
         const Grid &g = *p.g;
-        return OpView<double>{g.nx, g.ny, g.nz, g.per_cell ? g.gx64 : nullptr,
-                              g.per_cell ? g.gy64 : nullptr, p.su->lc64, sh.vx, sh.by, sh.zc};
+        OpView<double> v{g.nx, g.ny, g.nz, g.per_cell ? g.gx64 : nullptr,
+                         g.per_cell ? g.gy64 : nullptr, p.su->lc64, sh.vx, sh.by, sh.zc};
+        if (p.csr) {
+            v.csr_ptr = p.su->csr_ptr;
+            v.csr_col = p.su->csr_col;
+            v.csr_val = p.su->csr_val;
+        }
+        return v;
     }
 };
 
@@ -471,16 +482,17 @@ T *red_rr(Engine &E) { return eslot<T>(E, P_RED) + 2 * E.cap; }
 // z = q(A) r for every problem of the launch; returns the buffer index of z.
 // chk: the first kernel also runs the convergence test on the update's r^T r.
 template <typename T>
-int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, const Shape &sh, int k,
+int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const Shape &sh, int k,
                     bool chk, bool red, hipStream_t s, Grid *prof, int tag = -1) {
     InnerProb<T> *d = Sel<T>::d(E);
+    const bool h16 = cs == CS_F16;
     const T *rr_in = red ? red_rr<T>(E) : eslot<T>(E, P_UPD);
     if (k == 1 || pm != 0) {
         launch_scale_b<T>(d, nprob, nb, pc, pm, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
         return 0;
     }
-    launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1), rr_in, red,
+    launch_cheb_b<T>(d, nprob, nb, pc, cs, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1), rr_in, red,
                      eslot<T>(E, P_CHEB), s);
     // fused pairs of general sweeps (FP32)
     const bool fuse = sizeof(T) == 4 && sh.fr > 0;
@@ -504,7 +516,7 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, con
             n = y;
         } else {
             const int mode = (j == 2) ? 2 : 0;
-            launch_cheb_b<T>(d, nprob, nb, pc, h16, sh.vx, sh.by, mode, j == k - 1, false, j,
+            launch_cheb_b<T>(d, nprob, nb, pc, cs, sh.vx, sh.by, mode, j == k - 1, false, j,
                              zsel(n, p), rr_in, red, eslot<T>(E, P_CHEB), s);
             std::swap(n, p);
         }
@@ -525,18 +537,18 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, con
 }
 
 template <typename T>
-void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, bool h16, int pm, const Shape &sh, int k,
+void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const Shape &sh, int k,
                         int first_k, int count, int zfin, bool red, hipStream_t s, Grid *prof) {
     InnerProb<T> *d = Sel<T>::d(E);
     for (int q = 0; q < count; ++q) {
         const int par = (first_k + q) & 1;
-        launch_dir_b<T>(d, nprob, nb, pc, false, sh.vx, sh.by, par, zfin,
+        launch_dir_b<T>(d, nprob, nb, pc, cs == CS_CSR ? CS_CSR : CS_OWN, sh.vx, sh.by, par, zfin,
                         red ? red_rz<T>(E) : eslot<T>(E, P_CHEB), red, eslot<T>(E, P_DIR), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_DIR), red_pmu<T>(E), s);
         launch_update_b<T>(d, nprob, nb, sh.vx, sh.by, par, red ? red_pmu<T>(E) : eslot<T>(E, P_DIR),
                            red, eslot<T>(E, P_UPD), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_UPD), red_rr<T>(E), s);
-        enqueue_precond<T>(E, nprob, nb, pc, h16, pm, sh, k, true, red, s, prof, first_k + q);
+        enqueue_precond<T>(E, nprob, nb, pc, cs, pm, sh, k, true, red, s, prof, first_k + q);
     }
 }
 
@@ -556,6 +568,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     if (nprob == 0) return Status::ok();
     const bool pc = ps[which[0]]->g->per_cell;
     const bool h16 = pc && ps[which[0]]->h16;
+    const int cs = (sizeof(T) == 8 && ps[which[0]]->csr) ? CS_CSR : (h16 ? CS_F16 : CS_OWN);
     const int pm = ps[which[0]]->pm;
     bool red = false;
     const int above = reduce_above();
@@ -576,13 +589,13 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         p.stop = 0;
     }
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>) * nprob, hipMemcpyHostToDevice, s));
-    const int zfin = enqueue_precond<T>(E, nprob, nb, pc, h16, pm, sh, k, false, red, s, prof);
+    const int zfin = enqueue_precond<T>(E, nprob, nb, pc, cs, pm, sh, k, false, red, s, prof);
     const bool graph = use_graph && period % 2 == 0;
     hipGraphExec_t exec = nullptr;
     if (graph) {
         hipGraph_t gr = nullptr;
         CUTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_iterations<T>(E, nprob, nb, pc, h16, pm, sh, k, 0, period, zfin, red, s, nullptr);
+        enqueue_iterations<T>(E, nprob, nb, pc, cs, pm, sh, k, 0, period, zfin, red, s, nullptr);
         CUTH_HIP(hipStreamEndCapture(s, &gr));
         const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
@@ -596,7 +609,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     // check, and every iteration launched before that runs empty
     const int pi = sizeof(T) == 4 ? 1 : 0;
     Problem &p0 = *ps[which[0]];
-    const int pred = (nprob == 1 && !graph) ? p0.su->stop_iter[pi][std::min(p0.cycles, 15)] : 0;
+    const int pred = (nprob == 1 && !graph) ? p0.su->stop_iter[pi][p0.pm][std::min(p0.cycles, 15)] : 0;
     while (it < maxit) {
         int cnt = graph ? period : std::min(period, maxit - it);
         if (pred > it && pred - it < cnt) cnt = pred - it;
@@ -607,10 +620,10 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
                 break;
             }
         } else {
-            enqueue_iterations<T>(E, nprob, nb, pc, h16, pm, sh, k, it, cnt, zfin, red, s, prof);
+            enqueue_iterations<T>(E, nprob, nb, pc, cs, pm, sh, k, it, cnt, zfin, red, s, prof);
         }
         it += cnt;
-        launch_check_b<T>(Sel<T>::d(E), nprob, nb, pc, sh.vx, sh.by, eslot<T>(E, P_CHK), s);
+        launch_check_b<T>(Sel<T>::d(E), nprob, nb, pc, cs, sh.vx, sh.by, eslot<T>(E, P_CHK), s);
         ++nchecks;
         CUTH_HIP(hipMemcpyAsync(hs, Sel<T>::ds(E), sizeof(CgState<T>) * nprob, hipMemcpyDeviceToHost, s));
         CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<T>(E, P_CHK), sizeof(T) * 2 * (size_t)nb,
@@ -638,8 +651,8 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
             int why = hs[n].done;
             if (!why) {
                 if (!std::isfinite(tn)) why = 4;
-                else if (std::sqrt(b) >= 0.5 * tn) why = 2;
-                else if (p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
+                else if (!p.fixed32 && std::sqrt(b) >= 0.5 * tn) why = 2;
+                else if (!p.fixed32 && p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
                 else if (it >= maxit) why = 5;
                 if (why) {
                     // stop this problem on the device too (its launches exit early)
@@ -657,7 +670,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     if (exec) (void)hipGraphExecDestroy(exec);
     CUTH_TRY(sync_stream(s));
     CUTH_TRY(result);
-    if (nprob == 1 && p0.stop == 1) p0.su->stop_iter[pi][std::min(p0.cycles, 15)] = hs[0].iter;
+    if (nprob == 1 && p0.stop == 1) p0.su->stop_iter[pi][p0.pm][std::min(p0.cycles, 15)] = hs[0].iter;
     // per-problem results and byte accounting (launches after a problem's stop
     // exit early and move no data)
     for (int n = 0; n < nprob; ++n) {
@@ -770,6 +783,19 @@ void decide(Problem &p, const double *o, bool mixed, int max_outer) {
     if (bad > 0) {
         p.status = Status::err(CUTH_E_BREAKDOWN, "non-finite residual");
         p.finished = true;
+        return;
+    }
+    if (p.fixed32) {
+        if (cyc >= 1 && thinf > 0) p.err_est = dinf / thinf;
+        if (cyc >= 1 || rr == 0.0 || p.status.bad()) {
+            if (!p.status.bad() && p.reason == 5)
+                p.status = Status::err(CUTH_E_NOT_CONVERGED, "FP32 iteration limit reached");
+            p.finished = true;
+            return;
+        }
+        p.inner = true;
+        p.rr0 = (double)(float)rr;
+        p.tol2 = p.tol * p.tol * p.rr0;
         return;
     }
     if (!p.status.bad()) {
@@ -927,7 +953,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
     CUTH_HIP(hipMemcpyAsync(E.st32, hs32, sizeof(CgState<float>) * nprob, hipMemcpyHostToDevice, s));
     InnerProb<double> *d = E.in64;
     auto precond = [&]() {
-        (void)enqueue_precond<float>(E, nprob, nb32, pc, h16, pm, sh32, k, false, false, s, nullptr);
+        (void)enqueue_precond<float>(E, nprob, nb32, pc, h16 ? CS_F16 : CS_OWN, pm, sh32, k, false, false, s, nullptr);
         launch_promote_dot<double>(d, nprob, nb, sh64.vx, sh64.by, eslot<double>(E, P_CHEB), s);
         if (red) launch_reduce_b<double>(d, nprob, eslot<double>(E, P_CHEB), red_rz<double>(E), s);
     };
@@ -937,7 +963,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
         const int cnt = std::min(period, maxit - it);
         for (int q = 0; q < cnt; ++q) {
             const int par = (it + q) & 1;
-            launch_dir_b<double>(d, nprob, nb, pc, early, sh64.vx, sh64.by, par, 0,
+            launch_dir_b<double>(d, nprob, nb, pc, early ? CS_F32 : CS_OWN, sh64.vx, sh64.by, par, 0,
                                  red ? red_rz<double>(E) : eslot<double>(E, P_CHEB), red,
                                  eslot<double>(E, P_DIR), s);
             if (red) launch_reduce_b<double>(d, nprob, eslot<double>(E, P_DIR), red_pmu<double>(E), s);
@@ -949,7 +975,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
         }
         it += cnt;
         // FP64 true residual with the FP64 operator (switch tests b and c)
-        launch_check_b<double>(d, nprob, nb, pc, sh64.vx, sh64.by, eslot<double>(E, P_CHK), s);
+        launch_check_b<double>(d, nprob, nb, pc, CS_OWN, sh64.vx, sh64.by, eslot<double>(E, P_CHK), s);
         ++nchecks;
         CUTH_HIP(hipMemcpyAsync(hs, E.st64, sizeof(CgState<double>) * nprob, hipMemcpyDeviceToHost, s));
         CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<double>(E, P_CHK), sizeof(double) * 2 * (size_t)nb,
@@ -1530,7 +1556,8 @@ void fill_stats(const Problem &p, cuth_stats *stats, float ms_setup, float ms_so
 // Run the refinement for a set of problems on the engine's own stream (waiting
 // for `user` first, and making `user` wait for the result).
 Status run_set(Engine &E, std::vector<Problem *> &ps, hipStream_t user, const Shape &sh32,
-               const Shape &sh64, const cuth_options &o, int period, bool use_graph, Grid *prof) {
+               const Shape &sh64, const cuth_options &o, int period, bool use_graph, Grid *prof,
+               const Shape *sh64_inner = nullptr) {
     const hipStream_t s = E.own;
     CUTH_HIP(hipEventRecord(E.ev_in, user));
     CUTH_HIP(hipStreamWaitEvent(s, E.ev_in, 0));
@@ -1542,7 +1569,8 @@ Status run_set(Engine &E, std::vector<Problem *> &ps, hipStream_t user, const Sh
     else if (o.precision != CUTH_FP64)
         st = run_refinement<float>(E, ps, sh32, sh64, k, o, period, use_graph, s, prof);
     else
-        st = run_refinement<double>(E, ps, sh64, sh64, k, o, period, use_graph, s, prof);
+        st = run_refinement<double>(E, ps, sh64_inner ? *sh64_inner : sh64, sh64, k, o, period,
+                                    use_graph, s, prof);
     if (st.code == CUTH_E_DEVICE || st.code == CUTH_E_NOMEM) return st;
     for (Problem *p : ps)
         if (p->th_final) {
@@ -1585,6 +1613,26 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     p.w64 = g.w64;
     // the stage-switched scheme's preconditioner reads FP16 conductances too
     p.h16 = o.precision == CUTH_MIXED16 || o.precision == CUTH_ADAPTIVE;
+    p.fixed32 = o.precision == CUTH_FP32;
+    // CSR products: one row per lane (vx 1, one layer per lane, 4 wavefronts
+    // per workgroup, as the plain CSR kernel); the engine grows to this shape's
+    // number of workgroups if it has fewer slots
+    const Shape sh_csr{1, 4, 1};
+    if (o.storage == CUTH_STORAGE_CSR) {
+        CUTH_TRY(ensure_csr(g, *su));
+        p.csr = true;
+        const size_t need = (size_t)prob_tiles(g, sh_csr);
+        if (8 * need > g.eng.slot_doubles) {
+            Engine bigger;
+            Status es = engine_alloc(bigger, 1, g.eng.kcap, need);
+            if (es.bad()) {
+                engine_free(bigger);
+                return es;
+            }
+            engine_free(g.eng);
+            g.eng = bigger;
+        }
+    }
     p.thA = g.thA;
     p.thB = g.thB;
     p.tol = default_tol(o, dt);
@@ -1606,7 +1654,8 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         const int kk = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
         CUTH_TRY(tune_fuse<float>(g.eng, ps, kk, sh32, sig.str()));
     }
-    Status rs = run_set(g.eng, ps, g.stream, sh32, g.sh64, o, period, use_graph, &g);
+    Status rs = run_set(g.eng, ps, g.stream, sh32, g.sh64, o, period, use_graph, &g,
+                        p.csr ? &sh_csr : nullptr);
     if (rs.code == CUTH_E_DEVICE || rs.code == CUTH_E_NOMEM) return rs;
     CUTH_HIP(hipEventRecord(g.ev2, g.stream));
     CUTH_TRY(sync_stream(g.stream));
@@ -1697,11 +1746,11 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
         CUTH_HIP(hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s));
         const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
         for (int rep = 0; rep < 2; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2, zsel(1, 0),
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, sh.vx, sh.by, 0, false, false, 2, zsel(1, 0),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 6; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, sh.vx, sh.by, 0, false, false, 2,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, sh.vx, sh.by, 0, false, false, 2,
                              zsel(rep & 1, 1 - (rep & 1)),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e1, s));
@@ -1786,7 +1835,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         auto round = [&]() {
             if (c.fr == 0) {
                 for (int q = 0; q < 4; ++q)
-                    launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16, c.vx, c.by, 0, false, false, 3,
+                    launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, c.vx, c.by, 0, false, false, 3,
                                      zsel(q & 1, 1 - (q & 1)), eslot<T>(E, P_UPD), false,
                                      eslot<T>(E, P_CHEB), s);
             } else {
@@ -1830,7 +1879,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
 Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
                    double *const *T, const cuth_options &o, cuth_stats *stats) {
     if (o.cheb_degree > 256) return Status::err(CUTH_E_INVALID, "cheb_degree above 256");
-    const bool mixed = o.precision == CUTH_MIXED || o.precision == CUTH_MIXED16;
+    const bool mixed = o.precision == CUTH_MIXED || o.precision == CUTH_MIXED16 || o.precision == CUTH_FP32;
     const bool staged = o.precision == CUTH_ADAPTIVE;
     const hipStream_t user = grids[0]->stream;
     // per-system setup (Lanczos bounds cached in each grid)
@@ -1909,6 +1958,7 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                 off += N;
                 p.tol = default_tol(o, 0.0);
                 p.h16 = h16;
+                p.fixed32 = o.precision == CUTH_FP32;
                 p.th_in = p.init;
                 p.in_off = p.init_off;
                 p.th_out = p.thA;
@@ -1978,33 +2028,50 @@ Status apply_op(Grid &g, double dt, int precision, const void *x, void *y) {
     return sync_stream(g.stream);
 }
 
+// CSR copy of a setup's FP64 operator, built once on first use: row pointers on
+// the host (1 + one entry per existing face neighbour), columns and values by
+// k_csr_fill on the device.
+Status ensure_csr(Grid &g, Setup &su) {
+    if (su.csr_ptr) return Status::ok();
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    std::vector<int> ptr((size_t)g.N + 1);
+    int64_t k = 0;
+    size_t r = 0;
+    for (int l = 0; l < nz; ++l)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                ptr[r++] = (int)k;
+                k += 1 + (i > 0) + (i < nx - 1) + (j > 0) + (j < ny - 1) + (l > 0) + (l < nz - 1);
+                if (k >= ((int64_t)1 << 31) - 1)
+                    return Status::err(CUTH_E_INVALID, "CSR needs fewer than 2^31 nonzeros");
+            }
+    ptr[r] = (int)k;
+    int *p = nullptr, *c = nullptr;
+    double *v = nullptr;
+    Status st = dev_alloc(&p, ptr.size());
+    if (!st.bad()) st = dev_alloc(&c, (size_t)k);
+    if (!st.bad()) st = dev_alloc(&v, (size_t)k);
+    if (st.bad()) {
+        dev_free(p);
+        dev_free(c);
+        dev_free(v);
+        return st;
+    }
+    su.csr_ptr = p;
+    su.csr_col = c;
+    su.csr_val = v;
+    su.csr_nnz = k;
+    CUTH_HIP(hipMemcpy(p, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    launch_csr_fill(view64(g, su), p, c, v, g.stream);
+    CUTH_HIP(hipGetLastError());
+    return sync_stream(g.stream);
+}
+
 Status apply_csr(Grid &g, double dt, const double *x, double *y) {
     Status st;
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    if (!su->csr_ptr) {
-        // row pointers on the host: 1 + one entry per existing face neighbour
-        const int nx = g.nx, ny = g.ny, nz = g.nz;
-        std::vector<int> ptr((size_t)g.N + 1);
-        int64_t k = 0;
-        size_t r = 0;
-        for (int l = 0; l < nz; ++l)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i) {
-                    ptr[r++] = (int)k;
-                    k += 1 + (i > 0) + (i < nx - 1) + (j > 0) + (j < ny - 1) + (l > 0) + (l < nz - 1);
-                    if (k >= ((int64_t)1 << 31) - 1)
-                        return Status::err(CUTH_E_INVALID, "CSR needs fewer than 2^31 nonzeros");
-                }
-        ptr[r] = (int)k;
-        CUTH_TRY(dev_alloc(&su->csr_ptr, ptr.size()));
-        CUTH_TRY(dev_alloc(&su->csr_col, (size_t)k));
-        CUTH_TRY(dev_alloc(&su->csr_val, (size_t)k));
-        su->csr_nnz = k;
-        CUTH_HIP(hipMemcpy(su->csr_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
-        launch_csr_fill(view64(g, *su), su->csr_ptr, su->csr_col, su->csr_val, g.stream);
-        CUTH_HIP(hipGetLastError());
-    }
+    CUTH_TRY(ensure_csr(g, *su));
     launch_csr_spmv(g.N, su->csr_ptr, su->csr_col, su->csr_val, x, y, g.stream);
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
@@ -2069,7 +2136,7 @@ static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, con
     CgState<T> *hs = Sel<T>::hs(E);
     std::memset(hs, 0, sizeof(CgState<T>));
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
-    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, p.h16, 0, sh, cc.k, false, false, g.stream,
+    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, p.h16 ? CS_F16 : CS_OWN, 0, sh, cc.k, false, false, g.stream,
                                        nullptr);
     if (got != zfin) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
     CUTH_HIP(hipGetLastError());

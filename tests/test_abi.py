@@ -40,7 +40,7 @@ def test_default_options(lib):
     lib.cuth_default_options(ctypes.byref(o))
     assert o.precision == _lib.CUTH_MIXED and o.tol == 0.0
     assert o.cheb_degree == 30 and o.lanczos_steps == 30
-    assert o.preconditioner == 0
+    assert o.preconditioner == 0 and o.storage == 0
     # the ctypes mirror has the header's size (no field missing or misplaced)
     assert ctypes.sizeof(_lib.Options) == 48
 
@@ -113,9 +113,11 @@ def test_precision_names_match_header(lib):
     from paper_2606_17850_amd import _lib
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "cuth.h")).read()
     enum = dict((k, int(v)) for k, v in
-                re.findall(r"(CUTH_FP64|CUTH_MIXED16|CUTH_MIXED|CUTH_ADAPTIVE)\s*=\s*(\d+)", hdr))
+                re.findall(r"(CUTH_FP64|CUTH_FP32|CUTH_MIXED16|CUTH_MIXED|CUTH_ADAPTIVE)\s*=\s*(\d+)", hdr))
     assert enum == {"CUTH_FP64": _lib.CUTH_FP64, "CUTH_MIXED": _lib.CUTH_MIXED,
-                    "CUTH_MIXED16": _lib.CUTH_MIXED16, "CUTH_ADAPTIVE": _lib.CUTH_ADAPTIVE}
+                    "CUTH_MIXED16": _lib.CUTH_MIXED16, "CUTH_ADAPTIVE": _lib.CUTH_ADAPTIVE,
+                    "CUTH_FP32": _lib.CUTH_FP32}
+    assert cuth.options("fp32").precision == enum["CUTH_FP32"]
     assert cuth.options("mixed16").precision == enum["CUTH_MIXED16"]
     assert cuth.options("fp64").precision == enum["CUTH_FP64"]
     with pytest.raises(ValueError):

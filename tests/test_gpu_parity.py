@@ -332,6 +332,32 @@ def test_solve_adaptive_stage_switched():
         gg.close()
 
 
+def test_solve_fixed_fp32_drifts():
+    """The fixed-FP32 baseline of Ablation II: one FP32 PCG to ||r|| <= 1e-10
+    ||b|| on its own recursive residual, no refinement.  It takes about the FP64
+    iteration count, its FP64 true residual stays far above the tolerance its
+    recursive residual met, and its rise error is FP32-sized: larger than the
+    mixed scheme's and the FP64 solver's, yet bounded."""
+    say("solve fixed fp32")
+    for st, P in (w.config4_small(), w.config0()):
+        ref = _ref_steady(st, P)
+        g = grid_of(st)
+        T64, s64 = g.solve(t64(P), precision="fp64")
+        T32, s32 = g.solve(t64(P), precision="fp32")
+        Tm, _ = g.solve(t64(P), precision="mixed")
+        e32 = rise_err(T32.cpu().numpy(), ref, st.t_amb)
+        e64 = rise_err(T64.cpu().numpy(), ref, st.t_amb)
+        em = rise_err(Tm.cpu().numpy(), ref, st.t_amb)
+        say(f"  fp32 cg {s32['cg_iters']} (fp64 {s64['cg_iters']}) cycles {s32['outer_cycles']} "
+            f"true relres {s32['rel_residual']:.2e} err {e32:.2e} (mixed {em:.2e}, fp64 {e64:.2e})")
+        assert s32["outer_cycles"] == 1
+        assert abs(s32["cg_iters"] - s64["cg_iters"]) <= 0.25 * s64["cg_iters"] + 2
+        assert s32["rel_residual"] > 10 * 1e-10
+        assert e32 <= 1e-3
+        assert e32 > em and e32 > e64
+        g.close()
+
+
 @pytest.mark.parametrize("pcname", ["jacobi", "none"])
 def test_baseline_preconditioners_match_oracle_pcg(pcname):
     """Jacobi-PCG and plain CG (the baselines of Ablation III) in FP64: the
@@ -360,7 +386,56 @@ def test_baseline_preconditioners_match_oracle_pcg(pcname):
     Tm, _ = g.solve(t64(P), precision="mixed", preconditioner=pcname, max_inner=20000,
                     check_period=200, max_outer=40)
     assert rise_err(Tm.cpu().numpy(), _ref_steady(st, P), st.t_amb) <= 1e-8
+    # and so does the stage-switched scheme (Ablation III, optimisations on)
+    Ta, sa = g.solve(t64(P), precision="adaptive", preconditioner=pcname, max_inner=20000,
+                     check_period=200, max_outer=40)
+    say(f"  adaptive cg {sa['cg_iters']} cycles {sa['outer_cycles']}")
+    assert rise_err(Ta.cpu().numpy(), _ref_steady(st, P), st.t_amb) <= 1e-9
+    assert sa["rel_residual"] <= 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("pcname", ["chebyshev", "jacobi", "none"])
+def test_csr_storage_pcg(pcname):
+    """The CSR baseline storage (Ablation I; Ablation III with the optimisation
+    off) runs the same FP64 PCG with row-wise CSR products: the same CG
+    iteration count as the stencil within 2 (sums in another order), and both
+    meet the FP64 bar against the direct oracle, on config 0 and on a ragged
+    grid with per-cell multipliers; one backward-Euler step on CSR matches the
+    oracle too.  CSR with mixed precision, or in a batch, is refused."""
+    import paper_2606_17850_amd as cuth
+    say(f"csr storage {pcname}")
+    for st, P in (w.config0(), (ragged_stack(70, 9, mult=True), None)):
+        if P is None:
+            P = np.zeros(st.shape)
+            P[0] = np.random.default_rng(6).uniform(0, 2e-3, (st.ny, st.nx))
+        ref = _ref_steady(st, P)
+        g = grid_of(st)
+        kw = dict(precision="fp64", preconditioner=pcname, max_inner=20000,
+                  check_period=0 if pcname == "chebyshev" else 20000)
+        Ts, ss = g.solve(t64(P), **kw)
+        Tc, sc = g.solve(t64(P), storage="csr", **kw)
+        ec = rise_err(Tc.cpu().numpy(), ref, st.t_amb)
+        say(f"  {st.shape} stencil {ss['cg_iters']} csr {sc['cg_iters']} err {ec:.2e}")
+        assert abs(sc["cg_iters"] - ss["cg_iters"]) <= 2
+        assert ec <= 1e-9
+        assert sc["rel_residual"] <= 1e-10
+        if pcname == "chebyshev" and st.n < 10000:
+            dt = 1e-4
+            th0 = np.random.default_rng(8).uniform(0, 5.0, st.n)
+            ref_tr = transient.step(st, P.ravel(), th0, dt)
+            Tt, _ = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision="fp64",
+                                     storage="csr")
+            got = Tt.cpu().numpy() - st.t_amb
+            assert np.abs(got - ref_tr).max() <= 1e-10 * np.abs(ref_tr).max()
+        if pcname == "none":
+            with pytest.raises(cuth.CuthError) as e:
+                g.solve(t64(P), precision="mixed", storage="csr")
+            assert e.value.status == cuth._lib.CUTH_E_INVALID
+            with pytest.raises(cuth.CuthError) as e:
+                cuth.solve_batch([g], [t64(P)], nrhs=1, precision="fp64", storage="csr")
+            assert e.value.status == cuth._lib.CUTH_E_INVALID
+        g.close()
 
 
 @pytest.mark.parametrize("shape", ["2,8", "1,1", "3,4", "2,64"])
