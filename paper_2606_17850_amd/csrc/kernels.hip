@@ -33,6 +33,8 @@
 #include "cuth_internal.hpp"
 
 #include <algorithm>
+#include <cstdlib>
+#include <type_traits>
 #include <cmath>
 
 namespace cuth {
@@ -43,15 +45,110 @@ struct alignas(sizeof(T) * VX) Vec {
     T a[VX];
 };
 
+// Device memory (hipMalloc'd buffers only: never LDS or private memory) is
+// reached through global-address-space pointers: the vectors and coefficients
+// come from descriptors in memory, so the compiler cannot place them and would
+// emit flat accesses, which also count against the LDS counter (a wait for a
+// cross-lane exchange would then wait for every load in flight).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+// Raw words of B bytes (class types are moved through these, because
+// address-space-qualified class objects cannot be copied in host passes).
+template <int B> struct Words;
+template <> struct Words<2> { using type = unsigned short; };
+template <> struct Words<4> { using type = unsigned int; };
+template <> struct Words<8> { using type = unsigned int __attribute__((ext_vector_type(2))); };
+template <> struct Words<16> { using type = unsigned int __attribute__((ext_vector_type(4))); };
+
+// One value (a number, or a struct of 32-bit words such as LayerCoef).
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    if constexpr (std::is_arithmetic<T>::value) {
+        return *as_global(p);
+    } else {
+        static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+        const __attribute__((address_space(1))) unsigned int *q =
+            (const __attribute__((address_space(1))) unsigned int *)(const void *)p;
+        unsigned int w[sizeof(T) / 4];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+        T v;
+        __builtin_memcpy(&v, w, sizeof(T));
+        return v;
+    }
+}
+
+// A value that no kernel writes while it runs and every lane of the wavefront
+// reads at the same address (per-layer coefficients): loaded through the
+// constant address space, so that it can come through scalar loads.
+template <typename T>
+__device__ __forceinline__ T gldc(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    const __attribute__((address_space(4))) unsigned int *q =
+        (const __attribute__((address_space(4))) unsigned int *)(const void *)p;
+    unsigned int w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
 template <typename T, int VX>
 __device__ __forceinline__ Vec<T, VX> vload(const T *p) {
     // callers pass cells whose index is a multiple of VX (VX divides nx)
-    return *reinterpret_cast<const Vec<T, VX> *>(__builtin_assume_aligned(p, sizeof(T) * VX));
+    using W = typename Words<(int)sizeof(Vec<T, VX>)>::type;
+    const void *a = __builtin_assume_aligned(p, sizeof(T) * VX);
+    const W w = *(const __attribute__((address_space(1))) W *)a;
+    return __builtin_bit_cast(Vec<T, VX>, w);
 }
 
 template <typename T, int VX>
 __device__ __forceinline__ void vstore(T *p, const Vec<T, VX> &v) {
+    using W = typename Words<(int)sizeof(Vec<T, VX>)>::type;
+    *(__attribute__((address_space(1))) W *)(void *)p = __builtin_bit_cast(W, v);
+}
+
+// Vectors of the workgroup's LDS (pointers derived from a __shared__ array,
+// which the compiler turns into LDS instructions).  vload/vstore must never
+// see such a pointer: an LDS address taken as a global one is unmapped.
+template <typename T, int VX>
+__device__ __forceinline__ Vec<T, VX> lds_load(const T *p) {
+    return *reinterpret_cast<const Vec<T, VX> *>(p);
+}
+template <typename T, int VX>
+__device__ __forceinline__ void lds_store(T *p, const Vec<T, VX> &v) {
     *reinterpret_cast<Vec<T, VX> *>(p) = v;
+}
+
+// The value held by the lane to the left (lane - 1) or to the right (lane + 1)
+// in the wavefront, moved by a DPP wavefront shift (a VALU operation, no LDS
+// traffic); lane 0, respectively lane 63, receives 0.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+        w[i] = __builtin_amdgcn_update_dpp(0, w[i], CTRL, 0xf, 0xf, false);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T lane_left(T v) {
+    return dpp_move<0x138>(v);   // wave_shr:1
+}
+template <typename T>
+__device__ __forceinline__ T lane_right(T v) {
+    return dpp_move<0x130>(v);   // wave_shl:1
 }
 
 template <typename T, int VX>
@@ -213,57 +310,99 @@ __device__ __forceinline__ Vec<T, VX> f32load(const float *p) {
 
 // Lateral conductances of a per-cell operator at cell c of layer L for one
 // lane: gxp, gyp (to +x, +y), gym (from -y) and gxl (from -x, via the lane to the
-// left or a load on lane 0), from the source CS.
+// left or a load on lane 0), from the source CS.  Split in two so that a kernel
+// can issue the loads (lateral_load) a layer ahead of their use
+// (lateral_finish); lateral_coefs does both at once.
+//
+// Raw loads of one lane: the +x, +y and -y values and the west value.
+template <typename T, int VX, int CS>
+struct LatRaw {
+    Vec<T, VX> xp, yp, ym;
+    T xw;
+};
+template <typename T, int VX>
+struct LatRaw<T, VX, CS_F16> {
+    Vec<uint16_t, VX> xp, yp, ym;
+    uint16_t xw;
+};
+template <typename T, int VX>
+struct LatRaw<T, VX, CS_F32> {
+    Vec<float, VX> xp, yp, ym;
+    float xw;
+};
+
+template <typename T, int VX, int CS>
+__device__ __forceinline__ LatRaw<T, VX, CS> lateral_load(const OpView<T> &op, int64_t c, int lane,
+                                                          bool act, bool has_l, bool has_s) {
+    const int nx = op.nx;
+    LatRaw<T, VX, CS> q;
+    if constexpr (CS == CS_F16) {
+        // FP16-stored lateral conductances.  Every lane loads from an
+        // in-bounds cell (inactive lanes sit at cell 0, a missing south or
+        // west neighbour falls back to the cell itself) and selects after the
+        // promotion: a guarded load with the promotion inside made the
+        // compiler wait for each load in turn.
+        q.xp = vload<uint16_t, VX>(op.hx + c);
+        q.yp = vload<uint16_t, VX>(op.hy + c);
+        q.ym = vload<uint16_t, VX>(op.hy + (has_s ? c - nx : c));
+        q.xw = gld(op.hx + (has_l ? c - 1 : c));
+    } else if constexpr (CS == CS_F32) {
+        // FP32-stored lateral conductances, promoted (loads as above)
+        q.xp = vload<float, VX>(op.fx + c);
+        q.yp = vload<float, VX>(op.fy + c);
+        q.ym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
+        q.xw = gld(op.fx + (has_l ? c - 1 : c));
+    } else {
+        const Vec<T, VX> zero = vzero<T, VX>();
+        q.xp = act ? vload<T, VX>(op.gx + c) : zero;
+        q.yp = act ? vload<T, VX>(op.gy + c) : zero;
+        q.ym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+        q.xw = (lane == 0 && has_l) ? gld(op.gx + c - 1) : T(0);
+    }
+    return q;
+}
+
+template <typename T, int VX, int CS>
+__device__ __forceinline__ void lateral_finish(const LatRaw<T, VX, CS> &q, const LayerCoef<T> &L,
+                                               int lane, bool act, bool has_l, bool has_s,
+                                               Vec<T, VX> &gxp, Vec<T, VX> &gyp, Vec<T, VX> &gym,
+                                               T &gxl) {
+    if constexpr (CS == CS_F16 || CS == CS_F32) {
+        T west;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            if constexpr (CS == CS_F16) {
+                gxp.a[e] = act ? (T)h16one(q.xp.a[e]) * L.hs : T(0);
+                gyp.a[e] = act ? (T)h16one(q.yp.a[e]) * L.hs : T(0);
+                gym.a[e] = has_s ? (T)h16one(q.ym.a[e]) * L.hs : T(0);
+            } else {
+                gxp.a[e] = act ? (T)q.xp.a[e] : T(0);
+                gyp.a[e] = act ? (T)q.yp.a[e] : T(0);
+                gym.a[e] = has_s ? (T)q.ym.a[e] : T(0);
+            }
+        }
+        // every lane promotes its west value; lane 0 selects it (a branch
+        // around the promotion would wait for the load)
+        if constexpr (CS == CS_F16) west = has_l ? (T)h16one(q.xw) * L.hs : T(0);
+        else west = has_l ? (T)q.xw : T(0);
+        gxl = lane_left(gxp.a[VX - 1]);
+        gxl = lane == 0 ? west : gxl;
+    } else {
+        gxp = q.xp;
+        gyp = q.yp;
+        gym = q.ym;
+        gxl = lane_left(gxp.a[VX - 1]);
+        if (lane == 0) gxl = q.xw;
+    }
+}
+
 template <typename T, int VX, int CS>
 __device__ __forceinline__ void lateral_coefs(const OpView<T> &op, const LayerCoef<T> &L, int64_t c,
                                               int lane, bool act, bool has_l, bool has_s,
                                               Vec<T, VX> &gxp, Vec<T, VX> &gyp, Vec<T, VX> &gym,
                                               T &gxl) {
-    const int nx = op.nx;
-    const Vec<T, VX> zero = vzero<T, VX>();
-    if constexpr (CS == CS_F16) {
-        // FP16-stored lateral conductances.  Every lane loads from an
-        // in-bounds cell (inactive lanes sit at cell 0, a missing south or
-        // west neighbour falls back to the cell itself), promotes, then
-        // selects: a guarded load with the promotion inside made the
-        // compiler wait for each load in turn.
-        const Vec<uint16_t, VX> bxp = vload<uint16_t, VX>(op.hx + c);
-        const Vec<uint16_t, VX> byp = vload<uint16_t, VX>(op.hy + c);
-        const Vec<uint16_t, VX> bym = vload<uint16_t, VX>(op.hy + (has_s ? c - nx : c));
-        const uint16_t bxl = op.hx[has_l ? c - 1 : c];
-#pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            gxp.a[e] = act ? (T)h16one(bxp.a[e]) * L.hs : T(0);
-            gyp.a[e] = act ? (T)h16one(byp.a[e]) * L.hs : T(0);
-            gym.a[e] = has_s ? (T)h16one(bym.a[e]) * L.hs : T(0);
-        }
-        // every lane promotes its west value; lane 0 selects it (a branch
-        // around the promotion would wait for the load)
-        const T west = has_l ? (T)h16one(bxl) * L.hs : T(0);
-        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-        gxl = lane == 0 ? west : gxl;
-    } else if constexpr (CS == CS_F32) {
-        // FP32-stored lateral conductances, promoted (loads as above)
-        const Vec<float, VX> fxp = vload<float, VX>(op.fx + c);
-        const Vec<float, VX> fyp = vload<float, VX>(op.fy + c);
-        const Vec<float, VX> fym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
-        const float fxl = op.fx[has_l ? c - 1 : c];
-#pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            gxp.a[e] = act ? (T)fxp.a[e] : T(0);
-            gyp.a[e] = act ? (T)fyp.a[e] : T(0);
-            gym.a[e] = has_s ? (T)fym.a[e] : T(0);
-        }
-        const T west = has_l ? (T)fxl : T(0);
-        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-        gxl = lane == 0 ? west : gxl;
-    } else {
-        gxp = act ? vload<T, VX>(op.gx + c) : zero;
-        gyp = act ? vload<T, VX>(op.gy + c) : zero;
-        gym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
-        gxl = __shfl_up(gxp.a[VX - 1], 1, 64);
-        if (lane == 0) gxl = has_l ? op.gx[c - 1] : T(0);
-    }
+    lateral_finish<T, VX, CS>(lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s), L, lane, act,
+                              has_l, has_s, gxp, gyp, gym, gxl);
 }
 
 // March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
@@ -291,9 +430,10 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             Vec<T, VX> ax;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                const int k1 = op.csr_ptr[c + e + 1];
+                const int k1 = gld(op.csr_ptr + c + e + 1);
                 T a = T(0);
-                for (int k = op.csr_ptr[c + e]; k < k1; ++k) a += (T)op.csr_val[k] * XS(op.csr_col[k]);
+                for (int k = gld(op.csr_ptr + c + e); k < k1; ++k)
+                    a += (T)gld(op.csr_val + k) * XS(gld(op.csr_col + k));
                 ax.a[e] = a;
             }
             emit(l, c, xc, ax, PRE(c));
@@ -304,20 +444,46 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     const bool has_s = act && ln.j > 0, has_n = act && ln.j < ny - 1;
     int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
     const Vec<T, VX> zero = vzero<T, VX>();
+    // All loads of a layer are gathered in one Loads set, issued before any
+    // of them is used.  FP32 operators issue layer l + 1's set while layer l is
+    // computed (one layer of software pipelining; measured 2-4 % faster FP32
+    // sweeps); FP64 ones issue each set in its own layer (the second set's
+    // registers cost FP64 kernels occupancy: 5-16 % slower).  Inactive lanes
+    // sit at cells (l - l0) * plane, and a missing neighbour is not loaded,
+    // so every address is in bounds.
+    using Pre = decltype(PRE(int64_t(0)));
+    struct Loads {
+        Vec<T, VX> xup, xso, xno;
+        T west, east;
+        LatRaw<T, VX, CS> lat;
+        Pre pre;
+    };
+    auto issue = [&](int l, int64_t cc) {
+        Loads q;
+        q.xup = (act && l + 1 < nz) ? XV(cc + plane) : zero;
+        q.xso = has_s ? XV(cc - nx) : zero;
+        q.xno = has_n ? XV(cc + nx) : zero;
+        q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : T(0);
+        q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : T(0);
+        if constexpr (PC) q.lat = lateral_load<T, VX, CS>(op, cc, ln.lane, act, has_l, has_s);
+        q.pre = PRE(cc);
+        return q;
+    };
     Vec<T, VX> xdn = (act && ln.l0 > 0) ? XV(c - plane) : zero;
     Vec<T, VX> xc = act ? XV(c) : zero;
-    for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
-        const LayerCoef<T> L = op.lc[l];
-        const Vec<T, VX> xup = (act && l + 1 < nz) ? XV(c + plane) : zero;
-        const Vec<T, VX> xso = has_s ? XV(c - nx) : zero;
-        const Vec<T, VX> xno = has_n ? XV(c + nx) : zero;
-        T left = __shfl_up(xc.a[VX - 1], 1, 64);
-        T right = __shfl_down(xc.a[0], 1, 64);
-        if (ln.lane == 0) left = has_l ? XS(c - 1) : T(0);
-        if (ln.lane == kWave - 1) right = has_r ? XS(c + VX) : T(0);
+    // layer l's body with its loads already in registers (cur)
+    auto layer = [&](int l, int64_t c, const Loads &cur) {
+        const LayerCoef<T> L = gldc(op.lc + l);
+        const Vec<T, VX> &xup = cur.xup, &xso = cur.xso, &xno = cur.xno;
+        const auto &pre = cur.pre;
+        T left = lane_left(xc.a[VX - 1]);
+        T right = lane_right(xc.a[0]);
+        if (ln.lane == 0) left = cur.west;
+        if (ln.lane == kWave - 1) right = cur.east;
         Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
-        if constexpr (PC) lateral_coefs<T, VX, CS>(op, L, c, ln.lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+        if constexpr (PC)
+            lateral_finish<T, VX, CS>(cur.lat, L, ln.lane, act, has_l, has_s, gxp, gyp, gym, gxl);
         Vec<T, VX> ax;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
@@ -344,9 +510,29 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
             ax.a[e] = a;
         }
-        if (act) emit(l, c, xc, ax, PRE(c));
+        if (act) emit(l, c, xc, ax, pre);
         xdn = xc;
-        xc = xup;
+        xc = cur.xup;
+    };
+    if constexpr (sizeof(T) == 4) {
+        // two sets alternate (unrolled by hand: a copy from one set to the
+        // other would make the wavefront wait for the loads in flight)
+        Loads qa, qb;
+        int l = ln.l0;
+        if (l < ln.l1) qa = issue(l, c);
+        while (l < ln.l1) {
+            if (l + 1 < ln.l1) qb = issue(l + 1, c + plane);
+            layer(l, c, qa);
+            ++l;
+            c += plane;
+            if (l >= ln.l1) break;
+            if (l + 1 < ln.l1) qa = issue(l + 1, c + plane);
+            layer(l, c, qb);
+            ++l;
+            c += plane;
+        }
+    } else {
+        for (int l = ln.l0; l < ln.l1; ++l, c += plane) layer(l, c, issue(l, c));
     }
 }
 
@@ -377,7 +563,7 @@ __global__ __launch_bounds__(512) void k_apply(OpView<T> op, const T *__restrict
                                                T *__restrict__ y) {
     const Lane ln = lane_of<VX>(op);
     column_pre<T, PC, VX, H16 ? CS_F16 : CS_OWN>(
-        op, ln, [&](int64_t q) { return vload<T, VX>(x + q); }, [&](int64_t q) { return x[q]; },
+        op, ln, [&](int64_t q) { return vload<T, VX>(x + q); }, [&](int64_t q) { return gld(x + q); },
         [](int64_t) { return NoEx{}; },
         [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const NoEx &) {
             vstore<T, VX>(y + c, ax);
@@ -444,8 +630,8 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
         }
     };
     auto XS = [&](int64_t q) -> T {
-        if constexpr (MODE == 1) return r[q] * inv_th;
-        else return z[q];
+        if constexpr (MODE == 1) return gld(r + q) * inv_th;
+        else return gld(z + q);
     };
     struct Ex {
         Vec<T, VX> r, zm;
@@ -545,18 +731,23 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
         T gxl = T(0);
         if (doA) {
             // ---- stage A: z_{j+1} at layer l
-            const LayerCoef<T> L = op.lc[l];
+            const LayerCoef<T> L = gldc(op.lc + l);
+            // every load of the layer is issued before the first use
             xup = (act && l + 1 < nz) ? vload<T, VX>(zN + c + plane) : zero;
             const Vec<T, VX> xso = has_s ? vload<T, VX>(zN + c - nx) : zero;
             const Vec<T, VX> xno = has_n ? vload<T, VX>(zN + c + nx) : zero;
-            T left = __shfl_up(xc.a[VX - 1], 1, 64);
-            T right = __shfl_down(xc.a[0], 1, 64);
-            if (lane == 0) left = has_l ? zN[c - 1] : T(0);
-            if (lane == kWave - 1) right = has_r ? zN[c + VX] : T(0);
-            if constexpr (PC)
-                lateral_coefs<T, VX, CS>(op, L, c, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+            const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
+            const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
+            [[maybe_unused]] LatRaw<T, VX, CS> lat;
+            if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
             rv = act ? vload<T, VX>(r + c) : zero;
             const Vec<T, VX> zm = act ? vload<T, VX>(zP + c) : zero;
+            T left = lane_left(xc.a[VX - 1]);
+            T right = lane_right(xc.a[0]);
+            if (lane == 0) left = west;
+            if (lane == kWave - 1) right = east;
+            if constexpr (PC)
+                lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
                 const int i = xo + e;
@@ -582,17 +773,17 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                 if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
                 zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * (rv.a[e] - a) : T(0);
             }
-            if (xo < W) vstore<T, VX>(ring_at(l, rs) + xo, zn);
+            if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
             if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
         }
         __syncthreads();
         // ---- stage B: z_{j+2} at layer lb = l - 1
         const int lb = l - 1;
         if (inner && lb >= l0 && lb < l1) {
-            const LayerCoef<T> L = op.lc[lb];
+            const LayerCoef<T> L = gldc(op.lc + lb);
             const T *rowc = ring_at(lb, rs);
-            const Vec<T, VX> so = vload<T, VX>(ring_at(lb, rs - 1) + xo);
-            const Vec<T, VX> no = vload<T, VX>(ring_at(lb, rs + 1) + xo);
+            const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, rs - 1) + xo);
+            const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, rs + 1) + xo);
             const T left = has_l ? rowc[xo - 1] : T(0);
             const T right = has_r ? rowc[xo + VX] : T(0);
             const Vec<T, VX> &y = zA_m1;
@@ -673,7 +864,7 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
         const Vec<T, VX> rv = vload<T, VX>(r + c);
         Vec<T, VX> zv;
         [[maybe_unused]] LayerCoef<T> L;
-        if constexpr (PM == PM_JACOBI) L = op.lc[l];
+        if constexpr (PM == PM_JACOBI) L = gldc(op.lc + l);
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
             if constexpr (PM == PM_SCALE) {
@@ -683,8 +874,8 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
                 T d = L.sink + (l > 0 ? L.gzd : T(0)) + (l < nz - 1 ? L.gzu : T(0));
                 if constexpr (PC) {
                     const int64_t q = c + e;
-                    d += op.gx[q] + op.gy[q] + (i > 0 ? op.gx[q - 1] : T(0)) +
-                         (ln.j > 0 ? op.gy[q - nx] : T(0));
+                    d += gld(op.gx + q) + gld(op.gy + q) + (i > 0 ? gld(op.gx + q - 1) : T(0)) +
+                         (ln.j > 0 ? gld(op.gy + q - nx) : T(0));
                 } else {
                     d += L.gx * (T)((i > 0) + (i < nx - 1)) + L.gy * (T)((ln.j > 0) + (ln.j < ny - 1));
                 }
@@ -737,7 +928,7 @@ __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ 
         }
         return v;
     };
-    auto XS = [&](int64_t q) -> T { return has_p ? z[q] + beta * pold[q] : z[q]; };
+    auto XS = [&](int64_t q) -> T { return has_p ? gld(z + q) + beta * gld(pold + q) : gld(z + q); };
     column_pre<T, PC, VX, CS>(op, ln, XV, XS, [](int64_t) { return NoEx{}; },
                       [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap, const NoEx &) {
                           vstore<T, VX>(pnew + c, p);
@@ -877,7 +1068,7 @@ __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict_
     column_pre<T, PC, VX, CS>(
         op, ln,
         [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
-        [&](int64_t q) { return have_x ? x[q] : T(0); },
+        [&](int64_t q) { return have_x ? gld(x + q) : T(0); },
         [&](int64_t c) { return Ex{vload<T, VX>(rhat + c), vload<T, VX>(rlow + c)}; },
         [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const Ex &ex) {
             const Vec<T, VX> &rh = ex.rh, &rr = ex.rr;
@@ -911,8 +1102,8 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     const double in_off = P.in_off, tn_off = P.tn_off;
     double acc[kResidualValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
     auto XS = [&](int64_t q) -> double {
-        double v = th_in ? th_in[q] - in_off : 0.0;
-        if (delta) v += (double)delta[q];
+        double v = th_in ? gld(th_in + q) - in_off : 0.0;
+        if (delta) v += (double)gld(delta + q);
         return v;
     };
     auto XV = [&](int64_t q) -> Vec<double, VX> {
@@ -930,7 +1121,7 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     };
     column<double, PC, VX>(
         op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
-            const double cap = op.lc[l].cap;
+            const double cap = gldc(op.lc + l).cap;
             const Vec<double, VX> pv = vload<double, VX>(pw + c);
             const Vec<double, VX> tv = tn ? vload<double, VX>(tn + c) : vzero<double, VX>();
             Vec<TD, VX> dv;
