@@ -353,10 +353,11 @@ __device__ __forceinline__ LatRaw<T, VX, CS> lateral_load(const OpView<T> &op, i
         q.ym = vload<float, VX>(op.fy + (has_s ? c - nx : c));
         q.xw = gld(op.fx + (has_l ? c - 1 : c));
     } else {
-        const Vec<T, VX> zero = vzero<T, VX>();
-        q.xp = act ? vload<T, VX>(op.gx + c) : zero;
-        q.yp = act ? vload<T, VX>(op.gy + c) : zero;
-        q.ym = has_s ? vload<T, VX>(op.gy + c - nx) : zero;
+        // vector loads unguarded as in the column walker (callers discard the
+        // terms of a missing neighbour); lane 0's west value guarded
+        q.xp = vload<T, VX>(op.gx + c);
+        q.yp = vload<T, VX>(op.gy + c);
+        q.ym = vload<T, VX>(op.gy + (has_s ? c - nx : c));
         q.xw = (lane == 0 && has_l) ? gld(op.gx + c - 1) : T(0);
     }
     return q;
@@ -445,7 +446,13 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     int64_t c = act ? ln.i0 + (int64_t)nx * ln.j + plane * ln.l0 : 0;
     const Vec<T, VX> zero = vzero<T, VX>();
     // All loads of a layer are gathered in one Loads set, issued before any
-    // of them is used.  FP32 operators issue layer l + 1's set while layer l is
+    // of them is used.  The vector loads are not guarded: a missing neighbour
+    // is read at the cell itself and an inactive lane at its own in-bounds
+    // cell, and every such value only feeds a term the boundary tests below
+    // discard (or a result that is not emitted); a guard costs a branch per
+    // load and makes the compiler wait for every load in flight where the
+    // branches meet.  Only the edge lanes' west and east values stay guarded
+    // (unguarded, they would be 64-lane gathers for two lanes' values).  FP32 operators issue layer l + 1's set while layer l is
     // computed (one layer of software pipelining; measured 2-4 % faster FP32
     // sweeps); FP64 ones issue each set in its own layer (the second set's
     // registers cost FP64 kernels occupancy: 5-16 % slower).  Inactive lanes
@@ -460,17 +467,17 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     };
     auto issue = [&](int l, int64_t cc) {
         Loads q;
-        q.xup = (act && l + 1 < nz) ? XV(cc + plane) : zero;
-        q.xso = has_s ? XV(cc - nx) : zero;
-        q.xno = has_n ? XV(cc + nx) : zero;
+        q.xup = XV((act && l + 1 < nz) ? cc + plane : cc);
+        q.xso = XV(has_s ? cc - nx : cc);
+        q.xno = XV(has_n ? cc + nx : cc);
         q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : T(0);
         q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : T(0);
         if constexpr (PC) q.lat = lateral_load<T, VX, CS>(op, cc, ln.lane, act, has_l, has_s);
         q.pre = PRE(cc);
         return q;
     };
-    Vec<T, VX> xdn = (act && ln.l0 > 0) ? XV(c - plane) : zero;
-    Vec<T, VX> xc = act ? XV(c) : zero;
+    Vec<T, VX> xdn = XV((act && ln.l0 > 0) ? c - plane : c);
+    Vec<T, VX> xc = XV(c);
     // layer l's body with its loads already in registers (cur)
     auto layer = [&](int l, int64_t c, const Loads &cur) {
         const LayerCoef<T> L = gldc(op.lc + l);
@@ -516,17 +523,26 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     };
     if constexpr (sizeof(T) == 4) {
         // two sets alternate (unrolled by hand: a copy from one set to the
-        // other would make the wavefront wait for the loads in flight)
+        // other would make the wavefront wait for the loads in flight), and
+        // the last layer is peeled, so that no prefetch sits under a branch
+        // (where the two paths meet, the compiler would wait for it)
         Loads qa, qb;
         int l = ln.l0;
         if (l < ln.l1) qa = issue(l, c);
         while (l < ln.l1) {
-            if (l + 1 < ln.l1) qb = issue(l + 1, c + plane);
+            if (l + 1 >= ln.l1) {
+                layer(l, c, qa);
+                break;
+            }
+            qb = issue(l + 1, c + plane);
             layer(l, c, qa);
             ++l;
             c += plane;
-            if (l >= ln.l1) break;
-            if (l + 1 < ln.l1) qa = issue(l + 1, c + plane);
+            if (l + 1 >= ln.l1) {
+                layer(l, c, qb);
+                break;
+            }
+            qa = issue(l + 1, c + plane);
             layer(l, c, qb);
             ++l;
             c += plane;
@@ -719,8 +735,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
     auto ring_at = [&](int l, int row) -> T * { return ring + ((size_t)((l % 3) * RR + row)) * W; };
 
     int64_t c = act ? xo + (int64_t)nx * jr + plane * la0 : 0;
-    Vec<T, VX> xdn = (act && la0 > 0) ? vload<T, VX>(zN + c - plane) : zero;
-    Vec<T, VX> xc = act ? vload<T, VX>(zN + c) : zero;
+    Vec<T, VX> xdn = vload<T, VX>(zN + ((act && la0 > 0) ? c - plane : c));
+    Vec<T, VX> xc = vload<T, VX>(zN + c);
     // previous layer's values kept for stage B
     Vec<T, VX> zA_m1 = zero, zA_m2 = zero, r_m1 = zero, zj_m1 = zero, gxp_m1 = zero,
                gyp_m1 = zero, gym_m1 = zero;
@@ -733,15 +749,16 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             // ---- stage A: z_{j+1} at layer l
             const LayerCoef<T> L = gldc(op.lc + l);
             // every load of the layer is issued before the first use
-            xup = (act && l + 1 < nz) ? vload<T, VX>(zN + c + plane) : zero;
-            const Vec<T, VX> xso = has_s ? vload<T, VX>(zN + c - nx) : zero;
-            const Vec<T, VX> xno = has_n ? vload<T, VX>(zN + c + nx) : zero;
+            // (unguarded, at in-bounds cells: see the column walker)
+            xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
+            const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
+            const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
             const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
             const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
             [[maybe_unused]] LatRaw<T, VX, CS> lat;
             if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
-            rv = act ? vload<T, VX>(r + c) : zero;
-            const Vec<T, VX> zm = act ? vload<T, VX>(zP + c) : zero;
+            rv = vload<T, VX>(r + c);
+            const Vec<T, VX> zm = vload<T, VX>(zP + c);
             T left = lane_left(xc.a[VX - 1]);
             T right = lane_right(xc.a[0]);
             if (lane == 0) left = west;
