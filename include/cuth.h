@@ -91,6 +91,9 @@ typedef enum {
                          breakdown or max_inner ends the iteration.           */
 } cuth_precision;
 
+/* cuth_options.cheb_degree: pick the degree from the spectral interval. */
+#define CUTH_DEGREE_AUTO (-1)
+
 /* Preconditioner of the inner PCG.  The Chebyshev polynomial is the paper's
  * (Section 4.3); Jacobi and none are the baselines of its Ablation III
  * (Section 5), here as single element-wise passes. */
@@ -143,7 +146,14 @@ typedef struct {
                                     default 1e-8.  CUTH_FP64, CUTH_ADAPTIVE: relative
                                     residual ||b - A T|| / ||b||, default 1e-10 for
                                     steady and 1e-12 for transient solves.            */
-    int32_t cheb_degree;         /* Chebyshev degree k, 1..256 (default 30)            */
+    int32_t cheb_degree;         /* Chebyshev degree k, 1..256 (default 30), or
+                                    CUTH_DEGREE_AUTO: the smallest k >= 2 with
+                                    2 s^k <= 0.3, s = (sqrt(c) - 1)/(sqrt(c) + 1),
+                                    c = lambda_max/lambda_min of the preconditioner's
+                                    interval, at most 64 (the damping the Chebyshev
+                                    polynomial gives on that interval; not from the
+                                    paper); a batch takes the largest over its
+                                    systems.  stats.cheb_degree reports the choice. */
     int32_t lanczos_steps;       /* Lanczos steps m, 2..256 (default 30)               */
     int32_t max_inner;           /* CG iterations per inner solve (default 2000)       */
     int32_t max_outer;           /* refinement cycles, CUTH_MIXED (default 12)         */
@@ -160,7 +170,7 @@ typedef struct {
     int64_t stencil_applies;     /* operator applications incl. Chebyshev and checks   */
     int32_t stop_reason;         /* last inner solve: 1 tol, 2 drift, 3 stagnation,
                                     4 breakdown, 5 iteration limit                      */
-    int32_t _pad;
+    int32_t cheb_degree;         /* Chebyshev degree used (1 without Chebyshev)        */
     double rel_residual;         /* final ||b - A theta||_2 / ||b||_2 (FP64)           */
     double err_est;              /* mixed: last correction ||delta||_inf/||theta||_inf */
     double setup_ms;             /* coefficient/Lanczos setup inside this call         */

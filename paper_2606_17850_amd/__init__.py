@@ -52,7 +52,7 @@ def options(precision: str = "mixed", tol: Optional[float] = None, cheb_degree: 
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
     o.precision = PRECISIONS[precision]
     o.tol = 0.0 if tol is None else float(tol)
-    o.cheb_degree = cheb_degree
+    o.cheb_degree = _lib.CUTH_DEGREE_AUTO if cheb_degree == "auto" else int(cheb_degree)
     o.lanczos_steps = lanczos_steps
     o.max_inner = max_inner
     o.max_outer = max_outer

@@ -19,6 +19,7 @@ CUTH_MIXED = 1
 CUTH_MIXED16 = 2
 CUTH_ADAPTIVE = 3
 CUTH_FP32 = 4
+CUTH_DEGREE_AUTO = -1
 PRECISIONS = {"fp64": CUTH_FP64, "mixed": CUTH_MIXED, "mixed16": CUTH_MIXED16,
               "adaptive": CUTH_ADAPTIVE, "fp32": CUTH_FP32}
 PRECONDITIONERS = {"chebyshev": 0, "jacobi": 1, "none": 2}
@@ -60,7 +61,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("outer_cycles", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
         ("stencil_applies", ctypes.c_int64), ("stop_reason", ctypes.c_int32),
-        ("_pad", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+        ("cheb_degree", ctypes.c_int32), ("rel_residual", ctypes.c_double),
         ("err_est", ctypes.c_double), ("setup_ms", ctypes.c_double),
         ("solve_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
         ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),

@@ -65,8 +65,8 @@ cuth_status check_opts(const cuth_options &o) {
         return fail(CUTH_E_INVALID, "CSR storage needs precision CUTH_FP64");
     if (!(o.tol == 0.0 || (finite_pos(o.tol) && o.tol < 1.0)))
         return fail(CUTH_E_INVALID, "tol must be 0 (default) or in (0, 1)");
-    if (o.cheb_degree < 1 || o.cheb_degree > 256)
-        return fail(CUTH_E_INVALID, "cheb_degree must be in 1..256");
+    if (o.cheb_degree != CUTH_DEGREE_AUTO && (o.cheb_degree < 1 || o.cheb_degree > 256))
+        return fail(CUTH_E_INVALID, "cheb_degree must be in 1..256 or CUTH_DEGREE_AUTO");
     if (o.lanczos_steps < 2 || o.lanczos_steps > 256)
         return fail(CUTH_E_INVALID, "lanczos_steps must be in 2..256");
     if (o.max_inner < 1 || o.max_outer < 1)

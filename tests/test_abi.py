@@ -118,6 +118,9 @@ def test_precision_names_match_header(lib):
                     "CUTH_MIXED16": _lib.CUTH_MIXED16, "CUTH_ADAPTIVE": _lib.CUTH_ADAPTIVE,
                     "CUTH_FP32": _lib.CUTH_FP32}
     assert cuth.options("fp32").precision == enum["CUTH_FP32"]
+    auto = re.search(r"#define\s+CUTH_DEGREE_AUTO\s+\((-?\d+)\)", hdr)
+    assert auto and int(auto.group(1)) == _lib.CUTH_DEGREE_AUTO
+    assert cuth.options(cheb_degree="auto").cheb_degree == _lib.CUTH_DEGREE_AUTO
     assert cuth.options("mixed16").precision == enum["CUTH_MIXED16"]
     assert cuth.options("fp64").precision == enum["CUTH_FP64"]
     with pytest.raises(ValueError):

@@ -395,6 +395,63 @@ def test_baseline_preconditioners_match_oracle_pcg(pcname):
     g.close()
 
 
+def _auto_degree_rule(lmin, lmax):
+    # the documented rule: smallest k >= 2 with 2 s^k <= 0.3, at most 64
+    c = lmax / lmin
+    s = (np.sqrt(c) - 1.0) / (np.sqrt(c) + 1.0)
+    k = 2
+    while k < 64 and 2.0 * s ** k > 0.3:
+        k += 1
+    return k
+
+
+def test_auto_degree():
+    """cheb_degree = CUTH_DEGREE_AUTO: the degree reported in the stats follows
+    the documented rule from the reported interval, and the solves still meet
+    the parity bars (steady mixed and FP64, one backward-Euler step, and a
+    two-grid batch, which takes the largest degree of its systems)."""
+    import paper_2606_17850_amd as cuth
+    say("auto degree")
+    for st, P in (w.config4_small(), w.config0()):
+        ref = _ref_steady(st, P)
+        g = grid_of(st)
+        for prec, bar in (("mixed", 1e-8), ("fp64", 1e-10)):
+            T, s = g.solve(t64(P), precision=prec, cheb_degree="auto")
+            k = _auto_degree_rule(s["lambda_min"], s["lambda_max"])
+            say(f"  {prec} degree {s['cheb_degree']} (rule {k}) cg {s['cg_iters']}")
+            assert s["cheb_degree"] == k
+            assert rise_err(T.cpu().numpy(), ref, st.t_amb) <= bar
+        _, s30 = g.solve(t64(P), precision="mixed")
+        assert s30["cheb_degree"] == 30
+        g.close()
+    st = ragged_stack(70, 9, mult=True)
+    P = np.zeros(st.shape)
+    P[0] = np.random.default_rng(6).uniform(0, 2e-3, (st.ny, st.nx))
+    g = grid_of(st)
+    dt = 1e-4
+    th0 = np.random.default_rng(8).uniform(0, 5.0, st.n)
+    ref_tr = transient.step(st, P.ravel(), th0, dt)
+    Tt, s = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision="mixed", cheb_degree="auto")
+    assert s["cheb_degree"] == _auto_degree_rule(s["lambda_min"], s["lambda_max"])
+    got = Tt.cpu().numpy() - st.t_amb
+    assert np.abs(got - ref_tr).max() <= 1e-8 * np.abs(ref_tr).max()
+    g.close()
+    stacks = [ragged_stack(70, 9, mult=True), ragged_stack(67, 1, mult=True)]
+    maps = [np.random.default_rng(40 + i).uniform(0, 2e-3, s_.n) for i, s_ in enumerate(stacks)]
+    grids = [grid_of(s_) for s_ in stacks]
+    degs = []
+    for gg, m in zip(grids, maps):
+        _, s1 = gg.solve(t64(m), precision="mixed", cheb_degree="auto")
+        degs.append(s1["cheb_degree"])
+    Tb, sb = cuth.solve_batch(grids, [t64(m) for m in maps], nrhs=1, precision="mixed",
+                              cheb_degree="auto")
+    for s_, m, t, sd in zip(stacks, maps, Tb, sb):
+        assert sd["cheb_degree"] == max(degs)
+        assert rise_err(t.cpu().numpy(), _ref_steady(s_, m), s_.t_amb) <= 1e-8
+    for gg in grids:
+        gg.close()
+
+
 @pytest.mark.parametrize("pcname", ["chebyshev", "jacobi", "none"])
 def test_csr_storage_pcg(pcname):
     """The CSR baseline storage (Ablation I; Ablation III with the optimisation
