@@ -19,6 +19,13 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   routine.
 * ``pcg`` - Algorithm 1 (preconditioned CG) with the stopping test
   ||r_k||_2 > eps on the recursive residual.
+* ``jacobi_chebyshev_precondition`` / ``jacobi_spectral_bounds`` - an
+  extension beyond the paper: the same Chebyshev algorithm applied to the
+  Jacobi-scaled system D^{-1} A x = D^{-1} r (D = diag(A)), i.e.
+  z = q_k(D^{-1} A) D^{-1} r, with the interval of D^{-1} A (the spectrum of
+  the symmetric S = D^{-1/2} A D^{-1/2}) from Lanczos on S, capped above by 2
+  (Gershgorin: |lambda - 1| <= sum_{j != i} |a_ij| / a_ii <= 1 for a
+  diagonally dominant A with positive diagonal).
 """
 
 from __future__ import annotations
@@ -136,3 +143,23 @@ def pcg(matvec: Matvec, b: np.ndarray, precond: Callable[[np.ndarray], np.ndarra
         rz = rz_new
         k += 1
     return x, k
+
+
+def jacobi_chebyshev_precondition(A, r: np.ndarray, lmin: float, lmax: float,
+                                  k: int) -> np.ndarray:
+    """z = q_k(D^{-1} A) D^{-1} r: ``chebyshev_precondition`` on the system
+    scaled by D^{-1} = diag(A)^{-1} (beyond the paper); lmin, lmax bound the
+    spectrum of D^{-1} A."""
+    d = A.diagonal()
+    return chebyshev_precondition(lambda v: (A @ v) / d, np.asarray(r, float) / d, lmin, lmax, k)
+
+
+def jacobi_spectral_bounds(A, v0: np.ndarray, m: int = 30,
+                           margin: float = 1.05) -> Tuple[float, float]:
+    """Interval of D^{-1} A as the Jacobi-scaled preconditioner uses it: Lanczos
+    on S = D^{-1/2} A D^{-1/2} (same spectrum, symmetric), the smallest Ritz
+    value, and the largest times the margin capped by 2."""
+    s = 1.0 / np.sqrt(A.diagonal())
+    a, b = lanczos(lambda x: s * (A @ (s * x)), v0, m)
+    ritz = ritz_values(a, b)
+    return float(ritz[0]), float(min(2.0, margin * ritz[-1]))
