@@ -118,10 +118,10 @@ def bench_transient(args) -> int:
     g = cuth.Grid.from_stack(st, device=dev)
     dt = 1e-4
 
-    def run(prec, nsteps, profile, degree=30):
+    def run(prec, nsteps, profile, degree=30, pc="chebyshev"):
         T = torch.full((st.n,), st.t_amb, dtype=torch.float64, device=dev)
         T2 = torch.empty_like(T)
-        o = cuth.options(prec, cheb_degree=degree)
+        o = cuth.options(prec, cheb_degree=degree, preconditioner=pc)
         for s in range(args.warmup):
             g.transient_step(dt, pmap(s), T, T2, opts=o)
         T.fill_(st.t_amb)
@@ -145,6 +145,8 @@ def bench_transient(args) -> int:
     ms64, stats64, _, T64 = run("fp64", args.steps, False)
     # the degree chosen from the spectral interval instead of 30 (not the paper's)
     msa, statsa, _, Ta = run("mixed", args.steps, False, "auto")
+    # and the Jacobi-scaled Chebyshev preconditioner with that rule (not the paper's)
+    msj, statsj, _, Tj = run("mixed", args.steps, False, "auto", "chebyshev_jacobi")
     rise = float((T64 - st.t_amb).abs().max())
     per = ms / args.steps
     value = sum(s["alg_bytes"] for s in stats) / (ms / 1e3) / 1e9
@@ -156,13 +158,18 @@ def bench_transient(args) -> int:
     out["time_to_tol_ms"] = {"mixed": round(per, 3), "fp64": round(ms64 / args.steps, 3),
                              "speedup_mixed_vs_fp64": round(ms64 / ms, 3),
                              "mixed_auto_degree": round(msa / args.steps, 3),
-                             "speedup_mixed_auto_degree_vs_fp64": round(ms64 / msa, 3)}
+                             "speedup_mixed_auto_degree_vs_fp64": round(ms64 / msa, 3),
+                             "mixed_chebyshev_jacobi_auto_degree": round(msj / args.steps, 3),
+                             "speedup_mixed_chebyshev_jacobi_auto_degree_vs_fp64": round(ms64 / msj, 3)}
     out["solve_detail"] = {"mixed_cg_iters_per_step": [s["cg_iters"] for s in stats][:10],
                            "fp64_cg_iters_per_step": [s["cg_iters"] for s in stats64][:10],
                            "mixed_vs_fp64_max_rise_rel_diff": float((Tm - T64).abs().max()) / rise,
                            "auto_degree": statsa[-1]["cheb_degree"],
                            "auto_degree_cg_iters_per_step": [s["cg_iters"] for s in statsa][:10],
-                           "auto_degree_vs_fp64_max_rise_rel_diff": float((Ta - T64).abs().max()) / rise}
+                           "auto_degree_vs_fp64_max_rise_rel_diff": float((Ta - T64).abs().max()) / rise,
+                           "chebyshev_jacobi_degree": statsj[-1]["cheb_degree"],
+                           "chebyshev_jacobi_cg_iters_per_step": [s["cg_iters"] for s in statsj][:10],
+                           "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": float((Tj - T64).abs().max()) / rise}
     out["roofline"] = {"bound": "hbm",
                        "kernel": ("k_cheb2_b fused pair of general sweeps, FP32, matrix-free"
                                   if prof["fused"] else "k_cheb_b general sweep, FP32, matrix-free"),
@@ -353,6 +360,7 @@ def main() -> int:
     fp64 = cuth.options("fp64")
     staged = cuth.options("adaptive")
     auto = cuth.options("mixed", cheb_degree="auto")
+    jac = cuth.options("mixed", preconditioner="chebyshev_jacobi")
 
     def step(opts):
         g.reset_bounds()
@@ -410,6 +418,10 @@ def main() -> int:
     step(auto)
     ms_au, st_au = timed(auto, args.steps)
     T_au = T.clone()
+    # the Jacobi-scaled Chebyshev preconditioner, k = 30 (not the paper's)
+    step(jac)
+    ms_j, st_j = timed(jac, args.steps)
+    T_j = T.clone()
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -428,6 +440,8 @@ def main() -> int:
     per_st = ms_st / k64
     per_au = ms_au / args.steps
     diff_au = float((T_au - T_fp64).abs().max()) / rise
+    per_j = ms_j / args.steps
+    diff_j = float((T_j - T_fp64).abs().max()) / rise
 
     per_step = ms_mixed / args.steps
     bytes_step = sum(s["alg_bytes"] for s in st_mixed) / args.steps
@@ -465,7 +479,9 @@ def main() -> int:
                            "stage_switched_to_fp64_tol": round(per_st, 3),
                            "speedup_stage_switched_vs_fp64": round(per64 / per_st, 3),
                            "mixed_auto_degree": round(per_au, 3),
-                           "speedup_mixed_auto_degree_vs_fp64": round(per64 / per_au, 3)},
+                           "speedup_mixed_auto_degree_vs_fp64": round(per64 / per_au, 3),
+                           "mixed_chebyshev_jacobi": round(per_j, 3),
+                           "speedup_mixed_chebyshev_jacobi_vs_fp64": round(per64 / per_j, 3)},
         "solve_detail": {
             "mixed_cg_iters": st_mixed[-1]["cg_iters"],
             "mixed_outer_cycles": st_mixed[-1]["outer_cycles"],
@@ -489,6 +505,9 @@ def main() -> int:
             "auto_degree": st_au[-1]["cheb_degree"],
             "auto_degree_cg_iters": st_au[-1]["cg_iters"],
             "auto_degree_vs_fp64_max_rise_rel_diff": diff_au,
+            "chebyshev_jacobi_cg_iters": st_j[-1]["cg_iters"],
+            "chebyshev_jacobi_interval": [st_j[-1]["lambda_min"], st_j[-1]["lambda_max"]],
+            "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": diff_j,
             "grid_create_ms": round(create_ms, 3),
             "unknown_stencils_per_s": round(st_mixed[-1]["stencil_applies"] * stack.n
                                             / (per_step / 1e3), 1),

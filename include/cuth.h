@@ -100,7 +100,15 @@ typedef enum {
 typedef enum {
     CUTH_PC_CHEBYSHEV = 0,  /* z = q(A) r, degree cheb_degree, Lanczos bounds     */
     CUTH_PC_JACOBI = 1,     /* z = r / diag(A), diag = sink + face conductances   */
-    CUTH_PC_NONE = 2        /* z = r (plain CG); no Lanczos setup either         */
+    CUTH_PC_NONE = 2,       /* z = r (plain CG); no Lanczos setup either         */
+    CUTH_PC_CHEBYSHEV_JACOBI = 3 /* beyond the paper: z = q(D^{-1} A) D^{-1} r, the
+                               Chebyshev polynomial of the Jacobi-scaled operator
+                               (D = diag(A) = sink + face conductances), degree
+                               cheb_degree, on the interval of D^{-1} A from
+                               Lanczos on D^{-1/2} A D^{-1/2} (upper end capped
+                               by 2, a bound of that spectrum).  Narrows the
+                               interval of layered stacks (config 0: condition
+                               number 7.2e4 -> 1.25e4).  Not with CSR storage. */
 } cuth_preconditioner;
 
 /* Storage of the operator in the CG and Chebyshev products.  The matrix-free
@@ -265,21 +273,29 @@ cuth_status cuth_apply_csr(cuth_grid g, double dt, const double *x, double *y);
  * b, T, r: device double [N]. */
 cuth_status cuth_residual(cuth_grid g, double dt, const double *b, const double *T, double *r);
 
-/* z = q(A) r: one application of the Chebyshev polynomial preconditioner of
- * degree `degree` on [lmin, lmax] (Section 4.3).  precision selects FP64
- * (double vectors), FP32 (CUTH_MIXED: float vectors, FP32 operator) or FP32
- * with the FP16-stored lateral conductances (CUTH_MIXED16, float vectors). */
-cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, double lmin,
-                               double lmax, int32_t degree, const void *r, void *z);
+/* z = M^{-1} r: one application of a preconditioner as the solver applies it.
+ * preconditioner (cuth_preconditioner): CUTH_PC_CHEBYSHEV, z = q(A) r, the
+ * Chebyshev polynomial of degree `degree` on [lmin, lmax] (Section 4.3);
+ * CUTH_PC_CHEBYSHEV_JACOBI, z = q(D^{-1} A) D^{-1} r with [lmin, lmax] an
+ * interval of D^{-1} A (beyond the paper); CUTH_PC_JACOBI, z = r / diag(A);
+ * CUTH_PC_NONE, z = r (lmin, lmax and degree still validated, then unused).
+ * precision selects FP64 (double vectors), FP32 (CUTH_MIXED: float vectors,
+ * FP32 operator) or FP32 with the FP16-stored lateral conductances in the
+ * Chebyshev sweeps (CUTH_MIXED16, float vectors). */
+cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, int32_t preconditioner,
+                               double lmin, double lmax, int32_t degree, const void *r, void *z);
 
-/* FP32 Lanczos with `steps` steps on the FP32 operator, start vector v0
+/* FP32 Lanczos with `steps` steps on the FP32 operator (preconditioner
+ * CUTH_PC_CHEBYSHEV: A; CUTH_PC_CHEBYSHEV_JACOBI: D^{-1/2} A D^{-1/2}, whose
+ * spectrum is that of D^{-1} A; other values CUTH_E_INVALID), start vector v0
  * (device float [N], or NULL for the library's own counter-based start vector),
  * followed by the FP64 host eigensolve of the tridiagonal.  alpha (host
  * [steps]) and beta (host [steps-1]) receive the tridiagonal (either may be
  * NULL); ritz_min/ritz_max its extreme eigenvalues; lmin/lmax the bounds the
- * solver uses: lmin = ritz_min, lmax = min(Gershgorin bound, 1.05 ritz_max). */
-cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t steps, const float *v0,
-                                 double *alpha, double *beta, double *ritz_min,
+ * solver uses: lmin = ritz_min, lmax = min(Gershgorin bound, 1.05 ritz_max),
+ * the Gershgorin bound of D^{-1} A being 2. */
+cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t preconditioner, int32_t steps,
+                                 const float *v0, double *alpha, double *beta, double *ritz_min,
                                  double *ritz_max, double *lmin, double *lmax);
 
 /* ---- setup control and measurement ---- */

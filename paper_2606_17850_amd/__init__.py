@@ -222,13 +222,15 @@ class Grid:
         return y
 
     def precond_apply(self, r: torch.Tensor, lmin: float, lmax: float, degree: int,
-                      dt: float = 0.0, fp16_coef: bool = False) -> torch.Tensor:
+                      dt: float = 0.0, fp16_coef: bool = False,
+                      preconditioner: str = "chebyshev") -> torch.Tensor:
         prec = CUTH_FP64 if r.dtype == torch.float64 else (CUTH_MIXED16 if fp16_coef else CUTH_MIXED)
+        pc = _lib.PRECONDITIONERS[preconditioner]
         z = self._new(r.dtype)
         with torch.cuda.device(self.device):
-            _check(library().cuth_precond_apply(self._h, float(dt), prec, float(lmin), float(lmax),
-                                                int(degree), self._vec(r, "r", r.dtype),
-                                                z.data_ptr()))
+            _check(library().cuth_precond_apply(self._h, float(dt), prec, pc, float(lmin),
+                                                float(lmax), int(degree),
+                                                self._vec(r, "r", r.dtype), z.data_ptr()))
         return z
 
     def reset_bounds(self):
@@ -245,13 +247,14 @@ class Grid:
                 "fused": bool(fu.value)}
 
     def spectral_bounds(self, dt: float = 0.0, steps: int = 30,
-                        v0: Optional[torch.Tensor] = None) -> dict:
+                        v0: Optional[torch.Tensor] = None,
+                        preconditioner: str = "chebyshev") -> dict:
         a = (ctypes.c_double * steps)()
         b = (ctypes.c_double * max(steps - 1, 1))()
         vals = [ctypes.c_double() for _ in range(4)]
         with torch.cuda.device(self.device):
             _check(library().cuth_spectral_bounds(
-                self._h, float(dt), int(steps),
+                self._h, float(dt), _lib.PRECONDITIONERS[preconditioner], int(steps),
                 self._vec(v0, "v0", torch.float32) if v0 is not None else None,
                 a, b, *[ctypes.byref(v) for v in vals]))
         return {"alpha": np.array(a[:]), "beta": np.array(b[: steps - 1]),

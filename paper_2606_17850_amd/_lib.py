@@ -22,7 +22,7 @@ CUTH_FP32 = 4
 CUTH_DEGREE_AUTO = -1
 PRECISIONS = {"fp64": CUTH_FP64, "mixed": CUTH_MIXED, "mixed16": CUTH_MIXED16,
               "adaptive": CUTH_ADAPTIVE, "fp32": CUTH_FP32}
-PRECONDITIONERS = {"chebyshev": 0, "jacobi": 1, "none": 2}
+PRECONDITIONERS = {"chebyshev": 0, "jacobi": 1, "none": 2, "chebyshev_jacobi": 3}
 STORAGES = {"stencil": 0, "csr": 1}
 
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BREAKDOWN"}
@@ -101,8 +101,8 @@ def load() -> ctypes.CDLL:
         "cuth_apply": (ctypes.c_int, [vp, dbl, i32, vp, vp]),
         "cuth_residual": (ctypes.c_int, [vp, dbl, vp, vp, vp]),
         "cuth_apply_csr": (ctypes.c_int, [vp, dbl, vp, vp]),
-        "cuth_precond_apply": (ctypes.c_int, [vp, dbl, i32, dbl, dbl, i32, vp, vp]),
-        "cuth_spectral_bounds": (ctypes.c_int, [vp, dbl, i32, vp, c_double_p, c_double_p,
+        "cuth_precond_apply": (ctypes.c_int, [vp, dbl, i32, i32, dbl, dbl, i32, vp, vp]),
+        "cuth_spectral_bounds": (ctypes.c_int, [vp, dbl, i32, i32, vp, c_double_p, c_double_p,
                                                 c_double_p, c_double_p, c_double_p, c_double_p]),
         "cuth_grid_reset_bounds": (ctypes.c_int, [vp]),
         "cuth_profile_enable": (ctypes.c_int, [vp, i32]),

@@ -57,8 +57,10 @@ cuth_status check_desc(const cuth_grid_desc *d) {
 cuth_status check_opts(const cuth_options &o) {
     if (o.precision < CUTH_FP64 || o.precision > CUTH_FP32)
         return fail(CUTH_E_INVALID, "precision must be a cuth_precision value");
-    if (o.preconditioner < CUTH_PC_CHEBYSHEV || o.preconditioner > CUTH_PC_NONE)
+    if (o.preconditioner < CUTH_PC_CHEBYSHEV || o.preconditioner > CUTH_PC_CHEBYSHEV_JACOBI)
         return fail(CUTH_E_INVALID, "preconditioner must be a cuth_preconditioner value");
+    if (o.storage == CUTH_STORAGE_CSR && o.preconditioner == CUTH_PC_CHEBYSHEV_JACOBI)
+        return fail(CUTH_E_INVALID, "the Jacobi-scaled Chebyshev preconditioner needs stencil storage");
     if (o.storage != CUTH_STORAGE_STENCIL && o.storage != CUTH_STORAGE_CSR)
         return fail(CUTH_E_INVALID, "storage must be a cuth_storage value");
     if (o.storage == CUTH_STORAGE_CSR && o.precision != CUTH_FP64)
@@ -258,8 +260,8 @@ cuth_status cuth_apply_csr(cuth_grid h, double dt, const double *x, double *y) {
     });
 }
 
-cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, double lmin, double lmax,
-                               int32_t degree, const void *r, void *z) {
+cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, int32_t preconditioner,
+                               double lmin, double lmax, int32_t degree, const void *r, void *z) {
     return guarded([&]() -> cuth_status {
         if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
         cuth::Grid &g = *h->g;
@@ -267,21 +269,26 @@ cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, double
         if (r == z) return fail(CUTH_E_INVALID, "r and z must not alias");
         if (precision != CUTH_FP64 && precision != CUTH_MIXED && precision != CUTH_MIXED16)
             return fail(CUTH_E_INVALID, "bad precision");
+        if (preconditioner < CUTH_PC_CHEBYSHEV || preconditioner > CUTH_PC_CHEBYSHEV_JACOBI)
+            return fail(CUTH_E_INVALID, "preconditioner must be a cuth_preconditioner value");
         if (!finite_pos(lmin) || !finite_pos(lmax) || !(lmax > lmin))
             return fail(CUTH_E_INVALID, "need 0 < lmin < lmax");
         if (degree < 1 || degree > 256) return fail(CUTH_E_INVALID, "degree must be in 1..256");
         if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
         if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
-        return report(cuth::precond_apply(g, dt, precision, lmin, lmax, degree, r, z));
+        return report(cuth::precond_apply(g, dt, precision, preconditioner, lmin, lmax, degree, r, z));
     });
 }
 
-cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t steps, const float *v0,
-                                 double *alpha, double *beta, double *ritz_min, double *ritz_max,
-                                 double *lmin, double *lmax) {
+cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t preconditioner, int32_t steps,
+                                 const float *v0, double *alpha, double *beta, double *ritz_min,
+                                 double *ritz_max, double *lmin, double *lmax) {
     return guarded([&]() -> cuth_status {
         if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
         cuth::Grid &g = *h->g;
+        if (preconditioner != CUTH_PC_CHEBYSHEV && preconditioner != CUTH_PC_CHEBYSHEV_JACOBI)
+            return fail(CUTH_E_INVALID, "preconditioner must be a Chebyshev one");
+        const bool scaled = preconditioner == CUTH_PC_CHEBYSHEV_JACOBI;
         if (steps < 2 || steps > 256) return fail(CUTH_E_INVALID, "steps must be in 2..256");
         if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
         if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
@@ -289,7 +296,7 @@ cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t steps, const fl
         cuth::Setup *su = cuth::get_setup(g, dt, st);
         if (!su) return report(st);
         std::vector<double> a, b;
-        st = cuth::run_lanczos(g, *su, steps, v0, a, b);
+        st = cuth::run_lanczos(g, *su, steps, v0, a, b, scaled);
         if (st.bad()) return report(st);
         double lo, hi;
         cuth::tridiag_extremes(a, b, lo, hi);
@@ -299,7 +306,7 @@ cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t steps, const fl
             for (int j = 0; j + 1 < steps; ++j) beta[j] = j < (int)b.size() ? b[j] : NAN;
         if (ritz_min) *ritz_min = lo;
         if (ritz_max) *ritz_max = hi;
-        double lx = std::min(su->gersh, 1.05 * hi), ln = lo;
+        double lx = std::min(scaled ? 2.0 : su->gersh, 1.05 * hi), ln = lo;
         if (!(ln > 0.0) || !(lx > ln * (1.0 + 1e-6))) ln = 0.5 * lx;
         if (lmin) *lmin = ln;
         if (lmax) *lmax = lx;

@@ -154,10 +154,13 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s);
 // problems (rr <= tol2).
 // cs (CoefSrc): CS_F16 reads the FP16-stored lateral conductances (FP32,
 // per-cell grids only), CS_CSR the CSR copy (FP64); otherwise CS_OWN.
+// jac: the Jacobi-scaled sweep z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 D^{-1}(r - A z_j)
+// with D = diag(A) (beyond the paper); mode 3 (z_1 read from z[in], z_0 = 0)
+// or 0 only, and no chk (its first kernel is the PM_JCHEB scale pass).
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
-                   int mode, bool last, bool chk, int j, int zsel, const T *part_in, bool red,
-                   T *part_out, hipStream_t s);
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, bool jac, int vx,
+                   int by, int mode, bool last, bool chk, int j, int zsel, const T *part_in,
+                   bool red, T *part_out, hipStream_t s);
 
 // Two consecutive general sweeps j, j+1 in one pass (temporal blocking):
 // zsel = N + 4 P + 16 X + 64 Y with z_j in z[N], z_{j-1} in z[P]; z_{j+1} is
@@ -167,11 +170,12 @@ void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs
 // f_ntiles) with f_ntiles = ceil(ny / R) * ceil(nz / zc).  FP32; h16: the
 // FP16-stored lateral conductances (per-cell grids).
 template <typename T>
-void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
-                    int zc, int wpr, int j, int zsel, hipStream_t s);
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac,
+                    int vx, int R, int zc, int wpr, int j, int zsel, hipStream_t s);
 
 // Single-pass preconditioner into z[0] (same chk/last behaviour as the sweeps):
-// pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r.
+// pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r,
+// 3: z = r/(theta diag(A)) (first iterate of the Jacobi-scaled Chebyshev).
 template <typename T>
 void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int pm, int vx, int by,
                     bool chk, const T *part_in, bool red, T *part_out, hipStream_t s);
@@ -254,7 +258,11 @@ void launch_norm2(int64_t n, const float *v, float *part_out, hipStream_t s);
 void launch_scale_rsqrt(int64_t n, const float *v, const float *part_in, int np_in, float *out,
                         hipStream_t s);
 void launch_lanczos_av(const OpView<float> &op, int j, const float *v, const float *vprev,
-                       const float *lz, float *w, float *part_out, hipStream_t s);
+                       const float *lz, const float *dis, float *w, float *part_out,
+                       hipStream_t s);
+// dis = D^{-1/2}, D = diag(A), per cell (FP32) of an FP64 operator; with dis,
+// launch_lanczos_av applies D^{-1/2} A D^{-1/2}
+void launch_jacobi_dis(const OpView<double> &op, float *dis, hipStream_t s);
 void launch_lanczos_orth(int64_t n, int j, float *w, const float *v, float *lz,
                          const float *part_in, int np_in, float *part_out, hipStream_t s);
 void launch_lanczos_div(int64_t n, int j, float *w, float *lz, const float *part_in, int np_in,

@@ -27,6 +27,12 @@ struct Setup {
     bool have_bounds = false;
     int bounds_steps = 0;
     double lmin = 0, lmax = 0, ritz_min = 0, ritz_max = 0, gersh = 0;
+    // interval of D^{-1} A for the Jacobi-scaled Chebyshev preconditioner
+    // (Lanczos on D^{-1/2} A D^{-1/2}, dis = D^{-1/2} per cell in FP32)
+    float *dis = nullptr;
+    bool have_jbounds = false;
+    int jbounds_steps = 0;
+    double jlmin = 0, jlmax = 0, jritz_min = 0, jritz_max = 0;
     // CSR copy of the FP64 operator (cuth_apply_csr), built on first use
     int *csr_ptr = nullptr, *csr_col = nullptr;
     double *csr_val = nullptr;
@@ -34,7 +40,7 @@ struct Setup {
     // CG iterations at which the last inner solve of refinement cycle c stopped
     // on its tolerance, per inner precision ([0]: FP64, [1]: FP32) and
     // preconditioner (cuth_preconditioner); 0 = unknown
-    int stop_iter[2][3][16] = {};
+    int stop_iter[2][4][16] = {};
 };
 
 struct Status {
@@ -132,9 +138,11 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out);
 void grid_destroy(Grid *g);
 
 Setup *get_setup(Grid &g, double dt, Status &st);
-Status ensure_bounds(Grid &g, Setup &su, int steps);
+// scaled: the interval of D^{-1} A (Lanczos on D^{-1/2} A D^{-1/2}), for the
+// Jacobi-scaled preconditioner
+Status ensure_bounds(Grid &g, Setup &su, int steps, bool scaled = false);
 Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<double> &alpha,
-                   std::vector<double> &beta);
+                   std::vector<double> &beta, bool scaled = false);
 void tridiag_extremes(const std::vector<double> &alpha, const std::vector<double> &beta,
                       double &lo, double &hi);
 
@@ -154,8 +162,8 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
 Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *P,
                    double *const *T, const cuth_options &o, cuth_stats *stats);
 
-Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax, int degree,
-                     const void *r, void *z);
+Status precond_apply(Grid &g, double dt, int precision, int preconditioner, double lmin,
+                     double lmax, int degree, const void *r, void *z);
 Status apply_op(Grid &g, double dt, int precision, const void *x, void *y);
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r);
 Status apply_csr(Grid &g, double dt, const double *x, double *y);

@@ -151,6 +151,14 @@ __device__ __forceinline__ T lane_right(T v) {
     return dpp_move<0x130>(v);   // wave_shl:1
 }
 
+// 1/d for the Jacobi scaling: the hardware reciprocal in FP32 (within 1 ulp:
+// the preconditioner only needs a fixed positive diagonal), a division in FP64.
+template <typename T>
+__device__ __forceinline__ T recip(T d) {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(d);
+    else return T(1) / d;
+}
+
 template <typename T, int VX>
 __device__ __forceinline__ Vec<T, VX> vzero() {
     Vec<T, VX> v;
@@ -437,7 +445,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
                     a += (T)gld(op.csr_val + k) * XS(gld(op.csr_col + k));
                 ax.a[e] = a;
             }
-            emit(l, c, xc, ax, PRE(c));
+            emit(l, c, xc, ax, PRE(c), vzero<T, VX>());
         }
         return;
     }
@@ -491,7 +499,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         T gxl = T(0);
         if constexpr (PC)
             lateral_finish<T, VX, CS>(cur.lat, L, ln.lane, act, has_l, has_s, gxp, gyp, gym, gxl);
-        Vec<T, VX> ax;
+        Vec<T, VX> ax, dg;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
             const int i = ln.i0 + e;
@@ -508,16 +516,19 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
                 gm = gp = L.gx;
                 gs = gn = L.gy;
             }
-            T a = L.sink * x;
-            if (i > 0) a += gm * (x - xl);
-            if (i < nx - 1) a += gp * (x - xr);
-            if (ln.j > 0) a += gs * (x - xso.a[e]);
-            if (ln.j < ny - 1) a += gn * (x - xno.a[e]);
-            if (l > 0) a += L.gzd * (x - xdn.a[e]);
-            if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
+            // A x in difference form and the diagonal of A (sink plus the
+            // conductances of the faces that exist), for the Jacobi scaling
+            T a = L.sink * x, d = L.sink;
+            if (i > 0) a += gm * (x - xl), d += gm;
+            if (i < nx - 1) a += gp * (x - xr), d += gp;
+            if (ln.j > 0) a += gs * (x - xso.a[e]), d += gs;
+            if (ln.j < ny - 1) a += gn * (x - xno.a[e]), d += gn;
+            if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
+            if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
             ax.a[e] = a;
+            dg.a[e] = d;
         }
-        if (act) emit(l, c, xc, ax, pre);
+        if (act) emit(l, c, xc, ax, pre, dg);
         xdn = xc;
         xc = cur.xup;
     };
@@ -559,9 +570,8 @@ __device__ __forceinline__ void column(const OpView<T> &op, const Lane &ln, FV &
                                        E &&emit) {
     column_pre<T, PC, VX, CS_OWN>(
         op, ln, XV, XS, [](int64_t) { return NoEx{}; },
-        [&](int l, int64_t c, const Vec<T, VX> &x, const Vec<T, VX> &ax, const NoEx &) {
-            emit(l, c, x, ax);
-        });
+        [&](int l, int64_t c, const Vec<T, VX> &x, const Vec<T, VX> &ax, const NoEx &,
+            const Vec<T, VX> &) { emit(l, c, x, ax); });
 }
 
 // Elementwise march over the cells of one lane (no stencil).
@@ -581,9 +591,8 @@ __global__ __launch_bounds__(512) void k_apply(OpView<T> op, const T *__restrict
     column_pre<T, PC, VX, H16 ? CS_F16 : CS_OWN>(
         op, ln, [&](int64_t q) { return vload<T, VX>(x + q); }, [&](int64_t q) { return gld(x + q); },
         [](int64_t) { return NoEx{}; },
-        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const NoEx &) {
-            vstore<T, VX>(y + c, ax);
-        });
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const NoEx &,
+            const Vec<T, VX> &) { vstore<T, VX>(y + c, ax); });
 }
 
 // Problem pidx's sum of the previous kernel's partials: summed here by every
@@ -611,7 +620,12 @@ __device__ __forceinline__ bool conv_test(CgState<T> *st, const T *part_in, int 
 }
 
 // ---------------------------------------------------- batched Chebyshev sweep
-template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, int CS>
+// MODE 1: z_1 = r/theta and z_0 = 0 implicit; 2: z_{j-1} = r/theta implicit;
+// 0: z_{j-1} read; 3: z_1 read (written by the scale pass) and z_0 = 0.  JAC:
+// the sweep of the Jacobi-scaled operator (beyond the paper): the residual term
+// is multiplied by 1/diag(A), z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 D^{-1} (r - A z_j)
+// (modes 0 and 3 only: its z_1 = D^{-1} r/theta needs the neighbours' diagonal).
+template <typename T, bool PC, int VX, int MODE, bool LAST, bool CHK, int CS, bool JAC>
 __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                 int j, int zsel, const T *__restrict__ part_in,
                                                 int red, T *__restrict__ part_out) {
@@ -660,7 +674,8 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
         return e;
     };
     column_pre<T, PC, VX, CS>(op, ln, XV, XS, PRE,
-                      [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az, const Ex &ex) {
+                      [&](int, int64_t c, const Vec<T, VX> &zj, const Vec<T, VX> &az, const Ex &ex,
+                          const Vec<T, VX> &dg) {
                           const Vec<T, VX> &rc = ex.r;
                           const Vec<T, VX> &zm = ex.zm;
                           Vec<T, VX> zn;
@@ -670,7 +685,9 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
                               if constexpr (MODE == 0) m = zm.a[e];
                               else if constexpr (MODE == 2) m = rc.a[e] * inv_th;
                               else m = T(0);
-                              zn.a[e] = zj.a[e] + c1 * (zj.a[e] - m) + c2 * (rc.a[e] - az.a[e]);
+                              T res = rc.a[e] - az.a[e];
+                              if constexpr (JAC) res *= recip(dg.a[e]);
+                              zn.a[e] = zj.a[e] + c1 * (zj.a[e] - m) + c2 * res;
                               if constexpr (LAST) acc[0] += rc.a[e] * zn.a[e];
                           }
                           vstore<T, VX>(zo + c, zn);
@@ -692,8 +709,9 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
 // the neighbouring workgroups with the same arithmetic.  One barrier per layer:
 // stage A of layer l writes ring slot l % 3 while stage B of layer l - 1 (other
 // wavefronts) reads slot (l - 1) % 3, and slot (l + 1) % 3 was last read before
-// the previous barrier.
-template <typename T, bool PC, int VX, int CS>
+// the previous barrier.  JAC: both sweeps of the Jacobi-scaled operator (the
+// residual terms times 1/diag(A), as k_cheb_b).
+template <typename T, bool PC, int VX, int CS, bool JAC>
 __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                   int j, int zsel, int R, int zcf, int wpr) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -781,14 +799,16 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                     gm = gp = L.gx;
                     gs = gn = L.gy;
                 }
-                T a = L.sink * x;
-                if (i > 0) a += gm * (x - xl);
-                if (i < nx - 1) a += gp * (x - xr);
-                if (jr > 0) a += gs * (x - xso.a[e]);
-                if (jr < ny - 1) a += gn * (x - xno.a[e]);
-                if (l > 0) a += L.gzd * (x - xdn.a[e]);
-                if (l < nz - 1) a += L.gzu * (x - xup.a[e]);
-                zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * (rv.a[e] - a) : T(0);
+                T a = L.sink * x, d = L.sink;
+                if (i > 0) a += gm * (x - xl), d += gm;
+                if (i < nx - 1) a += gp * (x - xr), d += gp;
+                if (jr > 0) a += gs * (x - xso.a[e]), d += gs;
+                if (jr < ny - 1) a += gn * (x - xno.a[e]), d += gn;
+                if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
+                if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
+                T res = rv.a[e] - a;
+                if constexpr (JAC) res *= recip(d);
+                zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * res : T(0);
             }
             if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
             if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
@@ -821,14 +841,16 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                     gm = gp = L.gx;
                     gs = gn = L.gy;
                 }
-                T a = L.sink * x;
-                if (i > 0) a += gm * (x - xl);
-                if (i < nx - 1) a += gp * (x - xr);
-                if (jr > 0) a += gs * (x - so.a[e]);
-                if (jr < ny - 1) a += gn * (x - no.a[e]);
-                if (lb > 0) a += L.gzd * (x - zA_m2.a[e]);
-                if (lb < nz - 1) a += L.gzu * (x - zn.a[e]);
-                z2.a[e] = x + c1b * (x - zj_m1.a[e]) + c2b * (r_m1.a[e] - a);
+                T a = L.sink * x, d = L.sink;
+                if (i > 0) a += gm * (x - xl), d += gm;
+                if (i < nx - 1) a += gp * (x - xr), d += gp;
+                if (jr > 0) a += gs * (x - so.a[e]), d += gs;
+                if (jr < ny - 1) a += gn * (x - no.a[e]), d += gn;
+                if (lb > 0) a += L.gzd * (x - zA_m2.a[e]), d += L.gzd;
+                if (lb < nz - 1) a += L.gzu * (x - zn.a[e]), d += L.gzu;
+                T res = r_m1.a[e] - a;
+                if constexpr (JAC) res *= recip(d);
+                z2.a[e] = x + c1b * (x - zj_m1.a[e]) + c2b * res;
             }
             vstore<T, VX>(zY + c - plane, z2);
         }
@@ -852,8 +874,11 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
 //   PM_SCALE   z = r / theta (the Chebyshev polynomial of degree 1);
 //   PM_JACOBI  z = r / diag(A), diag = sink + the sum of the cell's face
 //              conductances (the Jacobi-PCG baseline of Section 5, Ablation III);
-//   PM_NONE    z = r (plain CG).
-enum PrecMode : int { PM_SCALE = 0, PM_JACOBI = 1, PM_NONE = 2 };
+//   PM_NONE    z = r (plain CG);
+//   PM_JCHEB   z = D^{-1} r / theta, the first iterate of the Jacobi-scaled
+//              Chebyshev preconditioner (beyond the paper; D as for PM_JACOBI,
+//              the reciprocal as in its sweeps).
+enum PrecMode : int { PM_SCALE = 0, PM_JACOBI = 1, PM_NONE = 2, PM_JCHEB = 3 };
 
 template <typename T, bool PC, int VX, bool CHK, int PM>
 __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict__ probs, int nprob,
@@ -881,12 +906,12 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
         const Vec<T, VX> rv = vload<T, VX>(r + c);
         Vec<T, VX> zv;
         [[maybe_unused]] LayerCoef<T> L;
-        if constexpr (PM == PM_JACOBI) L = gldc(op.lc + l);
+        if constexpr (PM == PM_JACOBI || PM == PM_JCHEB) L = gldc(op.lc + l);
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
             if constexpr (PM == PM_SCALE) {
                 zv.a[e] = rv.a[e] * inv_th;
-            } else if constexpr (PM == PM_JACOBI) {
+            } else if constexpr (PM == PM_JACOBI || PM == PM_JCHEB) {
                 const int i = ln.i0 + e;
                 T d = L.sink + (l > 0 ? L.gzd : T(0)) + (l < nz - 1 ? L.gzu : T(0));
                 if constexpr (PC) {
@@ -896,7 +921,8 @@ __global__ __launch_bounds__(512) void k_scale_b(const InnerProb<T> *__restrict_
                 } else {
                     d += L.gx * (T)((i > 0) + (i < nx - 1)) + L.gy * (T)((ln.j > 0) + (ln.j < ny - 1));
                 }
-                zv.a[e] = rv.a[e] / d;
+                if constexpr (PM == PM_JACOBI) zv.a[e] = rv.a[e] / d;
+                else zv.a[e] = rv.a[e] * inv_th * recip(d);
             } else {
                 zv.a[e] = rv.a[e];
             }
@@ -947,7 +973,8 @@ __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ 
     };
     auto XS = [&](int64_t q) -> T { return has_p ? gld(z + q) + beta * gld(pold + q) : gld(z + q); };
     column_pre<T, PC, VX, CS>(op, ln, XV, XS, [](int64_t) { return NoEx{}; },
-                      [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap, const NoEx &) {
+                      [&](int, int64_t c, const Vec<T, VX> &p, const Vec<T, VX> &ap, const NoEx &,
+                          const Vec<T, VX> &) {
                           vstore<T, VX>(pnew + c, p);
                           vstore<T, VX>(mu + c, ap);
 #pragma unroll
@@ -1087,7 +1114,8 @@ __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict_
         [&](int64_t q) { return have_x ? vload<T, VX>(x + q) : vzero<T, VX>(); },
         [&](int64_t q) { return have_x ? gld(x + q) : T(0); },
         [&](int64_t c) { return Ex{vload<T, VX>(rhat + c), vload<T, VX>(rlow + c)}; },
-        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const Ex &ex) {
+        [&](int, int64_t c, const Vec<T, VX> &, const Vec<T, VX> &ax, const Ex &ex,
+            const Vec<T, VX> &) {
             const Vec<T, VX> &rh = ex.rh, &rr = ex.rr;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
@@ -1337,25 +1365,70 @@ __global__ __launch_bounds__(256) void k_scale_rsqrt(int64_t n, const float *__r
         out[q] = v[q] * s;
 }
 
-template <bool PC, int VX>
+// dis = D^{-1/2}, D = diag(A) = sink + the conductances of the faces that
+// exist, per cell of an FP64 operator (one thread per cell).
+__global__ __launch_bounds__(256) void k_jacobi_dis(OpView<double> op, float *__restrict__ dis) {
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    const int64_t plane = (int64_t)nx * ny, n = plane * nz;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(q / plane);
+        const int64_t rem = q - (int64_t)l * plane;
+        const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
+        const LayerCoef<double> L = op.lc[l];
+        const bool pc = op.gx != nullptr;
+        double d = L.sink;
+        if (l > 0) d += L.gzd;
+        if (l < nz - 1) d += L.gzu;
+        if (i > 0) d += pc ? op.gx[q - 1] : L.gx;
+        if (i < nx - 1) d += pc ? op.gx[q] : L.gx;
+        if (j > 0) d += pc ? op.gy[q - nx] : L.gy;
+        if (j < ny - 1) d += pc ? op.gy[q] : L.gy;
+        dis[q] = (float)(1.0 / sqrt(d));
+    }
+}
+
+template <bool PC, int VX, bool SC>
 __global__ __launch_bounds__(512) void k_lanczos_av(OpView<float> op, int j,
                                                     const float *__restrict__ v,
                                                     const float *__restrict__ vprev,
                                                     const float *__restrict__ lz,
+                                                    const float *__restrict__ dis,
                                                     float *__restrict__ w,
                                                     float *__restrict__ part_out) {
+    // SC: the operator is D^{-1/2} A D^{-1/2} (dis = D^{-1/2} per cell; the
+    // interval of the Jacobi-scaled preconditioner)
     const float bp = j > 0 ? lz[256 + j - 1] : 0.f;
     const Lane ln = lane_of<VX>(op);
     float acc[1] = {0.f};
     column<float, PC, VX>(
-        op, ln, [&](int64_t q) { return vload<float, VX>(v + q); }, [&](int64_t q) { return v[q]; },
-        [&](int, int64_t c, const Vec<float, VX> &vc, const Vec<float, VX> &av) {
+        op, ln,
+        [&](int64_t q) {
+            Vec<float, VX> x = vload<float, VX>(v + q);
+            if constexpr (SC) {
+                const Vec<float, VX> s = vload<float, VX>(dis + q);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) x.a[e] *= s.a[e];
+            }
+            return x;
+        },
+        [&](int64_t q) {
+            if constexpr (SC) return gld(v + q) * gld(dis + q);
+            else return gld(v + q);
+        },
+        [&](int, int64_t c, const Vec<float, VX> &xv, const Vec<float, VX> &av) {
             Vec<float, VX> wc;
             Vec<float, VX> pv = vzero<float, VX>();
             if (j > 0) pv = vload<float, VX>(vprev + c);
+            Vec<float, VX> vc = xv, s;
+            if constexpr (SC) {
+                vc = vload<float, VX>(v + c);
+                s = vload<float, VX>(dis + c);
+            }
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                wc.a[e] = av.a[e] - bp * pv.a[e];
+                const float a = SC ? s.a[e] * av.a[e] : av.a[e];
+                wc.a[e] = a - bp * pv.a[e];
                 acc[0] += vc.a[e] * wc.a[e];
             }
             vstore<float, VX>(w + c, wc);
@@ -1500,11 +1573,25 @@ void launch_apply(const OpView<T> &op, const T *x, T *y, hipStream_t s) {
 
 template <typename T, bool PC, int VX, int CS>
 static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int mode, bool last,
-                       bool chk, int j, int zin, const T *pin, bool red, T *pout, hipStream_t s) {
+                       bool chk, bool jac, int j, int zin, const T *pin, bool red, T *pout,
+                       hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
 #define CUTH_CHEB(M, LST, CK)                                                                      \
-    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK, CS>), g, b, 0, s, probs, nprob, j, zin,  \
-                       pin, (int)red, pout)
+    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, CK, CS, false>), g, b, 0, s, probs, nprob, j, \
+                       zin, pin, (int)red, pout)
+#define CUTH_CHEBJ(M, LST)                                                                         \
+    hipLaunchKernelGGL((k_cheb_b<T, PC, VX, M, LST, false, CS, true>), g, b, 0, s, probs, nprob, j,\
+                       zin, pin, (int)red, pout)
+    if (jac) {
+        // Jacobi-scaled sweeps: mode 3 (z_1 read, z_0 = 0) or 0; the
+        // convergence test runs in the scale pass before them
+        if (mode == 3) {
+            if (last) CUTH_CHEBJ(3, true); else CUTH_CHEBJ(3, false);
+        } else {
+            if (last) CUTH_CHEBJ(0, true); else CUTH_CHEBJ(0, false);
+        }
+        return;
+    }
     if (mode == 1) {
         if (chk) {
             if (last) CUTH_CHEB(1, true, true); else CUTH_CHEB(1, false, true);
@@ -1517,44 +1604,52 @@ static void cheb_modes(const InnerProb<T> *probs, int nprob, int nb, int by, int
         if (last) CUTH_CHEB(0, true, false); else CUTH_CHEB(0, false, false);
     }
 #undef CUTH_CHEB
+#undef CUTH_CHEBJ
 }
 
 template <typename T>
-void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, int vx, int by,
-                   int mode, bool last, bool chk, int j, int zin, const T *part_in, bool red,
-                   T *part_out, hipStream_t s) {
+void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs, bool jac, int vx,
+                   int by, int mode, bool last, bool chk, int j, int zin, const T *part_in,
+                   bool red, T *part_out, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
         if (pc && cs == CS_F16) {
             CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, true, VX, CS_F16>(probs, nprob, nb, by, mode,
-                                                                     last, chk, j, zin, part_in,
-                                                                     red, part_out, s)));
+                                                                     last, chk, jac, j, zin,
+                                                                     part_in, red, part_out, s)));
             return;
         }
     } else {
         if (cs == CS_CSR) {
             CUTH_VX_DISPATCH(T, vx, (cheb_modes<T, false, VX, CS_CSR>(probs, nprob, nb, by, mode,
-                                                                      last, chk, j, zin, part_in,
-                                                                      red, part_out, s)));
+                                                                      last, chk, false, j, zin,
+                                                                      part_in, red, part_out, s)));
             return;
         }
     }
     CUTH_PC_VX_DISPATCH(T, pc, vx, (cheb_modes<T, PC, VX, CS_OWN>(probs, nprob, nb, by, mode, last,
-                                                                  chk, j, zin, part_in, red,
+                                                                  chk, jac, j, zin, part_in, red,
                                                                   part_out, s)));
 }
 
-template <typename T>
-void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
-                    int zc, int wpr, int j, int zsel, hipStream_t s) {
+template <typename T, bool JAC>
+static void cheb2_jac(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                      int zc, int wpr, int j, int zsel, hipStream_t s) {
     const dim3 g(nb), b(kWave, wpr * (R + 2));
     const size_t lds = (size_t)3 * (R + 2) * wpr * kWave * vx * sizeof(T);
     if (pc && h16) {
-        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb2_b<T, true, VX, CS_F16>), g, b, lds, s,
-                                                    probs, nprob, j, zsel, R, zc, wpr)));
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb2_b<T, true, VX, CS_F16, JAC>), g, b, lds,
+                                                    s, probs, nprob, j, zsel, R, zc, wpr)));
         return;
     }
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb2_b<T, PC, VX, CS_OWN>), g, b, lds, s,
-                                                       probs, nprob, j, zsel, R, zc, wpr)));
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb2_b<T, PC, VX, CS_OWN, JAC>), g, b, lds,
+                                                       s, probs, nprob, j, zsel, R, zc, wpr)));
+}
+
+template <typename T>
+void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac,
+                    int vx, int R, int zc, int wpr, int j, int zsel, hipStream_t s) {
+    if (jac) cheb2_jac<T, true>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
+    else cheb2_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
 template <typename T, bool PC, int VX, int PM>
@@ -1575,6 +1670,9 @@ void launch_scale_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int p
     if (pm == PM_JACOBI) {
         CUTH_PC_VX_DISPATCH(T, pc, vx, (scale_chk<T, PC, VX, PM_JACOBI>(probs, nprob, nb, by, chk,
                                                                         part_in, red, part_out, s)));
+    } else if (pm == PM_JCHEB) {
+        CUTH_PC_VX_DISPATCH(T, pc, vx, (scale_chk<T, PC, VX, PM_JCHEB>(probs, nprob, nb, by, chk,
+                                                                       part_in, red, part_out, s)));
     } else if (pm == PM_NONE) {
         CUTH_VX_DISPATCH(T, vx, (scale_chk<T, false, VX, PM_NONE>(probs, nprob, nb, by, chk, part_in,
                                                                   red, part_out, s)));
@@ -1711,11 +1809,24 @@ void launch_scale_rsqrt(int64_t n, const float *v, const float *part_in, int np_
 }
 
 void launch_lanczos_av(const OpView<float> &op, int j, const float *v, const float *vprev,
-                       const float *lz, float *w, float *part_out, hipStream_t s) {
+                       const float *lz, const float *dis, float *w, float *part_out,
+                       hipStream_t s) {
     const dim3 g(stencil_blocks(op)), b(kWave, op.by);
+    if (dis) {
+        CUTH_PC_VX_DISPATCH(float, op.gx != nullptr, op.vx,
+                            (hipLaunchKernelGGL((k_lanczos_av<PC, VX, true>), g, b, 0, s, op, j, v,
+                                                vprev, lz, dis, w, part_out)));
+        return;
+    }
     CUTH_PC_VX_DISPATCH(float, op.gx != nullptr, op.vx,
-                        (hipLaunchKernelGGL((k_lanczos_av<PC, VX>), g, b, 0, s, op, j, v, vprev, lz,
-                                            w, part_out)));
+                        (hipLaunchKernelGGL((k_lanczos_av<PC, VX, false>), g, b, 0, s, op, j, v,
+                                            vprev, lz, dis, w, part_out)));
+}
+
+void launch_jacobi_dis(const OpView<double> &op, float *dis, hipStream_t s) {
+    const int64_t n = (int64_t)op.nx * op.ny * op.nz;
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_jacobi_dis, dim3(nb), dim3(256), 0, s, op, dis);
 }
 
 void launch_lanczos_orth(int64_t n, int j, float *w, const float *v, float *lz,
@@ -1745,7 +1856,7 @@ void launch_adjoint(const OpView<double> &op, const double *lam, const double *T
 
 #define CUTH_INST(T)                                                                              \
     template void launch_apply<T>(const OpView<T> &, const T *, T *, hipStream_t);                \
-    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, int,      \
+    template void launch_cheb_b<T>(const InnerProb<T> *, int, int, bool, int, bool, int, int, int,\
                                    bool, bool, int, int, const T *, bool, T *, hipStream_t);      \
     template void launch_scale_b<T>(const InnerProb<T> *, int, int, bool, int, int, int, bool,    \
                                     const T *, bool, T *, hipStream_t);                           \
@@ -1760,8 +1871,8 @@ CUTH_INST(float)
 CUTH_INST(double)
 #undef CUTH_INST
 
-template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, bool, int, int, int,
-                                    int, int, int, hipStream_t);
+template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, bool, bool, int, int,
+                                      int, int, int, int, hipStream_t);
 template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
                                          hipStream_t);
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,

@@ -191,14 +191,18 @@ struct Bytes {
     double pair() const { return 5.0 * sizeof(T) + coef_sw; }
     double precond(int k, int pm = 0, bool fuse = false) const {
         if (pm == 1) return scale() + coef;   // Jacobi: also the lateral conductances
-        if (k == 1 || pm == 2) return scale();
-        double b = cheb(1);
+        if (pm == 2 || (k == 1 && pm == 0)) return scale();
+        // Jacobi-scaled Chebyshev: the scale pass (r and the conductances read,
+        // z_1 written), then a sweep that reads z_1 and r, then general sweeps
+        const bool jac = pm == 3;
+        if (jac && k == 1) return scale() + coef;
+        double b = jac ? scale() + coef + cheb(2) : cheb(1);
         for (int j = 2; j < k;) {
             if (fuse && j >= 3 && j + 1 < k - 1) {
                 b += pair();
                 j += 2;
             } else {
-                b += cheb(j == 2 ? 2 : 0);
+                b += cheb(j == 2 && !jac ? 2 : 0);
                 j += 1;
             }
         }
@@ -249,7 +253,19 @@ struct Problem {
     Status status;
     // slots of the current launches
     int tile0 = 0, ntiles = 0;
+    // interval of the preconditioner's operator (A, or D^{-1} A when scaled)
+    double ilo = 0.0, ihi = 0.0;
 };
+
+// The two Chebyshev preconditioners (the paper's, and the Jacobi-scaled one).
+inline bool is_cheb(int pm) { return pm == CUTH_PC_CHEBYSHEV || pm == CUTH_PC_CHEBYSHEV_JACOBI; }
+
+// Interval of the operator the preconditioner's polynomial acts on (bounds
+// already computed).
+inline void pc_interval(const Setup &su, int pm, double &lo, double &hi) {
+    lo = pm == CUTH_PC_CHEBYSHEV_JACOBI ? su.jlmin : su.lmin;
+    hi = pm == CUTH_PC_CHEBYSHEV_JACOBI ? su.jlmax : su.lmax;
+}
 
 template <typename T> struct Sel;
 template <> struct Sel<float> {
@@ -453,7 +469,7 @@ inline void free_pair(int n, int p, int &x, int &y) {
 // writes z[1]; every single sweep writes over the older of (newest, older);
 // a fused pair writes the two other buffers.
 int precond_final(int k, int pm, bool fuse) {
-    if (k == 1 || pm != 0) return 0;
+    if (k == 1 || pm == 1 || pm == 2) return 0;
     if (k == 2) return 1;
     int n = 0, p = 1;   // after mode 2
     for (int j = 3; j < k;) {
@@ -486,14 +502,23 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
                     bool chk, bool red, hipStream_t s, Grid *prof, int tag = -1) {
     InnerProb<T> *d = Sel<T>::d(E);
     const bool h16 = cs == CS_F16;
+    const bool jac = pm == 3;   // Jacobi-scaled Chebyshev (beyond the paper)
     const T *rr_in = red ? red_rr<T>(E) : eslot<T>(E, P_UPD);
-    if (k == 1 || pm != 0) {
+    if (pm == 1 || pm == 2 || k == 1) {
         launch_scale_b<T>(d, nprob, nb, pc, pm, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
         if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
         return 0;
     }
-    launch_cheb_b<T>(d, nprob, nb, pc, cs, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1), rr_in, red,
-                     eslot<T>(E, P_CHEB), s);
+    if (jac) {
+        // z_1 = D^{-1} r / theta into z[0] (with the convergence test), then
+        // the first sweep from the stored z_1 into z[1]
+        launch_scale_b<T>(d, nprob, nb, pc, pm, sh.vx, sh.by, chk, rr_in, red, eslot<T>(E, P_CHEB), s);
+        launch_cheb_b<T>(d, nprob, nb, pc, cs, true, sh.vx, sh.by, 3, k == 2, false, 1, zsel(0, 1),
+                         rr_in, red, eslot<T>(E, P_CHEB), s);
+    } else {
+        launch_cheb_b<T>(d, nprob, nb, pc, cs, false, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1),
+                         rr_in, red, eslot<T>(E, P_CHEB), s);
+    }
     // fused pairs of general sweeps (FP32)
     const bool fuse = sizeof(T) == 4 && sh.fr > 0;
     int nbf = 0;
@@ -510,13 +535,15 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
             int x, y;
             free_pair(n, p, x, y);
             if constexpr (sizeof(T) == 4)
-                launch_cheb2_b<T>(d, nprob, nbf, pc, h16, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
+                launch_cheb2_b<T>(d, nprob, nbf, pc, h16, jac, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
                                   n + 4 * p + 16 * x + 64 * y, s);
             p = x;
             n = y;
         } else {
-            const int mode = (j == 2) ? 2 : 0;
-            launch_cheb_b<T>(d, nprob, nb, pc, cs, sh.vx, sh.by, mode, j == k - 1, false, j,
+            // j = 2 reads z_1 where the scale pass stored it (Jacobi) or
+            // takes it as r/theta (mode 2)
+            const int mode = (j == 2 && !jac) ? 2 : 0;
+            launch_cheb_b<T>(d, nprob, nb, pc, cs, jac, sh.vx, sh.by, mode, j == k - 1, false, j,
                              zsel(n, p), rr_in, red, eslot<T>(E, P_CHEB), s);
             std::swap(n, p);
         }
@@ -1364,6 +1391,7 @@ void grid_destroy(Grid *g) {
         dev_free(su.csr_ptr);
         dev_free(su.csr_col);
         dev_free(su.csr_val);
+        dev_free(su.dis);
     }
     dev_free(g->gx64);
     dev_free(g->gy64);
@@ -1459,10 +1487,16 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
 // beta_j = ||w||, v_{j+1} = w / beta_j.  Scalars stay on the device until the
 // end; one readback returns the tridiagonal.
 Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<double> &alpha,
-                   std::vector<double> &beta) {
+                   std::vector<double> &beta, bool scaled) {
     steps = (int)std::max<int64_t>(1, std::min<int64_t>(steps, g.N));
     steps = std::min(steps, 256);
     const OpView<float> op = view32(g, su);
+    if (scaled && !su.dis) {
+        CUTH_TRY(dev_alloc(&su.dis, (size_t)g.N));
+        launch_jacobi_dis(view64(g, su), su.dis, g.stream);
+        CUTH_HIP(hipGetLastError());
+    }
+    const float *dis = scaled ? su.dis : nullptr;
     const int nbs = stencil_blocks(op), nb1 = red_blocks(g.N);
     float *pa = g.slot<float>(S_LZA), *pb = g.slot<float>(S_LZB);
     float *bufs[3] = {g.w32.pA, g.w32.pB, g.w32.mu};
@@ -1476,7 +1510,8 @@ Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<d
     }
     int ip = 0, iv = 1, iw = 2;
     for (int j = 0; j < steps; ++j) {
-        launch_lanczos_av(op, j, bufs[iv], j > 0 ? bufs[ip] : nullptr, g.lz, bufs[iw], pa, g.stream);
+        launch_lanczos_av(op, j, bufs[iv], j > 0 ? bufs[ip] : nullptr, g.lz, dis, bufs[iw], pa,
+                          g.stream);
         launch_lanczos_orth(g.N, j, bufs[iw], bufs[iv], g.lz, pa, nbs, pb, g.stream);
         if (j == steps - 1) break;
         launch_lanczos_div(g.N, j, bufs[iw], g.lz, pb, nb1, g.stream);
@@ -1506,7 +1541,24 @@ Status run_lanczos(Grid &g, Setup &su, int steps, const float *v0, std::vector<d
     return Status::ok();
 }
 
-Status ensure_bounds(Grid &g, Setup &su, int steps) {
+Status ensure_bounds(Grid &g, Setup &su, int steps, bool scaled) {
+    if (scaled) {
+        // D^{-1} A: its spectrum lies in (0, 2] for a diagonally dominant A with
+        // positive diagonal (Gershgorin: |lambda - 1| <= sum_j |a_ij| / a_ii <= 1)
+        if (su.have_jbounds && su.jbounds_steps == steps) return Status::ok();
+        std::vector<double> a, b;
+        CUTH_TRY(run_lanczos(g, su, steps, nullptr, a, b, true));
+        double lo, hi;
+        tridiag_extremes(a, b, lo, hi);
+        su.jritz_min = lo;
+        su.jritz_max = hi;
+        su.jlmax = std::min(2.0, 1.05 * hi);
+        su.jlmin = lo;
+        if (!(su.jlmin > 0.0) || !(su.jlmax > su.jlmin * (1.0 + 1e-6))) su.jlmin = 0.5 * su.jlmax;
+        su.have_jbounds = true;
+        su.jbounds_steps = steps;
+        return Status::ok();
+    }
     if (su.have_bounds && su.bounds_steps == steps) return Status::ok();
     std::vector<double> a, b;
     CUTH_TRY(run_lanczos(g, su, steps, nullptr, a, b));
@@ -1565,8 +1617,8 @@ void fill_stats(const Problem &p, cuth_stats *stats, float ms_setup, float ms_so
     stats->setup_ms = ms_setup;
     stats->solve_ms = ms_solve;
     stats->alg_bytes = p.bytes;
-    stats->lambda_min = p.su->lmin;
-    stats->lambda_max = p.su->lmax;
+    stats->lambda_min = is_cheb(p.pm) ? p.ilo : p.su->lmin;
+    stats->lambda_max = is_cheb(p.pm) ? p.ihi : p.su->lmax;
 }
 
 // Run the refinement for a set of problems on the engine's own stream (waiting
@@ -1579,7 +1631,7 @@ Status run_set(Engine &E, std::vector<Problem *> &ps, hipStream_t user, const Sh
     CUTH_HIP(hipStreamWaitEvent(s, E.ev_in, 0));
     Status st;
     // Jacobi and no preconditioning are single passes (degree-1 path)
-    const int k = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+    const int k = is_cheb(o.preconditioner) ? o.cheb_degree : 1;
     if (o.precision == CUTH_ADAPTIVE)
         st = run_staged(E, ps, sh32, sh64, k, o, period, s);
     else if (o.precision != CUTH_FP64)
@@ -1611,15 +1663,21 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     CUTH_HIP(hipEventRecord(g.ev0, g.stream));
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    const bool cheb = o.preconditioner == CUTH_PC_CHEBYSHEV;
-    if (cheb) CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps));
-    if (o.cheb_degree == CUTH_DEGREE_AUTO) o.cheb_degree = cheb ? auto_degree(su->lmin, su->lmax) : 1;
+    const bool cheb = is_cheb(o.preconditioner);
+    double ilo = 0.0, ihi = 0.0;
+    if (cheb) {
+        CUTH_TRY(ensure_bounds(g, *su, o.lanczos_steps, o.preconditioner == CUTH_PC_CHEBYSHEV_JACOBI));
+        pc_interval(*su, o.preconditioner, ilo, ihi);
+    }
+    if (o.cheb_degree == CUTH_DEGREE_AUTO) o.cheb_degree = cheb ? auto_degree(ilo, ihi) : 1;
     CUTH_HIP(hipEventRecord(g.ev1, g.stream));
     if (o.precision == CUTH_FP64 || o.precision == CUTH_ADAPTIVE) CUTH_TRY(alloc_work(g.w64, g.N));
     Problem p;
     p.g = &g;
     p.su = su;
-    p.cc = cheb ? make_cheb(su->lmin, su->lmax, o.cheb_degree) : ChebConsts{};
+    p.cc = cheb ? make_cheb(ilo, ihi, o.cheb_degree) : ChebConsts{};
+    p.ilo = ilo;
+    p.ihi = ihi;
     p.pm = o.preconditioner;
     p.P = P;
     p.Tn = Tn;
@@ -1669,7 +1727,7 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
         sig << "single " << g.nx << 'x' << g.ny << 'x' << g.nz << (g.per_cell ? " pc" : " mf")
             << (p.h16 && g.per_cell ? "16" : "") << ' ' << g.sh32.vx << ',' << g.sh32.by << ','
             << g.sh32.zc;
-        const int kk = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+        const int kk = is_cheb(o.preconditioner) ? o.cheb_degree : 1;
         CUTH_TRY(tune_fuse<float>(g.eng, ps, kk, sh32, sig.str()));
     }
     Status rs = run_set(g.eng, ps, g.stream, sh32, g.sh64, o, period, use_graph, &g,
@@ -1762,13 +1820,13 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
         CUTH_HIP(hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * n,
                                 hipMemcpyHostToDevice, s));
         CUTH_HIP(hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s));
-        const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
+        const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16, jac = ps[0]->pm == CUTH_PC_CHEBYSHEV_JACOBI;
         for (int rep = 0; rep < 2; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, sh.vx, sh.by, 0, false, false, 2, zsel(1, 0),
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, jac, sh.vx, sh.by, 0, false, false, 2, zsel(1, 0),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 6; ++rep)
-            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, sh.vx, sh.by, 0, false, false, 2,
+            launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, jac, sh.vx, sh.by, 0, false, false, 2,
                              zsel(rep & 1, 1 - (rep & 1)),
                              eslot<T>(E, P_UPD), false, eslot<T>(E, P_CHEB), s);
         CUTH_HIP(hipEventRecord(e1, s));
@@ -1811,7 +1869,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         set_fuse(sh, max_nx);
         return Status::ok();
     }
-    if (k < 6 || ps[0]->pm != 0) return Status::ok();   // no pair of general sweeps
+    if (k < 6 || !is_cheb(ps[0]->pm)) return Status::ok();   // no pair of general sweeps
     for (Problem *p : ps)
         if (!Sel<T>::w(*p).zC || !Sel<T>::w(*p).zD) return Status::ok();
     const std::string key = sig + " fuse";
@@ -1823,7 +1881,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
             return Status::ok();
         }
     }
-    const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16;
+    const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16, jac = ps[0]->pm == CUTH_PC_CHEBYSHEV_JACOBI;
     const int cand[][2] = {{0, 0}, {2, 8}, {4, 8}, {2, 16}, {4, 4}, {1, 16}};
     const hipStream_t s = E.own;
     hipEvent_t e0, e1;
@@ -1853,14 +1911,14 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         auto round = [&]() {
             if (c.fr == 0) {
                 for (int q = 0; q < 4; ++q)
-                    launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, c.vx, c.by, 0, false, false, 3,
+                    launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, jac, c.vx, c.by, 0, false, false, 3,
                                      zsel(q & 1, 1 - (q & 1)), eslot<T>(E, P_UPD), false,
                                      eslot<T>(E, P_CHEB), s);
             } else {
                 if constexpr (sizeof(T) == 4) {
-                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, c.vx, c.fr, c.fzc, c.fwpr, 3,
+                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3,
                                       0 + 4 * 1 + 16 * 2 + 64 * 3, s);
-                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, c.vx, c.fr, c.fzc, c.fwpr, 3,
+                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3,
                                       3 + 4 * 2 + 16 * 0 + 64 * 1, s);
                 }
             }
@@ -1907,13 +1965,18 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         Status st;
         sus[s] = get_setup(*grids[s], 0.0, st);
         if (!sus[s]) return st;
-        if (o.preconditioner == CUTH_PC_CHEBYSHEV)
-            CUTH_TRY(ensure_bounds(*grids[s], *sus[s], o.lanczos_steps));
+        if (is_cheb(o.preconditioner))
+            CUTH_TRY(ensure_bounds(*grids[s], *sus[s], o.lanczos_steps,
+                                   o.preconditioner == CUTH_PC_CHEBYSHEV_JACOBI));
     }
     if (o.cheb_degree == CUTH_DEGREE_AUTO) {
         int k = 1;
-        if (o.preconditioner == CUTH_PC_CHEBYSHEV)
-            for (int s = 0; s < nsys; ++s) k = std::max(k, auto_degree(sus[s]->lmin, sus[s]->lmax));
+        if (is_cheb(o.preconditioner))
+            for (int s = 0; s < nsys; ++s) {
+                double lo, hi;
+                pc_interval(*sus[s], o.preconditioner, lo, hi);
+                k = std::max(k, auto_degree(lo, hi));
+            }
         o.cheb_degree = k;
     }
     // problems grouped by coefficient storage (one launch family per group)
@@ -1956,9 +2019,10 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                 Problem &p = probs[n];
                 p.g = &g;
                 p.su = sus[s];
-                p.cc = o.preconditioner == CUTH_PC_CHEBYSHEV
-                           ? make_cheb(sus[s]->lmin, sus[s]->lmax, o.cheb_degree)
-                           : ChebConsts{};
+                if (is_cheb(o.preconditioner)) {
+                    pc_interval(*sus[s], o.preconditioner, p.ilo, p.ihi);
+                    p.cc = make_cheb(p.ilo, p.ihi, o.cheb_degree);
+                }
                 p.pm = o.preconditioner;
                 p.P = P[s] + (int64_t)q * g.N;
                 p.out = T[s] + (int64_t)q * g.N;
@@ -2016,7 +2080,7 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                         : autotune<double>(E, ps, o.cheb_degree, sig.str() + " in", sh_in);
         if (!mixed && !staged) sh64 = sh_in;
         if (fuse32 && !ts.bad()) {
-            const int kk = o.preconditioner == CUTH_PC_CHEBYSHEV ? o.cheb_degree : 1;
+            const int kk = is_cheb(o.preconditioner) ? o.cheb_degree : 1;
             for (Problem *p : ps) p->pm = o.preconditioner;
             ts = tune_fuse<float>(E, ps, kk, sh_in, sig.str());
         }
@@ -2133,17 +2197,18 @@ Status residual(Grid &g, double dt, const double *b, const double *T, double *r)
 
 template <typename T>
 static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, const ChebConsts &cc,
-                            bool h16, const T *r, T *z) {
+                            int pm, bool h16, const T *r, T *z) {
     // the result lands in the buffer the sweep rotation ends in (fused pairs
     // exactly where enqueue_precond uses them: FP32)
     Engine &E = g.eng;
     const bool h16e = h16 && g.per_cell;
     const bool fuse = sizeof(T) == 4 && sh.fr > 0;
-    const int zfin = precond_final(cc.k, 0, fuse);
+    const int zfin = precond_final(cc.k, pm, fuse);
     Problem p;
     p.g = &g;
     p.su = &su;
     p.cc = cc;
+    p.pm = pm;
     p.h16 = h16e;
     Work<T> &pw = Sel<T>::w(p);
     pw = w;
@@ -2161,29 +2226,31 @@ static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, con
     CgState<T> *hs = Sel<T>::hs(E);
     std::memset(hs, 0, sizeof(CgState<T>));
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>), hipMemcpyHostToDevice, g.stream));
-    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, p.h16 ? CS_F16 : CS_OWN, 0, sh, cc.k, false, false, g.stream,
-                                       nullptr);
+    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, p.h16 ? CS_F16 : CS_OWN, pm, sh, cc.k,
+                                       false, false, g.stream, nullptr);
     if (got != zfin) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
 }
 
-Status precond_apply(Grid &g, double dt, int precision, double lmin, double lmax, int degree,
-                     const void *r, void *z) {
+Status precond_apply(Grid &g, double dt, int precision, int pm, double lmin, double lmax,
+                     int degree, const void *r, void *z) {
     Status st;
     if (degree > g.eng.kcap) return Status::err(CUTH_E_INVALID, "degree above 256");
     Setup *su = get_setup(g, dt, st);
     if (!su) return st;
-    const ChebConsts cc = make_cheb(lmin, lmax, degree);
+    // Jacobi and none are single passes; their degree is 1 (the constants are unused)
+    const ChebConsts cc = make_cheb(lmin, lmax, is_cheb(pm) ? degree : 1);
     if (precision != CUTH_FP64) {
         Shape sh32 = g.sh32;
         set_fuse(sh32, g.nx);
         if (sh32.fr > 0) CUTH_TRY(alloc_work(g.w32, g.N, true));
-        return precond_typed<float>(g, *su, g.w32, sh32, cc, precision == CUTH_MIXED16,
+        return precond_typed<float>(g, *su, g.w32, sh32, cc, pm, precision == CUTH_MIXED16,
                                     (const float *)r, (float *)z);
     }
     CUTH_TRY(alloc_work(g.w64, g.N));
-    return precond_typed<double>(g, *su, g.w64, g.sh64, cc, false, (const double *)r, (double *)z);
+    return precond_typed<double>(g, *su, g.w64, g.sh64, cc, pm, false, (const double *)r,
+                                 (double *)z);
 }
 
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,

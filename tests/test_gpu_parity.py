@@ -95,6 +95,111 @@ def test_chebyshev_matches_oracle(case, degree):
     g.close()
 
 
+@pytest.mark.parametrize("case", ["ragged_mult", "ragged_uniform", "c0"])
+@pytest.mark.parametrize("degree", [1, 2, 3, 6, 30])
+def test_chebyshev_jacobi_matches_oracle(monkeypatch, case, degree):
+    """The Jacobi-scaled Chebyshev preconditioner (beyond the paper):
+    q_k(D^{-1} A) D^{-1} r against the oracle's definition, in FP64 and FP32,
+    with single sweeps and with fused sweep pairs (two workgroup shapes)."""
+    say(f"chebyshev-jacobi {case} k={degree}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    lo, hi = krylov.jacobi_spectral_bounds(A, w.lanczos_start(st.n))
+    r = np.random.default_rng(7).standard_normal(st.n)
+    ref = krylov.jacobi_chebyshev_precondition(A, r, lo, hi, degree)
+    z = g.precond_apply(t64(r), lo, hi, degree, preconditioner="chebyshev_jacobi").cpu().numpy()
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+    for env in ({"CUTH_FUSE": "0"}, {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8"},
+                {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "1,1"}):
+        for k_, v_ in env.items():
+            monkeypatch.setenv(k_, v_)
+        z32 = g.precond_apply(t32(r), lo, hi, degree,
+                              preconditioner="chebyshev_jacobi").cpu().numpy().astype(np.float64)
+        assert np.abs(z32 - ref).max() <= 2e-3 * np.abs(ref).max(), env
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["ragged_mult", "c0"])
+def test_single_pass_preconditioners_match_oracle(case):
+    """Jacobi (z = r / diag(A)) and none (z = r) through cuth_precond_apply."""
+    say(f"single-pass preconditioners {case}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    r = np.random.default_rng(9).standard_normal(st.n)
+    zj = g.precond_apply(t64(r), 1.0, 2.0, 1, preconditioner="jacobi").cpu().numpy()
+    np.testing.assert_allclose(zj, r / A.diagonal(), rtol=1e-14)
+    zn = g.precond_apply(t64(r), 1.0, 2.0, 1, preconditioner="none").cpu().numpy()
+    assert np.array_equal(zn, r)
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["c0", "ragged_mult"])
+def test_jacobi_lanczos_matches_oracle(case):
+    """Lanczos on D^{-1/2} A D^{-1/2} against the oracle's, from the same start
+    vector; the interval used lies in (0, 2]."""
+    say(f"jacobi lanczos {case}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    v0 = w.lanczos_start(st.n)
+    b = g.spectral_bounds(steps=30, v0=t32(v0.astype(np.float32)), preconditioner="chebyshev_jacobi")
+    s = 1.0 / np.sqrt(A.diagonal())
+    a_ref, b_ref = krylov.lanczos(lambda v: s * (A @ (s * v)),
+                                  v0.astype(np.float32).astype(np.float64), 30)
+    ritz = krylov.ritz_values(a_ref, b_ref)
+    np.testing.assert_allclose(b["alpha"][:5], a_ref[:5], rtol=1e-4)
+    assert b["ritz_max"] == pytest.approx(ritz[-1], rel=1e-4)
+    assert b["ritz_min"] == pytest.approx(ritz[0], rel=5e-2)
+    assert 0.0 < b["lmin"] < b["lmax"] <= 2.0
+    g.close()
+
+
+def test_solve_chebyshev_jacobi():
+    """Solves with the Jacobi-scaled Chebyshev preconditioner meet the parity
+    bars in every precision (steady, one backward-Euler step, a two-grid
+    batch), and take fewer CG iterations than the paper's preconditioner of the
+    same degree on the layered stacks."""
+    import paper_2606_17850_amd as cuth
+    say("solve chebyshev-jacobi")
+    for st, P in (w.config4_small(), w.config0()):
+        ref = _ref_steady(st, P)
+        g = grid_of(st)
+        for prec, bar in (("fp64", 1e-10), ("mixed", 1e-8), ("mixed16", 1e-8), ("adaptive", 1e-10)):
+            T, s = g.solve(t64(P), precision=prec, preconditioner="chebyshev_jacobi")
+            e = rise_err(T.cpu().numpy(), ref, st.t_amb)
+            _, s0 = g.solve(t64(P), precision=prec)
+            say(f"  {st.shape} {prec} cg {s['cg_iters']} (chebyshev {s0['cg_iters']}) err {e:.2e} "
+                f"interval {s['lambda_min']:.3e}..{s['lambda_max']:.3e}")
+            assert e <= bar
+            assert 0.0 < s["lambda_min"] < s["lambda_max"] <= 2.0
+            if prec == "fp64":
+                assert s["cg_iters"] < s0["cg_iters"]
+        g.close()
+    st = ragged_stack(70, 9, mult=True)
+    P = np.zeros(st.shape)
+    P[0] = np.random.default_rng(6).uniform(0, 2e-3, (st.ny, st.nx))
+    g = grid_of(st)
+    dt = 1e-4
+    th0 = np.random.default_rng(8).uniform(0, 5.0, st.n)
+    ref_tr = transient.step(st, P.ravel(), th0, dt)
+    Tt, _ = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision="mixed",
+                             preconditioner="chebyshev_jacobi")
+    got = Tt.cpu().numpy() - st.t_amb
+    assert np.abs(got - ref_tr).max() <= 1e-8 * np.abs(ref_tr).max()
+    g.close()
+    stacks = [ragged_stack(70, 9, mult=True), ragged_stack(67, 1, mult=True)]
+    maps = [np.random.default_rng(40 + i).uniform(0, 2e-3, s_.n) for i, s_ in enumerate(stacks)]
+    grids = [grid_of(s_) for s_ in stacks]
+    Tb, _ = cuth.solve_batch(grids, [t64(m) for m in maps], nrhs=1, precision="mixed",
+                             preconditioner="chebyshev_jacobi")
+    for s_, m, t in zip(stacks, maps, Tb):
+        assert rise_err(t.cpu().numpy(), _ref_steady(s_, m), s_.t_amb) <= 1e-8
+    for gg in grids:
+        gg.close()
+
+
 @pytest.mark.parametrize("case", ["c0", "ragged_mult"])
 def test_lanczos_matches_oracle(case):
     say(f"lanczos {case}")
