@@ -43,14 +43,17 @@ def c1():
     return st, P
 
 
-@pytest.mark.parametrize("prec,tol", [("mixed", 1e-8), ("mixed16", 1e-8), ("fp64", 1e-10)])
-def test_config1_full_size(c1, prec, tol):
+@pytest.mark.parametrize("prec,tol,pc", [("mixed", 1e-8, "chebyshev"), ("mixed16", 1e-8, "chebyshev"),
+                                         ("fp64", 1e-10, "chebyshev"),
+                                         ("mixed", 1e-8, "chebyshev_jacobi"),
+                                         ("fp64", 1e-10, "chebyshev_jacobi")])
+def test_config1_full_size(c1, prec, tol, pc):
     st, P = c1
-    say(f"config1 full size {prec}")
+    say(f"config1 full size {prec} {pc}")
     with open(GOLD) as f:
         ref = json.load(f)
     g = grid_of(st)
-    T, stats = g.solve(t64(P), precision=prec)
+    T, stats = g.solve(t64(P), precision=prec, preconditioner=pc)
     th = T.cpu().numpy() - st.t_amb
     g.close()
     cells = np.array(ref["cells"])
