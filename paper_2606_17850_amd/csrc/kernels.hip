@@ -517,10 +517,13 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
                 gs = gn = L.gy;
             }
             // A x in difference form and the diagonal of A (sink plus the
-            // conductances of the faces that exist), for the Jacobi scaling
+            // conductances of the faces that exist), for the Jacobi scaling.
+            // Per-cell conductances need no x-boundary test: the +x one is 0
+            // on the last column, and lane 0's west conductance and value are
+            // 0 on the first, so those terms add exactly zero.
             T a = L.sink * x, d = L.sink;
-            if (i > 0) a += gm * (x - xl), d += gm;
-            if (i < nx - 1) a += gp * (x - xr), d += gp;
+            if (PC || i > 0) a += gm * (x - xl), d += gm;
+            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
             if (ln.j > 0) a += gs * (x - xso.a[e]), d += gs;
             if (ln.j < ny - 1) a += gn * (x - xno.a[e]), d += gn;
             if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
@@ -800,8 +803,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                     gs = gn = L.gy;
                 }
                 T a = L.sink * x, d = L.sink;
-                if (i > 0) a += gm * (x - xl), d += gm;
-                if (i < nx - 1) a += gp * (x - xr), d += gp;
+                if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
+                if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
                 if (jr > 0) a += gs * (x - xso.a[e]), d += gs;
                 if (jr < ny - 1) a += gn * (x - xno.a[e]), d += gn;
                 if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
@@ -842,8 +845,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                     gs = gn = L.gy;
                 }
                 T a = L.sink * x, d = L.sink;
-                if (i > 0) a += gm * (x - xl), d += gm;
-                if (i < nx - 1) a += gp * (x - xr), d += gp;
+                if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
+                if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
                 if (jr > 0) a += gs * (x - so.a[e]), d += gs;
                 if (jr < ny - 1) a += gn * (x - no.a[e]), d += gn;
                 if (lb > 0) a += L.gzd * (x - zA_m2.a[e]), d += L.gzd;
