@@ -759,118 +759,122 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
     Vec<T, VX> xdn = vload<T, VX>(zN + ((act && la0 > 0) ? c - plane : c));
     Vec<T, VX> xc = vload<T, VX>(zN + c);
     // previous layer's values kept for stage B
-    Vec<T, VX> zA_m1 = zero, zA_m2 = zero, r_m1 = zero, zj_m1 = zero, gxp_m1 = zero,
-               gyp_m1 = zero, gym_m1 = zero;
+    Vec<T, VX> zA_m1 = zero, zA_m2 = zero, r_m1 = zero, gxp_m1 = zero, gyp_m1 = zero,
+               gym_m1 = zero;
     T gxl_m1 = T(0);
-    for (int l = la0; l <= la1; ++l, c += plane) {
-        const bool doA = l < la1;
-        Vec<T, VX> zn = zero, rv = zero, gxp = zero, gyp = zero, gym = zero, xup = zero;
-        T gxl = T(0);
-        if (doA) {
-            // ---- stage A: z_{j+1} at layer l
-            const LayerCoef<T> L = gldc(op.lc + l);
-            // every load of the layer is issued before the first use
-            // (unguarded, at in-bounds cells: see the column walker)
-            xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
-            const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
-            const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
-            const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
-            const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
-            [[maybe_unused]] LatRaw<T, VX, CS> lat;
-            if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
-            rv = vload<T, VX>(r + c);
-            const Vec<T, VX> zm = vload<T, VX>(zP + c);
-            T left = lane_left(xc.a[VX - 1]);
-            T right = lane_right(xc.a[0]);
-            if (lane == 0) left = west;
-            if (lane == kWave - 1) right = east;
-            if constexpr (PC)
-                lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
-#pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const int i = xo + e;
-                const T x = xc.a[e];
-                const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
-                const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
-                T gm, gp, gs, gn;
-                if constexpr (PC) {
-                    gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
-                    gp = gxp.a[e];
-                    gs = gym.a[e];
-                    gn = gyp.a[e];
-                } else {
-                    gm = gp = L.gx;
-                    gs = gn = L.gy;
-                }
-                T a = L.sink * x, d = L.sink;
-                if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
-                if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
-                if (jr > 0) a += gs * (x - xso.a[e]), d += gs;
-                if (jr < ny - 1) a += gn * (x - xno.a[e]), d += gn;
-                if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
-                if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
-                T res = rv.a[e] - a;
-                if constexpr (JAC) res *= recip(d);
-                zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * res : T(0);
-            }
-            if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
-            if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
-        }
-        __syncthreads();
-        // ---- stage B: z_{j+2} at layer lb = l - 1
+    // stage B: z_{j+2} at layer lb = l - 1 of this lane's cell (cl is its cell
+    // at layer l), from the ring (x and y neighbours), the registers of the
+    // layers below and the stage-A result `up` of layer l
+    auto stage_b = [&](int l, int64_t cl, const Vec<T, VX> &up) {
         const int lb = l - 1;
-        if (inner && lb >= l0 && lb < l1) {
-            const LayerCoef<T> L = gldc(op.lc + lb);
-            const T *rowc = ring_at(lb, rs);
-            const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, rs - 1) + xo);
-            const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, rs + 1) + xo);
-            const T left = has_l ? rowc[xo - 1] : T(0);
-            const T right = has_r ? rowc[xo + VX] : T(0);
-            const Vec<T, VX> &y = zA_m1;
-            Vec<T, VX> z2;
+        if (!(inner && lb >= l0 && lb < l1)) return;
+        const LayerCoef<T> L = gldc(op.lc + lb);
+        const T *rowc = ring_at(lb, rs);
+        const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, rs - 1) + xo);
+        const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, rs + 1) + xo);
+        const T left = has_l ? rowc[xo - 1] : T(0);
+        const T right = has_r ? rowc[xo + VX] : T(0);
+        const Vec<T, VX> &y = zA_m1;
+        Vec<T, VX> z2;
 #pragma unroll
-            for (int e = 0; e < VX; ++e) {
-                const int i = xo + e;
-                const T x = y.a[e];
-                const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
-                const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
-                T gm, gp, gs, gn;
-                if constexpr (PC) {
-                    gm = (e == 0) ? gxl_m1 : gxp_m1.a[e > 0 ? e - 1 : 0];
-                    gp = gxp_m1.a[e];
-                    gs = gym_m1.a[e];
-                    gn = gyp_m1.a[e];
-                } else {
-                    gm = gp = L.gx;
-                    gs = gn = L.gy;
-                }
-                T a = L.sink * x, d = L.sink;
-                if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
-                if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
-                if (jr > 0) a += gs * (x - so.a[e]), d += gs;
-                if (jr < ny - 1) a += gn * (x - no.a[e]), d += gn;
-                if (lb > 0) a += L.gzd * (x - zA_m2.a[e]), d += L.gzd;
-                if (lb < nz - 1) a += L.gzu * (x - zn.a[e]), d += L.gzu;
-                T res = r_m1.a[e] - a;
-                if constexpr (JAC) res *= recip(d);
-                z2.a[e] = x + c1b * (x - zj_m1.a[e]) + c2b * res;
+        for (int e = 0; e < VX; ++e) {
+            const int i = xo + e;
+            const T x = y.a[e];
+            const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
+            const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
+            T gm, gp, gs, gn;
+            if constexpr (PC) {
+                gm = (e == 0) ? gxl_m1 : gxp_m1.a[e > 0 ? e - 1 : 0];
+                gp = gxp_m1.a[e];
+                gs = gym_m1.a[e];
+                gn = gyp_m1.a[e];
+            } else {
+                gm = gp = L.gx;
+                gs = gn = L.gy;
             }
-            vstore<T, VX>(zY + c - plane, z2);
+            T a = L.sink * x, d = L.sink;
+            if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
+            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
+            if (jr > 0) a += gs * (x - so.a[e]), d += gs;
+            if (jr < ny - 1) a += gn * (x - no.a[e]), d += gn;
+            if (lb > 0) a += L.gzd * (x - zA_m2.a[e]), d += L.gzd;
+            if (lb < nz - 1) a += L.gzu * (x - up.a[e]), d += L.gzu;
+            T res = r_m1.a[e] - a;
+            if constexpr (JAC) res *= recip(d);
+            z2.a[e] = x + c1b * (x - xdn.a[e]) + c2b * res;   // xdn: z_j at layer lb
         }
+        vstore<T, VX>(zY + cl - plane, z2);
+    };
+    // the loop holds every stage A (the last layer, with stage B only, is
+    // peeled below, so no value needs a placeholder)
+    for (int l = la0; l < la1; ++l, c += plane) {
+        Vec<T, VX> zn, rv, gxp = zero, gyp = zero, gym = zero, xup;
+        T gxl = T(0);
+        // ---- stage A: z_{j+1} at layer l
+        const LayerCoef<T> L = gldc(op.lc + l);
+        // every load of the layer is issued before the first use
+        // (unguarded, at in-bounds cells: see the column walker)
+        xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
+        const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
+        const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
+        const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
+        const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
+        [[maybe_unused]] LatRaw<T, VX, CS> lat;
+        if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
+        rv = vload<T, VX>(r + c);
+        const Vec<T, VX> zm = vload<T, VX>(zP + c);
+        T left = lane_left(xc.a[VX - 1]);
+        T right = lane_right(xc.a[0]);
+        if (lane == 0) left = west;
+        if (lane == kWave - 1) right = east;
+        if constexpr (PC)
+            lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            const int i = xo + e;
+            const T x = xc.a[e];
+            const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
+            const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
+            T gm, gp, gs, gn;
+            if constexpr (PC) {
+                gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                gp = gxp.a[e];
+                gs = gym.a[e];
+                gn = gyp.a[e];
+            } else {
+                gm = gp = L.gx;
+                gs = gn = L.gy;
+            }
+            T a = L.sink * x, d = L.sink;
+            if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
+            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
+            if (jr > 0) a += gs * (x - xso.a[e]), d += gs;
+            if (jr < ny - 1) a += gn * (x - xno.a[e]), d += gn;
+            if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
+            if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
+            T res = rv.a[e] - a;
+            if constexpr (JAC) res *= recip(d);
+            zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * res : T(0);
+        }
+        if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
+        if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
+        __syncthreads();
+        stage_b(l, c, zn);
         // shift the layer registers
         zA_m2 = zA_m1;
         zA_m1 = zn;
         r_m1 = rv;
-        zj_m1 = xc;
         gxp_m1 = gxp;
         gyp_m1 = gyp;
         gym_m1 = gym;
         gxl_m1 = gxl;
-        if (doA) {
-            xdn = xc;
-            xc = xup;
-        }
+        xdn = xc;
+        xc = xup;
     }
+    // stage B of layer la1 - 1: it runs only when la1 = nz, where its
+    // up-neighbour term does not exist
+    __syncthreads();
+    stage_b(la1, c, zero);
 }
 
 // Single-pass preconditioners, partials of r^T z:
