@@ -305,9 +305,10 @@ cuth_status cuth_spectral_bounds(cuth_grid g, double dt, int32_t preconditioner,
 cuth_status cuth_grid_reset_bounds(cuth_grid g);
 
 /* Kernel timing for measurement.  When on, each preconditioner application
- * brackets its first launch of general Chebyshev sweeps (one sweep, or a fused
- * pair of sweeps) with HIP events on the handle's stream; cuth_profile_read
- * returns the summed duration (ms), the number of timed launches, the
+ * brackets its run of back-to-back general Chebyshev launches from the third
+ * sweep on (the fused pairs of sweeps, else the single sweeps before the last)
+ * with two HIP events on the handle's stream; cuth_profile_read returns the
+ * summed duration of those runs (ms), the number of launches they hold, the
  * algorithmic bytes of one such launch (N times the bytes per unknown) and
  * whether the timed launches were fused pairs (*fused 1) or single sweeps (0).
  * Any output pointer may be NULL.  Enabling resets the counters and

@@ -120,7 +120,8 @@ struct Grid {
     // Chebyshev sweep of each preconditioner application
     bool prof = false;
     std::vector<hipEvent_t> pev;
-    std::vector<int> pev_tag;   // CG iteration of each recorded pair (-1: initial)
+    std::vector<int> pev_tag;   // CG iteration of each recorded block (-1: initial)
+    std::vector<int> pev_cnt;   // launches in each recorded block
     size_t pev_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
     bool prof_fused = false;   // the timed launch was a fused sweep pair

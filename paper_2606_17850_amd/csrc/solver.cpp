@@ -34,16 +34,16 @@ namespace cuth {
         if (s_.bad()) return s_;     \
     } while (0)
 
-// Accumulate the durations of the recorded sweep events (stream already
-// synced).  Pairs recorded in CG iterations at or after `valid_below` ran after
-// the device-side stop and did no work; they are dropped.
+// Accumulate the durations of the recorded blocks of sweep launches (stream
+// already synced).  Blocks recorded in CG iterations at or after `valid_below`
+// ran after the device-side stop and did no work; they are dropped.
 Status prof_flush(Grid &g, int valid_below) {
     for (size_t i = 0; i + 1 < g.pev_used; i += 2) {
         float ms = 0.f;
         if (g.pev_tag.size() > i / 2 && g.pev_tag[i / 2] >= valid_below) continue;
         if (hipEventElapsedTime(&ms, g.pev[i], g.pev[i + 1]) == hipSuccess) {
             g.prof_ms += ms;
-            g.prof_count += 1;
+            g.prof_count += g.pev_cnt.size() > i / 2 ? g.pev_cnt[i / 2] : 1;
         }
     }
     g.pev_used = 0;
@@ -527,10 +527,17 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
         nbf = last.f_tile0 + last.f_ntiles;
     }
     int n = 1, p = 0;   // newest and older iterate after mode 1
+    // Timed block: the launches of the one general kernel from j = 3 on (the
+    // fused pairs, else the sweeps before the last), back to back on the
+    // stream; its duration over its launch count is the average launch
+    // duration, with the two event markers spread over the whole block.
+    const bool timing = prof && prof->prof && prof->pev_used + 2 <= prof->pev.size();
+    int blk = 0;
+    auto in_block = [&](int jj) { return jj >= 3 && (fuse ? jj + 1 < k - 1 : jj < k - 1); };
     for (int j = 2; j < k;) {
         const bool pair = fuse && j >= 3 && j + 1 < k - 1;
-        const bool timed = prof && prof->prof && j == 3 && prof->pev_used + 2 <= prof->pev.size();
-        if (timed) (void)hipEventRecord(prof->pev[prof->pev_used], s);
+        const bool timed = timing && in_block(j);
+        if (timed && blk == 0) (void)hipEventRecord(prof->pev[prof->pev_used], s);
         if (pair) {
             int x, y;
             free_pair(n, p, x, y);
@@ -547,16 +554,21 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
                              zsel(n, p), rr_in, red, eslot<T>(E, P_CHEB), s);
             std::swap(n, p);
         }
-        if (timed) {
+        ++blk;
+        if (timed && !in_block(j + (pair ? 2 : 1))) {
             (void)hipEventRecord(prof->pev[prof->pev_used + 1], s);
-            if (prof->pev_tag.size() < prof->pev.size() / 2) prof->pev_tag.resize(prof->pev.size() / 2);
-            prof->pev_tag[prof->pev_used / 2] = tag;
+            const size_t slot = prof->pev_used / 2;
+            if (prof->pev_tag.size() <= slot) prof->pev_tag.resize(prof->pev.size() / 2);
+            if (prof->pev_cnt.size() <= slot) prof->pev_cnt.resize(prof->pev.size() / 2);
+            prof->pev_tag[slot] = tag;
+            prof->pev_cnt[slot] = blk;
             prof->pev_used += 2;
             // a fused pair reads z_j, z_{j-1}, r (+ gx, gy) once and writes two iterates
             const Bytes<T> by(pc, h16);
             prof->prof_bytes = (pair ? by.pair() : by.cheb(0)) * (double)prof->N;
             prof->prof_fused = pair;
         }
+        if (!timed) blk = 0;
         j += pair ? 2 : 1;
     }
     if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
@@ -1167,6 +1179,11 @@ double bisect_kth(const std::vector<double> &a, const std::vector<double> &b, in
     }
     return 0.5 * (lo + hi);
 }
+
+// A later tuning candidate replaces the best so far only when it is faster by
+// more than this margin: near-ties keep the earlier candidate, so timing noise
+// does not flip the chosen shape from one process to the next.
+constexpr float kTuneMargin = 0.97f;
 
 // Fused pairs of general FP32 Chebyshev sweeps: CUTH_FUSE=0 never, CUTH_FUSE=1
 // always (shape CUTH_FUSE_SHAPE="R,zc", default 2,8), unset: chosen per grid by
@@ -1834,7 +1851,7 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
         float ms = 0;
         CUTH_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (log_on()) std::fprintf(stderr, "cuth: autotune %d,%d,%d %.3f ms\n", sh.vx, sh.by, sh.zc, ms / 6);
-        if (ms < best_ms) {
+        if (ms < best_ms * kTuneMargin) {
             best_ms = ms;
             best = sh;
         }
@@ -1882,7 +1899,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         }
     }
     const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16, jac = ps[0]->pm == CUTH_PC_CHEBYSHEV_JACOBI;
-    const int cand[][2] = {{0, 0}, {2, 8}, {4, 8}, {2, 16}, {4, 4}, {1, 16}};
+    const int cand[][2] = {{0, 0}, {4, 8}, {2, 8}, {2, 16}, {4, 4}, {1, 16}};
     const hipStream_t s = E.own;
     hipEvent_t e0, e1;
     CUTH_HIP(hipEventCreate(&e0));
@@ -1935,7 +1952,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (log_on())
             std::fprintf(stderr, "cuth: fuse %d,%d %.3f ms per 4 sweeps\n", c.fr, c.fzc, ms / 3);
-        if (ms < best_ms) {
+        if (ms < best_ms * kTuneMargin) {
             best_ms = ms;
             best = c;
         }

@@ -663,6 +663,32 @@ def test_fused_sweep_solves(monkeypatch):
         gg.close()
 
 
+@pytest.mark.parametrize("fuse", ["0", "1"])
+def test_kernel_timing_blocks(monkeypatch, fuse):
+    """The measurement hook times whole back-to-back runs of the general FP32
+    kernel: at k = 30 every preconditioner application contributes 13 fused
+    pairs (j = 3..28) or 26 single sweeps (j = 3..28), so the launch count is a
+    multiple of that, and the bytes per launch are those of the kernel timed
+    (28 or 24 B per unknown on a per-cell grid)."""
+    say(f"kernel timing blocks, CUTH_FUSE={fuse}")
+    monkeypatch.setenv("CUTH_FUSE", fuse)
+    monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+    st, P = w.config4_small()
+    g = grid_of(st)
+    g.profile_enable(True)
+    T, stats = g.solve(t64(P), precision="mixed", cheb_degree=30)
+    prof = g.profile_read()
+    g.profile_enable(False)
+    g.close()
+    per = 13 if fuse == "1" else 26
+    say(f"  {prof} cg {stats['cg_iters']}")
+    assert prof["fused"] == (fuse == "1")
+    assert prof["launches"] >= per and prof["launches"] % per == 0
+    assert prof["launches"] <= per * (stats["cg_iters"] + stats["outer_cycles"] + 1)
+    assert prof["bytes_per_launch"] == (28 if fuse == "1" else 24) * st.n
+    assert prof["total_ms"] > 0
+
+
 def test_solve_single_cell_and_zero_power():
     say("solve single cell / zero power")
     st = w.Stack(1, 1, ["Cu"])
