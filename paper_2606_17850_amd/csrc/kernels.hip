@@ -698,6 +698,21 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
+// diag(A) at cell (i, jr, l) from the face conductances of the stencil: the
+// sink plus every face that exists (the Jacobi-scaled sweeps).
+template <typename T>
+__device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T gn, int i, int nx,
+                                      int jr, int ny, int l, int nz) {
+    T d = L.sink;
+    if (i > 0) d += gm;
+    if (i < nx - 1) d += gp;
+    if (jr > 0) d += gs;
+    if (jr < ny - 1) d += gn;
+    if (l > 0) d += L.gzd;
+    if (l < nz - 1) d += L.gzu;
+    return d;
+}
+
 // ------------------------------------------- fused pair of Chebyshev sweeps
 // Sweeps j and j+1 of the two-term recurrence in one pass over HBM (temporal
 // blocking, possible because every sweep's constants are fixed in advance):
@@ -770,8 +785,10 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
         if (!(inner && lb >= l0 && lb < l1)) return;
         const LayerCoef<T> L = gldc(op.lc + lb);
         const T *rowc = ring_at(lb, rs);
-        const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, rs - 1) + xo);
-        const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, rs + 1) + xo);
+        // a y neighbour outside the grid is read at the row itself, so its
+        // term vanishes (the ring rows beyond the grid hold no values)
+        const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, jr > 0 ? rs - 1 : rs) + xo);
+        const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, jr < ny - 1 ? rs + 1 : rs) + xo);
         const T left = has_l ? rowc[xo - 1] : T(0);
         const T right = has_r ? rowc[xo + VX] : T(0);
         const Vec<T, VX> &y = zA_m1;
@@ -792,15 +809,18 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                 gm = gp = L.gx;
                 gs = gn = L.gy;
             }
-            T a = L.sink * x, d = L.sink;
-            if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
-            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
-            if (jr > 0) a += gs * (x - so.a[e]), d += gs;
-            if (jr < ny - 1) a += gn * (x - no.a[e]), d += gn;
-            if (lb > 0) a += L.gzd * (x - zA_m2.a[e]), d += L.gzd;
-            if (lb < nz - 1) a += L.gzu * (x - up.a[e]), d += L.gzu;
+            // y terms: see the loads above; z terms: gzd is zero on the
+            // bottom layer and gzu on the top one, where the neighbour
+            // registers hold zeros
+            T a = L.sink * x;
+            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
+            if (PC || i < nx - 1) a += gp * (x - xr);
+            a += gs * (x - so.a[e]);
+            a += gn * (x - no.a[e]);
+            a += L.gzd * (x - zA_m2.a[e]);
+            a += L.gzu * (x - up.a[e]);
             T res = r_m1.a[e] - a;
-            if constexpr (JAC) res *= recip(d);
+            if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, lb, nz));
             z2.a[e] = x + c1b * (x - xdn.a[e]) + c2b * res;   // xdn: z_j at layer lb
         }
         vstore<T, VX>(zY + cl - plane, z2);
@@ -845,16 +865,20 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
                 gm = gp = L.gx;
                 gs = gn = L.gy;
             }
-            T a = L.sink * x, d = L.sink;
-            if (PC || i > 0) a += gm * (x - xl), d += gm;   // (see the column walker)
-            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
-            if (jr > 0) a += gs * (x - xso.a[e]), d += gs;
-            if (jr < ny - 1) a += gn * (x - xno.a[e]), d += gn;
-            if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
-            if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
+            // a missing y or z neighbour was loaded at the cell itself, so
+            // its term vanishes without a test
+            T a = L.sink * x;
+            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
+            if (PC || i < nx - 1) a += gp * (x - xr);
+            a += gs * (x - xso.a[e]);
+            a += gn * (x - xno.a[e]);
+            a += L.gzd * (x - xdn.a[e]);
+            a += L.gzu * (x - xup.a[e]);
             T res = rv.a[e] - a;
-            if constexpr (JAC) res *= recip(d);
-            zn.a[e] = act ? x + c1a * (x - zm.a[e]) + c2a * res : T(0);
+            if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, l, nz));
+            // lanes outside the grid compute finite values from in-bounds
+            // loads; no stage B reads them (see its loads)
+            zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
         }
         if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
         if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
