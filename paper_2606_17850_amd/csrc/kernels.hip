@@ -414,6 +414,21 @@ __device__ __forceinline__ void lateral_coefs(const OpView<T> &op, const LayerCo
                               has_l, has_s, gxp, gyp, gym, gxl);
 }
 
+// diag(A) at cell (i, jr, l) from the face conductances of the stencil: the
+// sink plus every face that exists (the Jacobi-scaled sweeps).
+template <typename T>
+__device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T gn, int i, int nx,
+                                      int jr, int ny, int l, int nz) {
+    T d = L.sink;
+    if (i > 0) d += gm;
+    if (i < nx - 1) d += gp;
+    if (jr > 0) d += gs;
+    if (jr < ny - 1) d += gn;
+    if (l > 0) d += L.gzd;
+    if (l < nz - 1) d += L.gzu;
+    return d;
+}
+
 // March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
 // layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
 // starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
@@ -518,18 +533,19 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             }
             // A x in difference form and the diagonal of A (sink plus the
             // conductances of the faces that exist), for the Jacobi scaling.
-            // Per-cell conductances need no x-boundary test: the +x one is 0
-            // on the last column, and lane 0's west conductance and value are
-            // 0 on the first, so those terms add exactly zero.
-            T a = L.sink * x, d = L.sink;
-            if (PC || i > 0) a += gm * (x - xl), d += gm;
-            if (PC || i < nx - 1) a += gp * (x - xr), d += gp;
-            if (ln.j > 0) a += gs * (x - xso.a[e]), d += gs;
-            if (ln.j < ny - 1) a += gn * (x - xno.a[e]), d += gn;
-            if (l > 0) a += L.gzd * (x - xdn.a[e]), d += L.gzd;
-            if (l < nz - 1) a += L.gzu * (x - xup.a[e]), d += L.gzu;
+            // Terms of missing neighbours add exactly zero without a test:
+            // per-cell conductances, the +x one is 0 on the last column and
+            // lane 0's west conductance and value are 0 on the first; a
+            // missing y or z neighbour was loaded at the cell itself.
+            T a = L.sink * x;
+            if (PC || i > 0) a += gm * (x - xl);
+            if (PC || i < nx - 1) a += gp * (x - xr);
+            a += gs * (x - xso.a[e]);
+            a += gn * (x - xno.a[e]);
+            a += L.gzd * (x - xdn.a[e]);
+            a += L.gzu * (x - xup.a[e]);
             ax.a[e] = a;
-            dg.a[e] = d;
+            dg.a[e] = jac_diag(L, gm, gp, gs, gn, i, nx, ln.j, ny, l, nz);
         }
         if (act) emit(l, c, xc, ax, pre, dg);
         xdn = xc;
@@ -696,21 +712,6 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
                           vstore<T, VX>(zo + c, zn);
                       });
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
-}
-
-// diag(A) at cell (i, jr, l) from the face conductances of the stencil: the
-// sink plus every face that exists (the Jacobi-scaled sweeps).
-template <typename T>
-__device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T gn, int i, int nx,
-                                      int jr, int ny, int l, int nz) {
-    T d = L.sink;
-    if (i > 0) d += gm;
-    if (i < nx - 1) d += gp;
-    if (jr > 0) d += gs;
-    if (jr < ny - 1) d += gn;
-    if (l > 0) d += L.gzd;
-    if (l < nz - 1) d += L.gzu;
-    return d;
 }
 
 // ------------------------------------------- fused pair of Chebyshev sweeps
