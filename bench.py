@@ -34,11 +34,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# counter summaries of the dominant launch of the 512x512x16 bench (a fused pair
-# of sweeps or a single sweep, whichever the library ran)
-def counters_file(fused: bool) -> str:
-    return os.path.join(ROOT, "profiles", ("cheb_pair" if fused else "cheb_sweep")
-                        + "_512x512x16_counters.json")
+# the timed general sweep launch by its width (cuth_profile_read's `fused`:
+# sweeps per launch minus one): profile summary stem and kernel description
+SWEEP_KERNELS = {0: ("cheb_sweep", "k_cheb_b (general Chebyshev sweep, FP32, {})"),
+                 1: ("cheb_pair", "k_cheb2_b (fused pair of general Chebyshev sweeps, FP32, {})"),
+                 2: ("cheb_triple", "k_cheb3_b (fused triple of general Chebyshev sweeps, FP32, {})")}
+
+
+# counter summaries of the dominant launch of the 512x512x16 bench (whichever
+# sweep launch the library ran)
+def counters_file(fused: int) -> str:
+    return os.path.join(ROOT, "profiles", SWEEP_KERNELS[fused][0] + "_512x512x16_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_17850_amd", "csrc", "kernels.hip")
 
 
@@ -47,7 +53,7 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(fused: bool):
+def traffic_from_profiles(fused: int):
     """HBM bytes per launch of the sweep kernel from committed counter runs."""
     try:
         with open(counters_file(fused)) as f:
@@ -171,8 +177,7 @@ def bench_transient(args) -> int:
                            "chebyshev_jacobi_cg_iters_per_step": [s["cg_iters"] for s in statsj][:10],
                            "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": float((Tj - T64).abs().max()) / rise}
     out["roofline"] = {"bound": "hbm",
-                       "kernel": ("k_cheb2_b fused pair of general sweeps, FP32, matrix-free"
-                                  if prof["fused"] else "k_cheb_b general sweep, FP32, matrix-free"),
+                       "kernel": SWEEP_KERNELS[prof["fused"]][1].format("matrix-free"),
                        "achieved": round(ach, 2) if ach else None, "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4) if ach else None,
                        "traffic": None, "bytes_per_launch": prof["bytes_per_launch"],
@@ -394,16 +399,28 @@ def main() -> int:
     step(mixed16)
     ms_m16, st_m16 = timed(mixed16, args.steps)
     T_m16 = T.clone()
-    # and with one general sweep per launch (the fused pairs switched off)
-    fuse_prev = os.environ.get("CUTH_FUSE")
-    os.environ["CUTH_FUSE"] = "0"
-    step(mixed)
-    ms_fu, st_fu = timed(mixed, args.steps)
+    # and with one general sweep per launch (the fused launches switched off),
+    # and with fused pairs but no triples
+    def with_env(env, fn):
+        prev = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            return fn()
+        finally:
+            for k, v in prev.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+
+    def single():
+        step(mixed)
+        return timed(mixed, args.steps)
+
+    ms_fu, st_fu = with_env({"CUTH_FUSE": "0"}, single)
     T_fu = T.clone()
-    if fuse_prev is None:
-        del os.environ["CUTH_FUSE"]
-    else:
-        os.environ["CUTH_FUSE"] = fuse_prev
+    ms_pr, st_pr = with_env({"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "4,8", "CUTH_FUSE3": "0"}, single)
+    T_pr = T.clone()
 
     k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
     for _ in range(min(args.warmup, 1)):
@@ -437,6 +454,8 @@ def main() -> int:
     diff_st = float((T_st - T_fp64).abs().max()) / rise
     diff_fu = float((T_fu - T_fp64).abs().max()) / rise
     per_fu = ms_fu / args.steps
+    diff_pr = float((T_pr - T_fp64).abs().max()) / rise
+    per_pr = ms_pr / args.steps
     per_st = ms_st / k64
     per_au = ms_au / args.steps
     diff_au = float((T_au - T_fp64).abs().max()) / rise
@@ -476,6 +495,8 @@ def main() -> int:
                            "speedup_mixed16_vs_fp64": round(per64 / per16, 3),
                            "mixed_single_sweeps": round(per_fu, 3),
                            "speedup_mixed_single_sweeps_vs_fp64": round(per64 / per_fu, 3),
+                           "mixed_fused_pairs_only": round(per_pr, 3),
+                           "speedup_mixed_fused_pairs_only_vs_fp64": round(per64 / per_pr, 3),
                            "stage_switched_to_fp64_tol": round(per_st, 3),
                            "speedup_stage_switched_vs_fp64": round(per64 / per_st, 3),
                            "mixed_auto_degree": round(per_au, 3),
@@ -498,6 +519,8 @@ def main() -> int:
             "mixed_single_sweeps_cg_iters": st_fu[-1]["cg_iters"],
             "mixed_single_sweeps_GBps": round(sum(s["alg_bytes"] for s in st_fu) / args.steps / (per_fu / 1e3) / 1e9, 2),
             "mixed_single_sweeps_vs_fp64_max_rise_rel_diff": diff_fu,
+            "mixed_fused_pairs_only_cg_iters": st_pr[-1]["cg_iters"],
+            "mixed_fused_pairs_only_vs_fp64_max_rise_rel_diff": diff_pr,
             "stage_switched_cg_iters": st_st[-1]["cg_iters"],
             "stage_switched_cycles": st_st[-1]["outer_cycles"],
             "stage_switched_rel_residual": st_st[-1]["rel_residual"],
@@ -514,9 +537,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_cheb2_b (fused pair of general Chebyshev sweeps, FP32, per-cell lateral "
-                       "conductances)" if prof["fused"] else
-                       "k_cheb_b (general Chebyshev sweep, FP32, per-cell lateral conductances)"),
+            "kernel": SWEEP_KERNELS[prof["fused"]][1].format("per-cell lateral conductances"),
             "achieved": round(achieved, 2) if achieved else None,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

@@ -306,11 +306,12 @@ cuth_status cuth_grid_reset_bounds(cuth_grid g);
 
 /* Kernel timing for measurement.  When on, each preconditioner application
  * brackets its run of back-to-back general Chebyshev launches from the third
- * sweep on (the fused pairs of sweeps, else the single sweeps before the last)
- * with two HIP events on the handle's stream; cuth_profile_read returns the
- * summed duration of those runs (ms), the number of launches they hold, the
- * algorithmic bytes of one such launch (N times the bytes per unknown) and
- * whether the timed launches were fused pairs (*fused 1) or single sweeps (0).
+ * sweep on (the fused triples of sweeps, else the fused pairs, else the single
+ * sweeps before the last) with two HIP events on the handle's stream;
+ * cuth_profile_read returns the summed duration of those runs (ms), the number
+ * of launches they hold, the algorithmic bytes of one such launch (N times the
+ * bytes per unknown) and the sweeps per timed launch minus one (*fused 2:
+ * fused triples, 1: fused pairs, 0: single sweeps).
  * Any output pointer may be NULL.  Enabling resets the counters and
  * synchronises the stream. */
 cuth_status cuth_profile_enable(cuth_grid g, int32_t on);

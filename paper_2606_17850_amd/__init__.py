@@ -243,8 +243,9 @@ class Grid:
         ms, cnt, by, fu = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
         _check(library().cuth_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt),
                                            ctypes.byref(by), ctypes.byref(fu)))
+        # fused: sweeps per timed launch minus one (2 triples, 1 pairs, 0 single)
         return {"total_ms": ms.value, "launches": cnt.value, "bytes_per_launch": by.value,
-                "fused": bool(fu.value)}
+                "fused": fu.value}
 
     def spectral_bounds(self, dt: float = 0.0, steps: int = 30,
                         v0: Optional[torch.Tensor] = None,

@@ -352,7 +352,7 @@ cuth_status cuth_profile_read(cuth_grid h, double *total_ms, int64_t *launches,
         if (total_ms) *total_ms = g.prof_ms;
         if (launches) *launches = g.prof_count;
         if (bytes_per_launch) *bytes_per_launch = g.prof_bytes;
-        if (fused) *fused = g.prof_fused ? 1 : 0;
+        if (fused) *fused = g.prof_width - 1;
         return CUTH_OK;
     });
 }

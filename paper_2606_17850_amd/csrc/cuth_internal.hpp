@@ -110,6 +110,7 @@ struct InnerProb {
     const T *cheb;            // 1/theta at [0], c1_j at [1 + j], c2_j at [1 + kcap + j]
     int kcap, pad;
     int f_tile0 = 0, f_ntiles = 0;   // workgroup slots of fused sweep pairs (launch_cheb2_b)
+    int t_tile0 = 0, t_ntiles = 0;   // ... of fused sweep triples (launch_cheb3_b)
     // FP64 CG with an FP32 preconditioner (the paper's stage-switched scheme):
     // the update also writes r_lo = (float) r; k_promote_dot reads the
     // preconditioner's z_lo; k_reduce_conv mirrors the stop flag to *done_lo.
@@ -172,6 +173,17 @@ void launch_cheb_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int cs
 template <typename T>
 void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac,
                     int vx, int R, int zc, int wpr, int j, int zsel, hipStream_t s);
+
+// Three consecutive general sweeps j, j+1, j+2 in one pass: zsel as for the
+// pair, z_{j+2} written to z[X] and z_{j+3} to z[Y] (z_{j+1} stays on chip).
+// A workgroup is R + 4 rows of wpr wavefronts and a chunk of zc layers; the
+// launch covers the problems' slots [t_tile0, t_tile0 + t_ntiles) with
+// t_ntiles = ceil(ny / R) * ceil(nz / zc); dynamic LDS 3 (2R + 6) rows of
+// 64*vx*wpr values.  FP32, Chebyshev sweeps (not Jacobi-scaled); h16 as for
+// the pair.
+template <typename T>
+void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                    int zc, int wpr, int j, int zsel, hipStream_t s);
 
 // Single-pass preconditioner into z[0] (same chk/last behaviour as the sweeps):
 // pm 0: z = r/theta (degree-1 Chebyshev), 1: z = r/diag(A) (Jacobi), 2: z = r,

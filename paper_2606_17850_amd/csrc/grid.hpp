@@ -61,7 +61,8 @@ struct Status {
 // and fwpr wavefronts per row (FP32 only).
 struct Shape {
     int vx = 1, by = 1, zc = 8;
-    int fr = 0, fzc = 8, fwpr = 1;
+    int fr = 0, fzc = 8, fwpr = 1;   // fused pairs: rows per workgroup (0: off), layers, wavefronts per row
+    int tr = 0, tzc = 8, twpr = 1;   // fused triples (used only with pairs on)
 };
 
 // Device descriptors, states and reduction partials for up to `cap` problems
@@ -124,7 +125,7 @@ struct Grid {
     std::vector<int> pev_cnt;   // launches in each recorded block
     size_t pev_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
-    bool prof_fused = false;   // the timed launch was a fused sweep pair
+    int prof_width = 1;   // sweeps per timed launch (2: fused pair, 3: fused triple)
     int64_t prof_count = 0;
 
     template <typename T>

@@ -902,6 +902,227 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
     stage_b(la1, c, zero);
 }
 
+// ----------------------------------------- fused triple of Chebyshev sweeps
+// Sweeps j, j+1 and j+2 in one pass over HBM, the pair's scheme with a third
+// stage.  A workgroup owns R whole grid rows (wavefront w holds row slot
+// w / wpr, grid row ty R - 2 + slot) and a chunk of layers.  Stage A computes
+// z_{j+1} on all R + 4 row slots, over the chunk plus two halo layers below
+// and above, into ring A (three layers); stage B, one layer behind, computes
+// z_{j+2} on slots 1 .. R + 2 into ring B (three layers); stage C, two layers
+// behind, computes z_{j+3} on the R owned slots 2 .. R + 1.  B and C take the
+// x and y neighbours of their input from the ring and the z neighbours from
+// registers.  z_{j+1} never reaches HBM: the launch reads z_j, z_{j-1}, r (and
+// the conductances) and writes z_{j+2} (zX) and z_{j+3} (zY), the two iterates
+// the next sweep reads.  One barrier per layer: before it, stage A of layer l
+// writes ring A slot l % 3; after it, stage B of layer l - 1 reads ring A slot
+// (l - 1) % 3 and writes ring B slot (l - 1) % 3, and stage C of layer l - 2
+// reads ring B slot (l - 2) % 3 (written before the barrier).  Every slot is
+// written again only two barriers after its last read.  A y neighbour outside
+// the grid is read at the cell's own slot, so its term vanishes; ring rows
+// outside the grid are never read.  Chebyshev (not Jacobi-scaled) sweeps only.
+template <typename T, bool PC, int VX, int CS>
+__global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict__ probs, int nprob,
+                                                  int j, int zsel, int R, int zcf, int wpr) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int slot = xcd_slot();
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].t_tile0 <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    const InnerProb<T> &P = probs[lo];
+    if (P.st->done) return;   // the same for every wavefront of the workgroup
+    const OpView<T> op = P.op;
+    const int nx = op.nx, ny = op.ny, nz = op.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const int ntzf = (nz + zcf - 1) / zcf;
+    const int local = slot - P.t_tile0;
+    const int tz = local % ntzf, ty = local / ntzf;
+    const int lane = threadIdx.x, w = threadIdx.y, rs = w / wpr, sg = w % wpr;
+    const int W = wpr * kWave * VX;            // ring row length (cells)
+    const int RA = R + 4, RB = R + 2;          // ring rows
+    T *ringA = reinterpret_cast<T *>(lds_raw);
+    T *ringB = ringA + (size_t)3 * RA * W;
+    const int xo = (sg * kWave + lane) * VX;   // x of this lane's first cell
+    const int jr = ty * R - 2 + rs;            // grid row of this wavefront
+    const bool act = jr >= 0 && jr < ny && xo < nx;
+    const bool rowB = act && rs >= 1 && rs <= R + 2;
+    const bool rowC = act && rs >= 2 && rs <= R + 1;
+    const int l0 = tz * zcf, l1 = min(nz, l0 + zcf);
+    const int la0 = max(0, l0 - 2), la1 = min(nz, l1 + 2);
+    const int lb0 = max(0, l0 - 1), lb1 = min(nz, l1 + 1);
+    const bool has_l = act && xo > 0, has_r = act && xo + VX < nx;
+    const bool has_s = act && jr > 0, has_n = act && jr < ny - 1;
+    const T c1a = P.cheb[1 + j], c2a = P.cheb[1 + P.kcap + j];
+    const T c1b = P.cheb[2 + j], c2b = P.cheb[2 + P.kcap + j];
+    const T c1c = P.cheb[3 + j], c2c = P.cheb[3 + P.kcap + j];
+    const T *__restrict__ zN = P.z[zsel & 3];
+    const T *__restrict__ zP = P.z[(zsel >> 2) & 3];
+    T *__restrict__ zX = P.z[(zsel >> 4) & 3];
+    T *__restrict__ zY = P.z[(zsel >> 6) & 3];
+    const T *__restrict__ r = P.r;
+    const Vec<T, VX> zero = vzero<T, VX>();
+    // ring rows of the y neighbours (the own slot outside the grid)
+    const int sA = jr > 0 ? rs - 1 : rs, nA = jr < ny - 1 ? rs + 1 : rs;
+    auto ringA_at = [&](int l, int row) -> T * { return ringA + ((size_t)((l % 3) * RA + row)) * W; };
+    auto ringB_at = [&](int l, int row) -> T * { return ringB + ((size_t)((l % 3) * RB + row - 1)) * W; };
+
+    int64_t c = act ? xo + (int64_t)nx * jr + plane * la0 : 0;
+    Vec<T, VX> xdn = vload<T, VX>(zN + ((act && la0 > 0) ? c - plane : c));
+    Vec<T, VX> xc = vload<T, VX>(zN + c);
+    // stage A results of the two layers below, stage B results of the two
+    // layers below its current one, and the inputs the later stages reuse
+    Vec<T, VX> zA_m1 = zero, zA_m2 = zero, zB_m1 = zero, zB_m2 = zero;
+    Vec<T, VX> r_m1 = zero, r_m2 = zero;
+    [[maybe_unused]] Vec<T, VX> gxp_m1 = zero, gyp_m1 = zero, gym_m1 = zero;
+    [[maybe_unused]] Vec<T, VX> gxp_m2 = zero, gyp_m2 = zero, gym_m2 = zero;
+    [[maybe_unused]] T gxl_m1 = T(0), gxl_m2 = T(0);
+
+    // one stencil sweep at layer ls of this lane's cells: input y (own cells),
+    // its x neighbours from ring row `row`, y neighbours from rows so/no,
+    // z neighbours dn/up, previous iterate pv, residual input rr
+    auto sweep = [&](const T *row, const T *so_row, const T *no_row, int ls, const Vec<T, VX> &y,
+                     const Vec<T, VX> &dn, const Vec<T, VX> &up, const Vec<T, VX> &pv,
+                     const Vec<T, VX> &rr, const Vec<T, VX> &gxp, const Vec<T, VX> &gyp,
+                     const Vec<T, VX> &gym, T gxl, T c1, T c2) {
+        const LayerCoef<T> L = gldc(op.lc + ls);
+        const Vec<T, VX> so = lds_load<T, VX>(so_row + xo);
+        const Vec<T, VX> no = lds_load<T, VX>(no_row + xo);
+        const T left = has_l ? row[xo - 1] : T(0);
+        const T right = has_r ? row[xo + VX] : T(0);
+        Vec<T, VX> out;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            const int i = xo + e;
+            const T x = y.a[e];
+            const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
+            const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
+            T gm, gp, gs, gn;
+            if constexpr (PC) {
+                gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                gp = gxp.a[e];
+                gs = gym.a[e];
+                gn = gyp.a[e];
+            } else {
+                gm = gp = L.gx;
+                gs = gn = L.gy;
+            }
+            // the z conductances are zero where dn / up do not exist
+            T a = L.sink * x;
+            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
+            if (PC || i < nx - 1) a += gp * (x - xr);
+            a += gs * (x - so.a[e]);
+            a += gn * (x - no.a[e]);
+            a += L.gzd * (x - dn.a[e]);
+            a += L.gzu * (x - up.a[e]);
+            out.a[e] = x + c1 * (x - pv.a[e]) + c2 * (rr.a[e] - a);
+        }
+        return out;
+    };
+
+    // stages B and C after the barrier of iteration l (zn: stage A's layer l,
+    // zero in the two closing iterations), then the register shifts
+    auto stage_bc = [&](int l, int64_t cl, const Vec<T, VX> &zn, const Vec<T, VX> &rv,
+                        const Vec<T, VX> &gxp, const Vec<T, VX> &gyp, const Vec<T, VX> &gym, T gxl,
+                        const Vec<T, VX> &xup) {
+        // ---- stage B: z_{j+2} at layer l - 1 (zn: stage A's layer above)
+        const int lb = l - 1;
+        Vec<T, VX> z2 = zero;
+        if (rowB && lb >= lb0 && lb < lb1) {
+            z2 = sweep(ringA_at(lb, rs), ringA_at(lb, sA), ringA_at(lb, nA), lb, zA_m1, zA_m2, zn, xdn,
+                       r_m1, gxp_m1, gyp_m1, gym_m1, gxl_m1, c1b, c2b);
+            lds_store<T, VX>(ringB_at(lb, rs) + xo, z2);
+            if (rowC && lb >= l0 && lb < l1) vstore<T, VX>(zX + cl - plane, z2);
+        }
+        // ---- stage C: z_{j+3} at layer l - 2 (z2: stage B's layer above)
+        const int lc = l - 2;
+        if (rowC && lc >= l0 && lc < l1) {
+            const Vec<T, VX> z3 =
+                sweep(ringB_at(lc, rs), ringB_at(lc, sA), ringB_at(lc, nA), lc, zB_m1, zB_m2, z2,
+                      zA_m2, r_m2, gxp_m2, gyp_m2, gym_m2, gxl_m2, c1c, c2c);
+            vstore<T, VX>(zY + cl - 2 * plane, z3);
+        }
+        // shift the layer registers
+        zA_m2 = zA_m1;
+        zA_m1 = zn;
+        zB_m2 = zB_m1;
+        zB_m1 = z2;
+        r_m2 = r_m1;
+        r_m1 = rv;
+        if constexpr (PC) {
+            gxp_m2 = gxp_m1;
+            gyp_m2 = gyp_m1;
+            gym_m2 = gym_m1;
+            gxl_m2 = gxl_m1;
+            gxp_m1 = gxp;
+            gyp_m1 = gyp;
+            gym_m1 = gym;
+            gxl_m1 = gxl;
+        }
+        xdn = xc;
+        xc = xup;
+    };
+
+    // every iteration of the loop holds a stage A; the two closing layers of
+    // stages B and C follow it (no load sits under a branch)
+    int l = la0;
+    for (; l < la1; ++l, c += plane) {
+        Vec<T, VX> zn, rv, gxp = zero, gyp = zero, gym = zero;
+        T gxl = T(0);
+        // ---- stage A: z_{j+1} at layer l (loads as in the pair)
+        const LayerCoef<T> L = gldc(op.lc + l);
+        const Vec<T, VX> xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
+        const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
+        const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
+        const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
+        const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
+        [[maybe_unused]] LatRaw<T, VX, CS> lat;
+        if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
+        rv = vload<T, VX>(r + c);
+        const Vec<T, VX> zm = vload<T, VX>(zP + c);
+        T left = lane_left(xc.a[VX - 1]);
+        T right = lane_right(xc.a[0]);
+        if (lane == 0) left = west;
+        if (lane == kWave - 1) right = east;
+        if constexpr (PC)
+            lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            const int i = xo + e;
+            const T x = xc.a[e];
+            const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
+            const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
+            T gm, gp, gs, gn;
+            if constexpr (PC) {
+                gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                gp = gxp.a[e];
+                gs = gym.a[e];
+                gn = gyp.a[e];
+            } else {
+                gm = gp = L.gx;
+                gs = gn = L.gy;
+            }
+            // missing y and z neighbours were loaded at the cell itself
+            T a = L.sink * x;
+            if (PC || i > 0) a += gm * (x - xl);
+            if (PC || i < nx - 1) a += gp * (x - xr);
+            a += gs * (x - xso.a[e]);
+            a += gn * (x - xno.a[e]);
+            a += L.gzd * (x - xdn.a[e]);
+            a += L.gzu * (x - xup.a[e]);
+            zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * (rv.a[e] - a);
+        }
+        if (xo < W) lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
+        __syncthreads();
+        stage_bc(l, c, zn, rv, gxp, gyp, gym, gxl, xup);
+    }
+    for (int q = 0; q < 2; ++q, ++l, c += plane) {
+        __syncthreads();
+        stage_bc(l, c, zero, zero, zero, zero, zero, T(0), zero);
+    }
+}
+
 // Single-pass preconditioners, partials of r^T z:
 //   PM_SCALE   z = r / theta (the Chebyshev polynomial of degree 1);
 //   PM_JACOBI  z = r / diag(A), diag = sink + the sum of the cell's face
@@ -1684,6 +1905,20 @@ void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool 
     else cheb2_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
+template <typename T>
+void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                    int zc, int wpr, int j, int zsel, hipStream_t s) {
+    const dim3 g(nb), b(kWave, wpr * (R + 4));
+    const size_t lds = (size_t)3 * ((R + 4) + (R + 2)) * wpr * kWave * vx * sizeof(T);
+    if (pc && h16) {
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb3_b<T, true, VX, CS_F16>), g, b, lds, s,
+                                                    probs, nprob, j, zsel, R, zc, wpr)));
+        return;
+    }
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb3_b<T, PC, VX, CS_OWN>), g, b, lds, s,
+                                                       probs, nprob, j, zsel, R, zc, wpr)));
+}
+
 template <typename T, bool PC, int VX, int PM>
 static void scale_chk(const InnerProb<T> *probs, int nprob, int nb, int by, bool chk,
                       const T *part_in, bool red, T *part_out, hipStream_t s) {
@@ -1905,6 +2140,8 @@ CUTH_INST(double)
 
 template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, bool, bool, int, int,
                                       int, int, int, int, hipStream_t);
+template void launch_cheb3_b<float>(const InnerProb<float> *, int, int, bool, bool, int, int, int,
+                                      int, int, int, hipStream_t);
 template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
                                          hipStream_t);
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,

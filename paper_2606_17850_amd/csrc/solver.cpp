@@ -173,6 +173,30 @@ ChebConsts make_cheb(double lmin, double lmax, int k) {
     return cc;
 }
 
+// Sweep fusion of a shape: 3 fused triples (and pairs for what is left), 2
+// fused pairs, 0 single sweeps only.
+inline int fuse_level(const Shape &sh) { return sh.tr > 0 && sh.fr > 0 ? 3 : sh.fr > 0 ? 2 : 0; }
+
+// The fusion level the preconditioner pm runs at in precision T: fused
+// launches are FP32 only, and the Jacobi-scaled sweeps have no triple kernel.
+template <typename T>
+int fuse_for(const Shape &sh, int pm) {
+    if (sizeof(T) != 4) return 0;
+    const int f = fuse_level(sh);
+    return pm == 3 ? std::min(f, 2) : f;
+}
+
+// Number of general sweeps the launch at sweep j of a degree-k preconditioner
+// covers at fusion level `fuse`: fused launches start at j = 3 (sweeps 1 and 2
+// read the implicit z_0 / z_1) and end before the last sweep, which also
+// forms the r^T z partials.
+inline int sweep_width(int j, int k, int fuse) {
+    if (j < 3) return 1;
+    if (fuse >= 3 && j + 2 < k - 1) return 3;
+    if (fuse >= 2 && j + 1 < k - 1) return 2;
+    return 1;
+}
+
 // Algorithmic bytes per unknown of each kernel (what the method must move).
 template <typename T>
 struct Bytes {
@@ -189,7 +213,10 @@ struct Bytes {
     // a fused pair of general sweeps: z_j, z_{j-1}, r (+ conductances) read once,
     // z_{j+1} and z_{j+2} written
     double pair() const { return 5.0 * sizeof(T) + coef_sw; }
-    double precond(int k, int pm = 0, bool fuse = false) const {
+    // a fused triple moves the same: z_{j+1} stays on chip, z_{j+2} and
+    // z_{j+3} are written
+    double triple() const { return pair(); }
+    double precond(int k, int pm = 0, int fuse = 0) const {
         if (pm == 1) return scale() + coef;   // Jacobi: also the lateral conductances
         if (pm == 2 || (k == 1 && pm == 0)) return scale();
         // Jacobi-scaled Chebyshev: the scale pass (r and the conductances read,
@@ -198,13 +225,9 @@ struct Bytes {
         if (jac && k == 1) return scale() + coef;
         double b = jac ? scale() + coef + cheb(2) : cheb(1);
         for (int j = 2; j < k;) {
-            if (fuse && j >= 3 && j + 1 < k - 1) {
-                b += pair();
-                j += 2;
-            } else {
-                b += cheb(j == 2 && !jac ? 2 : 0);
-                j += 1;
-            }
+            const int wd = sweep_width(j, k, fuse);
+            b += wd == 3 ? triple() : wd == 2 ? pair() : cheb(j == 2 && !jac ? 2 : 0);
+            j += wd;
         }
         return b;
     }
@@ -405,7 +428,7 @@ Status upload_cheb(Engine &E, std::vector<Problem *> &ps, hipStream_t s) {
 template <typename T>
 int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vector<int> &which) {
     InnerProb<T> *h = Sel<T>::h(E);
-    int tile = 0, ftile = 0, n = 0;
+    int tile = 0, ftile = 0, ttile = 0, n = 0;
     which.clear();
     for (size_t i = 0; i < ps.size(); ++i) {
         Problem &p = *ps[i];
@@ -430,11 +453,17 @@ int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vec
         d.z[2] = w.zC;
         d.z[3] = w.zD;
         d.f_tile0 = d.f_ntiles = 0;
+        d.t_tile0 = d.t_ntiles = 0;
         if (sh.fr > 0) {
             if (!w.zC || !w.zD) return -1;
             d.f_tile0 = ftile;
             d.f_ntiles = tiles_y(p.g->ny, sh.fr) * tiles_z(p.g->nz, sh.fzc);
             ftile += d.f_ntiles;
+        }
+        if (sh.tr > 0) {
+            d.t_tile0 = ttile;
+            d.t_ntiles = tiles_y(p.g->ny, sh.tr) * tiles_z(p.g->nz, sh.tzc);
+            ttile += d.t_ntiles;
         }
         d.st = Sel<T>::ds(E) + n;
         d.cheb = Sel<T>::dc(E) + i * (1 + 2 * E.kcap);
@@ -467,22 +496,22 @@ inline void free_pair(int n, int p, int &x, int &y) {
 
 // Buffer that holds z = q(A) r after enqueue_precond (same rotation): mode 1
 // writes z[1]; every single sweep writes over the older of (newest, older);
-// a fused pair writes the two other buffers.
-int precond_final(int k, int pm, bool fuse) {
+// a fused pair or triple writes the two other buffers.
+int precond_final(int k, int pm, int fuse) {
     if (k == 1 || pm == 1 || pm == 2) return 0;
     if (k == 2) return 1;
     int n = 0, p = 1;   // after mode 2
     for (int j = 3; j < k;) {
-        if (fuse && j + 1 < k - 1) {
+        const int wd = sweep_width(j, k, fuse);
+        if (wd > 1) {
             int x, y;
             free_pair(n, p, x, y);
             p = x;
             n = y;
-            j += 2;
         } else {
             std::swap(n, p);
-            j += 1;
         }
+        j += wd;
     }
     return n;
 }
@@ -519,31 +548,41 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
         launch_cheb_b<T>(d, nprob, nb, pc, cs, false, sh.vx, sh.by, 1, k == 2, chk, 1, zsel(0, 1),
                          rr_in, red, eslot<T>(E, P_CHEB), s);
     }
-    // fused pairs of general sweeps (FP32)
-    const bool fuse = sizeof(T) == 4 && sh.fr > 0;
-    int nbf = 0;
-    if (fuse) {
+    // fused pairs and triples of general sweeps (FP32)
+    const int fuse = fuse_for<T>(sh, pm);
+    int nbf = 0, nbt = 0;
+    if (fuse >= 2) {
         const InnerProb<T> &last = Sel<T>::h(E)[nprob - 1];
         nbf = last.f_tile0 + last.f_ntiles;
+        nbt = last.t_tile0 + last.t_ntiles;
     }
     int n = 1, p = 0;   // newest and older iterate after mode 1
     // Timed block: the launches of the one general kernel from j = 3 on (the
-    // fused pairs, else the sweeps before the last), back to back on the
-    // stream; its duration over its launch count is the average launch
-    // duration, with the two event markers spread over the whole block.
+    // fused triples, else the fused pairs, else the sweeps before the last),
+    // back to back on the stream; its duration over its launch count is the
+    // average launch duration, with the two event markers spread over the
+    // whole block.
     const bool timing = prof && prof->prof && prof->pev_used + 2 <= prof->pev.size();
+    const int wtop = sweep_width(3, k, fuse);
     int blk = 0;
-    auto in_block = [&](int jj) { return jj >= 3 && (fuse ? jj + 1 < k - 1 : jj < k - 1); };
+    auto in_block = [&](int jj) {
+        return jj >= 3 && jj < k - 1 && sweep_width(jj, k, fuse) == wtop;
+    };
     for (int j = 2; j < k;) {
-        const bool pair = fuse && j >= 3 && j + 1 < k - 1;
+        const int wd = sweep_width(j, k, fuse);
         const bool timed = timing && in_block(j);
         if (timed && blk == 0) (void)hipEventRecord(prof->pev[prof->pev_used], s);
-        if (pair) {
+        if (wd > 1) {
             int x, y;
             free_pair(n, p, x, y);
-            if constexpr (sizeof(T) == 4)
-                launch_cheb2_b<T>(d, nprob, nbf, pc, h16, jac, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
-                                  n + 4 * p + 16 * x + 64 * y, s);
+            if constexpr (sizeof(T) == 4) {
+                if (wd == 3)
+                    launch_cheb3_b<T>(d, nprob, nbt, pc, h16, sh.vx, sh.tr, sh.tzc, sh.twpr, j,
+                                      n + 4 * p + 16 * x + 64 * y, s);
+                else
+                    launch_cheb2_b<T>(d, nprob, nbf, pc, h16, jac, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
+                                      n + 4 * p + 16 * x + 64 * y, s);
+            }
             p = x;
             n = y;
         } else {
@@ -555,7 +594,7 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
             std::swap(n, p);
         }
         ++blk;
-        if (timed && !in_block(j + (pair ? 2 : 1))) {
+        if (timed && !in_block(j + wd)) {
             (void)hipEventRecord(prof->pev[prof->pev_used + 1], s);
             const size_t slot = prof->pev_used / 2;
             if (prof->pev_tag.size() <= slot) prof->pev_tag.resize(prof->pev.size() / 2);
@@ -563,13 +602,14 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
             prof->pev_tag[slot] = tag;
             prof->pev_cnt[slot] = blk;
             prof->pev_used += 2;
-            // a fused pair reads z_j, z_{j-1}, r (+ gx, gy) once and writes two iterates
+            // a fused pair or triple reads z_j, z_{j-1}, r (+ gx, gy) once and
+            // writes two iterates
             const Bytes<T> by(pc, h16);
-            prof->prof_bytes = (pair ? by.pair() : by.cheb(0)) * (double)prof->N;
-            prof->prof_fused = pair;
+            prof->prof_bytes = (wd == 3 ? by.triple() : wd == 2 ? by.pair() : by.cheb(0)) * (double)prof->N;
+            prof->prof_width = wd;
         }
         if (!timed) blk = 0;
-        j += pair ? 2 : 1;
+        j += wd;
     }
     if (red) launch_reduce_b<T>(d, nprob, eslot<T>(E, P_CHEB), red_rz<T>(E), s);
     return n;
@@ -721,7 +761,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
         p.cg_iters += iters;
         p.reason = reason;
-        const bool fused = sizeof(T) == 4 && sh.fr > 0;
+        const int fused = fuse_for<T>(sh, p.pm);
         p.bytes += precs_run * by.precond(k, p.pm, fused) * N + iters * (by.dir() + by.update()) * N +
                    nchecks * by.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
@@ -961,7 +1001,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
     bool red = false;
     const int above = reduce_above();
     for (int n = 0; n < nprob; ++n) red = red || ps[which[n]]->ntiles > above;
-    const int zfin32 = precond_final(k, pm, sh32.fr > 0);
+    const int zfin32 = precond_final(k, pm, fuse_for<float>(sh32, pm));
     InnerProb<double> *h64 = E.h_in64;
     for (int n = 0; n < nprob; ++n) {
         Problem &p = *ps[which[n]];
@@ -1063,7 +1103,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
         const double dir64 = 32.0 + (p.g->per_cell ? (p.early ? 8.0 : 16.0) : 0.0);
         p.cg_iters += iters;
         p.reason = reason;
-        p.bytes += precs_run * (b32.precond(k, p.pm) + 20.0) * N + iters * (dir64 + b64.update() + 4.0) * N +
+        p.bytes += precs_run * (b32.precond(k, p.pm, fuse_for<float>(sh32, p.pm)) + 20.0) * N + iters * (dir64 + b64.update() + 4.0) * N +
                    nchecks * b64.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
         p.last_red = p.rr0 > 0 ? std::sqrt(p.true_rr / p.rr0) : 0.0;
@@ -1209,9 +1249,45 @@ bool fuse_fit(Shape &sh, int max_nx, int R, int zc) {
     return true;
 }
 
-// Shape forced from the environment (CUTH_FUSE=1), or no fusion.
+// Fused triples (on top of pairs): CUTH_FUSE3=0 never, CUTH_FUSE3=1 always
+// where pairs run (shape CUTH_FUSE3_SHAPE="R,zc", default 4,8), unset: chosen
+// by timing against the pairs (tune_fuse).  A workgroup holds R + 4 rows of
+// whole-row wavefronts (at most 16) and two rings of three layers in LDS.
+int fuse3_env() {
+    const char *e = std::getenv("CUTH_FUSE3");
+    if (!e) return -1;
+    return e[0] == '0' ? 0 : 1;
+}
+
+// Dynamic LDS a workgroup may use on the current device.
+size_t lds_cap() {
+    static const size_t cap = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            return (size_t)65536;
+        return (size_t)v;
+    }();
+    return cap;
+}
+
+// Fit the triple shape (R, zc) to rows of max_nx cells; false when it cannot fit.
+bool fuse3_fit(Shape &sh, int max_nx, int R, int zc) {
+    sh.tr = 0;
+    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
+    auto lds = [&](int r) { return (size_t)3 * ((r + 4) + (r + 2)) * wpr * kWave * sh.vx * sizeof(float); };
+    while (R > 1 && (wpr * (R + 4) > 16 || lds(R) > lds_cap())) --R;
+    if (R < 1 || wpr * (R + 4) > 16 || lds(R) > lds_cap()) return false;
+    sh.tr = R;
+    sh.tzc = zc;
+    sh.twpr = wpr;
+    return true;
+}
+
+// Shapes forced from the environment (CUTH_FUSE=1, CUTH_FUSE3=1), or no fusion.
 void set_fuse(Shape &sh, int max_nx) {
     sh.fr = 0;
+    sh.tr = 0;
     if (fuse_env() != 1) return;
     int R = 2, zc = 8;
     if (const char *f = std::getenv("CUTH_FUSE_SHAPE")) {
@@ -1221,7 +1297,17 @@ void set_fuse(Shape &sh, int max_nx) {
             zc = b;
         }
     }
-    (void)fuse_fit(sh, max_nx, R, zc);
+    if (!fuse_fit(sh, max_nx, R, zc) || fuse3_env() != 1) return;
+    R = 4;
+    zc = 8;
+    if (const char *f = std::getenv("CUTH_FUSE3_SHAPE")) {
+        int a = 0, b = 0;
+        if (std::sscanf(f, "%d,%d", &a, &b) == 2 && a >= 1 && a <= 12 && b >= 1) {
+            R = a;
+            zc = b;
+        }
+    }
+    (void)fuse3_fit(sh, max_nx, R, zc);
 }
 
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
@@ -1870,13 +1956,16 @@ Status autotune(Engine &E, std::vector<Problem *> &ps, int kcheb, const std::str
     return Status::ok();
 }
 
-// Fused pairs or single sweeps for these problems (FP32 general sweeps): the
-// environment decides if it says so (fuse_env), else the faster of four single
-// sweeps and two fused pairs per candidate shape, timed on the problems
-// themselves and cached per signature.  Needs the four iterate buffers.
+// Fused pairs or single sweeps for these problems (FP32 general sweeps), then
+// fused triples on top of the pairs: the environment decides if it says so
+// (fuse_env, fuse3_env), else timing on the problems themselves: the faster of
+// four single sweeps and two fused pairs per candidate shape, then two fused
+// triples per candidate against the pairs' time per sweep.  Cached per
+// signature.  Needs the four iterate buffers.
 template <typename T>
 Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const std::string &sig) {
     sh.fr = 0;
+    sh.tr = 0;
     if (sizeof(T) != 4 || ps.empty()) return Status::ok();
     const int fe = fuse_env();
     int max_nx = 1;
@@ -1894,67 +1983,96 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            if (it->second.fr > 0) (void)fuse_fit(sh, max_nx, it->second.fr, it->second.fzc);
+            if (it->second.fr > 0 && fuse_fit(sh, max_nx, it->second.fr, it->second.fzc) && it->second.tr > 0)
+                (void)fuse3_fit(sh, max_nx, it->second.tr, it->second.tzc);
             return Status::ok();
         }
     }
     const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16, jac = ps[0]->pm == CUTH_PC_CHEBYSHEV_JACOBI;
-    const int cand[][2] = {{0, 0}, {4, 8}, {2, 8}, {2, 16}, {4, 4}, {1, 16}};
     const hipStream_t s = E.own;
     hipEvent_t e0, e1;
     CUTH_HIP(hipEventCreate(&e0));
     CUTH_HIP(hipEventCreate(&e1));
     for (Problem *p : ps) p->inner = true;
-    float best_ms = INFINITY;
-    Shape best = sh;
-    best.fr = 0;
     Status st = Status::ok();
-    for (const auto &cd : cand) {
-        Shape c = sh;
-        c.fr = 0;
-        if (cd[0] > 0 && !fuse_fit(c, max_nx, cd[0], cd[1])) continue;
+    // milliseconds per general sweep of shape c with launches of `width`
+    // sweeps (1, 2 or 3), from three timed rounds after a warm-up round; a
+    // negative value if the shape does not fit or its launch fails
+    auto per_sweep = [&](const Shape &c, int width) -> float {
         std::vector<int> which;
         const int nb = build_inner<T>(E, ps, c, which);
-        if (nb < 0) continue;
+        if (nb < 0) return -1.f;
         const int n = (int)which.size();
         const InnerProb<T> &last = Sel<T>::h(E)[n - 1];
-        const int nbf = last.f_tile0 + last.f_ntiles;
+        const int nbf = last.f_tile0 + last.f_ntiles, nbt = last.t_tile0 + last.t_ntiles;
         if (hipMemcpyAsync(Sel<T>::d(E), Sel<T>::h(E), sizeof(InnerProb<T>) * n,
                            hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemsetAsync(Sel<T>::ds(E), 0, sizeof(CgState<T>) * n, s) != hipSuccess) {
             st = Status::err(CUTH_E_DEVICE, "tune_fuse: upload failed");
-            break;
+            return -1.f;
         }
         auto round = [&]() {
-            if (c.fr == 0) {
+            if (width == 1) {
                 for (int q = 0; q < 4; ++q)
                     launch_cheb_b<T>(Sel<T>::d(E), n, nb, pc, h16 ? CS_F16 : CS_OWN, jac, c.vx, c.by, 0, false, false, 3,
                                      zsel(q & 1, 1 - (q & 1)), eslot<T>(E, P_UPD), false,
                                      eslot<T>(E, P_CHEB), s);
-            } else {
-                if constexpr (sizeof(T) == 4) {
-                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3,
-                                      0 + 4 * 1 + 16 * 2 + 64 * 3, s);
-                    launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3,
-                                      3 + 4 * 2 + 16 * 0 + 64 * 1, s);
+            } else if constexpr (sizeof(T) == 4) {
+                // two launches from j = 3 over the four buffers (reads N, P; writes X, Y)
+                for (int q = 0; q < 2; ++q) {
+                    const int zs = q == 0 ? 0 + 4 * 1 + 16 * 2 + 64 * 3 : 3 + 4 * 2 + 16 * 0 + 64 * 1;
+                    if (width == 3)
+                        launch_cheb3_b<T>(Sel<T>::d(E), n, nbt, pc, h16, c.vx, c.tr, c.tzc, c.twpr, 3, zs, s);
+                    else
+                        launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3, zs, s);
                 }
             }
         };
         round();
+        if (hipGetLastError() != hipSuccess) return -1.f;   // e.g. more LDS than a launch may take
         (void)hipEventRecord(e0, s);
         for (int rep = 0; rep < 3; ++rep) round();
         (void)hipEventRecord(e1, s);
         if (hipStreamSynchronize(s) != hipSuccess) {
             st = Status::err(CUTH_E_DEVICE, "tune_fuse: timing launch failed");
-            break;
+            return -1.f;
         }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        const float sw = ms / 3 / (width == 1 ? 4 : 2 * width);
         if (log_on())
-            std::fprintf(stderr, "cuth: fuse %d,%d %.3f ms per 4 sweeps\n", c.fr, c.fzc, ms / 3);
-        if (ms < best_ms * kTuneMargin) {
-            best_ms = ms;
+            std::fprintf(stderr, "cuth: fuse width %d shape %d,%d %.4f ms per sweep\n", width,
+                         width == 3 ? c.tr : c.fr, width == 3 ? c.tzc : c.fzc, sw);
+        return sw;
+    };
+    float best_sw = INFINITY;
+    Shape best = sh;
+    const int cand[][2] = {{0, 0}, {4, 8}, {2, 8}, {2, 16}, {4, 4}, {1, 16}};
+    for (const auto &cd : cand) {
+        Shape c = sh;
+        c.fr = 0;
+        if (cd[0] > 0 && !fuse_fit(c, max_nx, cd[0], cd[1])) continue;
+        const float sw = per_sweep(c, cd[0] > 0 ? 2 : 1);
+        if (st.bad()) break;
+        if (sw >= 0.f && sw < best_sw * kTuneMargin) {
+            best_sw = sw;
             best = c;
+        }
+    }
+    // fused triples where pairs run and a triple fits before the last sweep
+    const int f3 = fuse3_env();
+    if (!st.bad() && best.fr > 0 && f3 != 0 && !jac && k >= 7) {
+        const int cand3[][2] = {{4, 8}, {2, 8}};
+        for (const auto &cd : cand3) {
+            Shape c = best;
+            if (!fuse3_fit(c, max_nx, cd[0], cd[1])) continue;
+            const float sw = per_sweep(c, 3);
+            if (st.bad()) break;
+            if (sw >= 0.f && (f3 == 1 || sw < best_sw * kTuneMargin)) {
+                best_sw = sw;
+                best = c;
+                if (f3 == 1) break;
+            }
         }
     }
     for (Problem *p : ps) p->inner = false;
@@ -2076,9 +2194,9 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         for (Problem *p : ps)
             nb_max += (size_t)tiles_x(p->g->nx, 1) * p->g->ny * tiles_z(p->g->nz, 4);
         Engine E;
-        // the tuners' timed sweeps read the constants of sweeps up to j = 4, so
-        // the constant rows hold at least 5 sweeps whatever the degree
-        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 5), nb_max)).bad()) {
+        // the tuners' timed sweeps read the constants of sweeps up to j = 5, so
+        // the constant rows hold at least 6 sweeps whatever the degree
+        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 6), nb_max)).bad()) {
             engine_free(E);
             dev_free(pool32);
             dev_free(pool64);
@@ -2219,8 +2337,7 @@ static Status precond_typed(Grid &g, Setup &su, Work<T> &w, const Shape &sh, con
     // exactly where enqueue_precond uses them: FP32)
     Engine &E = g.eng;
     const bool h16e = h16 && g.per_cell;
-    const bool fuse = sizeof(T) == 4 && sh.fr > 0;
-    const int zfin = precond_final(cc.k, pm, fuse);
+    const int zfin = precond_final(cc.k, pm, fuse_for<T>(sh, pm));
     Problem p;
     p.g = &g;
     p.su = &su;

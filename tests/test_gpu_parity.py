@@ -635,6 +635,82 @@ def test_fused_sweep_pairs(monkeypatch, case, shape):
     g.close()
 
 
+@pytest.mark.parametrize("shape", ["4,8", "2,8", "1,1", "3,4", "2,64"])
+@pytest.mark.parametrize("case", ["ragged_mult", "ragged_uniform", "c0"])
+def test_fused_sweep_triples(monkeypatch, case, shape):
+    """General Chebyshev sweeps fused in threes (z_{j+1} kept on chip, two halo
+    rows and layers per side): the FP32 preconditioner against the oracle's
+    polynomial and against single sweeps, for degrees with no triple (6), one
+    triple (7), a triple and a single sweep (8), a triple and a pair (9) and
+    the default (30), and workgroup shapes from one row and one layer to
+    chunks deeper than the stack."""
+    say(f"fused triples {case} shape {shape}")
+    st = CASES[case]()
+    A = assembly.assemble(st)
+    lmin, lmax = krylov.spectral_bounds(A, w.lanczos_start(st.n))
+    r = np.random.default_rng(13).standard_normal(st.n)
+    g = grid_of(st)
+    A16 = None
+    if st.k_lat_mult is not None:
+        A16 = assembly.assemble(st, cond=assembly.fp16_lateral(assembly.conductances(st)))
+    for degree in (6, 7, 8, 9, 30):
+        ref = krylov.chebyshev_precondition(lambda v: A @ v, r, lmin, lmax, degree)
+        monkeypatch.setenv("CUTH_FUSE", "0")
+        z1 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
+        monkeypatch.setenv("CUTH_FUSE", "1")
+        monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+        monkeypatch.setenv("CUTH_FUSE3", "1")
+        monkeypatch.setenv("CUTH_FUSE3_SHAPE", shape)
+        z2 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
+        monkeypatch.delenv("CUTH_FUSE3")
+        assert np.abs(z2 - ref).max() <= 2e-3 * np.abs(ref).max()
+        # same arithmetic in the same order as three single sweeps
+        assert np.abs(z2 - z1).max() <= 1e-6 * np.abs(z1).max()
+        if A16 is not None:
+            monkeypatch.setenv("CUTH_FUSE3", "1")
+            ref16 = krylov.chebyshev_precondition(lambda v: A16 @ v, r, lmin, lmax, degree)
+            z3 = g.precond_apply(t32(r), lmin, lmax, degree, fp16_coef=True).cpu().numpy()
+            monkeypatch.delenv("CUTH_FUSE3")
+            assert np.abs(z3.astype(np.float64) - ref16).max() <= 2e-3 * np.abs(ref16).max()
+    g.close()
+
+
+def test_fused_triple_solves(monkeypatch):
+    """Mixed solves with fused sweep triples (and pairs for the rest) reach the
+    1e-8 bar: steady on a lognormal and a uniform grid, one backward-Euler step,
+    and a two-grid batch; the timed launches are the triples."""
+    import paper_2606_17850_amd as cuth
+    say("fused triple solves")
+    monkeypatch.setenv("CUTH_FUSE", "1")
+    monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+    monkeypatch.setenv("CUTH_FUSE3", "1")
+    monkeypatch.setenv("CUTH_FUSE3_SHAPE", "4,8")
+    for st, P in (w.config4_small(), w.config0()):
+        g = grid_of(st)
+        g.profile_enable(True)
+        T, stats = g.solve(t64(P), precision="mixed")
+        prof = g.profile_read()
+        g.profile_enable(False)
+        err = rise_err(T.cpu().numpy(), _ref_steady(st, P), st.t_amb)
+        say(f"  err {err:.3e} cg {stats['cg_iters']} {prof}")
+        assert err <= 1e-8
+        assert prof["fused"] == 2 and prof["launches"] % 8 == 0
+        dt = 1e-4
+        th0 = np.random.default_rng(12).uniform(0, 5.0, st.n)
+        ref_tr = transient.step(st, P.ravel(), th0, dt)
+        Tt, _ = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision="mixed")
+        assert np.abs(Tt.cpu().numpy() - st.t_amb - ref_tr).max() <= 1e-8 * np.abs(ref_tr).max()
+        g.close()
+    stacks = [ragged_stack(70, 9, mult=True), ragged_stack(131, 6, mult=False)]
+    maps = [np.random.default_rng(50 + i).uniform(0, 2e-3, s.n) for i, s in enumerate(stacks)]
+    grids = [grid_of(s) for s in stacks]
+    Tb, _ = cuth.solve_batch(grids, [t64(m) for m in maps], nrhs=1, precision="mixed")
+    for s, m, t in zip(stacks, maps, Tb):
+        assert rise_err(t.cpu().numpy(), _ref_steady(s, m), s.t_amb) <= 1e-8
+    for gg in grids:
+        gg.close()
+
+
 def test_fused_sweep_solves(monkeypatch):
     """Mixed solves with fused sweep pairs reach the 1e-8 bar: steady on a
     lognormal and a uniform grid, one backward-Euler step, and a two-grid batch."""
@@ -663,16 +739,19 @@ def test_fused_sweep_solves(monkeypatch):
         gg.close()
 
 
-@pytest.mark.parametrize("fuse", ["0", "1"])
+@pytest.mark.parametrize("fuse", ["0", "1", "3"])
 def test_kernel_timing_blocks(monkeypatch, fuse):
     """The measurement hook times whole back-to-back runs of the general FP32
-    kernel: at k = 30 every preconditioner application contributes 13 fused
-    pairs (j = 3..28) or 26 single sweeps (j = 3..28), so the launch count is a
-    multiple of that, and the bytes per launch are those of the kernel timed
-    (28 or 24 B per unknown on a per-cell grid)."""
-    say(f"kernel timing blocks, CUTH_FUSE={fuse}")
-    monkeypatch.setenv("CUTH_FUSE", fuse)
+    kernel: at k = 30 every preconditioner application contributes 8 fused
+    triples (j = 3..26), 13 fused pairs (j = 3..28) or 26 single sweeps
+    (j = 3..28), so the launch count is a multiple of that, and the bytes per
+    launch are those of the kernel timed (28, 28 or 24 B per unknown on a
+    per-cell grid)."""
+    say(f"kernel timing blocks, fusion {fuse}")
+    monkeypatch.setenv("CUTH_FUSE", "0" if fuse == "0" else "1")
     monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+    monkeypatch.setenv("CUTH_FUSE3", "1" if fuse == "3" else "0")
+    monkeypatch.setenv("CUTH_FUSE3_SHAPE", "4,8")
     st, P = w.config4_small()
     g = grid_of(st)
     g.profile_enable(True)
@@ -680,12 +759,12 @@ def test_kernel_timing_blocks(monkeypatch, fuse):
     prof = g.profile_read()
     g.profile_enable(False)
     g.close()
-    per = 13 if fuse == "1" else 26
+    per = {"0": 26, "1": 13, "3": 8}[fuse]
     say(f"  {prof} cg {stats['cg_iters']}")
-    assert prof["fused"] == (fuse == "1")
+    assert prof["fused"] == {"0": 0, "1": 1, "3": 2}[fuse]
     assert prof["launches"] >= per and prof["launches"] % per == 0
     assert prof["launches"] <= per * (stats["cg_iters"] + stats["outer_cycles"] + 1)
-    assert prof["bytes_per_launch"] == (28 if fuse == "1" else 24) * st.n
+    assert prof["bytes_per_launch"] == (24 if fuse == "0" else 28) * st.n
     assert prof["total_ms"] > 0
 
 
