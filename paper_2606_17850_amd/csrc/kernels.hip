@@ -919,8 +919,9 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
 // reads ring B slot (l - 2) % 3 (written before the barrier).  Every slot is
 // written again only two barriers after its last read.  A y neighbour outside
 // the grid is read at the cell's own slot, so its term vanishes; ring rows
-// outside the grid are never read.  Chebyshev (not Jacobi-scaled) sweeps only.
-template <typename T, bool PC, int VX, int CS>
+// outside the grid are never read.  JAC: the sweeps of the Jacobi-scaled
+// operator (the residual terms times 1/diag(A), as k_cheb_b).
+template <typename T, bool PC, int VX, int CS, bool JAC>
 __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                   int j, int zsel, int R, int zcf, int wpr) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1016,7 +1017,9 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             a += gn * (x - no.a[e]);
             a += L.gzd * (x - dn.a[e]);
             a += L.gzu * (x - up.a[e]);
-            out.a[e] = x + c1 * (x - pv.a[e]) + c2 * (rr.a[e] - a);
+            T res = rr.a[e] - a;
+            if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, ls, nz));
+            out.a[e] = x + c1 * (x - pv.a[e]) + c2 * res;
         }
         return out;
     };
@@ -1111,7 +1114,9 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             a += gn * (x - xno.a[e]);
             a += L.gzd * (x - xdn.a[e]);
             a += L.gzu * (x - xup.a[e]);
-            zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * (rv.a[e] - a);
+            T res = rv.a[e] - a;
+            if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, l, nz));
+            zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
         }
         if (xo < W) lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
         __syncthreads();
@@ -1905,18 +1910,25 @@ void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool 
     else cheb2_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
-template <typename T>
-void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
-                    int zc, int wpr, int j, int zsel, hipStream_t s) {
+template <typename T, bool JAC>
+static void cheb3_jac(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
+                      int zc, int wpr, int j, int zsel, hipStream_t s) {
     const dim3 g(nb), b(kWave, wpr * (R + 4));
     const size_t lds = (size_t)3 * ((R + 4) + (R + 2)) * wpr * kWave * vx * sizeof(T);
     if (pc && h16) {
-        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb3_b<T, true, VX, CS_F16>), g, b, lds, s,
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb3_b<T, true, VX, CS_F16, JAC>), g, b, lds, s,
                                                     probs, nprob, j, zsel, R, zc, wpr)));
         return;
     }
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb3_b<T, PC, VX, CS_OWN>), g, b, lds, s,
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb3_b<T, PC, VX, CS_OWN, JAC>), g, b, lds, s,
                                                        probs, nprob, j, zsel, R, zc, wpr)));
+}
+
+template <typename T>
+void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac, int vx,
+                    int R, int zc, int wpr, int j, int zsel, hipStream_t s) {
+    if (jac) cheb3_jac<T, true>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
+    else cheb3_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
 template <typename T, bool PC, int VX, int PM>
@@ -2140,8 +2152,8 @@ CUTH_INST(double)
 
 template void launch_cheb2_b<float>(const InnerProb<float> *, int, int, bool, bool, bool, int, int,
                                       int, int, int, int, hipStream_t);
-template void launch_cheb3_b<float>(const InnerProb<float> *, int, int, bool, bool, int, int, int,
-                                      int, int, int, hipStream_t);
+template void launch_cheb3_b<float>(const InnerProb<float> *, int, int, bool, bool, bool, int, int,
+                                      int, int, int, int, hipStream_t);
 template void launch_promote_dot<double>(const InnerProb<double> *, int, int, int, int, double *,
                                          hipStream_t);
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,

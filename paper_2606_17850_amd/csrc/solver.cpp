@@ -177,13 +177,12 @@ ChebConsts make_cheb(double lmin, double lmax, int k) {
 // fused pairs, 0 single sweeps only.
 inline int fuse_level(const Shape &sh) { return sh.tr > 0 && sh.fr > 0 ? 3 : sh.fr > 0 ? 2 : 0; }
 
-// The fusion level the preconditioner pm runs at in precision T: fused
-// launches are FP32 only, and the Jacobi-scaled sweeps have no triple kernel.
+// The fusion level the preconditioner runs at in precision T (fused launches
+// are FP32 only).
 template <typename T>
 int fuse_for(const Shape &sh, int pm) {
-    if (sizeof(T) != 4) return 0;
-    const int f = fuse_level(sh);
-    return pm == 3 ? std::min(f, 2) : f;
+    (void)pm;
+    return sizeof(T) == 4 ? fuse_level(sh) : 0;
 }
 
 // Number of general sweeps the launch at sweep j of a degree-k preconditioner
@@ -577,7 +576,7 @@ int enqueue_precond(Engine &E, int nprob, int nb, bool pc, int cs, int pm, const
             free_pair(n, p, x, y);
             if constexpr (sizeof(T) == 4) {
                 if (wd == 3)
-                    launch_cheb3_b<T>(d, nprob, nbt, pc, h16, sh.vx, sh.tr, sh.tzc, sh.twpr, j,
+                    launch_cheb3_b<T>(d, nprob, nbt, pc, h16, jac, sh.vx, sh.tr, sh.tzc, sh.twpr, j,
                                       n + 4 * p + 16 * x + 64 * y, s);
                 else
                     launch_cheb2_b<T>(d, nprob, nbf, pc, h16, jac, sh.vx, sh.fr, sh.fzc, sh.fwpr, j,
@@ -2022,7 +2021,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
                 for (int q = 0; q < 2; ++q) {
                     const int zs = q == 0 ? 0 + 4 * 1 + 16 * 2 + 64 * 3 : 3 + 4 * 2 + 16 * 0 + 64 * 1;
                     if (width == 3)
-                        launch_cheb3_b<T>(Sel<T>::d(E), n, nbt, pc, h16, c.vx, c.tr, c.tzc, c.twpr, 3, zs, s);
+                        launch_cheb3_b<T>(Sel<T>::d(E), n, nbt, pc, h16, jac, c.vx, c.tr, c.tzc, c.twpr, 3, zs, s);
                     else
                         launch_cheb2_b<T>(Sel<T>::d(E), n, nbf, pc, h16, jac, c.vx, c.fr, c.fzc, c.fwpr, 3, zs, s);
                 }
@@ -2061,7 +2060,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
     }
     // fused triples where pairs run and a triple fits before the last sweep
     const int f3 = fuse3_env();
-    if (!st.bad() && best.fr > 0 && f3 != 0 && !jac && k >= 7) {
+    if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 7) {
         const int cand3[][2] = {{4, 8}, {2, 8}};
         for (const auto &cd : cand3) {
             Shape c = best;

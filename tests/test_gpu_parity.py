@@ -96,11 +96,12 @@ def test_chebyshev_matches_oracle(case, degree):
 
 
 @pytest.mark.parametrize("case", ["ragged_mult", "ragged_uniform", "c0"])
-@pytest.mark.parametrize("degree", [1, 2, 3, 6, 30])
+@pytest.mark.parametrize("degree", [1, 2, 3, 6, 7, 9, 30])
 def test_chebyshev_jacobi_matches_oracle(monkeypatch, case, degree):
     """The Jacobi-scaled Chebyshev preconditioner (beyond the paper):
     q_k(D^{-1} A) D^{-1} r against the oracle's definition, in FP64 and FP32,
-    with single sweeps and with fused sweep pairs (two workgroup shapes)."""
+    with single sweeps, fused sweep pairs (two workgroup shapes) and fused
+    triples (two shapes); the fused results also against the single sweeps."""
     say(f"chebyshev-jacobi {case} k={degree}")
     st = CASES[case]()
     A = assembly.assemble(st)
@@ -110,13 +111,21 @@ def test_chebyshev_jacobi_matches_oracle(monkeypatch, case, degree):
     ref = krylov.jacobi_chebyshev_precondition(A, r, lo, hi, degree)
     z = g.precond_apply(t64(r), lo, hi, degree, preconditioner="chebyshev_jacobi").cpu().numpy()
     assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
-    for env in ({"CUTH_FUSE": "0"}, {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8"},
-                {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "1,1"}):
+    z_single = None
+    for env in ({"CUTH_FUSE": "0"}, {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8", "CUTH_FUSE3": "0"},
+                {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "1,1", "CUTH_FUSE3": "0"},
+                {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8", "CUTH_FUSE3": "1", "CUTH_FUSE3_SHAPE": "4,8"},
+                {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8", "CUTH_FUSE3": "1", "CUTH_FUSE3_SHAPE": "1,1"}):
         for k_, v_ in env.items():
             monkeypatch.setenv(k_, v_)
         z32 = g.precond_apply(t32(r), lo, hi, degree,
                               preconditioner="chebyshev_jacobi").cpu().numpy().astype(np.float64)
         assert np.abs(z32 - ref).max() <= 2e-3 * np.abs(ref).max(), env
+        if z_single is None:
+            z_single = z32
+        else:
+            # the same arithmetic in the same order as single sweeps
+            assert np.abs(z32 - z_single).max() <= 1e-6 * np.abs(z_single).max(), env
     g.close()
 
 
