@@ -2061,7 +2061,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
     // fused triples where pairs run and a triple fits before the last sweep
     const int f3 = fuse3_env();
     if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 7) {
-        const int cand3[][2] = {{4, 8}, {2, 8}};
+        const int cand3[][2] = {{4, 8}, {2, 8}, {4, 16}};
         for (const auto &cd : cand3) {
             Shape c = best;
             if (!fuse3_fit(c, max_nx, cd[0], cd[1])) continue;
