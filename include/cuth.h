@@ -35,6 +35,22 @@
  *    CUTH_E_INVALID is returned before any device work when host-side
  *    arguments are bad.
  *  - A handle may be used by one thread at a time.
+ *
+ * Environment (tuning and diagnostics; none is needed for correct results):
+ *  - CUTH_FUSE=0/1: never / always fuse the general FP32 Chebyshev sweeps in
+ *    pairs (unset: chosen per grid or batch by timing); CUTH_FUSE_SHAPE="R,zc"
+ *    with CUTH_FUSE=1: rows per workgroup and layers per chunk (default 2,8).
+ *  - CUTH_FUSE3=0/1: never / always fuse them in triples where pairs run
+ *    (unset: chosen by timing against the pairs); CUTH_FUSE3_SHAPE="R,zc"
+ *    with CUTH_FUSE=1 and CUTH_FUSE3=1 (default 4,8).
+ *  - CUTH_AUTOTUNE_CACHE=<file>: keep the tuned tile shapes of batches there.
+ *  - CUTH_GRAPH=0/1: replay CG chunks from a captured HIP graph (default:
+ *    batches of more than one problem).
+ *  - CUTH_REDUCE_ABOVE=<n>: workgroups per problem above which the CG sums go
+ *    through a separate reduce launch (default 4096).
+ *  - CUTH_LOG=1: tuning results and one line per refinement cycle on stderr.
+ * Fused and single sweeps compute the same polynomial in the same order of
+ * operations; the choice changes speed, not results beyond FP32 rounding.
  */
 #ifndef CUTH_H
 #define CUTH_H
