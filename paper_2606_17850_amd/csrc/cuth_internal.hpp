@@ -179,7 +179,8 @@ void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool 
 // A workgroup is R + 4 rows of wpr wavefronts and a chunk of zc layers; the
 // launch covers the problems' slots [t_tile0, t_tile0 + t_ntiles) with
 // t_ntiles = ceil(ny / R) * ceil(nz / zc); dynamic LDS 3 (2R + 6) rows of
-// 64*vx*wpr values.  FP32; h16 and jac as for the pair.
+// 64*vx*wpr values.  FP32; h16 and jac as for the pair.  At j = 2 without jac
+// z_{j-1} = z_1 = r / theta is formed from r (z[P] is not read).
 template <typename T>
 void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac, int vx,
                     int R, int zc, int wpr, int j, int zsel, hipStream_t s);

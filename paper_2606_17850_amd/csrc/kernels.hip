@@ -920,8 +920,10 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
 // written again only two barriers after its last read.  A y neighbour outside
 // the grid is read at the cell's own slot, so its term vanishes; ring rows
 // outside the grid are never read.  JAC: the sweeps of the Jacobi-scaled
-// operator (the residual terms times 1/diag(A), as k_cheb_b).
-template <typename T, bool PC, int VX, int CS, bool JAC>
+// operator (the residual terms times 1/diag(A), as k_cheb_b).  M2: the triple
+// starts at j = 2 of the plain polynomial, whose z_1 = r / theta is formed from
+// r instead of read (as k_cheb_b mode 2).
+template <typename T, bool PC, int VX, int CS, bool JAC, bool M2>
 __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict__ probs, int nprob,
                                                   int j, int zsel, int R, int zcf, int wpr) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -958,6 +960,7 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
     const T c1a = P.cheb[1 + j], c2a = P.cheb[1 + P.kcap + j];
     const T c1b = P.cheb[2 + j], c2b = P.cheb[2 + P.kcap + j];
     const T c1c = P.cheb[3 + j], c2c = P.cheb[3 + P.kcap + j];
+    [[maybe_unused]] const T inv_th = P.cheb[0];
     const T *__restrict__ zN = P.z[zsel & 3];
     const T *__restrict__ zP = P.z[(zsel >> 2) & 3];
     T *__restrict__ zX = P.z[(zsel >> 4) & 3];
@@ -1083,7 +1086,13 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
         [[maybe_unused]] LatRaw<T, VX, CS> lat;
         if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
         rv = vload<T, VX>(r + c);
-        const Vec<T, VX> zm = vload<T, VX>(zP + c);
+        Vec<T, VX> zm;
+        if constexpr (M2) {
+#pragma unroll
+            for (int e = 0; e < VX; ++e) zm.a[e] = rv.a[e] * inv_th;
+        } else {
+            zm = vload<T, VX>(zP + c);
+        }
         T left = lane_left(xc.a[VX - 1]);
         T right = lane_right(xc.a[0]);
         if (lane == 0) left = west;
@@ -1910,25 +1919,26 @@ void launch_cheb2_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool 
     else cheb2_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
-template <typename T, bool JAC>
+template <typename T, bool JAC, bool M2>
 static void cheb3_jac(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, int vx, int R,
                       int zc, int wpr, int j, int zsel, hipStream_t s) {
     const dim3 g(nb), b(kWave, wpr * (R + 4));
     const size_t lds = (size_t)3 * ((R + 4) + (R + 2)) * wpr * kWave * vx * sizeof(T);
     if (pc && h16) {
-        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb3_b<T, true, VX, CS_F16, JAC>), g, b, lds, s,
-                                                    probs, nprob, j, zsel, R, zc, wpr)));
+        CUTH_VX_DISPATCH(T, vx, (hipLaunchKernelGGL((k_cheb3_b<T, true, VX, CS_F16, JAC, M2>), g, b, lds,
+                                                    s, probs, nprob, j, zsel, R, zc, wpr)));
         return;
     }
-    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb3_b<T, PC, VX, CS_OWN, JAC>), g, b, lds, s,
-                                                       probs, nprob, j, zsel, R, zc, wpr)));
+    CUTH_PC_VX_DISPATCH(T, pc, vx, (hipLaunchKernelGGL((k_cheb3_b<T, PC, VX, CS_OWN, JAC, M2>), g, b,
+                                                       lds, s, probs, nprob, j, zsel, R, zc, wpr)));
 }
 
 template <typename T>
 void launch_cheb3_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, bool h16, bool jac, int vx,
                     int R, int zc, int wpr, int j, int zsel, hipStream_t s) {
-    if (jac) cheb3_jac<T, true>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
-    else cheb3_jac<T, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
+    if (jac) cheb3_jac<T, true, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
+    else if (j == 2) cheb3_jac<T, false, true>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
+    else cheb3_jac<T, false, false>(probs, nprob, nb, pc, h16, vx, R, zc, wpr, j, zsel, s);
 }
 
 template <typename T, bool PC, int VX, int PM>

@@ -185,13 +185,15 @@ int fuse_for(const Shape &sh, int pm) {
     return sizeof(T) == 4 ? fuse_level(sh) : 0;
 }
 
-// Number of general sweeps the launch at sweep j of a degree-k preconditioner
-// covers at fusion level `fuse`: fused launches start at j = 3 (sweeps 1 and 2
-// read the implicit z_0 / z_1) and end before the last sweep, which also
-// forms the r^T z partials.
+// Number of sweeps the launch at sweep j of a degree-k preconditioner covers
+// at fusion level `fuse`: fused launches end before the last sweep, which
+// also forms the r^T z partials; triples start at j = 2 (forming the implicit
+// z_1 = r / theta of the plain polynomial themselves), pairs at j = 3; sweep 1
+// (implicit z_0 = 0, the convergence test) is always single.
 inline int sweep_width(int j, int k, int fuse) {
-    if (j < 3) return 1;
+    if (j < 2) return 1;
     if (fuse >= 3 && j + 2 < k - 1) return 3;
+    if (j < 3) return 1;
     if (fuse >= 2 && j + 1 < k - 1) return 2;
     return 1;
 }
@@ -225,7 +227,9 @@ struct Bytes {
         double b = jac ? scale() + coef + cheb(2) : cheb(1);
         for (int j = 2; j < k;) {
             const int wd = sweep_width(j, k, fuse);
-            b += wd == 3 ? triple() : wd == 2 ? pair() : cheb(j == 2 && !jac ? 2 : 0);
+            // at j = 2 the plain polynomial's z_1 is formed from r, not read
+            const double m2 = j == 2 && !jac ? sizeof(T) : 0.0;
+            b += wd == 3 ? triple() - m2 : wd == 2 ? pair() : cheb(j == 2 && !jac ? 2 : 0);
             j += wd;
         }
         return b;
@@ -499,8 +503,8 @@ inline void free_pair(int n, int p, int &x, int &y) {
 int precond_final(int k, int pm, int fuse) {
     if (k == 1 || pm == 1 || pm == 2) return 0;
     if (k == 2) return 1;
-    int n = 0, p = 1;   // after mode 2
-    for (int j = 3; j < k;) {
+    int n = 1, p = 0;   // after mode 1
+    for (int j = 2; j < k;) {
         const int wd = sweep_width(j, k, fuse);
         if (wd > 1) {
             int x, y;
