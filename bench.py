@@ -520,6 +520,7 @@ def main() -> int:
             "mixed_single_sweeps_GBps": round(sum(s["alg_bytes"] for s in st_fu) / args.steps / (per_fu / 1e3) / 1e9, 2),
             "mixed_single_sweeps_vs_fp64_max_rise_rel_diff": diff_fu,
             "mixed_fused_pairs_only_cg_iters": st_pr[-1]["cg_iters"],
+            "mixed_fused_pairs_only_GBps": round(sum(s["alg_bytes"] for s in st_pr) / args.steps / (per_pr / 1e3) / 1e9, 2),
             "mixed_fused_pairs_only_vs_fp64_max_rise_rel_diff": diff_pr,
             "stage_switched_cg_iters": st_st[-1]["cg_iters"],
             "stage_switched_cycles": st_st[-1]["outer_cycles"],
