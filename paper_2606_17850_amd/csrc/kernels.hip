@@ -917,7 +917,7 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
 // writes ring A slot l % 3; after it, stage B of layer l - 1 reads ring A slot
 // (l - 1) % 3 and writes ring B slot (l - 1) % 3, and stage C of layer l - 2
 // reads ring B slot (l - 2) % 3 (written before the barrier).  Every slot is
-// written again only two barriers after its last read.  A y neighbour outside
+// written again only after a barrier that follows its last read.  A y neighbour outside
 // the grid is read at the cell's own slot, so its term vanishes; ring rows
 // outside the grid are never read.  JAC: the sweeps of the Jacobi-scaled
 // operator (the residual terms times 1/diag(A), as k_cheb_b).  M2: the triple
