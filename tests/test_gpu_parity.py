@@ -684,6 +684,39 @@ def test_fused_sweep_triples(monkeypatch, case, shape):
     g.close()
 
 
+@pytest.mark.parametrize("shape", ["4,8", "1,1", "2,2"])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (65, 3, 1), (33, 2, 2), (70, 9, 3), (7, 21, 2)])
+def test_fused_triples_shallow_and_narrow(monkeypatch, dims, shape):
+    """Forced fused triples on stacks of 1-3 layers and on grids narrower or
+    shorter than a workgroup (one cell, one row, a ragged lane tail): the
+    closing iterations of stages B and C carry most of the work there.  The
+    FP32 preconditioner equals single sweeps to 1e-6 of its scale and the
+    oracle's polynomial to the FP32 bar."""
+    nx, ny, nl = dims
+    layers = ("Si", "BEOL", "Cu")[:nl] if nl < 3 else ("Si", "bond", "Cu")
+    say(f"shallow triples {dims} shape {shape}")
+    st = ragged_stack(nx, ny, layers=layers, mult=True, seed=5)
+    A = assembly.assemble(st)
+    lmin, lmax = krylov.spectral_bounds(A, w.lanczos_start(st.n))
+    # a widened interval (a one-cell grid has lmin = lmax); both sides use it
+    lmin, lmax = 0.9 * lmin, 1.05 * lmax
+    r = np.random.default_rng(17).standard_normal(st.n)
+    g = grid_of(st)
+    for degree in (6, 9):
+        ref = krylov.chebyshev_precondition(lambda v: A @ v, r, lmin, lmax, degree)
+        monkeypatch.setenv("CUTH_FUSE", "0")
+        z1 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
+        monkeypatch.setenv("CUTH_FUSE", "1")
+        monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+        monkeypatch.setenv("CUTH_FUSE3", "1")
+        monkeypatch.setenv("CUTH_FUSE3_SHAPE", shape)
+        z3 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
+        monkeypatch.delenv("CUTH_FUSE3")
+        assert np.abs(z3 - z1).max() <= 1e-6 * np.abs(z1).max()
+        assert np.abs(z3 - ref).max() <= 2e-3 * np.abs(ref).max()
+    g.close()
+
+
 def test_fused_triple_solves(monkeypatch):
     """Mixed solves with fused sweep triples (and pairs for the rest) reach the
     1e-8 bar: steady on a lognormal and a uniform grid, one backward-Euler step,
