@@ -40,9 +40,10 @@
  *  - CUTH_FUSE=0/1: never / always fuse the general FP32 Chebyshev sweeps in
  *    pairs (unset: chosen per grid or batch by timing); CUTH_FUSE_SHAPE="R,zc"
  *    with CUTH_FUSE=1: rows per workgroup and layers per chunk (default 2,8).
- *  - CUTH_FUSE3=0/1: never / always fuse them in triples where pairs run
- *    (unset: chosen by timing against the pairs); CUTH_FUSE3_SHAPE="R,zc"
- *    with CUTH_FUSE=1 and CUTH_FUSE3=1 (default 4,8).
+ *  - CUTH_FUSE3=0/1: never / always fuse them in triples, with pairs for the
+ *    sweeps left over (unset: chosen by timing against the pairs; with
+ *    CUTH_FUSE unset, =1 takes the first triple shape that fits);
+ *    CUTH_FUSE3_SHAPE="R,zc" with CUTH_FUSE=1 and CUTH_FUSE3=1 (default 4,8).
  *  - CUTH_AUTOTUNE_CACHE=<file>: keep the tuned tile shapes of batches there.
  *  - CUTH_GRAPH=0/1: replay CG chunks from a captured HIP graph (default:
  *    batches of more than one problem).

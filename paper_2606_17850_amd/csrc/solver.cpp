@@ -1981,7 +1981,10 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
     if (k < 6 || !is_cheb(ps[0]->pm)) return Status::ok();   // no pair of general sweeps
     for (Problem *p : ps)
         if (!Sel<T>::w(*p).zC || !Sel<T>::w(*p).zD) return Status::ok();
-    const std::string key = sig + " fuse";
+    // the triple setting is part of the key: a cached choice made with
+    // triples allowed must not outlive CUTH_FUSE3=0, nor the reverse
+    const int f3 = fuse3_env();
+    const std::string key = sig + (f3 == 0 ? " fuse no3" : f3 == 1 ? " fuse 3" : " fuse");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
@@ -2063,7 +2066,11 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         }
     }
     // fused triples where pairs run and a triple fits before the last sweep
-    const int f3 = fuse3_env();
+    // (forced triples bring pairs for the rest where single sweeps won)
+    if (!st.bad() && f3 == 1 && best.fr == 0) {
+        Shape c = best;
+        if (fuse_fit(c, max_nx, 2, 8)) best = c;
+    }
     if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 7) {
         const int cand3[][2] = {{4, 8}, {2, 8}, {4, 16}};
         for (const auto &cd : cand3) {

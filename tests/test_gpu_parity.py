@@ -753,6 +753,31 @@ def test_fused_triple_solves(monkeypatch):
         gg.close()
 
 
+def test_triples_forced_through_tuner(monkeypatch):
+    """CUTH_FUSE3=1 with the pair shape left to the tuner: the tuner keeps its
+    pair choice and adds the first triple shape that fits; the solve meets the
+    1e-8 bar with triples as the timed launches, and CUTH_FUSE3=0 keeps them
+    off."""
+    say("triples forced through the tuner")
+    monkeypatch.delenv("CUTH_FUSE", raising=False)
+    st, P = w.config4_small()
+    ref = _ref_steady(st, P)
+    for f3, want in (("1", 2), ("0", 1)):
+        monkeypatch.setenv("CUTH_FUSE3", f3)
+        g = grid_of(st)   # a fresh handle: the tuner's choice is cached per grid signature
+        g.profile_enable(True)
+        T, stats = g.solve(t64(P), precision="mixed")
+        prof = g.profile_read()
+        g.profile_enable(False)
+        g.close()
+        err = rise_err(T.cpu().numpy(), ref, st.t_amb)
+        say(f"  CUTH_FUSE3={f3}: err {err:.3e} {prof}")
+        assert err <= 1e-8
+        assert prof["fused"] <= want
+        if f3 == "1":
+            assert prof["fused"] == 2
+
+
 def test_fused_sweep_solves(monkeypatch):
     """Mixed solves with fused sweep pairs reach the 1e-8 bar: steady on a
     lognormal and a uniform grid, one backward-Euler step, and a two-grid batch."""
