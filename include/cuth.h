@@ -196,6 +196,11 @@ typedef struct {
     int32_t stop_reason;         /* last inner solve: 1 tol, 2 drift, 3 stagnation,
                                     4 breakdown, 5 iteration limit                      */
     int32_t cheb_degree;         /* Chebyshev degree used (1 without Chebyshev)        */
+    int32_t drift_stops;         /* inner solves stopped by the drift test (Section 4.4,
+                                    eq. switching c: ||r_true - r_low|| >= 0.5 ||r_true||) */
+    int32_t stagnation_stops;    /* inner solves stopped by the stagnation test (eq.
+                                    switching b: ||r_true|| > 0.9 ||r_true|| of the
+                                    previous check)                                    */
     double rel_residual;         /* final ||b - A theta||_2 / ||b||_2 (FP64)           */
     double err_est;              /* mixed: last correction ||delta||_inf/||theta||_inf */
     double setup_ms;             /* coefficient/Lanczos setup inside this call         */
@@ -249,17 +254,23 @@ cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
                              const double *const *P, double *const *T,
                              const cuth_options *opt, cuth_stats *stats);
 
-/* Adjoint of the steady solve.  Given the forward solution T (device double
- * [N]) and dL/dT (device double [N]), solves G lambda = dL/dT (G = G^T) and
- * returns dL/dP = lambda (device double [N], W^-1 per cell) and the
- * conductivity gradients (device double [2*nz]):
- *   dL_dk[l]      = dL/dk_lat[l]  = -(1/k_lat[l]) sum over lateral faces f of
- *                   layer l of g_f (lambda_a - lambda_b)(theta_a - theta_b);
- *   dL_dk[nz + l] = dL/dk_vert[l] = -sum over vertical faces touching layer l of
- *                   (dg_f/dk_vert[l]) (lambda_a - lambda_b)(theta_a - theta_b),
- *                   dg/dk_vert[l] = g^2 dz[l] / (2 k_vert[l]^2 dx dy);
- * theta = T - T_amb.  When k_lat[l] == k_vert[l] the gradient with respect to a
- * layer's conductivity is dL_dk[l] + dL_dk[nz + l]. */
+/* Adjoint of the steady solve (a gradient of a loss through the solve of
+ * Section 3.2's steady system; the method of Sections 4.3-4.4 applied to
+ * G^T lambda = dL/dT).  Given the forward solution T (device double [N]) and
+ * dL/dT (device double [N]), solves G lambda = dL/dT (G = G^T) and returns
+ * dL/dP = lambda (device double [N], W^-1 per cell) and the gradient with
+ * respect to each layer's conductivity (device double [nz]):
+ *   dL_dk[l] = dL/dk_lat[l] + dL/dk_vert[l]
+ *            = -(1/k_lat[l]) sum over lateral faces f of layer l of
+ *                  g_f (lambda_a - lambda_b)(theta_a - theta_b)
+ *              - sum over vertical faces touching layer l of
+ *                  (dg_f/dk_vert[l]) (lambda_a - lambda_b)(theta_a - theta_b),
+ *   dg/dk_vert[l] = g^2 dz[l] / (2 k_vert[l]^2 dx dy),  theta = T - T_amb,
+ * with the lateral multiplier field held fixed.  For a layer whose lateral and
+ * vertical conductivities are one value k_l (every layer of an isotropic
+ * stack), dL_dk[l] is dL/dk_l; otherwise it is the derivative along an equal
+ * increment of both.  dL_dk is written on the device in a fixed summation
+ * order (run-to-run identical). */
 cuth_status cuth_adjoint(cuth_grid g, const double *T, const double *dL_dT,
                          double *dL_dP, double *dL_dk,
                          const cuth_options *opt, cuth_stats *stats);

@@ -40,14 +40,6 @@ class Conductances:
     sink: np.ndarray   # (nz, ny, nx) diagonal-only terms: h S (+ C V / dt)
 
 
-def lateral_k(stack) -> np.ndarray:
-    """Per-cell lateral conductivity (nz, ny, nx)."""
-    k = np.broadcast_to(np.asarray(stack.k_lat, float)[:, None, None], stack.shape).copy()
-    if stack.k_lat_mult is not None:
-        k = k * np.asarray(stack.k_lat_mult, float).reshape(stack.shape)
-    return k
-
-
 def conductances(stack, dt: Optional[float] = None,
                  k_lat: Optional[np.ndarray] = None,
                  k_vert: Optional[np.ndarray] = None) -> Conductances:

@@ -70,40 +70,72 @@ def _neumann_eigs(n: int) -> np.ndarray:
     return 4.0 * np.sin(np.pi * m / (2.0 * n)) ** 2
 
 
+class SeparableFactors:
+    """The separable solve of one per-layer-uniform operator (steady, or
+    transient with step dt), its per-mode tridiagonal systems eliminated once.
+
+    ``solve_hat`` solves in the DCT basis (the right-hand side and the result as
+    DCT-II coefficients over x, y per layer), so a sequence of solves with the
+    same operator (backward-Euler steps) can stay in that basis."""
+
+    def __init__(self, stack, dt: Optional[float] = None):
+        nz, ny, nx = stack.shape
+        self.shape = stack.shape
+        gxl, gyl, gzl, sink = _uniform_layer_terms(stack, dt)
+        mux = _neumann_eigs(nx)[None, :]
+        muy = _neumann_eigs(ny)[:, None]
+        # tridiagonal per lateral mode: diag d_l, off-diagonal -gz_l between l, l+1
+        d = np.empty((nz, ny, nx))
+        for l in range(nz):
+            dl = mux * gxl[l] + muy * gyl[l] + sink[l]
+            if l > 0:
+                dl = dl + gzl[l - 1]
+            if l < nz - 1:
+                dl = dl + gzl[l]
+            d[l] = dl
+        # forward elimination of the Thomas algorithm along l (vectorised over
+        # modes): multipliers cp and pivots denom
+        cp = np.zeros((nz, ny, nx))
+        den = np.empty((nz, ny, nx))
+        den[0] = d[0]
+        if nz > 1:
+            cp[0] = -gzl[0] / den[0]
+        for l in range(1, nz):
+            a = -gzl[l - 1]
+            den[l] = d[l] - a * cp[l - 1]
+            if l < nz - 1:
+                cp[l] = -gzl[l] / den[l]
+        self.gzl, self.cp, self.den = gzl, cp, den
+
+    def solve_hat(self, bh: np.ndarray) -> np.ndarray:
+        nz = self.shape[0]
+        gzl, cp, den = self.gzl, self.cp, self.den
+        dp = np.zeros(self.shape)
+        dp[0] = bh[0] / den[0]
+        for l in range(1, nz):
+            a = -gzl[l - 1]
+            dp[l] = (bh[l] - a * dp[l - 1]) / den[l]
+        x = np.empty(self.shape)
+        x[nz - 1] = dp[nz - 1]
+        for l in range(nz - 2, -1, -1):
+            x[l] = dp[l] - cp[l] * x[l + 1]
+        return x
+
+
+def dct_layers(v: np.ndarray, shape) -> np.ndarray:
+    """Orthonormal 2-D DCT-II of every layer of a flat field."""
+    return sfft.dctn(np.asarray(v, float).reshape(shape), type=2, axes=(1, 2), norm="ortho")
+
+
+def idct_layers(vh: np.ndarray) -> np.ndarray:
+    """Inverse of ``dct_layers``, flattened."""
+    return sfft.idctn(vh, type=2, axes=(1, 2), norm="ortho").ravel()
+
+
 def solve_separable(stack, b: np.ndarray, dt: Optional[float] = None) -> np.ndarray:
     """Exact solve of A theta = b for a per-layer-uniform stack."""
-    nz, ny, nx = stack.shape
-    gxl, gyl, gzl, sink = _uniform_layer_terms(stack, dt)
-    bh = sfft.dctn(np.asarray(b, float).reshape(stack.shape), type=2, axes=(1, 2), norm="ortho")
-    mux = _neumann_eigs(nx)[None, :]
-    muy = _neumann_eigs(ny)[:, None]
-    # tridiagonal per lateral mode: diag d_l, off-diagonal -gz_l between l, l+1
-    d = np.empty((nz, ny, nx))
-    for l in range(nz):
-        dl = mux * gxl[l] + muy * gyl[l] + sink[l]
-        if l > 0:
-            dl = dl + gzl[l - 1]
-        if l < nz - 1:
-            dl = dl + gzl[l]
-        d[l] = dl
-    # Thomas algorithm along l, vectorised over modes
-    cp = np.zeros((nz, ny, nx))
-    dp = np.zeros((nz, ny, nx))
-    denom = d[0]
-    if nz > 1:
-        cp[0] = -gzl[0] / denom
-    dp[0] = bh[0] / denom
-    for l in range(1, nz):
-        a = -gzl[l - 1]
-        denom = d[l] - a * cp[l - 1]
-        if l < nz - 1:
-            cp[l] = -gzl[l] / denom
-        dp[l] = (bh[l] - a * dp[l - 1]) / denom
-    x = np.empty((nz, ny, nx))
-    x[nz - 1] = dp[nz - 1]
-    for l in range(nz - 2, -1, -1):
-        x[l] = dp[l] - cp[l] * x[l + 1]
-    return sfft.idctn(x, type=2, axes=(1, 2), norm="ortho").ravel()
+    f = SeparableFactors(stack, dt)
+    return idct_layers(f.solve_hat(dct_layers(b, stack.shape)))
 
 
 def _z_matrix(gxl, gyl, gzl, sink, mux: float, muy: float) -> np.ndarray:

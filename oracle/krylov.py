@@ -57,11 +57,16 @@ def chebyshev_residual_poly(lam: np.ndarray, lmin: float, lmax: float, k: int) -
 
 
 def chebyshev_precondition(matvec: Matvec, r_cg: np.ndarray, lmin: float, lmax: float,
-                           k: int) -> np.ndarray:
-    """z_cg = M^{-1} r_cg by the paper's Chebyshev algorithm (k loop passes)."""
+                           k: int, dtype=np.float64) -> np.ndarray:
+    """z_cg = M^{-1} r_cg by the paper's Chebyshev algorithm (k loop passes).
+
+    ``dtype`` is the precision of the vectors (the scalars rho, theta, delta
+    stay FP64 and are rounded where they meet a vector); with float32 and a
+    float32 ``matvec`` the same steps run in single precision, which the tests
+    use only as a scale for the rounding error of an FP32 application."""
     theta = 0.5 * (lmax + lmin)
     delta = 0.5 * (lmax - lmin)
-    r_ch = np.array(r_cg, dtype=float, copy=True)
+    r_ch = np.array(r_cg, dtype=dtype, copy=True)
     sigma1 = theta / delta
     rho = 1.0 / sigma1
     d = r_ch / theta
@@ -146,12 +151,15 @@ def pcg(matvec: Matvec, b: np.ndarray, precond: Callable[[np.ndarray], np.ndarra
 
 
 def jacobi_chebyshev_precondition(A, r: np.ndarray, lmin: float, lmax: float,
-                                  k: int) -> np.ndarray:
+                                  k: int, dtype=np.float64) -> np.ndarray:
     """z = q_k(D^{-1} A) D^{-1} r: ``chebyshev_precondition`` on the system
     scaled by D^{-1} = diag(A)^{-1} (beyond the paper); lmin, lmax bound the
-    spectrum of D^{-1} A."""
+    spectrum of D^{-1} A.  ``dtype`` as for ``chebyshev_precondition`` (A, its
+    diagonal and r rounded to it first)."""
+    A = A.astype(dtype)
     d = A.diagonal()
-    return chebyshev_precondition(lambda v: (A @ v) / d, np.asarray(r, float) / d, lmin, lmax, k)
+    return chebyshev_precondition(lambda v: (A @ v) / d, np.asarray(r, dtype) / d, lmin, lmax, k,
+                                  dtype=dtype)
 
 
 def jacobi_spectral_bounds(A, v0: np.ndarray, m: int = 30,

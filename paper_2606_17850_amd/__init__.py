@@ -184,10 +184,10 @@ class Grid:
         return T_next, st.as_dict()
 
     def adjoint(self, T: torch.Tensor, dL_dT: torch.Tensor, opts=None, **kw):
-        """Returns (dL/dP [N], dL/dk [2 nz]: lateral then vertical, stats)."""
+        """Returns (dL/dP [N], dL/dk [nz] per layer conductivity, stats)."""
         o = opts if opts is not None else options(**kw)
         dP = self._new()
-        dk = torch.empty(2 * self.nz, dtype=torch.float64, device=self.device)
+        dk = torch.empty(self.nz, dtype=torch.float64, device=self.device)
         st = _lib.Stats()
         with torch.cuda.device(self.device):
             s = library().cuth_adjoint(self._h, self._vec(T, "T"), self._vec(dL_dT, "dL_dT"),
@@ -286,31 +286,25 @@ def solve_batch(grids: Sequence[Grid], P: Sequence[torch.Tensor], T: Optional[Se
 class ThermalSolve(torch.autograd.Function):
     """T = solve(P, k) with gradients by one adjoint solve.
 
-    forward(P, k_scale, grid_factory): k_scale is a [nz] tensor that multiplies
-    both the lateral and vertical conductivity of each layer; grid_factory(k)
-    returns a Grid built with those conductivities.
+    forward(P, k, grid_factory, opts): k is a [nz] tensor of layer
+    conductivities, each setting both the lateral and the vertical conductivity
+    of its layer (the lateral multiplier field, if any, stays fixed);
+    grid_factory(k) returns a Grid built with them.  backward returns the
+    library's dL/dP and its per-layer dL/dk unchanged.
     """
 
     @staticmethod
-    def forward(ctx, P, k_scale, grid_factory, opts=None):
-        g = grid_factory(k_scale.detach().cpu().numpy())
+    def forward(ctx, P, k, grid_factory, opts=None):
+        g = grid_factory(k.detach().cpu().numpy())
         T, _ = g.solve(P.contiguous(), opts=opts)
         ctx.grid = g
         ctx.opts = opts
-        ctx.k_base = k_scale.detach().cpu().numpy()
-        ctx.k_device = k_scale.device
+        ctx.k_device = k.device
         ctx.save_for_backward(T)
         return T
 
     @staticmethod
     def backward(ctx, gT):
         (T,) = ctx.saved_tensors
-        g = ctx.grid
-        dP, dk, _ = g.adjoint(T, gT.contiguous(), opts=ctx.opts)
-        nz = g.nz
-        # d/ds_l with k_lat[l] = s_l k0_lat[l], k_vert[l] = s_l k0_vert[l]
-        kl = torch.as_tensor(g._kl, device=dk.device)
-        kv = torch.as_tensor(g._kv, device=dk.device)
-        s = torch.as_tensor(ctx.k_base, device=dk.device, dtype=torch.float64)
-        dscale = (dk[:nz] * kl + dk[nz:] * kv) / s
-        return dP, dscale.to(ctx.k_device), None, None
+        dP, dk, _ = ctx.grid.adjoint(T, gT.contiguous(), opts=ctx.opts)
+        return dP, dk.to(ctx.k_device), None, None

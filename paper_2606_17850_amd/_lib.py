@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("outer_cycles", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
         ("stencil_applies", ctypes.c_int64), ("stop_reason", ctypes.c_int32),
-        ("cheb_degree", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+        ("cheb_degree", ctypes.c_int32), ("drift_stops", ctypes.c_int32),
+        ("stagnation_stops", ctypes.c_int32), ("rel_residual", ctypes.c_double),
         ("err_est", ctypes.c_double), ("setup_ms", ctypes.c_double),
         ("solve_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
         ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),

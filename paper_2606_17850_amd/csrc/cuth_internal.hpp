@@ -283,8 +283,8 @@ void launch_lanczos_div(int64_t n, int j, float *w, float *lz, const float *part
 // Adjoint gradient: per layer l, S_lat[l] = sum over lateral faces of
 // g (la_a - la_b)(th_a - th_b) and S_vert[l] = sum over the faces between l and
 // l+1 of (la_l - la_{l+1})(th_l - th_{l+1}); then
-// dL/dk_lat[l] = -fac_lat[l] S_lat[l],
-// dL/dk_vert[l] = -(fac_up[l] S_vert[l] + fac_dn[l] S_vert[l-1]).
+// dL_dk[l] = dL/dk_lat[l] + dL/dk_vert[l]
+//          = -(fac_lat[l] S_lat[l] + fac_up[l] S_vert[l] + fac_dn[l] S_vert[l-1]).
 void launch_adjoint(const OpView<double> &op, const double *lam, const double *T, double t_amb,
                     const double *fac, double *part, double *dL_dk, hipStream_t s);
 

@@ -1782,7 +1782,10 @@ __global__ __launch_bounds__(256) void k_adjoint_sums(OpView<double> op,
     }
 }
 
-// One workgroup: per-layer fixed-order sums of the partials, then the gradient.
+// One workgroup: per-layer fixed-order sums of the partials, then the gradient
+// with respect to each layer's conductivity: the lateral faces of layer l
+// (dg/dk = g / k_lat[l]) plus the vertical faces touching it (dg/dk_vert[l]
+// from the faces above and below), summed in that order.
 __global__ __launch_bounds__(256) void k_adjoint_finish(int nz, int np,
                                                         const double *__restrict__ part,
                                                         const double *__restrict__ fac,
@@ -1796,11 +1799,11 @@ __global__ __launch_bounds__(256) void k_adjoint_finish(int nz, int np,
     const int l = tid_lin();
     if (l < nz) {
         const double *fac_lat = fac, *fac_up = fac + nz, *fac_dn = fac + 2 * nz;
-        dk[l] = -fac_lat[l] * sums[l];
+        const double lat = fac_lat[l] * sums[l];
         double v = 0.0;
         if (l < nz - 1) v += fac_up[l] * sums[nz + l];
         if (l > 0) v += fac_dn[l] * sums[nz + l - 1];
-        dk[nz + l] = -v;
+        dk[l] = -(lat + v);
     }
 }
 

@@ -273,7 +273,7 @@ struct Problem {
     double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, true_rr = 0.0;
     int stop = 0;
     // results
-    int cycles = 0, cg_iters = 0, reason = 0;
+    int cycles = 0, cg_iters = 0, reason = 0, drift_stops = 0, stag_stops = 0;
     int64_t stencils = 0;
     double bytes = 0.0, relres = 0.0, err_est = 0.0;
     Status status;
@@ -634,6 +634,23 @@ void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, int cs, int pm, c
     }
 }
 
+// Host-side stop rule of an inner solve at a true-residual check (Section 4.4):
+// dev_done is the device's own stop (1 tolerance, 4 breakdown), tn the norm of
+// the true residual r_true = rhat - A x, dn the norm of r_true - r_low (r_low
+// the recursive residual), prev the true-residual norm of the previous check
+// (< 0 at the first).  Returns 0 to continue, 4 for a non-finite value, 2 for
+// drift (eq. switching c: dn >= 0.5 tn), 3 for stagnation (eq. switching b:
+// tn > 0.9 prev), 5 at the iteration limit.  Without tests (the fixed-FP32
+// baseline) only the device stop, non-finite values and the limit apply.
+int stop_rule(int dev_done, double tn, double dn, double prev, bool tests, bool at_limit) {
+    if (dev_done) return dev_done;
+    if (!std::isfinite(tn)) return 4;
+    if (tests && dn >= 0.5 * tn) return 2;
+    if (tests && prev >= 0.0 && tn > 0.9 * prev) return 3;
+    if (at_limit) return 5;
+    return 0;
+}
+
 // Inner PCG (Algorithm 1 with the Chebyshev preconditioner) on every problem
 // with p->inner set: A x = rhat from x = 0, r = rhat already written by the
 // residual kernel.  Chunks of `period` iterations run back to back for all
@@ -730,18 +747,12 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
             }
             p.true_rr = a;
             const double tn = std::sqrt(a);
-            int why = hs[n].done;
-            if (!why) {
-                if (!std::isfinite(tn)) why = 4;
-                else if (!p.fixed32 && std::sqrt(b) >= 0.5 * tn) why = 2;
-                else if (!p.fixed32 && p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
-                else if (it >= maxit) why = 5;
-                if (why) {
-                    // stop this problem on the device too (its launches exit early)
-                    hs[n].done = why;
-                    CUTH_HIP(hipMemcpyAsync(&Sel<T>::ds(E)[n].done, &hs[n].done, sizeof(int),
-                                            hipMemcpyHostToDevice, s));
-                }
+            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), p.true_prev, !p.fixed32, it >= maxit);
+            if (why && !hs[n].done) {
+                // stop this problem on the device too (its launches exit early)
+                hs[n].done = why;
+                CUTH_HIP(hipMemcpyAsync(&Sel<T>::ds(E)[n].done, &hs[n].done, sizeof(int),
+                                        hipMemcpyHostToDevice, s));
             }
             p.true_prev = tn;
             if (why) p.stop = why;
@@ -764,6 +775,8 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         const int precs_run = 1 + iters - (reason == 1 ? 1 : 0);
         p.cg_iters += iters;
         p.reason = reason;
+        p.drift_stops += reason == 2;
+        p.stag_stops += reason == 3;
         const int fused = fuse_for<T>(sh, p.pm);
         p.bytes += precs_run * by.precond(k, p.pm, fused) * N + iters * (by.dir() + by.update()) * N +
                    nchecks * by.check() * N;
@@ -1074,19 +1087,13 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
             }
             p.true_rr = a;
             const double tn = std::sqrt(a);
-            int why = hs[n].done;
-            if (!why) {
-                if (!std::isfinite(tn)) why = 4;
-                else if (std::sqrt(b) >= 0.5 * tn) why = 2;
-                else if (p.true_prev >= 0.0 && tn > 0.9 * p.true_prev) why = 3;
-                else if (it >= maxit) why = 5;
-                if (why) {
-                    hs[n].done = why;
-                    CUTH_HIP(hipMemcpyAsync(&E.st64[n].done, &hs[n].done, sizeof(int),
-                                            hipMemcpyHostToDevice, s));
-                    CUTH_HIP(hipMemcpyAsync(&E.st32[n].done, &hs[n].done, sizeof(int),
-                                            hipMemcpyHostToDevice, s));
-                }
+            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), p.true_prev, true, it >= maxit);
+            if (why && !hs[n].done) {
+                hs[n].done = why;
+                CUTH_HIP(hipMemcpyAsync(&E.st64[n].done, &hs[n].done, sizeof(int),
+                                        hipMemcpyHostToDevice, s));
+                CUTH_HIP(hipMemcpyAsync(&E.st32[n].done, &hs[n].done, sizeof(int),
+                                        hipMemcpyHostToDevice, s));
             }
             p.true_prev = tn;
             if (why) p.stop = why;
@@ -1106,6 +1113,8 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
         const double dir64 = 32.0 + (p.g->per_cell ? (p.early ? 8.0 : 16.0) : 0.0);
         p.cg_iters += iters;
         p.reason = reason;
+        p.drift_stops += reason == 2;
+        p.stag_stops += reason == 3;
         p.bytes += precs_run * (b32.precond(k, p.pm, fuse_for<float>(sh32, p.pm)) + 20.0) * N + iters * (dir64 + b64.update() + 4.0) * N +
                    nchecks * b64.check() * N;
         p.stencils += (int64_t)precs_run * (k - 1) + iters + nchecks;
@@ -1723,6 +1732,8 @@ void fill_stats(const Problem &p, cuth_stats *stats, float ms_setup, float ms_so
     stats->cg_iters = p.cg_iters;
     stats->stencil_applies = p.stencils;
     stats->stop_reason = p.reason;
+    stats->drift_stops = p.drift_stops;
+    stats->stagnation_stops = p.stag_stops;
     stats->rel_residual = p.relres;
     stats->err_est = p.err_est;
     stats->setup_ms = ms_setup;

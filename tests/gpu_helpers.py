@@ -43,3 +43,25 @@ def rise_err(T, ref, t_amb):
 
 def say(msg: str):
     print(msg, flush=True)
+
+
+def fp32_cheb_bar(A, r, lmin, lmax, k, ref, jacobi=False):
+    """Error bar of an FP32 Chebyshev application against the FP64 oracle's
+    ``ref`` (inf-norm).  The scale is the oracle's own spread: the paper's
+    listing run with FP32 vectors and the FP32-rounded matrix, against the same
+    listing in FP64.  The solver evaluates the polynomial in the two-term form,
+    whose rounding errors propagate through a three-term recurrence; on the
+    interval its amplification is bounded by Chebyshev polynomials of the
+    second kind, which grow at most linearly in the degree.  Hence the bar
+    4 max(k, 4) times the spread (floored at one FP32 unit roundoff of the
+    scale)."""
+    from oracle import krylov
+    if jacobi:
+        ref32 = krylov.jacobi_chebyshev_precondition(A, r, lmin, lmax, k, dtype=np.float32)
+    else:
+        A32 = A.astype(np.float32)
+        ref32 = krylov.chebyshev_precondition(lambda v: A32 @ v, np.asarray(r, np.float32),
+                                              lmin, lmax, k, dtype=np.float32)
+    scale = float(np.abs(ref).max())
+    spread = max(float(np.abs(ref32.astype(np.float64) - ref).max()), 2.0 ** -24 * scale)
+    return 4.0 * max(k, 4) * spread

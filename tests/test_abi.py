@@ -125,3 +125,21 @@ def test_precision_names_match_header(lib):
     assert cuth.options("fp64").precision == enum["CUTH_FP64"]
     with pytest.raises(ValueError):
         cuth.options("fp16")
+
+
+def _struct_fields(name):
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    return [f for decl in body.split(";") if decl.strip()
+            for f in re.findall(r"\*?\s*([a-z_0-9]+)\s*(?:,|$)", decl.strip().split(None, 1)[1])]
+
+
+def test_ctypes_mirrors_match_header_structs():
+    """Field names and order of the ctypes mirrors equal the header's structs
+    (a field added on one side only would shift every later field)."""
+    from paper_2606_17850_amd import _lib
+    for cls, name in ((_lib.Stats, "cuth_stats"), (_lib.Options, "cuth_options"),
+                      (_lib.GridDesc, "cuth_grid_desc")):
+        assert [f for f, _ in cls._fields_] == _struct_fields(name), name
+    assert ctypes.sizeof(_lib.Stats) == 88

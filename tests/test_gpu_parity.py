@@ -6,6 +6,8 @@ Tolerances ("Parity bar"):
 * FP32 operator: <= 2e-6 * (|A| |x|)_i (inputs rounded to FP32, 7 terms);
 * FP64 Chebyshev application: <= 1e-10 * ||z||_inf (29 sweeps of rounding
   amplified by the polynomial's norm);
+* FP32 Chebyshev application: <= 4 max(k, 4) times the spread between the
+  oracle's listing in FP32 and in FP64 (gpu_helpers.fp32_cheb_bar);
 * solves: plain FP64 <= 1e-10 and mixed <= 1e-8 rise-relative inf-norm error.
 """
 
@@ -15,7 +17,7 @@ import torch
 
 import workloads as w
 from oracle import assembly, cpu_cg, direct, krylov, transient
-from tests.gpu_helpers import dev, grid_of, ragged_stack, rise_err, say, t32, t64
+from tests.gpu_helpers import dev, fp32_cheb_bar, grid_of, ragged_stack, rise_err, say, t32, t64
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +93,7 @@ def test_chebyshev_matches_oracle(case, degree):
     assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
     # FP32: same polynomial in single precision
     z32 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
-    assert np.abs(z32 - ref).max() <= 2e-3 * np.abs(ref).max()
+    assert np.abs(z32 - ref).max() <= fp32_cheb_bar(A, r, lmin, lmax, degree, ref)
     g.close()
 
 
@@ -112,6 +114,7 @@ def test_chebyshev_jacobi_matches_oracle(monkeypatch, case, degree):
     z = g.precond_apply(t64(r), lo, hi, degree, preconditioner="chebyshev_jacobi").cpu().numpy()
     assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
     z_single = None
+    bar32 = fp32_cheb_bar(A, r, lo, hi, degree, ref, jacobi=True)
     for env in ({"CUTH_FUSE": "0"}, {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8", "CUTH_FUSE3": "0"},
                 {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "1,1", "CUTH_FUSE3": "0"},
                 {"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "2,8", "CUTH_FUSE3": "1", "CUTH_FUSE3_SHAPE": "4,8"},
@@ -120,7 +123,7 @@ def test_chebyshev_jacobi_matches_oracle(monkeypatch, case, degree):
             monkeypatch.setenv(k_, v_)
         z32 = g.precond_apply(t32(r), lo, hi, degree,
                               preconditioner="chebyshev_jacobi").cpu().numpy().astype(np.float64)
-        assert np.abs(z32 - ref).max() <= 2e-3 * np.abs(ref).max(), env
+        assert np.abs(z32 - ref).max() <= bar32, env
         if z_single is None:
             z_single = z32
         else:
@@ -363,7 +366,7 @@ def test_chebyshev_fp16_coefficients(degree):
     ref = krylov.chebyshev_precondition(lambda v: A16 @ v, r, lmin, lmax, degree)
     g = grid_of(st)
     z = g.precond_apply(t32(r), lmin, lmax, degree, fp16_coef=True).cpu().numpy().astype(np.float64)
-    assert np.abs(z - ref).max() <= 2e-3 * np.abs(ref).max()
+    assert np.abs(z - ref).max() <= fp32_cheb_bar(A16, r, lmin, lmax, degree, ref)
     g.close()
 
 
@@ -633,14 +636,15 @@ def test_fused_sweep_pairs(monkeypatch, case, shape):
         monkeypatch.setenv("CUTH_FUSE", "1")
         monkeypatch.setenv("CUTH_FUSE_SHAPE", shape)
         z2 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
-        assert np.abs(z2 - ref).max() <= 2e-3 * np.abs(ref).max()
+        assert np.abs(z2 - ref).max() <= fp32_cheb_bar(A, r, lmin, lmax, degree, ref)
         # same arithmetic in the same order as two single sweeps
         assert np.abs(z2 - z1).max() <= 1e-6 * np.abs(z1).max()
         if A16 is not None:
             # and with the FP16-stored conductances
             ref16 = krylov.chebyshev_precondition(lambda v: A16 @ v, r, lmin, lmax, degree)
             z3 = g.precond_apply(t32(r), lmin, lmax, degree, fp16_coef=True).cpu().numpy()
-            assert np.abs(z3.astype(np.float64) - ref16).max() <= 2e-3 * np.abs(ref16).max()
+            assert np.abs(z3.astype(np.float64) - ref16).max() <= \
+                fp32_cheb_bar(A16, r, lmin, lmax, degree, ref16)
     g.close()
 
 
@@ -672,7 +676,7 @@ def test_fused_sweep_triples(monkeypatch, case, shape):
         monkeypatch.setenv("CUTH_FUSE3_SHAPE", shape)
         z2 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
         monkeypatch.delenv("CUTH_FUSE3")
-        assert np.abs(z2 - ref).max() <= 2e-3 * np.abs(ref).max()
+        assert np.abs(z2 - ref).max() <= fp32_cheb_bar(A, r, lmin, lmax, degree, ref)
         # same arithmetic in the same order as three single sweeps
         assert np.abs(z2 - z1).max() <= 1e-6 * np.abs(z1).max()
         if A16 is not None:
@@ -680,7 +684,8 @@ def test_fused_sweep_triples(monkeypatch, case, shape):
             ref16 = krylov.chebyshev_precondition(lambda v: A16 @ v, r, lmin, lmax, degree)
             z3 = g.precond_apply(t32(r), lmin, lmax, degree, fp16_coef=True).cpu().numpy()
             monkeypatch.delenv("CUTH_FUSE3")
-            assert np.abs(z3.astype(np.float64) - ref16).max() <= 2e-3 * np.abs(ref16).max()
+            assert np.abs(z3.astype(np.float64) - ref16).max() <= \
+                fp32_cheb_bar(A16, r, lmin, lmax, degree, ref16)
     g.close()
 
 
@@ -713,7 +718,7 @@ def test_fused_triples_shallow_and_narrow(monkeypatch, dims, shape):
         z3 = g.precond_apply(t32(r), lmin, lmax, degree).cpu().numpy().astype(np.float64)
         monkeypatch.delenv("CUTH_FUSE3")
         assert np.abs(z3 - z1).max() <= 1e-6 * np.abs(z1).max()
-        assert np.abs(z3 - ref).max() <= 2e-3 * np.abs(ref).max()
+        assert np.abs(z3 - ref).max() <= fp32_cheb_bar(A, r, lmin, lmax, degree, ref)
     g.close()
 
 
@@ -896,6 +901,62 @@ def test_invalid_and_failure_paths():
     assert e.value.stats is not None and e.value.stats["cg_iters"] >= 1
     g.close()
     g2.close()
+
+
+def test_inner_stop_on_drift():
+    """Eq. switching (c), drift: FP64 Chebyshev-PCG asked for an unattainable
+    relative residual (1e-300).  Its recursive residual keeps falling
+    geometrically while the true residual rhat - A x settles at the FP64
+    rounding floor, so every inner solve ends on ||r_true - r_low|| >=
+    0.5 ||r_true|| (checked every 5 iterations).  The hot restart after it
+    cannot halve the true residual, so the call reports NOT_CONVERGED with the
+    best iterate, which meets the FP64 bar against the oracle."""
+    import paper_2606_17850_amd as cuth
+    say("stop rule: drift")
+    st, P = w.config0()
+    g = grid_of(st)
+    T = torch.empty(st.n, dtype=torch.float64, device=dev())
+    with pytest.raises(cuth.CuthError) as e:
+        g.solve(t64(P), T=T, precision="fp64", tol=1e-300, check_period=5, max_inner=5000)
+    s = e.value.stats
+    say(f"  {s}")
+    assert e.value.status == cuth._lib.CUTH_E_NOT_CONVERGED
+    assert s["stop_reason"] == 2
+    assert s["drift_stops"] == s["outer_cycles"] >= 1
+    assert s["stagnation_stops"] == 0
+    assert rise_err(T.cpu().numpy(), _ref_steady(st, P), st.t_amb) <= 1e-10
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_inner_stop_on_stagnation(prec):
+    """Eq. switching (b), stagnation: plain CG (no preconditioner) with the true
+    residual checked after every iteration.  On this stack plain CG's residual
+    norm does not fall by a tenth from one iteration to the next (it first
+    rises several-fold), so every inner solve ends at its second check on
+    ||r_true|| > 0.9 ||r_true^prev||, and the refinement gives up
+    (NOT_CONVERGED).  The best iterate is returned: the relative residual the
+    call reports is that of the returned T, recomputed by the oracle."""
+    import paper_2606_17850_amd as cuth
+    say(f"stop rule: stagnation {prec}")
+    st, P = w.config0()
+    A = assembly.assemble(st)
+    g = grid_of(st)
+    T = torch.empty(st.n, dtype=torch.float64, device=dev())
+    with pytest.raises(cuth.CuthError) as e:
+        g.solve(t64(P), T=T, precision=prec, preconditioner="none", check_period=1, max_outer=4)
+    s = e.value.stats
+    say(f"  {s}")
+    assert e.value.status == cuth._lib.CUTH_E_NOT_CONVERGED
+    assert s["stop_reason"] == 3
+    assert s["stagnation_stops"] == s["outer_cycles"] >= 1
+    assert s["drift_stops"] == 0
+    assert s["cg_iters"] == 2 * s["outer_cycles"]
+    th = T.cpu().numpy() - st.t_amb
+    b = P.ravel()
+    relres = np.linalg.norm(b - A @ th) / np.linalg.norm(b)
+    assert relres == pytest.approx(s["rel_residual"], rel=1e-6)
+    g.close()
 
 
 def test_run_twice_bitwise_identical():

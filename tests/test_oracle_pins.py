@@ -250,6 +250,30 @@ def test_metamorphic(c4s):
     np.testing.assert_allclose(ths * s, th, rtol=1e-10)
 
 
+def test_separable_steps_match_lu_and_single_steps():
+    """The trajectory stepper (operator eliminated once, right-hand side formed
+    in the DCT basis) against a chain of SuperLU steps of the assembled
+    transient matrix, over six steps with a floorplan switch; and one stepper
+    step against the plain separable step."""
+    st = w.config2_stack(24, 17)
+    dt = 1e-4
+    maps = [w.config2_power(st, f) for f in (0, 3)]
+    A = assembly.assemble(st, dt=dt)
+    stp = transient.SeparableSteps(st, dt)
+    th_lu = np.zeros(st.n)
+    th_hat = stp.to_hat(np.zeros(st.n))
+    maps_hat = [stp.to_hat(m) for m in maps]
+    for s in range(6):
+        f = s // 3
+        th_lu = transient.step(st, maps[f], th_lu, dt, solve=direct.solve_splu, A=A)
+        th_hat = stp.step_hat(maps_hat[f], th_hat)
+        got = stp.from_hat(th_hat)
+        assert np.abs(got - th_lu).max() <= 1e-12 * np.abs(th_lu).max()
+    one = stp.step(maps[1], th_lu)
+    ref = transient.step(st, maps[1], th_lu, dt)
+    assert np.abs(one - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_transient_converges_to_steady():
     st = w.uniform_stack(6, 6, ["Si", "BEOL", "TIM", "Cu"])
     rng = np.random.default_rng(4)
@@ -431,6 +455,20 @@ def test_adjoint_against_perturbation_fd():
                 g = gr.dk_vert[l]
             fd = (L(tp) - L(tm)) / (2 * h)
             assert fd == pytest.approx(g, rel=1e-5, abs=1e-9 * abs(gr.dk_layer).max())
+    # dL/dk per layer (the library's output): both conductivities of layer l
+    # moved by the same step in one perturbation solve
+    for l in range(st.nz):
+        h = 1e-4 * st.k_lat[l]
+        klp, klm = st.k_lat.copy(), st.k_lat.copy()
+        kvp, kvm = st.k_vert.copy(), st.k_vert.copy()
+        klp[l] += h
+        kvp[l] += h
+        klm[l] -= h
+        kvm[l] -= h
+        tp = _perturbed_theta(st, th, A, kl=klp, kv=kvp)
+        tm = _perturbed_theta(st, th, A, kl=klm, kv=kvm)
+        fd = (L(tp) - L(tm)) / (2 * h)
+        assert fd == pytest.approx(gr.dk_layer[l], rel=1e-5, abs=1e-9 * abs(gr.dk_layer).max())
 
 
 def test_adjoint_special_cases():
