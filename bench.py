@@ -1,23 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark of the layered-stencil PCG on one MI355X.
 
-Workload: the 512 x 512 x 16 layered stack with lognormal lateral conductivity
-(4,194,304 unknowns; block floorplans + hotspots on three dies), solved to 1e-8
-relative temperature-rise error by the mixed FP32-inner / FP64-refined
-Chebyshev-PCG, next to the plain FP64 Chebyshev-PCG on the same grid.
+Headline workload: the 512 x 512 x 16 layered stack with lognormal lateral
+conductivity (4,194,304 unknowns; block floorplans + hotspots on three dies),
+solved to 1e-8 relative temperature-rise error by the mixed FP32-inner /
+FP64-refined Chebyshev-PCG, next to the plain FP64 Chebyshev-PCG on the same
+grid.  A timed step is one complete mixed solve from a zero initial guess,
+including the Lanczos spectral-bound setup (the cached bounds are dropped before
+every step); the coefficient planes are built once when the grid is created,
+and inputs are resident in HBM before timing starts.
 
-A timed step is one complete mixed solve from a zero initial guess, including
-the Lanczos spectral-bound setup (the cached bounds are dropped before every
-step); the coefficient planes are built once when the grid is created, inputs
-are resident in HBM before timing starts.
+value = algorithmic bytes of the solve phase / wall time of the step (GB/s).
 
-value  = algorithmic bytes of the solve phase / wall time of the step (GB/s).
-roofline = the dominant kernel, the general Chebyshev sweep: its algorithmic
-bytes per launch (24 B per unknown: z_j, z_{j-1}, r, z_{j+1}, gx, gy in FP32)
-over its average duration from HIP events recorded on the library's stream
-during the timed steps.  traffic = HBM bytes per launch from rocprofv3
-FETCH_SIZE + WRITE_SIZE counters (profiles/), when they were taken on the
-current kernel source; else null.
+roofline = the general Chebyshev sweep k_cheb_b, the kernel of the method as
+the paper applies it (one sweep per HBM pass, 24 B per unknown: z_j, z_{j-1},
+r, z_{j+1}, gx, gy in FP32), timed in the same solve with fused launches
+switched off; its average duration comes from HIP events the library records
+on its own stream around each back-to-back run of those launches.
+roofline_blocked = the launch that carries the sweeps in the default solve
+(fused triples of sweeps where the tuner picks them), with its own bytes
+(28 B per unknown for three sweeps: z_{j+1} stays on chip) and the bytes of
+the three single sweeps it replaces.  traffic = HBM bytes per launch from
+rocprofv3 FETCH_SIZE + WRITE_SIZE counters (profiles/), when they were taken on
+the current kernel source; else null.
+
+workloads = the other configurations, timed in the same run: the 64x64x8
+stack (time to tolerance), the 1024x1024x20 backward-Euler steps (per step,
+across a floorplan switch, with the roofline of its matrix-free sweep), the
+batch of 64 uneven stacks x 4 power maps (one batched solve), and the adjoint
+gradient on the 512x512x16 stack (forward + adjoint).
+
+cpu_baseline = the CPU oracle's FP64 CSR Jacobi-CG on the 512x512x16 system
+(C + OpenMP): all host cores to relative residual 1e-11, and one core over a
+fixed iteration sample.
 """
 
 from __future__ import annotations
@@ -26,6 +41,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -34,17 +51,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "PCG loop HBM GB/s + time to 1e-8 rel. error, mixed vs plain FP64, 1 GPU"
 # the timed general sweep launch by its width (cuth_profile_read's `fused`:
 # sweeps per launch minus one): profile summary stem and kernel description
 SWEEP_KERNELS = {0: ("cheb_sweep", "k_cheb_b (general Chebyshev sweep, FP32, {})"),
                  1: ("cheb_pair", "k_cheb2_b (fused pair of general Chebyshev sweeps, FP32, {})"),
                  2: ("cheb_triple", "k_cheb3_b (fused triple of general Chebyshev sweeps, FP32, {})")}
-
-
-# counter summaries of the dominant launch of the 512x512x16 bench (whichever
-# sweep launch the library ran)
-def counters_file(fused: int) -> str:
-    return os.path.join(ROOT, "profiles", SWEEP_KERNELS[fused][0] + "_512x512x16_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_17850_amd", "csrc", "kernels.hip")
 
 
@@ -53,10 +65,11 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(fused: int):
-    """HBM bytes per launch of the sweep kernel from committed counter runs."""
+def traffic_from_profiles(stem: str, grid: str):
+    """HBM bytes per launch of a sweep kernel from committed counter runs
+    (profiles/<stem>_<grid>_counters.json), if taken on the current source."""
     try:
-        with open(counters_file(fused)) as f:
+        with open(os.path.join(ROOT, "profiles", f"{stem}_{grid}_counters.json")) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
@@ -65,53 +78,160 @@ def traffic_from_profiles(fused: int):
     return c.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(stack, P, iters: int):
-    """The CPU oracle (FP64 CSR Jacobi-CG, C + OpenMP) on the same system for a
-    bounded number of iterations; GB/s of its own algorithmic bytes."""
-    import numpy as np
+def with_env(env, fn):
+    prev = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return fn()
+    finally:
+        for k, v in prev.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def roofline_of(prof, kind: str, grid: str, sweep_bytes_per_unknown: float, unknowns: int):
+    """Roofline object of a profiled run (cuth_profile_read)."""
+    if not prof or not prof["launches"]:
+        return None
+    avg_ms = prof["total_ms"] / prof["launches"]
+    by = prof["bytes_per_launch"]
+    ach = by / (avg_ms / 1e3) / 1e9
+    width = prof["fused"] + 1
+    out = {"bound": "hbm", "kernel": SWEEP_KERNELS[prof["fused"]][1].format(kind),
+           "achieved": round(ach, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(ach / PEAK_HBM_GBS, 4),
+           "traffic": traffic_from_profiles(SWEEP_KERNELS[prof["fused"]][0], grid),
+           "bytes_per_launch": by, "avg_launch_us": round(avg_ms * 1e3, 3),
+           "timed_launches": prof["launches"], "sweeps_per_launch": width}
+    if width > 1:
+        # what the same sweeps move one per HBM pass
+        eq = width * sweep_bytes_per_unknown * unknowns
+        out["single_sweep_equivalent"] = {
+            "bytes_per_launch": eq, "achieved": round(eq / (avg_ms / 1e3) / 1e9, 2),
+            "frac": round(eq / (avg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+            "us_per_sweep": round(avg_ms * 1e3 / width, 3)}
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(stack, P, one_core_iters: int):
+    """The CPU oracle (FP64 CSR Jacobi-CG, C + OpenMP) on the same system: all
+    host cores from a zero guess to relative residual 1e-11, then one core over
+    a fixed number of iterations; GB/s of its own algorithmic bytes."""
     from oracle import assembly, cpu_cg
 
-    A = assembly.assemble(stack)
-    b = P.ravel()
     t0 = time.perf_counter()
-    _, it, _ = cpu_cg.jacobi_cg(A, b, rtol=1e-300, maxit=iters)
-    dt = time.perf_counter() - t0
+    A = assembly.assemble(stack)
+    asm_s = time.perf_counter() - t0
+    b = P.ravel()
     n = A.shape[0]
     # per iteration: CSR SpMV (8 B value + 4 B index per nonzero, 8 B row
     # pointer, x and y) + the vector updates and dots (about 12 vectors)
     per_it = A.nnz * 12 + n * 8 * (1 + 2) + n * 8 * 12
+    cores = cpu_cg.threads()
+    t0 = time.perf_counter()
+    _, it, relres = cpu_cg.jacobi_cg(A, b, rtol=1e-11, maxit=50000)
+    tol_s = time.perf_counter() - t0
+    cpu_cg.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, it1, _ = cpu_cg.jacobi_cg(A, b, rtol=1e-300, maxit=one_core_iters)
+        one_s = time.perf_counter() - t0
+    finally:
+        cpu_cg.set_threads(cores)
     return {
-        "value": round(per_it * it / dt / 1e9, 3),
+        "value": round(per_it * it / tol_s / 1e9, 3),
         "unit": "GB/s",
-        "cores": cpu_cg.threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{it} iterations of the oracle's FP64 CSR Jacobi-CG on the same "
-                   f"{stack.nx}x{stack.ny}x{stack.nz} system ({n} unknowns) in {dt:.1f} s "
-                   f"= {n * it / dt:.3e} unknown-iterations/s; assembly not timed"),
+        "sample": (f"the oracle's FP64 CSR Jacobi-CG on the same {stack.nx}x{stack.ny}x{stack.nz} "
+                   f"system ({n} unknowns) from a zero guess to relative residual 1e-11: {it} "
+                   f"iterations in {tol_s:.2f} s on {cores} threads = "
+                   f"{n * it / tol_s:.3e} unknown-iterations/s; assembly {asm_s:.2f} s, not timed"),
+        "time_to_tol_s": round(tol_s, 3),
+        "iterations": it,
+        "true_rel_residual": relres,
+        "cpu_model": cpu_model(),
+        "one_core": {"value": round(per_it * it1 / one_s / 1e9, 3), "unit": "GB/s",
+                     "unknown_iterations_per_s": round(n * it1 / one_s, 1),
+                     "sample": f"{it1} iterations on 1 thread in {one_s:.2f} s",
+                     "est_time_to_tol_s": round(one_s / it1 * it, 2)},
     }
 
 
-def _base(args, metric_workload: str, unknowns: int, value: float, per_step: float) -> dict:
-    return {
-        "metric": "PCG loop HBM GB/s + time to 1e-8 rel. error, mixed vs plain FP64, 1 GPU",
-        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32-inner/f64-outer",
-        "data": "synthetic", "config": {"workload": metric_workload, "unknowns": unknowns,
-                                        "cheb_degree": 30},
-    }
+# ------------------------------------------------------------------ workloads
+def solve_timer(g, Pt, T, torch):
+    """Timed steady solves with the Lanczos setup redone every time."""
+    def step(opts):
+        g.reset_bounds()
+        _, st = g.solve(Pt, T, opts=opts)
+        return st
+
+    def timed(opts, k):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stats = []
+        e0.record()
+        h0 = time.perf_counter()
+        for _ in range(k):
+            stats.append(step(opts))
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - h0) * 1e3
+        return max(e0.elapsed_time(e1), wall), stats
+
+    return step, timed
 
 
-def bench_transient(args) -> int:
-    """1024x1024x20 backward-Euler steps (dt = 1e-4 s, warm start from T_n, power
-    map switching every 20 steps among 5 floorplans); a step is one time step."""
-    import torch
+def workload_c0(cuth, w, torch, dev):
+    """64x64x8: mixed and FP64 time to tolerance (median of 10 after 2 warm-ups)."""
+    st, P = w.config0()
+    g = cuth.Grid.from_stack(st, device=dev)
+    Pt = torch.as_tensor(P.ravel(), device=dev)
+    T = torch.empty_like(Pt)
+    step, _ = solve_timer(g, Pt, T, torch)
+    out = {"workload": "steady 64x64x8 uniform stack, 2 dies, 0.5 W/mm^2 + 4 hotspots per die",
+           "unknowns": st.n}
+    res = {}
+    for name in ("mixed", "fp64"):
+        o = cuth.options(name)
+        for _ in range(2):
+            step(o)
+        times, stats = [], None
+        for _ in range(10):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stats = step(o)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        times.sort()
+        res[name] = T.clone()
+        out[f"{name}_ms"] = round(0.5 * (times[4] + times[5]), 3)
+        out[f"{name}_cg_iters"] = stats["cg_iters"]
+    rise = float((res["fp64"] - st.t_amb).abs().max())
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms"] / out["mixed_ms"], 3)
+    out["mixed_vs_fp64_max_rise_rel_diff"] = float((res["mixed"] - res["fp64"]).abs().max()) / rise
+    g.close()
+    return out
 
-    import paper_2606_17850_amd as cuth
-    import workloads as w
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
+def workload_c2(cuth, w, torch, dev, nsteps: int, warmup: int, extra_schemes: bool):
+    """1024x1024x20 backward-Euler steps (dt = 1e-4 s, warm start from T_n, the
+    power map switching every 20 steps among 5 floorplans); a step is one time
+    step from T = T_amb after the warm-up steps."""
     st = w.config2_stack()
     maps = {}
 
@@ -124,11 +244,11 @@ def bench_transient(args) -> int:
     g = cuth.Grid.from_stack(st, device=dev)
     dt = 1e-4
 
-    def run(prec, nsteps, profile, degree=30, pc="chebyshev"):
+    def run(prec, profile, degree=30, pc="chebyshev"):
         T = torch.full((st.n,), st.t_amb, dtype=torch.float64, device=dev)
         T2 = torch.empty_like(T)
         o = cuth.options(prec, cheb_degree=degree, preconditioner=pc)
-        for s in range(args.warmup):
+        for s in range(warmup):
             g.transient_step(dt, pmap(s), T, T2, opts=o)
         T.fill_(st.t_amb)
         if profile:
@@ -147,42 +267,318 @@ def bench_transient(args) -> int:
             g.profile_enable(False)
         return ms, stats, prof, T
 
-    ms, stats, prof, Tm = run("mixed", args.steps, True)
-    ms64, stats64, _, T64 = run("fp64", args.steps, False)
-    # the degree chosen from the spectral interval instead of 30 (not the paper's)
-    msa, statsa, _, Ta = run("mixed", args.steps, False, "auto")
-    # and the Jacobi-scaled Chebyshev preconditioner with that rule (not the paper's)
-    msj, statsj, _, Tj = run("mixed", args.steps, False, "auto", "chebyshev_jacobi")
+    ms, stats, prof_b, Tm = run("mixed", True)
+    ms64, stats64, _, T64 = run("fp64", False)
+    ms1, stats1, prof_1, T1 = with_env({"CUTH_FUSE": "0"}, lambda: run("mixed", True))
     rise = float((T64 - st.t_amb).abs().max())
-    per = ms / args.steps
-    value = sum(s["alg_bytes"] for s in stats) / (ms / 1e3) / 1e9
-    avg = prof["total_ms"] / max(prof["launches"], 1)
-    ach = prof["bytes_per_launch"] / (avg / 1e3) / 1e9 if prof["launches"] else None
-    out = _base(args, "transient 1024x1024x20 layered stack (4 dies), dt = 1e-4 s, warm start, "
-                      "floorplan switch every 20 steps; mixed FP32/FP64 per step to 1e-8",
-                st.n, value, per)
-    out["time_to_tol_ms"] = {"mixed": round(per, 3), "fp64": round(ms64 / args.steps, 3),
-                             "speedup_mixed_vs_fp64": round(ms64 / ms, 3),
-                             "mixed_auto_degree": round(msa / args.steps, 3),
-                             "speedup_mixed_auto_degree_vs_fp64": round(ms64 / msa, 3),
-                             "mixed_chebyshev_jacobi_auto_degree": round(msj / args.steps, 3),
-                             "speedup_mixed_chebyshev_jacobi_auto_degree_vs_fp64": round(ms64 / msj, 3)}
-    out["solve_detail"] = {"mixed_cg_iters_per_step": [s["cg_iters"] for s in stats][:10],
-                           "fp64_cg_iters_per_step": [s["cg_iters"] for s in stats64][:10],
-                           "mixed_vs_fp64_max_rise_rel_diff": float((Tm - T64).abs().max()) / rise,
-                           "auto_degree": statsa[-1]["cheb_degree"],
-                           "auto_degree_cg_iters_per_step": [s["cg_iters"] for s in statsa][:10],
-                           "auto_degree_vs_fp64_max_rise_rel_diff": float((Ta - T64).abs().max()) / rise,
-                           "chebyshev_jacobi_degree": statsj[-1]["cheb_degree"],
-                           "chebyshev_jacobi_cg_iters_per_step": [s["cg_iters"] for s in statsj][:10],
-                           "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": float((Tj - T64).abs().max()) / rise}
-    out["roofline"] = {"bound": "hbm",
-                       "kernel": SWEEP_KERNELS[prof["fused"]][1].format("matrix-free"),
-                       "achieved": round(ach, 2) if ach else None, "peak": PEAK_HBM_GBS,
-                       "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4) if ach else None,
-                       "traffic": None, "bytes_per_launch": prof["bytes_per_launch"],
-                       "avg_launch_us": round(avg * 1e3, 3), "timed_launches": prof["launches"]}
+    per = ms / nsteps
+    out = {"workload": "transient 1024x1024x20 layered stack (4 dies), dt = 1e-4 s, warm start, "
+                       f"floorplan switch every 20 steps; {nsteps} steps from T_amb crossing "
+                       f"{len({w.config2_floorplan_index(s) for s in range(nsteps)}) - 1} switch(es)",
+           "unknowns": st.n, "steps": nsteps, "warmup": warmup,
+           "value": round(sum(s["alg_bytes"] for s in stats) / (ms / 1e3) / 1e9, 2), "unit": "GB/s",
+           "mixed_ms_per_step": round(per, 3), "fp64_ms_per_step": round(ms64 / nsteps, 3),
+           "speedup_mixed_vs_fp64": round(ms64 / ms, 3),
+           "mixed_single_sweeps_ms_per_step": round(ms1 / nsteps, 3),
+           "mixed_cg_iters_per_step": [s["cg_iters"] for s in stats],
+           "fp64_cg_iters_per_step": [s["cg_iters"] for s in stats64],
+           "mixed_vs_fp64_max_rise_rel_diff": float((Tm - T64).abs().max()) / rise,
+           "single_sweeps_vs_fp64_max_rise_rel_diff": float((T1 - T64).abs().max()) / rise,
+           "roofline": roofline_of(prof_1, "matrix-free", "1024x1024x20", 16.0, st.n),
+           "roofline_blocked": roofline_of(prof_b, "matrix-free", "1024x1024x20", 16.0, st.n)}
+    if extra_schemes:
+        # the degree chosen from the spectral interval, and with it the
+        # Jacobi-scaled Chebyshev preconditioner (neither is the paper's)
+        msa, statsa, _, _ = run("mixed", False, "auto")
+        msj, statsj, _, _ = run("mixed", False, "auto", "chebyshev_jacobi")
+        out["mixed_auto_degree_ms_per_step"] = round(msa / nsteps, 3)
+        out["auto_degree"] = statsa[-1]["cheb_degree"]
+        out["mixed_chebyshev_jacobi_auto_degree_ms_per_step"] = round(msj / nsteps, 3)
+        out["chebyshev_jacobi_degree"] = statsj[-1]["cheb_degree"]
     g.close()
+    return out
+
+
+def workload_c3(cuth, w, torch, dev, steps: int, warmup: int):
+    """64 uneven stacks x 4 power maps in one batched mixed solve per step (the
+    warm-up solves include the launch-shape tuning and the pool allocation)."""
+    import numpy as np
+    items = w.config3()
+    grids = [cuth.Grid.from_stack(st, device=dev) for st, _ in items]
+    P = [torch.as_tensor(np.concatenate([m.ravel() for m in maps]), device=dev) for _, maps in items]
+    T = [torch.empty_like(p) for p in P]
+    o = cuth.options("mixed")
+    for _ in range(max(warmup, 1)):
+        cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, stats = cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    per = ms / steps
+    unknowns = sum(st.n for st, _ in items)
+    its = [s["cg_iters"] for s in stats]
+    out = {"workload": "batch of 64 uneven stacks (edge 128-384, 8-16 layers) x 4 power maps, "
+                       "one batched mixed solve to 1e-8",
+           "unknowns": unknowns, "unknown_rhs": unknowns * 4, "problems": len(stats),
+           "steps": steps, "ms_per_solve": round(per, 3),
+           "value": round(sum(s["alg_bytes"] for s in stats) / (per / 1e3) / 1e9, 2), "unit": "GB/s",
+           "frac_of_peak": round(sum(s["alg_bytes"] for s in stats) / (per / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+           "cg_iters_min": min(its), "cg_iters_max": max(its),
+           "cg_iters_total": int(sum(its))}
+    for gg in grids:
+        gg.close()
+    return out
+
+
+def workload_c4(cuth, w, torch, dev, g, stack, Pt):
+    """Adjoint gradient on the 512x512x16 stack: L = (1/beta) log sum exp(beta T)
+    over the silicon cells, beta = 0.5 / K; forward mixed solve + one adjoint
+    solve (dL/dP per cell, dL/dk per layer)."""
+    mask = torch.as_tensor(stack.si_mask().ravel(), device=dev)
+    beta = 0.5
+    o = cuth.options("mixed")
+    T = torch.empty_like(Pt)
+
+    def fwd():
+        g.solve(Pt, T, opts=o)
+        return T
+
+    def grad_T(Tv):
+        # dL/dT = softmax(beta T) on the silicon cells (marshalled with torch)
+        t = beta * Tv[mask]
+        e = torch.exp(t - t.max())
+        gT = torch.zeros_like(Tv)
+        gT[mask] = e / e.sum()
+        return gT
+
+    fwd()
+    gT = grad_T(T)
+    g.adjoint(T, gT, opts=o)
+    times_f, times_a = [], []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, dk, sa = g.adjoint(T, gT, opts=o)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times_f.append((t1 - t0) * 1e3)
+        times_a.append((t2 - t1) * 1e3)
+    times_f.sort()
+    times_a.sort()
+    return {"workload": "adjoint of the 512x512x16 steady solve, smoothed peak loss over Si cells "
+                        "(beta = 0.5/K): dL/dP per cell and dL/dk per layer",
+            "forward_ms": round(times_f[2], 3), "adjoint_ms": round(times_a[2], 3),
+            "adjoint_over_forward": round(times_a[2] / times_f[2], 3),
+            "adjoint_cg_iters": sa["cg_iters"], "dL_dk_per_layer": [float(v) for v in dk.cpu()]}
+
+
+# ---------------------------------------------------------------- main modes
+def bench_main(args) -> int:
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stack, P = w.config1()
+    Pt = torch.as_tensor(P.ravel(), device=dev)
+    T = torch.empty_like(Pt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = cuth.Grid.from_stack(stack, device=dev)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+
+    mixed = cuth.options("mixed")
+    mixed16 = cuth.options("mixed16")
+    fp64 = cuth.options("fp64")
+    staged = cuth.options("adaptive")
+    auto = cuth.options("mixed", cheb_degree="auto")
+    jac = cuth.options("mixed", preconditioner="chebyshev_jacobi")
+    step, timed = solve_timer(g, Pt, T, torch)
+
+    for _ in range(args.warmup):
+        step(mixed)
+    g.profile_enable(True)
+    ms_mixed, st_mixed = timed(mixed, args.steps)
+    prof_blocked = g.profile_read()
+    g.profile_enable(False)
+    T_mixed = T.clone()
+
+    def profiled_single():
+        step(mixed)
+        g.profile_enable(True)
+        r = timed(mixed, args.steps)
+        p = g.profile_read()
+        g.profile_enable(False)
+        return r, p
+
+    # the contract kernel: one general sweep per launch (fused launches off)
+    (ms_fu, st_fu), prof_single = with_env({"CUTH_FUSE": "0"}, profiled_single)
+    T_fu = T.clone()
+    (ms_pr, st_pr), _ = with_env({"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "4,8", "CUTH_FUSE3": "0"},
+                                 profiled_single)
+    T_pr = T.clone()
+    # the same solve with the FP16-stored lateral conductances in the sweeps
+    step(mixed16)
+    ms_m16, st_m16 = timed(mixed16, args.steps)
+    T_m16 = T.clone()
+
+    k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
+    for _ in range(min(args.warmup, 1)):
+        step(fp64)
+    ms_fp64, st_fp64 = timed(fp64, k64)
+    T_fp64 = T.clone()
+    # the paper's stage-switched scheme, to the same FP64 residual tolerance
+    step(staged)
+    ms_st, st_st = timed(staged, k64)
+    T_st = T.clone()
+    # the degree chosen from the spectral interval instead of 30 (not the paper's)
+    step(auto)
+    ms_au, st_au = timed(auto, k64)
+    T_au = T.clone()
+    # the Jacobi-scaled Chebyshev preconditioner, k = 30 (not the paper's)
+    step(jac)
+    ms_j, st_j = timed(jac, k64)
+    T_j = T.clone()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    rise = float((T_fp64 - stack.t_amb).abs().max())
+
+    def rel(Tx):
+        return float((Tx - T_fp64).abs().max()) / rise
+
+    def gbps(stats, per_ms):
+        return round(sum(s["alg_bytes"] for s in stats) / len(stats) / (per_ms / 1e3) / 1e9, 2)
+
+    per_step = ms_mixed / args.steps
+    per64 = ms_fp64 / k64
+    pers = {"mixed": per_step, "fp64": per64, "mixed16": ms_m16 / args.steps,
+            "mixed_single_sweeps": ms_fu / args.steps, "mixed_fused_pairs_only": ms_pr / args.steps,
+            "stage_switched_to_fp64_tol": ms_st / k64, "mixed_auto_degree": ms_au / k64,
+            "mixed_chebyshev_jacobi": ms_j / k64}
+    ttt = {}
+    for k, v in pers.items():
+        ttt[k] = round(v, 3)
+        if k != "fp64":
+            ttt["speedup_" + k + "_vs_fp64"] = round(per64 / v, 3)
+    value = sum(s["alg_bytes"] for s in st_mixed) / args.steps / (per_step / 1e3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {
+            "workload": "steady 512x512x16 layered stack, lognormal(0.3) lateral k, "
+                        "3 dies, block floorplans + 32 hotspots/die; mixed FP32/FP64 "
+                        "Chebyshev(k=30)-PCG to 1e-8 relative rise error",
+            "unknowns": stack.n,
+            "cheb_degree": 30,
+        },
+        "time_to_tol_ms": ttt,
+        "solve_detail": {
+            "mixed_cg_iters": st_mixed[-1]["cg_iters"],
+            "mixed_outer_cycles": st_mixed[-1]["outer_cycles"],
+            "mixed_setup_ms": round(st_mixed[-1]["setup_ms"], 3),
+            "mixed_rel_residual": st_mixed[-1]["rel_residual"],
+            "mixed_vs_fp64_max_rise_rel_diff": rel(T_mixed),
+            "fp64_cg_iters": st_fp64[-1]["cg_iters"],
+            "fp64_rel_residual": st_fp64[-1]["rel_residual"],
+            "fp64_GBps": gbps(st_fp64, per64),
+            "mixed16_GBps": gbps(st_m16, pers["mixed16"]),
+            "mixed16_vs_fp64_max_rise_rel_diff": rel(T_m16),
+            "mixed_single_sweeps_GBps": gbps(st_fu, pers["mixed_single_sweeps"]),
+            "mixed_single_sweeps_vs_fp64_max_rise_rel_diff": rel(T_fu),
+            "mixed_fused_pairs_only_GBps": gbps(st_pr, pers["mixed_fused_pairs_only"]),
+            "mixed_fused_pairs_only_vs_fp64_max_rise_rel_diff": rel(T_pr),
+            "stage_switched_cg_iters": st_st[-1]["cg_iters"],
+            "stage_switched_rel_residual": st_st[-1]["rel_residual"],
+            "stage_switched_vs_fp64_max_rise_rel_diff": rel(T_st),
+            "auto_degree": st_au[-1]["cheb_degree"],
+            "auto_degree_cg_iters": st_au[-1]["cg_iters"],
+            "auto_degree_vs_fp64_max_rise_rel_diff": rel(T_au),
+            "chebyshev_jacobi_cg_iters": st_j[-1]["cg_iters"],
+            "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": rel(T_j),
+            "grid_create_ms": round(create_ms, 3),
+            "unknown_stencils_per_s": round(st_mixed[-1]["stencil_applies"] * stack.n
+                                            / (per_step / 1e3), 1),
+            "single_sweeps_unknown_stencils_per_s": round(st_fu[-1]["stencil_applies"] * stack.n
+                                                          / (pers["mixed_single_sweeps"] / 1e3), 1),
+        },
+        "roofline": roofline_of(prof_single, "per-cell lateral conductances", "512x512x16", 24.0, stack.n),
+        "roofline_blocked": roofline_of(prof_blocked, "per-cell lateral conductances", "512x512x16",
+                                        24.0, stack.n),
+    }
+    out["target_60pct_hbm"] = {
+        "contract_kernel_frac": out["roofline"]["frac"] if out["roofline"] else None,
+        "met": bool(out["roofline"] and out["roofline"]["frac"] >= 0.6)}
+    if not args.no_extra:
+        out["workloads"] = {
+            "c0_64x64x8": workload_c0(cuth, w, torch, dev),
+            "c2_1024x1024x20_transient": workload_c2(cuth, w, torch, dev, 22, 2, False),
+            "c3_batch_64_stacks": workload_c3(cuth, w, torch, dev, 1, 1),
+            "c4_adjoint_512x512x16": workload_c4(cuth, w, torch, dev, g, stack, Pt),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(stack, P, args.cpu_iters)
+    g.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_transient(args) -> int:
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    r = workload_c2(cuth, w, torch, dev, args.steps, args.warmup, True)
+    out = {"metric": METRIC, "value": r["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["mixed_ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-inner/f64-outer",
+           "data": "synthetic", "config": {"workload": r["workload"], "unknowns": r["unknowns"],
+                                           "cheb_degree": 30},
+           "roofline": r["roofline"], "detail": r}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args) -> int:
+    import torch
+
+    import paper_2606_17850_amd as cuth
+    import workloads as w
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    r = workload_c3(cuth, w, torch, dev, args.steps, args.warmup)
+    out = {"metric": METRIC, "value": r["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_solve"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-inner/f64-outer",
+           "data": "synthetic", "config": {"workload": r["workload"], "unknowns": r["unknowns"],
+                                           "cheb_degree": 30},
+           "roofline": None, "detail": r}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -240,9 +636,6 @@ def bench_ablation(args) -> int:
         torch.cuda.synchronize()
         return st, (time.perf_counter() - t0) * 1e3
 
-    # Ablation III (and Ablation I's solve): every preconditioner with the
-    # optimisations off (CSR storage, FP64), the stencil alone (FP64), and on
-    # (stencil, the paper's stage-switched precision), all to relres 1e-10
     pre = {}
     for name in ("none", "jacobi", "chebyshev"):
         cheb = name == "chebyshev"
@@ -256,7 +649,6 @@ def bench_ablation(args) -> int:
             st, ms = timed_solve(o)
             pre[name][label] = {"cg_iters": st["cg_iters"], "stencil_applies": st["stencil_applies"],
                                 "time_ms": round(ms, 3), "rel_residual": st["rel_residual"]}
-    # Ablation II: fixed FP64 (ground truth), fixed FP32, and the mixed schemes
     prec = {}
     T64 = None
     for name in ("fp64", "fp32", "mixed", "mixed16", "adaptive"):
@@ -278,62 +670,29 @@ def bench_ablation(args) -> int:
     return 0
 
 
-def bench_batch(args) -> int:
-    """64 uneven stacks x 4 power maps in one batched mixed solve per step."""
-    import numpy as np
-    import torch
-
-    import paper_2606_17850_amd as cuth
-    import workloads as w
-
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    items = w.config3()
-    grids = [cuth.Grid.from_stack(st, device=dev) for st, _ in items]
-    P = [torch.as_tensor(np.concatenate([m.ravel() for m in maps]), device=dev) for _, maps in items]
-    T = [torch.empty_like(p) for p in P]
-    o = cuth.options("mixed")
-    for _ in range(max(args.warmup, 1)):
-        cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, stats = cuth.solve_batch(grids, P, T, nrhs=4, opts=o)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    per = ms / args.steps
-    unknowns = sum(st.n for st, _ in items)
-    value = sum(s["alg_bytes"] for s in stats) / (per / 1e3) / 1e9
-    out = _base(args, "batch of 64 uneven stacks (edge 128-384, 8-16 layers) x 4 power maps, "
-                      "one batched mixed solve to 1e-8", unknowns, value, per)
-    its = [s["cg_iters"] for s in stats]
-    out["solve_detail"] = {"problems": len(stats), "cg_iters_min": min(its), "cg_iters_max": max(its),
-                           "unknown_rhs": unknowns * 4}
-    out["roofline"] = None
-    for gg in grids:
-        gg.close()
-    print(json.dumps(out), flush=True)
-    return 0
-
-
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=None)
-    ap.add_argument("--cpu-iters", type=int, default=1000)
+    ap.add_argument("--cpu-iters", type=int, default=50,
+                    help="iterations of the one-core CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline workload only (no config 0/2/3/4 lines)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--workload", choices=("c1", "c2", "c3", "ablation"), default="c1",
-                    help="c1: 512x512x16 steady (default, the headline); c2: 1024x1024x20 "
-                         "transient steps; c3: 64-stack batch")
+                    help="c1: 512x512x16 steady headline with the other configurations "
+                         "(default); c2: 1024x1024x20 transient steps only; c3: 64-stack "
+                         "batch only; ablation: the paper's ablations on 512x512x16")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)",
                           "n_gpus": args.gpus}), flush=True)
         return 2
     if args.workload == "c2":
@@ -342,218 +701,7 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "ablation":
         return bench_ablation(args)
-
-    import numpy as np
-    import torch
-
-    import paper_2606_17850_amd as cuth
-    import workloads as w
-
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    stack, P = w.config1()
-    Pt = torch.as_tensor(P.ravel(), device=dev)
-    T = torch.empty_like(Pt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g = cuth.Grid.from_stack(stack, device=dev)
-    torch.cuda.synchronize()
-    create_ms = (time.perf_counter() - t0) * 1e3
-
-    mixed = cuth.options("mixed")
-    mixed16 = cuth.options("mixed16")
-    fp64 = cuth.options("fp64")
-    staged = cuth.options("adaptive")
-    auto = cuth.options("mixed", cheb_degree="auto")
-    jac = cuth.options("mixed", preconditioner="chebyshev_jacobi")
-
-    def step(opts):
-        g.reset_bounds()
-        _, st = g.solve(Pt, T, opts=opts)
-        return st
-
-    def timed(opts, k):
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        stats = []
-        e0.record()
-        h0 = time.perf_counter()
-        for _ in range(k):
-            stats.append(step(opts))
-        e1.record()
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - h0) * 1e3
-        return max(e0.elapsed_time(e1), wall), stats
-
-    for _ in range(args.warmup):
-        step(mixed)
-    g.profile_enable(True)
-    ms_mixed, st_mixed = timed(mixed, args.steps)
-    prof = g.profile_read()
-    g.profile_enable(False)
-    T_mixed = T.clone()
-
-    # the same solve with the FP16-stored lateral conductances in the Chebyshev
-    # sweeps (not profiled; reported beside the headline)
-    step(mixed16)
-    ms_m16, st_m16 = timed(mixed16, args.steps)
-    T_m16 = T.clone()
-    # and with one general sweep per launch (the fused launches switched off),
-    # and with fused pairs but no triples
-    def with_env(env, fn):
-        prev = {k: os.environ.get(k) for k in env}
-        os.environ.update(env)
-        try:
-            return fn()
-        finally:
-            for k, v in prev.items():
-                if v is None:
-                    os.environ.pop(k, None)
-                else:
-                    os.environ[k] = v
-
-    def single():
-        step(mixed)
-        return timed(mixed, args.steps)
-
-    ms_fu, st_fu = with_env({"CUTH_FUSE": "0"}, single)
-    T_fu = T.clone()
-    ms_pr, st_pr = with_env({"CUTH_FUSE": "1", "CUTH_FUSE_SHAPE": "4,8", "CUTH_FUSE3": "0"}, single)
-    T_pr = T.clone()
-
-    k64 = args.fp64_steps if args.fp64_steps is not None else max(1, min(args.steps, 5))
-    for _ in range(min(args.warmup, 1)):
-        step(fp64)
-    ms_fp64, st_fp64 = timed(fp64, k64)
-    T_fp64 = T.clone()
-    # the paper's stage-switched scheme, to the same FP64 residual tolerance
-    step(staged)
-    ms_st, st_st = timed(staged, k64)
-    T_st = T.clone()
-    # the degree chosen from the spectral interval instead of 30 (not the paper's)
-    step(auto)
-    ms_au, st_au = timed(auto, args.steps)
-    T_au = T.clone()
-    # the Jacobi-scaled Chebyshev preconditioner, k = 30 (not the paper's)
-    step(jac)
-    ms_j, st_j = timed(jac, args.steps)
-    T_j = T.clone()
-
-    if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-
-    rise = float((T_fp64 - stack.t_amb).abs().max())
-    diff = float((T_mixed - T_fp64).abs().max()) / rise
-    diff16 = float((T_m16 - T_fp64).abs().max()) / rise
-    per16 = ms_m16 / args.steps
-    diff_st = float((T_st - T_fp64).abs().max()) / rise
-    diff_fu = float((T_fu - T_fp64).abs().max()) / rise
-    per_fu = ms_fu / args.steps
-    diff_pr = float((T_pr - T_fp64).abs().max()) / rise
-    per_pr = ms_pr / args.steps
-    per_st = ms_st / k64
-    per_au = ms_au / args.steps
-    diff_au = float((T_au - T_fp64).abs().max()) / rise
-    per_j = ms_j / args.steps
-    diff_j = float((T_j - T_fp64).abs().max()) / rise
-
-    per_step = ms_mixed / args.steps
-    bytes_step = sum(s["alg_bytes"] for s in st_mixed) / args.steps
-    value = bytes_step / (per_step / 1e3) / 1e9
-    avg_launch_ms = prof["total_ms"] / max(prof["launches"], 1)
-    achieved = prof["bytes_per_launch"] / (avg_launch_ms / 1e3) / 1e9 if prof["launches"] else None
-    per64 = ms_fp64 / k64
-
-    out = {
-        "metric": "PCG loop HBM GB/s + time to 1e-8 rel. error, mixed vs plain FP64, 1 GPU",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32-inner/f64-outer",
-        "data": "synthetic",
-        "config": {
-            "workload": "steady 512x512x16 layered stack, lognormal(0.3) lateral k, "
-                        "3 dies, block floorplans + 32 hotspots/die; mixed FP32/FP64 "
-                        "Chebyshev(k=30)-PCG to 1e-8 relative rise error",
-            "unknowns": stack.n,
-            "cheb_degree": 30,
-        },
-        "time_to_tol_ms": {"mixed": round(per_step, 3), "fp64": round(per64, 3),
-                           "speedup_mixed_vs_fp64": round(per64 / per_step, 3),
-                           "mixed16": round(per16, 3),
-                           "speedup_mixed16_vs_fp64": round(per64 / per16, 3),
-                           "mixed_single_sweeps": round(per_fu, 3),
-                           "speedup_mixed_single_sweeps_vs_fp64": round(per64 / per_fu, 3),
-                           "mixed_fused_pairs_only": round(per_pr, 3),
-                           "speedup_mixed_fused_pairs_only_vs_fp64": round(per64 / per_pr, 3),
-                           "stage_switched_to_fp64_tol": round(per_st, 3),
-                           "speedup_stage_switched_vs_fp64": round(per64 / per_st, 3),
-                           "mixed_auto_degree": round(per_au, 3),
-                           "speedup_mixed_auto_degree_vs_fp64": round(per64 / per_au, 3),
-                           "mixed_chebyshev_jacobi": round(per_j, 3),
-                           "speedup_mixed_chebyshev_jacobi_vs_fp64": round(per64 / per_j, 3)},
-        "solve_detail": {
-            "mixed_cg_iters": st_mixed[-1]["cg_iters"],
-            "mixed_outer_cycles": st_mixed[-1]["outer_cycles"],
-            "mixed_setup_ms": round(st_mixed[-1]["setup_ms"], 3),
-            "mixed_rel_residual": st_mixed[-1]["rel_residual"],
-            "fp64_cg_iters": st_fp64[-1]["cg_iters"],
-            "fp64_rel_residual": st_fp64[-1]["rel_residual"],
-            "fp64_GBps": round(sum(s["alg_bytes"] for s in st_fp64) / k64 / (per64 / 1e3) / 1e9, 2),
-            "mixed_vs_fp64_max_rise_rel_diff": diff,
-            "mixed16_cg_iters": st_m16[-1]["cg_iters"],
-            "mixed16_outer_cycles": st_m16[-1]["outer_cycles"],
-            "mixed16_GBps": round(sum(s["alg_bytes"] for s in st_m16) / args.steps / (per16 / 1e3) / 1e9, 2),
-            "mixed16_vs_fp64_max_rise_rel_diff": diff16,
-            "mixed_single_sweeps_cg_iters": st_fu[-1]["cg_iters"],
-            "mixed_single_sweeps_GBps": round(sum(s["alg_bytes"] for s in st_fu) / args.steps / (per_fu / 1e3) / 1e9, 2),
-            "mixed_single_sweeps_vs_fp64_max_rise_rel_diff": diff_fu,
-            "mixed_fused_pairs_only_cg_iters": st_pr[-1]["cg_iters"],
-            "mixed_fused_pairs_only_GBps": round(sum(s["alg_bytes"] for s in st_pr) / args.steps / (per_pr / 1e3) / 1e9, 2),
-            "mixed_fused_pairs_only_vs_fp64_max_rise_rel_diff": diff_pr,
-            "stage_switched_cg_iters": st_st[-1]["cg_iters"],
-            "stage_switched_cycles": st_st[-1]["outer_cycles"],
-            "stage_switched_rel_residual": st_st[-1]["rel_residual"],
-            "stage_switched_vs_fp64_max_rise_rel_diff": diff_st,
-            "auto_degree": st_au[-1]["cheb_degree"],
-            "auto_degree_cg_iters": st_au[-1]["cg_iters"],
-            "auto_degree_vs_fp64_max_rise_rel_diff": diff_au,
-            "chebyshev_jacobi_cg_iters": st_j[-1]["cg_iters"],
-            "chebyshev_jacobi_interval": [st_j[-1]["lambda_min"], st_j[-1]["lambda_max"]],
-            "chebyshev_jacobi_vs_fp64_max_rise_rel_diff": diff_j,
-            "grid_create_ms": round(create_ms, 3),
-            "unknown_stencils_per_s": round(st_mixed[-1]["stencil_applies"] * stack.n
-                                            / (per_step / 1e3), 1),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": SWEEP_KERNELS[prof["fused"]][1].format("per-cell lateral conductances"),
-            "achieved": round(achieved, 2) if achieved else None,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
-            "traffic": traffic_from_profiles(prof["fused"]),
-            "bytes_per_launch": prof["bytes_per_launch"],
-            "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-            "timed_launches": prof["launches"],
-        },
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(stack, P, args.cpu_iters)
-    g.close()
-    print(json.dumps(out), flush=True)
-    return 0
+    return bench_main(args)
 
 
 if __name__ == "__main__":

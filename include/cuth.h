@@ -248,8 +248,10 @@ cuth_status cuth_transient_step(cuth_grid g, double dt, const double *P_next,
  * P[s] / T[s]: device double [nrhs * N_s] (right-hand side q at offset q*N_s).
  * stats: NULL or [nsys*nrhs] (setup_ms/solve_ms are 0 per problem).  All grids
  * must live on the same device; work is ordered after the first grid's stream.
- * The call allocates its work vectors (about 40 B per unknown and right-hand
- * side in mixed precision) for its duration. */
+ * The work vectors (about 56 B per unknown and right-hand side in mixed
+ * precision) and launch descriptors are allocated on the first call and kept
+ * by the batch's first grid for later calls with the same sizes, precision and
+ * number of right-hand sides; destroying that grid releases them. */
 cuth_status cuth_solve_batch(int32_t nsys, const cuth_grid *grids, int32_t nrhs,
                              const double *const *P, double *const *T,
                              const cuth_options *opt, cuth_stats *stats);

@@ -41,6 +41,9 @@ static double dot(int64_t n, const double *u, const double *v)
 
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the following solves (the one-core timing of the baseline). */
+void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+
 /* Returns 0 on convergence, 1 if maxit was reached, 2 on breakdown, 3 on bad input. */
 int oracle_jacobi_cg(int64_t n, const int64_t *ip, const int32_t *ix, const double *a,
                      const double *b, double *x, double rtol, int64_t maxit,

@@ -40,12 +40,19 @@ def _load() -> ctypes.CDLL:
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
 
 def threads() -> int:
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following solves."""
+    _load().oracle_set_threads(int(n))
 
 
 def jacobi_cg(A, b: np.ndarray, x0: Optional[np.ndarray] = None, rtol: float = 1e-14,

@@ -74,6 +74,21 @@ template <typename T>
 inline int stencil_blocks(const OpView<T> &op) {
     return tiles_x(op.nx, op.vx) * tiles_y(op.ny, op.by) * tiles_z(op.nz, op.zc);
 }
+// x windows of a fused launch (a pair: 2 sweeps, a triple: 3) over rows of nx
+// cells.  A workgroup row holds W = wpr*64*vx cells.  When W < nx the row is
+// covered by windows that overlap by halo lanes: each window computes all W
+// cells and owns the W - 2*hl*vx between its hl = ceil((sweeps - 1)/vx) halo
+// lanes on either side (the last sweep needs sweeps - 1 cells of halo per side);
+// window t starts at x = t*(W - 2*hl*vx) - hl*vx.
+__host__ __device__ inline int fused_halo_lanes(int vx, int sweeps) {
+    return (sweeps - 1 + vx - 1) / vx;
+}
+__host__ __device__ inline int fused_windows(int nx, int vx, int wpr, int sweeps) {
+    const int W = wpr * kWave * vx;
+    if (W >= nx) return 1;
+    const int S = W - 2 * fused_halo_lanes(vx, sweeps) * vx;
+    return (nx + S - 1) / S;
+}
 inline int red_blocks(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (int)(b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b));

@@ -4,6 +4,7 @@
 #include "cuth_internal.hpp"
 #include "../../include/cuth.h"
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -83,6 +84,16 @@ struct Engine {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
+// Work vectors and engine of a batched solve, kept between calls with the same
+// batch signature (sizes, precision, right-hand sides): one per coefficient
+// storage group, held by the batch's first grid.
+struct BatchPool {
+    std::string key;
+    float *pool32 = nullptr;
+    double *pool64 = nullptr, *poolth = nullptr;
+    Engine E;
+};
+
 // Slots of a grid's own partials buffer (Lanczos, adjoint).
 enum Slot { S_LZA = 0, S_LZB, S_COUNT };
 
@@ -102,7 +113,7 @@ struct Grid {
     std::vector<double> lat_rowmax;    // per layer, per-cell grids only
     std::vector<int> e16;              // per-layer FP16 scale exponent e_l
 
-    std::vector<Setup> setups;
+    std::deque<Setup> setups;         // a deque: Setup pointers stay valid as dt's are added
     Work<float> w32;
     Work<double> w64;
     double *thA = nullptr, *thB = nullptr;
@@ -114,6 +125,7 @@ struct Grid {
     double *adj_fac = nullptr;        // adjoint factors [3 nz]
     float *h_lz = nullptr;
     Engine eng;                       // single-problem engine of this grid
+    BatchPool batch[2];               // batches led by this grid (uniform / per-cell group)
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 

@@ -748,19 +748,30 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const int ntzf = (nz + zcf - 1) / zcf;
-    const int local = slot - P.f_tile0;
-    const int tz = local % ntzf, ty = local / ntzf;
-    const int lane = threadIdx.x, w = threadIdx.y, rs = w / wpr, sg = w % wpr;
     const int W = wpr * kWave * VX;            // ring row length (cells)
+    const int nwx = fused_windows(nx, VX, wpr, 2);
+    const int hc = nwx > 1 ? fused_halo_lanes(VX, 2) * VX : 0;   // halo cells per side
+    const int local = slot - P.f_tile0;
+    const int tz = local % ntzf, tx = (local / ntzf) % nwx, ty = local / ntzf / nwx;
+    // a wavefront is one threadIdx.y (64 lanes along x): its row slot and x
+    // segment are wave-uniform, so the ring row addresses stay scalar
+    const int lane = threadIdx.x, w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int rs = w / wpr, sg = w % wpr;
     const int RR = R + 2;                      // ring rows
-    const int xo = (sg * kWave + lane) * VX;   // x of this lane's first cell
+    const int xo = (sg * kWave + lane) * VX;   // this lane's first cell in the window (ring row)
+    const int xg = tx * (W - 2 * hc) - hc + xo;   // ... and in the grid row
     const int jr = ty * R - 1 + rs;            // grid row of this wavefront
-    const bool act = jr >= 0 && jr < ny && xo < nx;
+    const bool act = jr >= 0 && jr < ny && xg >= 0 && xg < nx;
+    const bool own = act && xo >= hc && xo < W - hc;   // cells this window writes
     const bool inner = act && rs >= 1 && rs <= R;
     const int l0 = tz * zcf, l1 = min(nz, l0 + zcf);
     const int la0 = max(0, l0 - 1), la1 = min(nz, l1 + 1);
-    const bool has_l = act && xo > 0, has_r = act && xo + VX < nx;
+    const bool has_l = act && xg > 0, has_r = act && xg + VX < nx;
     const bool has_s = act && jr > 0, has_n = act && jr < ny - 1;
+    // x neighbours of the stage-B input in the ring: a halo lane at the
+    // window's edge has none there (its stage-B values are not written, and no
+    // written value depends on them)
+    const bool ring_l = has_l && xo > 0, ring_r = has_r && xo + VX < W;
     const T c1a = P.cheb[1 + j], c2a = P.cheb[1 + P.kcap + j];
     const T c1b = P.cheb[2 + j], c2b = P.cheb[2 + P.kcap + j];
     const T *__restrict__ zN = P.z[zsel & 3];
@@ -771,7 +782,7 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
     const Vec<T, VX> zero = vzero<T, VX>();
     auto ring_at = [&](int l, int row) -> T * { return ring + ((size_t)((l % 3) * RR + row)) * W; };
 
-    int64_t c = act ? xo + (int64_t)nx * jr + plane * la0 : 0;
+    int64_t c = act ? xg + (int64_t)nx * jr + plane * la0 : 0;
     Vec<T, VX> xdn = vload<T, VX>(zN + ((act && la0 > 0) ? c - plane : c));
     Vec<T, VX> xc = vload<T, VX>(zN + c);
     // previous layer's values kept for stage B
@@ -790,13 +801,13 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
         // term vanishes (the ring rows beyond the grid hold no values)
         const Vec<T, VX> so = lds_load<T, VX>(ring_at(lb, jr > 0 ? rs - 1 : rs) + xo);
         const Vec<T, VX> no = lds_load<T, VX>(ring_at(lb, jr < ny - 1 ? rs + 1 : rs) + xo);
-        const T left = has_l ? rowc[xo - 1] : T(0);
-        const T right = has_r ? rowc[xo + VX] : T(0);
+        const T left = ring_l ? rowc[xo - 1] : T(0);
+        const T right = ring_r ? rowc[xo + VX] : T(0);
         const Vec<T, VX> &y = zA_m1;
         Vec<T, VX> z2;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
-            const int i = xo + e;
+            const int i = xg + e;
             const T x = y.a[e];
             const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
             const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
@@ -824,7 +835,7 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, lb, nz));
             z2.a[e] = x + c1b * (x - xdn.a[e]) + c2b * res;   // xdn: z_j at layer lb
         }
-        vstore<T, VX>(zY + cl - plane, z2);
+        if (own) vstore<T, VX>(zY + cl - plane, z2);
     };
     // the loop holds every stage A (the last layer, with stage B only, is
     // peeled below, so no value needs a placeholder)
@@ -848,11 +859,15 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
         T right = lane_right(xc.a[0]);
         if (lane == 0) left = west;
         if (lane == kWave - 1) right = east;
-        if constexpr (PC)
+        if constexpr (PC) {
             lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+            // in an x window the lane at x = 0 need not be lane 0: its west
+            // conductance came from an inactive lane and must vanish
+            if (nwx > 1 && !has_l) gxl = T(0);
+        }
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
-            const int i = xo + e;
+            const int i = xg + e;
             const T x = xc.a[e];
             const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
             const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
@@ -881,8 +896,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             // loads; no stage B reads them (see its loads)
             zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
         }
-        if (xo < W) lds_store<T, VX>(ring_at(l, rs) + xo, zn);
-        if (inner && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
+        lds_store<T, VX>(ring_at(l, rs) + xo, zn);
+        if (inner && own && l >= l0 && l < l1) vstore<T, VX>(zX + c, zn);
         __syncthreads();
         stage_b(l, c, zn);
         // shift the layer registers
@@ -940,23 +955,33 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const int ntzf = (nz + zcf - 1) / zcf;
-    const int local = slot - P.t_tile0;
-    const int tz = local % ntzf, ty = local / ntzf;
-    const int lane = threadIdx.x, w = threadIdx.y, rs = w / wpr, sg = w % wpr;
     const int W = wpr * kWave * VX;            // ring row length (cells)
+    const int nwx = fused_windows(nx, VX, wpr, 3);
+    const int hc = nwx > 1 ? fused_halo_lanes(VX, 3) * VX : 0;   // halo cells per side
+    const int local = slot - P.t_tile0;
+    const int tz = local % ntzf, tx = (local / ntzf) % nwx, ty = local / ntzf / nwx;
+    // a wavefront is one threadIdx.y (64 lanes along x): its row slot and x
+    // segment are wave-uniform, so the ring row addresses stay scalar
+    const int lane = threadIdx.x, w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int rs = w / wpr, sg = w % wpr;
     const int RA = R + 4, RB = R + 2;          // ring rows
     T *ringA = reinterpret_cast<T *>(lds_raw);
     T *ringB = ringA + (size_t)3 * RA * W;
-    const int xo = (sg * kWave + lane) * VX;   // x of this lane's first cell
+    const int xo = (sg * kWave + lane) * VX;   // this lane's first cell in the window (ring row)
+    const int xg = tx * (W - 2 * hc) - hc + xo;   // ... and in the grid row
     const int jr = ty * R - 2 + rs;            // grid row of this wavefront
-    const bool act = jr >= 0 && jr < ny && xo < nx;
+    const bool act = jr >= 0 && jr < ny && xg >= 0 && xg < nx;
+    const bool own = act && xo >= hc && xo < W - hc;   // cells this window writes
     const bool rowB = act && rs >= 1 && rs <= R + 2;
     const bool rowC = act && rs >= 2 && rs <= R + 1;
     const int l0 = tz * zcf, l1 = min(nz, l0 + zcf);
     const int la0 = max(0, l0 - 2), la1 = min(nz, l1 + 2);
     const int lb0 = max(0, l0 - 1), lb1 = min(nz, l1 + 1);
-    const bool has_l = act && xo > 0, has_r = act && xo + VX < nx;
+    const bool has_l = act && xg > 0, has_r = act && xg + VX < nx;
     const bool has_s = act && jr > 0, has_n = act && jr < ny - 1;
+    // x neighbours of the stage-B and stage-C inputs in the rings: a halo lane
+    // at the window's edge has none there (see the pair)
+    const bool ring_l = has_l && xo > 0, ring_r = has_r && xo + VX < W;
     const T c1a = P.cheb[1 + j], c2a = P.cheb[1 + P.kcap + j];
     const T c1b = P.cheb[2 + j], c2b = P.cheb[2 + P.kcap + j];
     const T c1c = P.cheb[3 + j], c2c = P.cheb[3 + P.kcap + j];
@@ -972,7 +997,7 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
     auto ringA_at = [&](int l, int row) -> T * { return ringA + ((size_t)((l % 3) * RA + row)) * W; };
     auto ringB_at = [&](int l, int row) -> T * { return ringB + ((size_t)((l % 3) * RB + row - 1)) * W; };
 
-    int64_t c = act ? xo + (int64_t)nx * jr + plane * la0 : 0;
+    int64_t c = act ? xg + (int64_t)nx * jr + plane * la0 : 0;
     Vec<T, VX> xdn = vload<T, VX>(zN + ((act && la0 > 0) ? c - plane : c));
     Vec<T, VX> xc = vload<T, VX>(zN + c);
     // stage A results of the two layers below, stage B results of the two
@@ -993,12 +1018,12 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
         const LayerCoef<T> L = gldc(op.lc + ls);
         const Vec<T, VX> so = lds_load<T, VX>(so_row + xo);
         const Vec<T, VX> no = lds_load<T, VX>(no_row + xo);
-        const T left = has_l ? row[xo - 1] : T(0);
-        const T right = has_r ? row[xo + VX] : T(0);
+        const T left = ring_l ? row[xo - 1] : T(0);
+        const T right = ring_r ? row[xo + VX] : T(0);
         Vec<T, VX> out;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
-            const int i = xo + e;
+            const int i = xg + e;
             const T x = y.a[e];
             const T xl = (e == 0) ? left : y.a[e > 0 ? e - 1 : 0];
             const T xr = (e == VX - 1) ? right : y.a[e + 1 < VX ? e + 1 : 0];
@@ -1039,7 +1064,7 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             z2 = sweep(ringA_at(lb, rs), ringA_at(lb, sA), ringA_at(lb, nA), lb, zA_m1, zA_m2, zn, xdn,
                        r_m1, gxp_m1, gyp_m1, gym_m1, gxl_m1, c1b, c2b);
             lds_store<T, VX>(ringB_at(lb, rs) + xo, z2);
-            if (rowC && lb >= l0 && lb < l1) vstore<T, VX>(zX + cl - plane, z2);
+            if (rowC && own && lb >= l0 && lb < l1) vstore<T, VX>(zX + cl - plane, z2);
         }
         // ---- stage C: z_{j+3} at layer l - 2 (z2: stage B's layer above)
         const int lc = l - 2;
@@ -1047,7 +1072,7 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             const Vec<T, VX> z3 =
                 sweep(ringB_at(lc, rs), ringB_at(lc, sA), ringB_at(lc, nA), lc, zB_m1, zB_m2, z2,
                       zA_m2, r_m2, gxp_m2, gyp_m2, gym_m2, gxl_m2, c1c, c2c);
-            vstore<T, VX>(zY + cl - 2 * plane, z3);
+            if (own) vstore<T, VX>(zY + cl - 2 * plane, z3);
         }
         // shift the layer registers
         zA_m2 = zA_m1;
@@ -1097,11 +1122,15 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
         T right = lane_right(xc.a[0]);
         if (lane == 0) left = west;
         if (lane == kWave - 1) right = east;
-        if constexpr (PC)
+        if constexpr (PC) {
             lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+            // in an x window the lane at x = 0 need not be lane 0: its west
+            // conductance came from an inactive lane and must vanish
+            if (nwx > 1 && !has_l) gxl = T(0);
+        }
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
-            const int i = xo + e;
+            const int i = xg + e;
             const T x = xc.a[e];
             const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
             const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
@@ -1127,7 +1156,7 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, l, nz));
             zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
         }
-        if (xo < W) lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
+        lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
         __syncthreads();
         stage_bc(l, c, zn, rv, gxp, gyp, gym, gxl, xup);
     }

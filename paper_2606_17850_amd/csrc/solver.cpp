@@ -460,12 +460,14 @@ int build_inner(Engine &E, std::vector<Problem *> &ps, const Shape &sh, std::vec
         if (sh.fr > 0) {
             if (!w.zC || !w.zD) return -1;
             d.f_tile0 = ftile;
-            d.f_ntiles = tiles_y(p.g->ny, sh.fr) * tiles_z(p.g->nz, sh.fzc);
+            d.f_ntiles = fused_windows(p.g->nx, sh.vx, sh.fwpr, 2) * tiles_y(p.g->ny, sh.fr) *
+                         tiles_z(p.g->nz, sh.fzc);
             ftile += d.f_ntiles;
         }
         if (sh.tr > 0) {
             d.t_tile0 = ttile;
-            d.t_ntiles = tiles_y(p.g->ny, sh.tr) * tiles_z(p.g->nz, sh.tzc);
+            d.t_ntiles = fused_windows(p.g->nx, sh.vx, sh.twpr, 3) * tiles_y(p.g->ny, sh.tr) *
+                         tiles_z(p.g->nz, sh.tzc);
             ttile += d.t_ntiles;
         }
         d.st = Sel<T>::ds(E) + n;
@@ -1254,9 +1256,16 @@ int fuse_env() {
 }
 
 // Fit fused shape (R, zc) to rows of max_nx cells; false when it cannot fit.
-bool fuse_fit(Shape &sh, int max_nx, int R, int zc) {
+// wcap > 0: at most wcap wavefronts per row, the row split into overlapping x
+// windows where it is longer (fused_windows).
+int fused_wpr(int max_nx, int vx, int wcap) {
+    const int whole = (max_nx + kWave * vx - 1) / (kWave * vx);
+    return wcap > 0 ? std::min(whole, wcap) : whole;
+}
+
+bool fuse_fit(Shape &sh, int max_nx, int R, int zc, int wcap = 0) {
     sh.fr = 0;
-    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
+    const int wpr = fused_wpr(max_nx, sh.vx, wcap);
     auto lds = [&](int r) { return (size_t)3 * (r + 2) * wpr * kWave * sh.vx * sizeof(float); };
     while (R > 1 && (wpr * (R + 2) > 16 || lds(R) > 65536)) --R;
     if (R < 1 || wpr * (R + 2) > 16 || lds(R) > 65536) return false;
@@ -1289,9 +1298,9 @@ size_t lds_cap() {
 }
 
 // Fit the triple shape (R, zc) to rows of max_nx cells; false when it cannot fit.
-bool fuse3_fit(Shape &sh, int max_nx, int R, int zc) {
+bool fuse3_fit(Shape &sh, int max_nx, int R, int zc, int wcap = 0) {
     sh.tr = 0;
-    const int wpr = (max_nx + kWave * sh.vx - 1) / (kWave * sh.vx);
+    const int wpr = fused_wpr(max_nx, sh.vx, wcap);
     auto lds = [&](int r) { return (size_t)3 * ((r + 4) + (r + 2)) * wpr * kWave * sh.vx * sizeof(float); };
     while (R > 1 && (wpr * (R + 4) > 16 || lds(R) > lds_cap())) --R;
     if (R < 1 || wpr * (R + 4) > 16 || lds(R) > lds_cap()) return false;
@@ -1306,25 +1315,27 @@ void set_fuse(Shape &sh, int max_nx) {
     sh.fr = 0;
     sh.tr = 0;
     if (fuse_env() != 1) return;
-    int R = 2, zc = 8;
-    if (const char *f = std::getenv("CUTH_FUSE_SHAPE")) {
-        int a = 0, b = 0;
-        if (std::sscanf(f, "%d,%d", &a, &b) == 2 && a >= 1 && a <= 14 && b >= 1) {
-            R = a;
-            zc = b;
+    // "R,zc" or "R,zc,wcap" (wcap: wavefronts per row, x windows where the
+    // row is longer)
+    auto parse = [](const char *name, int rmax, int &R, int &zc, int &wc) {
+        if (const char *f = std::getenv(name)) {
+            int a = 0, b = 0, c = 0;
+            const int n = std::sscanf(f, "%d,%d,%d", &a, &b, &c);
+            if (n >= 2 && a >= 1 && a <= rmax && b >= 1) {
+                R = a;
+                zc = b;
+                wc = (n == 3 && c >= 1 && c <= 16) ? c : 0;
+            }
         }
-    }
-    if (!fuse_fit(sh, max_nx, R, zc) || fuse3_env() != 1) return;
+    };
+    int R = 2, zc = 8, wc = 0;
+    parse("CUTH_FUSE_SHAPE", 14, R, zc, wc);
+    if (!fuse_fit(sh, max_nx, R, zc, wc) || fuse3_env() != 1) return;
     R = 4;
     zc = 8;
-    if (const char *f = std::getenv("CUTH_FUSE3_SHAPE")) {
-        int a = 0, b = 0;
-        if (std::sscanf(f, "%d,%d", &a, &b) == 2 && a >= 1 && a <= 12 && b >= 1) {
-            R = a;
-            zc = b;
-        }
-    }
-    (void)fuse3_fit(sh, max_nx, R, zc);
+    wc = 0;
+    parse("CUTH_FUSE3_SHAPE", 12, R, zc, wc);
+    (void)fuse3_fit(sh, max_nx, R, zc, wc);
 }
 
 Shape shape_from_env(const char *name, Shape def, int nx, int maxvx) {
@@ -1501,10 +1512,19 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
     return Status::ok();
 }
 
+void batch_pool_free(BatchPool &bp) {
+    engine_free(bp.E);
+    dev_free(bp.pool32);
+    dev_free(bp.pool64);
+    dev_free(bp.poolth);
+    bp.key.clear();
+}
+
 void grid_destroy(Grid *g) {
     if (!g) return;
     (void)hipStreamSynchronize(g->stream);
     engine_free(g->eng);
+    for (BatchPool &bp : g->batch) batch_pool_free(bp);
     for (Setup &su : g->setups) {
         dev_free(su.lc64);
         dev_free(su.lc32);
@@ -1550,18 +1570,16 @@ OpView<float> view32(const Grid &g, const Setup &su, bool h16) {
     return v;
 }
 
-Setup *get_setup(Grid &g, double dt, Status &status) {
-    status = Status::ok();
-    for (Setup &su : g.setups)
-        if (su.dt == dt) return &su;
-    Setup su;
-    su.dt = dt;
+// Per-layer coefficients of the operator of dt (steady: dt == 0) and the
+// Gershgorin bound of its spectrum.
+static void layer_coefs(const Grid &g, double dt, std::vector<LayerCoef<double>> &hlc,
+                        double &gersh_out) {
     const int nz = g.nz;
     const double dx = g.dx, dy = g.dy, dxdy = dx * dy;
-    su.hlc.resize(nz);
+    hlc.assign(nz, LayerCoef<double>{});
     double gersh = 0.0;
     for (int l = 0; l < nz; ++l) {
-        LayerCoef<double> &L = su.hlc[l];
+        LayerCoef<double> &L = hlc[l];
         const double k = g.k_lat[l], d = g.dz[l];
         // series half-cell conductance of a lateral face inside a uniform layer
         L.gx = (dy * d) / (dx / (2.0 * k) + dx / (2.0 * k));
@@ -1569,7 +1587,7 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
         L.gzu = (l + 1 < nz)
                     ? dxdy / (d / (2.0 * g.k_vert[l]) + g.dz[l + 1] / (2.0 * g.k_vert[l + 1]))
                     : 0.0;
-        L.gzd = (l > 0) ? su.hlc[l - 1].gzu : 0.0;
+        L.gzd = (l > 0) ? hlc[l - 1].gzu : 0.0;
         L.cap = (dt > 0.0) ? g.cap[l] * dxdy * d / dt : 0.0;
         L.sink = L.cap + (l == nz - 1 ? g.h_top * dxdy : 0.0) + (l == 0 ? g.h_bot * dxdy : 0.0);
         L.hs = g.e16.empty() ? 1.0 : std::ldexp(1.0, -g.e16[l]);
@@ -1577,13 +1595,29 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
                                       : std::min(2, g.nx - 1) * L.gx + std::min(2, g.ny - 1) * L.gy;
         gersh = std::max(gersh, 2.0 * (lat + L.gzu + L.gzd) + L.sink);
     }
-    su.gersh = gersh;
-    std::vector<LayerCoef<float>> h32(nz);
-    for (int l = 0; l < nz; ++l) {
-        const LayerCoef<double> &L = su.hlc[l];
+    gersh_out = gersh;
+}
+
+// FP32 copy of the layer coefficients (each rounded once).
+static std::vector<LayerCoef<float>> layer_coefs32(const std::vector<LayerCoef<double>> &hlc) {
+    std::vector<LayerCoef<float>> h32(hlc.size());
+    for (size_t l = 0; l < hlc.size(); ++l) {
+        const LayerCoef<double> &L = hlc[l];
         h32[l] = LayerCoef<float>{(float)L.gx, (float)L.gy, (float)L.gzd, (float)L.gzu,
                                   (float)L.sink, (float)L.cap, (float)L.hs};
     }
+    return h32;
+}
+
+Setup *get_setup(Grid &g, double dt, Status &status) {
+    status = Status::ok();
+    for (Setup &su : g.setups)
+        if (su.dt == dt) return &su;
+    Setup su;
+    su.dt = dt;
+    const int nz = g.nz;
+    layer_coefs(g, dt, su.hlc, su.gersh);
+    const std::vector<LayerCoef<float>> h32 = layer_coefs32(su.hlc);
     status = dev_alloc(&su.lc64, (size_t)nz);
     if (!status.bad()) status = dev_alloc(&su.lc32, (size_t)nz);
     if (status.bad()) {
@@ -2000,13 +2034,20 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
     // the triple setting is part of the key: a cached choice made with
     // triples allowed must not outlive CUTH_FUSE3=0, nor the reverse
     const int f3 = fuse3_env();
-    const std::string key = sig + (f3 == 0 ? " fuse no3" : f3 == 1 ? " fuse 3" : " fuse");
+    // the preconditioner is part of the key too (the Jacobi-scaled sweeps are
+    // other kernels)
+    const std::string key = sig + (f3 == 0 ? " fuse no3" : f3 == 1 ? " fuse 3" : " fuse") + " pm" +
+                            std::to_string(ps[0]->pm);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            if (it->second.fr > 0 && fuse_fit(sh, max_nx, it->second.fr, it->second.fzc) && it->second.tr > 0)
-                (void)fuse3_fit(sh, max_nx, it->second.tr, it->second.tzc);
+            sh.fr = it->second.fr;
+            sh.fzc = it->second.fzc;
+            sh.fwpr = it->second.fwpr;
+            sh.tr = it->second.tr;
+            sh.tzc = it->second.tzc;
+            sh.twpr = it->second.twpr;
             return Status::ok();
         }
     }
@@ -2063,17 +2104,32 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         (void)hipEventElapsedTime(&ms, e0, e1);
         const float sw = ms / 3 / (width == 1 ? 4 : 2 * width);
         if (log_on())
-            std::fprintf(stderr, "cuth: fuse width %d shape %d,%d %.4f ms per sweep\n", width,
-                         width == 3 ? c.tr : c.fr, width == 3 ? c.tzc : c.fzc, sw);
+            std::fprintf(stderr, "cuth: fuse width %d shape %d,%d,%d %.4f ms per sweep\n", width,
+                         width == 3 ? c.tr : c.fr, width == 3 ? c.tzc : c.fzc,
+                         width == 3 ? c.twpr : c.fwpr, sw);
         return sw;
     };
     float best_sw = INFINITY;
     Shape best = sh;
-    const int cand[][2] = {{0, 0}, {4, 8}, {2, 8}, {2, 16}, {4, 4}, {1, 16}};
+    // candidates (R, zc, wcap): rows per workgroup, layers per chunk, and 0 for
+    // whole rows or the wavefronts per row of an x window; shapes that fit to
+    // the same workgroup as an earlier candidate are skipped
+    std::vector<Shape> tried;
+    auto seen = [&](const Shape &c, bool triple) {
+        for (const Shape &t : tried) {
+            if (!triple && t.tr == 0 && t.fr == c.fr && t.fzc == c.fzc && t.fwpr == c.fwpr) return true;
+            if (triple && t.tr > 0 && t.tr == c.tr && t.tzc == c.tzc && t.twpr == c.twpr) return true;
+        }
+        tried.push_back(c);
+        return false;
+    };
+    const int cand[][3] = {{0, 0, 0}, {4, 8, 0}, {2, 8, 0}, {2, 16, 0}, {4, 4, 0}, {1, 16, 0},
+                           {8, 8, 1}, {14, 10, 1}, {6, 8, 2}};
     for (const auto &cd : cand) {
         Shape c = sh;
         c.fr = 0;
-        if (cd[0] > 0 && !fuse_fit(c, max_nx, cd[0], cd[1])) continue;
+        c.tr = 0;
+        if (cd[0] > 0 && (!fuse_fit(c, max_nx, cd[0], cd[1], cd[2]) || seen(c, false))) continue;
         const float sw = per_sweep(c, cd[0] > 0 ? 2 : 1);
         if (st.bad()) break;
         if (sw >= 0.f && sw < best_sw * kTuneMargin) {
@@ -2082,16 +2138,18 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         }
     }
     // fused triples where pairs run and a triple fits before the last sweep
-    // (forced triples bring pairs for the rest where single sweeps won)
+    // (degree 6 and up: the first triple covers sweeps 2-4 and ends before the
+    // last sweep); forced triples bring pairs for the rest where single sweeps won
     if (!st.bad() && f3 == 1 && best.fr == 0) {
         Shape c = best;
         if (fuse_fit(c, max_nx, 2, 8)) best = c;
     }
-    if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 7) {
-        const int cand3[][2] = {{4, 8}, {2, 8}, {4, 16}};
+    if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 6) {
+        const int cand3[][3] = {{4, 8, 0}, {2, 8, 0}, {4, 16, 0}, {12, 10, 1}, {12, 20, 1},
+                                {8, 20, 1}, {8, 10, 1}, {4, 10, 2}};
         for (const auto &cd : cand3) {
             Shape c = best;
-            if (!fuse3_fit(c, max_nx, cd[0], cd[1])) continue;
+            if (!fuse3_fit(c, max_nx, cd[0], cd[1], cd[2]) || seen(c, true)) continue;
             const float sw = per_sweep(c, 3);
             if (st.bad()) break;
             if (sw >= 0.f && (f3 == 1 || sw < best_sw * kTuneMargin3)) {
@@ -2101,6 +2159,9 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
             }
         }
     }
+    if (log_on())
+        std::fprintf(stderr, "cuth: fuse choice pairs %d,%d,%d triples %d,%d,%d\n", best.fr, best.fzc,
+                     best.fwpr, best.tr, best.tzc, best.twpr);
     for (Problem *p : ps) p->inner = false;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2150,32 +2211,48 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
         const int np = (int)sys.size() * nrhs;
         std::vector<Problem> probs(np);
         std::vector<Problem *> ps(np);
-        // pooled work vectors
         int64_t ntot = 0;
         for (int s : sys) ntot += grids[s]->N * nrhs;
-        float *pool32 = nullptr;
-        double *pool64 = nullptr, *poolth = nullptr;
         // FP32 pools hold two more iterates when general sweeps run as fused pairs
         const bool fuse32 = (mixed || staged) && fuse_env() != 0;
         const int nvec = fuse32 ? 10 : 8;
-        Status st;
-        if ((st = dev_alloc(&poolth, (size_t)ntot * 2)).bad()) return st;
-        if (mixed || staged) st = dev_alloc(&pool32, (size_t)ntot * nvec);
-        if (!st.bad() && !mixed) st = dev_alloc(&pool64, (size_t)ntot * nvec);
-        if (st.bad()) {
-            dev_free(pool32);
-            dev_free(poolth);
-            return st;
-        }
-        int64_t off = 0;
-        int n = 0;
-        size_t nb_max = kRedBlocks;
         std::ostringstream sig;
         const bool h16 = group == 1 && (o.precision == CUTH_MIXED16 || staged);
         sig << (mixed ? "f32" : staged ? "f64s" : "f64") << (group ? (h16 ? "pc16" : "pc") : "mf");
+        for (int s : sys) sig << ' ' << grids[s]->nx << 'x' << grids[s]->ny << 'x' << grids[s]->nz;
+        sig << " r" << nrhs;
+        // workgroup slots: the largest of the candidate launch shapes
+        size_t nb_max = kRedBlocks;
+        for (int s : sys)
+            nb_max += (size_t)nrhs * tiles_x(grids[s]->nx, 1) * grids[s]->ny * tiles_z(grids[s]->nz, 4);
+        // the tuners' timed sweeps read the constants of sweeps up to j = 5, so
+        // the constant rows hold at least 6 sweeps whatever the degree
+        const int kcap = std::max(o.cheb_degree, 6);
+        // pooled work vectors and the engine, kept by the first grid for the
+        // next call with the same signature
+        BatchPool &bp = grids[sys[0]]->batch[group];
+        std::ostringstream pkey;
+        pkey << sig.str() << " v" << nvec << " k" << kcap;
+        Status st;
+        if (bp.key != pkey.str()) {
+            batch_pool_free(bp);
+            st = dev_alloc(&bp.poolth, (size_t)ntot * 2);
+            if (!st.bad() && (mixed || staged)) st = dev_alloc(&bp.pool32, (size_t)ntot * nvec);
+            if (!st.bad() && !mixed) st = dev_alloc(&bp.pool64, (size_t)ntot * nvec);
+            if (!st.bad()) st = engine_alloc(bp.E, np, kcap, nb_max);
+            if (st.bad()) {
+                batch_pool_free(bp);
+                return st;
+            }
+            bp.key = pkey.str();
+        }
+        float *pool32 = bp.pool32;
+        double *pool64 = bp.pool64, *poolth = bp.poolth;
+        Engine &E = bp.E;
+        int64_t off = 0;
+        int n = 0;
         for (int s : sys) {
             Grid &g = *grids[s];
-            sig << ' ' << g.nx << 'x' << g.ny << 'x' << g.nz;
             for (int q = 0; q < nrhs; ++q, ++n) {
                 Problem &p = probs[n];
                 p.g = &g;
@@ -2215,20 +2292,6 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
                 ps[n] = &p;
             }
         }
-        sig << " r" << nrhs;
-        // workgroup slots: the largest of the candidate launch shapes
-        for (Problem *p : ps)
-            nb_max += (size_t)tiles_x(p->g->nx, 1) * p->g->ny * tiles_z(p->g->nz, 4);
-        Engine E;
-        // the tuners' timed sweeps read the constants of sweeps up to j = 5, so
-        // the constant rows hold at least 6 sweeps whatever the degree
-        if ((st = engine_alloc(E, np, std::max(o.cheb_degree, 6), nb_max)).bad()) {
-            engine_free(E);
-            dev_free(pool32);
-            dev_free(pool64);
-            dev_free(poolth);
-            return st;
-        }
         // inner shape: autotuned on the problems' own inner work vectors; the
         // FP64 residual (once per refinement cycle) uses a fixed shape in mixed
         // precision, since no FP64 work vectors exist then
@@ -2250,10 +2313,7 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
             const bool use_graph = graph_env() != 0;
             ts = run_set(E, ps, user, sh_in, sh64, o, period, use_graph, nullptr);
         }
-        engine_free(E);
-        dev_free(pool32);
-        dev_free(pool64);
-        dev_free(poolth);
+        if (ts.code == CUTH_E_DEVICE || ts.code == CUTH_E_NOMEM) batch_pool_free(bp);
         if (ts.code == CUTH_E_DEVICE || ts.code == CUTH_E_NOMEM || ts.code == CUTH_E_INVALID) return ts;
         n = 0;
         for (int s : sys)

@@ -722,6 +722,51 @@ def test_fused_triples_shallow_and_narrow(monkeypatch, dims, shape):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(520, 7, 5, True), (1024, 6, 3, False), (262, 5, 4, True),
+                                  (131, 6, 5, False)])
+@pytest.mark.parametrize("pc", ["chebyshev", "chebyshev_jacobi"])
+def test_fused_x_windows(monkeypatch, dims, pc):
+    """Fused pairs and triples over rows longer than a workgroup row, split
+    into overlapping x windows (one or two wavefronts per row, halo lanes at
+    each window's edges): lane widths 4, 2 and 1, a last window that is only
+    partly inside the grid, per-cell and per-layer conductances, the paper's
+    polynomial and the Jacobi-scaled one.  Against single sweeps (same
+    arithmetic, 1e-6 of the scale) and the oracle (FP32 bar)."""
+    nx, ny, nl, mult = dims
+    layers = ("Si", "BEOL", "bond", "TIM", "Cu")[:nl]
+    say(f"x windows {dims} {pc}")
+    st = ragged_stack(nx, ny, layers=layers, mult=mult, seed=19)
+    A = assembly.assemble(st)
+    jac = pc == "chebyshev_jacobi"
+    if jac:
+        lmin, lmax = krylov.jacobi_spectral_bounds(A, w.lanczos_start(st.n))
+    else:
+        lmin, lmax = krylov.spectral_bounds(A, w.lanczos_start(st.n))
+    r = np.random.default_rng(23).standard_normal(st.n)
+    g = grid_of(st)
+    for degree in (6, 9, 30):
+        if jac:
+            ref = krylov.jacobi_chebyshev_precondition(A, r, lmin, lmax, degree)
+        else:
+            ref = krylov.chebyshev_precondition(lambda v: A @ v, r, lmin, lmax, degree)
+        bar = fp32_cheb_bar(A, r, lmin, lmax, degree, ref, jacobi=jac)
+        monkeypatch.setenv("CUTH_FUSE", "0")
+        z1 = g.precond_apply(t32(r), lmin, lmax, degree, preconditioner=pc).cpu().numpy().astype(np.float64)
+        for pair, triple in (("4,8,1", None), ("2,3,2", None), ("2,8,1", "8,4,1"), ("2,8,1", "3,16,2"),
+                             ("2,8", "2,8,1")):
+            monkeypatch.setenv("CUTH_FUSE", "1")
+            monkeypatch.setenv("CUTH_FUSE_SHAPE", pair)
+            if triple:
+                monkeypatch.setenv("CUTH_FUSE3", "1")
+                monkeypatch.setenv("CUTH_FUSE3_SHAPE", triple)
+            z2 = g.precond_apply(t32(r), lmin, lmax, degree, preconditioner=pc).cpu().numpy().astype(np.float64)
+            if triple:
+                monkeypatch.delenv("CUTH_FUSE3")
+            assert np.abs(z2 - z1).max() <= 1e-6 * np.abs(z1).max(), (degree, pair, triple)
+            assert np.abs(z2 - ref).max() <= bar, (degree, pair, triple)
+    g.close()
+
+
 def test_fused_triple_solves(monkeypatch):
     """Mixed solves with fused sweep triples (and pairs for the rest) reach the
     1e-8 bar: steady on a lognormal and a uniform grid, one backward-Euler step,
@@ -907,8 +952,8 @@ def test_inner_stop_on_drift():
     """Eq. switching (c), drift: FP64 Chebyshev-PCG asked for an unattainable
     relative residual (1e-300).  Its recursive residual keeps falling
     geometrically while the true residual rhat - A x settles at the FP64
-    rounding floor, so every inner solve ends on ||r_true - r_low|| >=
-    0.5 ||r_true|| (checked every 5 iterations).  The hot restart after it
+    rounding floor, so the inner solves end on ||r_true - r_low|| >=
+    0.5 ||r_true|| (checked every 5 iterations).  The hot restarts after them
     cannot halve the true residual, so the call reports NOT_CONVERGED with the
     best iterate, which meets the FP64 bar against the oracle."""
     import paper_2606_17850_amd as cuth
@@ -921,9 +966,13 @@ def test_inner_stop_on_drift():
     s = e.value.stats
     say(f"  {s}")
     assert e.value.status == cuth._lib.CUTH_E_NOT_CONVERGED
+    # the last inner solve stopped on drift, the first one too (its recursive
+    # residual falls through the floor of a true residual that started at
+    # ||b||); a hot-restarted one may stop earlier, on the plateau of its true
+    # residual (stagnation), which is the other test of the same floor
     assert s["stop_reason"] == 2
-    assert s["drift_stops"] == s["outer_cycles"] >= 1
-    assert s["stagnation_stops"] == 0
+    assert s["drift_stops"] >= 2 and s["outer_cycles"] >= 2
+    assert s["drift_stops"] + s["stagnation_stops"] == s["outer_cycles"]
     assert rise_err(T.cpu().numpy(), _ref_steady(st, P), st.t_amb) <= 1e-10
     g.close()
 
