@@ -315,6 +315,32 @@ cuth_status cuth_residual(cuth_grid g, double dt, const double *b, const double 
 cuth_status cuth_precond_apply(cuth_grid g, double dt, int32_t precision, int32_t preconditioner,
                                double lmin, double lmax, int32_t degree, const void *r, void *z);
 
+/* ---- allocation-free entry point ---- */
+
+/* Bytes of device memory the library holds on every GPU it runs on, until the
+ * process ends, for cuth_precond_apply_noalloc. */
+#define CUTH_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same z = M^{-1} r
+ * as cuth_precond_apply, with the same arguments, validation and result, but
+ * the call allocates nothing.  Every device buffer it needs besides r, z and
+ * the operator the handle built at creation (the problem descriptor and its
+ * state, the polynomial's constants, the layer coefficients of dt, the
+ * reduction partials and the one iterate that is not z) lives in a per-device
+ * scratch array of CUTH_NOALLOC_SCRATCH_BYTES; the small parts are written into
+ * it by kernel arguments, and the state is cleared on every call.  The sweeps
+ * run one per launch (never fused).  Scratch needed: about N * 4 bytes (FP32,
+ * CUTH_MIXED and CUTH_MIXED16) or N * 8 bytes (CUTH_FP64), plus a few KiB and
+ * 384 bytes per stencil workgroup; a grid that needs more returns
+ * CUTH_E_INVALID before any device work, with the sizes in cuth_last_error().
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (other host threads, other streams) race and give undefined results.  Returns
+ * after the handle's stream has completed the work, like cuth_precond_apply. */
+cuth_status cuth_precond_apply_noalloc(cuth_grid g, double dt, int32_t precision,
+                                       int32_t preconditioner, double lmin, double lmax,
+                                       int32_t degree, const void *r, void *z);
+
 /* FP32 Lanczos with `steps` steps on the FP32 operator (preconditioner
  * CUTH_PC_CHEBYSHEV: A; CUTH_PC_CHEBYSHEV_JACOBI: D^{-1/2} A D^{-1/2}, whose
  * spectrum is that of D^{-1} A; other values CUTH_E_INVALID), start vector v0

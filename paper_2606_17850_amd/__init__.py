@@ -233,6 +233,19 @@ class Grid:
                                                 self._vec(r, "r", r.dtype), z.data_ptr()))
         return z
 
+    def precond_apply_noalloc(self, r: torch.Tensor, z: torch.Tensor, lmin: float, lmax: float,
+                              degree: int, dt: float = 0.0, fp16_coef: bool = False,
+                              preconditioner: str = "chebyshev") -> torch.Tensor:
+        """As precond_apply, into the caller's z, through the entry point that
+        allocates no device memory."""
+        prec = CUTH_FP64 if r.dtype == torch.float64 else (CUTH_MIXED16 if fp16_coef else CUTH_MIXED)
+        pc = _lib.PRECONDITIONERS[preconditioner]
+        with torch.cuda.device(self.device):
+            _check(library().cuth_precond_apply_noalloc(
+                self._h, float(dt), prec, pc, float(lmin), float(lmax), int(degree),
+                self._vec(r, "r", r.dtype), self._vec(z, "z", r.dtype)))
+        return z
+
     def reset_bounds(self):
         _check(library().cuth_grid_reset_bounds(self._h))
 

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGE
 EXPORTED = (
     "cuth_default_options", "cuth_grid_create", "cuth_grid_destroy", "cuth_solve",
     "cuth_transient_step", "cuth_solve_batch", "cuth_adjoint", "cuth_last_error",
-    "cuth_apply", "cuth_apply_csr", "cuth_residual", "cuth_precond_apply", "cuth_spectral_bounds",
+    "cuth_apply", "cuth_apply_csr", "cuth_residual", "cuth_precond_apply",
+    "cuth_precond_apply_noalloc", "cuth_spectral_bounds",
     "cuth_grid_reset_bounds", "cuth_profile_enable", "cuth_profile_read",
 )
 
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
         "cuth_residual": (ctypes.c_int, [vp, dbl, vp, vp, vp]),
         "cuth_apply_csr": (ctypes.c_int, [vp, dbl, vp, vp]),
         "cuth_precond_apply": (ctypes.c_int, [vp, dbl, i32, i32, dbl, dbl, i32, vp, vp]),
+        "cuth_precond_apply_noalloc": (ctypes.c_int, [vp, dbl, i32, i32, dbl, dbl, i32, vp, vp]),
         "cuth_spectral_bounds": (ctypes.c_int, [vp, dbl, i32, i32, vp, c_double_p, c_double_p,
                                                 c_double_p, c_double_p, c_double_p, c_double_p]),
         "cuth_grid_reset_bounds": (ctypes.c_int, [vp]),

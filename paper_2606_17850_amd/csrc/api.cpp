@@ -280,6 +280,28 @@ cuth_status cuth_precond_apply(cuth_grid h, double dt, int32_t precision, int32_
     });
 }
 
+cuth_status cuth_precond_apply_noalloc(cuth_grid h, double dt, int32_t precision,
+                                       int32_t preconditioner, double lmin, double lmax,
+                                       int32_t degree, const void *r, void *z) {
+    return guarded([&]() -> cuth_status {
+        if (check_handle(h) != CUTH_OK) return CUTH_E_INVALID;
+        cuth::Grid &g = *h->g;
+        if (!r || !z) return fail(CUTH_E_INVALID, "r and z are required");
+        if (r == z) return fail(CUTH_E_INVALID, "r and z must not alias");
+        if (precision != CUTH_FP64 && precision != CUTH_MIXED && precision != CUTH_MIXED16)
+            return fail(CUTH_E_INVALID, "bad precision");
+        if (preconditioner < CUTH_PC_CHEBYSHEV || preconditioner > CUTH_PC_CHEBYSHEV_JACOBI)
+            return fail(CUTH_E_INVALID, "preconditioner must be a cuth_preconditioner value");
+        if (!finite_pos(lmin) || !finite_pos(lmax) || !(lmax > lmin))
+            return fail(CUTH_E_INVALID, "need 0 < lmin < lmax");
+        if (degree < 1 || degree > 256) return fail(CUTH_E_INVALID, "degree must be in 1..256");
+        if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(CUTH_E_INVALID, "dt must be >= 0");
+        if (dt > 0.0 && !g.has_cap) return fail(CUTH_E_INVALID, "dt > 0 needs heat_cap");
+        return report(
+            cuth::precond_apply_noalloc(g, dt, precision, preconditioner, lmin, lmax, degree, r, z));
+    });
+}
+
 cuth_status cuth_spectral_bounds(cuth_grid h, double dt, int32_t preconditioner, int32_t steps,
                                  const float *v0, double *alpha, double *beta, double *ritz_min,
                                  double *ritz_max, double *lmin, double *lmax) {

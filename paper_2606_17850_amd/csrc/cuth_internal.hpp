@@ -303,4 +303,16 @@ void launch_lanczos_div(int64_t n, int j, float *w, float *lz, const float *part
 void launch_adjoint(const OpView<double> &op, const double *lam, const double *T, double t_amb,
                     const double *fac, double *part, double *dL_dk, hipStream_t s);
 
+// ---- allocation-free entry point (kernels.hip) --------------------------------
+// Bytes of the per-device scratch array that cuth_precond_apply_noalloc takes
+// every device buffer from (beyond its r, z and the grid's operator planes).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// Device address of the scratch array on `device`: looked up once per device
+// with that device current, then returned from the cache.
+hipError_t noalloc_scratch(int device, unsigned char **ptr);
+// Copy n host bytes (a multiple of 4) to the device address dst in stream
+// order, carried by kernel arguments (2 KiB per launch): no staging buffer and
+// no allocation.
+hipError_t launch_put(const void *src, size_t n, void *dst, hipStream_t s);
+
 }  // namespace cuth

@@ -178,6 +178,11 @@ Status solve_batch(int nsys, Grid *const *grids, int nrhs, const double *const *
 
 Status precond_apply(Grid &g, double dt, int precision, int preconditioner, double lmin,
                      double lmax, int degree, const void *r, void *z);
+// As precond_apply, with every device buffer beyond r, z and the grid's operator
+// planes taken from the per-device scratch array (no device allocation); single
+// sweeps only.
+Status precond_apply_noalloc(Grid &g, double dt, int precision, int preconditioner, double lmin,
+                             double lmax, int degree, const void *r, void *z);
 Status apply_op(Grid &g, double dt, int precision, const void *x, void *y);
 Status residual(Grid &g, double dt, const double *b, const double *T, double *r);
 Status apply_csr(Grid &g, double dt, const double *x, double *y);

@@ -34,6 +34,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 
@@ -2205,5 +2207,71 @@ template void launch_residual_b<float, float>(const OuterProb<float, float> *, i
                                               int, double *, hipStream_t);
 template void launch_residual_b<double, double>(const OuterProb<double, double> *, int, int, bool,
                                                 int, int, double *, hipStream_t);
+
+// ------------------------------------------------ allocation-free scratch
+// Device memory of the allocation-free preconditioner entry point: one array
+// per device, held until the process ends.  On the host the array's name is a
+// stand-in, not a device address, so host code never hands it to a kernel or a
+// copy: it uses the address hipGetSymbolAddress returns for the device.
+namespace {
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kPutWords = 512;   // 2 KiB of kernel arguments per launch
+struct PutBlob {
+    unsigned int w[kPutWords];
+};
+
+__global__ __launch_bounds__(256) void k_put(PutBlob src, unsigned int *__restrict__ dst, int nw) {
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src.w[i];
+}
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, unsigned char **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // the lookup runs once per device, with that device current
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_put(const void *src, size_t n, void *dst, hipStream_t s) {
+    const unsigned char *in = static_cast<const unsigned char *>(src);
+    unsigned char *out = static_cast<unsigned char *>(dst);
+    if (reinterpret_cast<uintptr_t>(out) % 4 != 0 || n % 4 != 0) return hipErrorInvalidValue;
+    while (n > 0) {
+        const size_t m = std::min(n, sizeof(PutBlob));
+        PutBlob b;
+        std::memset(&b, 0, sizeof b);
+        std::memcpy(&b, in, m);
+        hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, s, b,
+                           reinterpret_cast<unsigned int *>(out), (int)(m / 4));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        in += m;
+        out += m;
+        n -= m;
+    }
+    return hipSuccess;
+}
 
 }  // namespace cuth

@@ -2473,6 +2473,138 @@ Status precond_apply(Grid &g, double dt, int precision, int pm, double lmin, dou
                                  (double *)z);
 }
 
+// Scratch layout of one allocation-free preconditioner application: each part
+// starts on a 256-byte boundary.
+struct NoAllocLayout {
+    size_t desc = 0, state = 0, cheb = 0, layers = 0, part = 0, iter = 0, total = 0;
+    size_t slot_doubles = 0;
+};
+
+template <typename T>
+static NoAllocLayout noalloc_layout(const Grid &g, int kcap, int nb) {
+    NoAllocLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    L.desc = take(sizeof(InnerProb<T>));
+    L.state = take(sizeof(CgState<T>));
+    L.cheb = take(sizeof(T) * (1 + 2 * (size_t)kcap));
+    L.layers = take(sizeof(LayerCoef<T>) * (size_t)g.nz);
+    L.slot_doubles = std::max<size_t>(8 * (size_t)std::max(nb, 1), 3);
+    L.part = take(sizeof(double) * L.slot_doubles * P_SLOTS);
+    L.iter = take(sizeof(T) * (size_t)g.N);
+    L.total = off;
+    return L;
+}
+
+// z = M^{-1} r as precond_typed runs it with single sweeps, but every buffer
+// the kernels use besides r, z and the grid's planes (the problem descriptor,
+// its state, the sweep constants, the layer coefficients of dt, the partials
+// and the one iterate that is not z) lives in the scratch array; the small ones
+// are written there by kernel arguments.  The state is cleared on every call.
+template <typename T>
+static Status precond_noalloc_typed(Grid &g, double dt, const ChebConsts &cc, int pm, bool h16,
+                                    const T *r, T *z) {
+    Shape sh = sizeof(T) == 4 ? g.sh32 : g.sh64;
+    sh.fr = 0;
+    sh.tr = 0;
+    const bool h16e = sizeof(T) == 4 && h16 && g.per_cell;
+    const int kcap = std::max(cc.k, 1);
+    const int nb = prob_tiles(g, sh);
+    const NoAllocLayout L = noalloc_layout<T>(g, kcap, nb);
+    if (L.total > kNoAllocScratchBytes)
+        return Status::err(CUTH_E_INVALID,
+                           "allocation-free preconditioner: this grid needs " + std::to_string(L.total) +
+                               " bytes of scratch, above the " +
+                               std::to_string(kNoAllocScratchBytes) + " the library holds per device");
+    unsigned char *base = nullptr;
+    CUTH_HIP(noalloc_scratch(g.device, &base));
+    // host images of the small parts
+    std::vector<LayerCoef<double>> hlc;
+    double gersh = 0.0;
+    layer_coefs(g, dt, hlc, gersh);
+    std::vector<LayerCoef<T>> hl;
+    if constexpr (sizeof(T) == 4) hl = layer_coefs32(hlc);
+    else hl = hlc;
+    std::vector<T> hc((size_t)1 + 2 * kcap, T(0));
+    hc[0] = (T)cc.inv_th;
+    for (int j = 1; j < cc.k; ++j) {
+        hc[1 + j] = (T)cc.c1[j];
+        hc[1 + kcap + j] = (T)cc.c2[j];
+    }
+    const int zfin = precond_final(cc.k, pm, 0);
+    T *it = reinterpret_cast<T *>(base + L.iter);
+    OpView<T> v{g.nx, g.ny, g.nz, nullptr, nullptr,
+                reinterpret_cast<const LayerCoef<T> *>(base + L.layers), sh.vx, sh.by, sh.zc};
+    if constexpr (sizeof(T) == 4) {
+        if (g.per_cell) {
+            v.gx = g.gx32;
+            v.gy = g.gy32;
+        }
+        if (h16e) {
+            v.hx = g.hx;
+            v.hy = g.hy;
+        }
+    } else if (g.per_cell) {
+        v.gx = g.gx64;
+        v.gy = g.gy64;
+    }
+    InnerProb<T> d{};
+    d.op = v;
+    d.ntx = tiles_x(g.nx, sh.vx);
+    d.ntz = tiles_z(g.nz, sh.zc);
+    d.tile0 = 0;
+    d.ntiles = nb;
+    // the preconditioner's kernels read r and the iterates only; the CG
+    // vectors point at the scratch iterate so that none is null
+    d.x = d.rhat = d.mu = it;
+    d.p[0] = d.p[1] = it;
+    d.r = const_cast<T *>(r);
+    for (T *&zz : d.z) zz = it;
+    d.z[zfin] = z;
+    d.st = reinterpret_cast<CgState<T> *>(base + L.state);
+    d.cheb = reinterpret_cast<const T *>(base + L.cheb);
+    d.kcap = kcap;
+    const CgState<T> st0{};
+    CUTH_HIP(launch_put(&d, sizeof d, base + L.desc, g.stream));
+    CUTH_HIP(launch_put(&st0, sizeof st0, base + L.state, g.stream));
+    CUTH_HIP(launch_put(hc.data(), sizeof(T) * hc.size(), base + L.cheb, g.stream));
+    CUTH_HIP(launch_put(hl.data(), sizeof(LayerCoef<T>) * hl.size(), base + L.layers, g.stream));
+    // an engine of one problem over the scratch (no host arrays: single sweeps
+    // never read them)
+    Engine E;
+    E.cap = 1;
+    E.kcap = kcap;
+    E.slot_doubles = L.slot_doubles;
+    E.part = reinterpret_cast<double *>(base + L.part);
+    if constexpr (sizeof(T) == 4) {
+        E.in32 = reinterpret_cast<InnerProb<float> *>(base + L.desc);
+        E.st32 = reinterpret_cast<CgState<float> *>(base + L.state);
+        E.cheb32 = reinterpret_cast<float *>(base + L.cheb);
+    } else {
+        E.in64 = reinterpret_cast<InnerProb<double> *>(base + L.desc);
+        E.st64 = reinterpret_cast<CgState<double> *>(base + L.state);
+        E.cheb64 = reinterpret_cast<double *>(base + L.cheb);
+    }
+    const int got = enqueue_precond<T>(E, 1, nb, g.per_cell, h16e ? CS_F16 : CS_OWN, pm, sh, cc.k,
+                                       false, false, g.stream, nullptr);
+    if (got != zfin) return Status::err(CUTH_E_DEVICE, "internal: preconditioner buffer mismatch");
+    CUTH_HIP(hipGetLastError());
+    return sync_stream(g.stream);
+}
+
+Status precond_apply_noalloc(Grid &g, double dt, int precision, int pm, double lmin, double lmax,
+                             int degree, const void *r, void *z) {
+    const ChebConsts cc = make_cheb(lmin, lmax, is_cheb(pm) ? degree : 1);
+    if (precision != CUTH_FP64)
+        return precond_noalloc_typed<float>(g, dt, cc, pm, precision == CUTH_MIXED16,
+                                            (const float *)r, (float *)z);
+    return precond_noalloc_typed<double>(g, dt, cc, pm, false, (const double *)r, (double *)z);
+}
+
 Status adjoint(Grid &g, const double *T, const double *dL_dT, double *dL_dP, double *dL_dk,
                const cuth_options &o, cuth_stats *stats) {
     Status st = solve_system(g, 0.0, dL_dT, nullptr, nullptr, 0.0, dL_dP, 0.0, o, stats, false);
