@@ -41,12 +41,14 @@
  *    pairs (unset: chosen per grid or batch by timing); CUTH_FUSE_SHAPE="R,zc"
  *    with CUTH_FUSE=1: rows per workgroup and layers per chunk (default 2,8).
  *  - CUTH_FUSE3=0/1: never / always fuse them in triples, with pairs for the
- *    sweeps left over (unset: chosen by timing against the pairs; with
- *    CUTH_FUSE unset, =1 takes the first triple shape that fits);
+ *    sweeps left over (unset: chosen by timing against the single sweeps or
+ *    pairs that won; with CUTH_FUSE unset, =1 takes the first triple shape
+ *    that fits);
  *    CUTH_FUSE3_SHAPE="R,zc" with CUTH_FUSE=1 and CUTH_FUSE3=1 (default 4,8).
  *  - CUTH_AUTOTUNE_CACHE=<file>: keep the tuned tile shapes of batches there.
- *  - CUTH_GRAPH=0/1: replay CG chunks from a captured HIP graph (default:
- *    batches of more than one problem).
+ *  - CUTH_GRAPH=0/1: replay CG chunks from captured HIP graphs, kept by the
+ *    handle between solves (default: batches, and single solves of grids of
+ *    at most 2^21 unknowns, whose kernels are shorter than a host launch).
  *  - CUTH_REDUCE_ABOVE=<n>: workgroups per problem above which the CG sums go
  *    through a separate reduce launch (default 4096).
  *  - CUTH_LOG=1: tuning results and one line per refinement cycle on stderr.

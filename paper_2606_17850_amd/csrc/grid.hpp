@@ -82,6 +82,10 @@ struct Engine {
     double *part = nullptr, *h_part = nullptr;   // 5 slots of slot_doubles
     hipStream_t own = nullptr;                   // stream for graph capture
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // instantiated chunks of CG iterations, by launch configuration: a chunk's
+    // kernel arguments depend only on that configuration and the engine's own
+    // buffers (the descriptors they point to are re-uploaded per inner solve)
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
 };
 
 // Work vectors and engine of a batched solve, kept between calls with the same

@@ -133,15 +133,14 @@ bool log_on() {
     return on;
 }
 
-// CUTH_GRAPH=0/1 overrides whether a chunk of CG iterations is captured once
-// into a HIP graph and replayed (default: batches of more than one problem).
+// CUTH_GRAPH=0/1 overrides whether chunks of CG iterations are captured into
+// HIP graphs and replayed (default: batches, and single solves of grids up to
+// kGraphMaxN unknowns, whose kernels are shorter than a launch from the host).
 int graph_env() {
-    static const int v = [] {
-        const char *e = std::getenv("CUTH_GRAPH");
-        return e ? (e[0] == '1' ? 1 : 0) : -1;
-    }();
-    return v;
+    const char *e = std::getenv("CUTH_GRAPH");
+    return e ? (e[0] == '1' ? 1 : 0) : -1;
 }
+constexpr int64_t kGraphMaxN = int64_t(1) << 21;
 
 // Coefficients of the Chebyshev sweeps for degree k on [lmin, lmax]: with
 // theta = (lmax+lmin)/2, delta = (lmax-lmin)/2, sigma1 = theta/delta,
@@ -376,6 +375,8 @@ Status engine_alloc(Engine &E, int cap, int kcap, size_t nb_max) {
 
 void engine_free(Engine &E) {
     if (E.own) (void)hipStreamSynchronize(E.own);
+    for (auto &g : E.graphs) (void)hipGraphExecDestroy(g.second);
+    E.graphs.clear();
     dev_free(E.in32);
     dev_free(E.in64);
     dev_free(E.out32);
@@ -692,34 +693,62 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>) * nprob, hipMemcpyHostToDevice, s));
     const int zfin = enqueue_precond<T>(E, nprob, nb, pc, cs, pm, sh, k, false, red, s, prof);
     const bool graph = use_graph && period % 2 == 0;
-    hipGraphExec_t exec = nullptr;
-    if (graph) {
+    // instantiated chunk of `len` iterations (len even: the arguments repeat
+    // with the iteration's parity), captured on first use and kept by the
+    // engine for later inner solves of the same configuration
+    auto chunk_graph = [&](int len, hipGraphExec_t &out) -> Status {
+        std::ostringstream key;
+        key << sizeof(T) << ' ' << nprob << ' ' << nb << ' ' << pc << ' ' << cs << ' ' << pm << ' '
+            << k << ' ' << len << ' ' << zfin << ' ' << red << ' ' << sh.vx << ',' << sh.by << ','
+            << sh.zc << ',' << sh.fr << ',' << sh.fzc << ',' << sh.fwpr << ',' << sh.tr << ','
+            << sh.tzc << ',' << sh.twpr;
+        for (auto &g : E.graphs)
+            if (g.first == key.str()) {
+                out = g.second;
+                return Status::ok();
+            }
         hipGraph_t gr = nullptr;
         CUTH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_iterations<T>(E, nprob, nb, pc, cs, pm, sh, k, 0, period, zfin, red, s, nullptr);
+        enqueue_iterations<T>(E, nprob, nb, pc, cs, pm, sh, k, 0, len, zfin, red, s, nullptr);
         CUTH_HIP(hipStreamEndCapture(s, &gr));
-        const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(&out, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (ie != hipSuccess) return Status::err(CUTH_E_DEVICE, "hipGraphInstantiate failed");
-    }
+        E.graphs.emplace_back(key.str(), out);
+        return Status::ok();
+    };
+    hipGraphExec_t exec = nullptr, exec2 = nullptr;
+    if (graph) CUTH_TRY(chunk_graph(period, exec));
     std::vector<double> sums(2 * (size_t)nprob, 0.0);
     int it = 0, nchecks = 0;
     Status result = Status::ok();
     // one more host check where the last inner solve of this cycle on this
     // operator stopped: a stop found on the device is only seen at the next
-    // check, and every iteration launched before that runs empty
+    // check, and every iteration launched before that runs empty (with graphs,
+    // chunks of two iterations run up to the predicted stop)
     const int pi = sizeof(T) == 4 ? 1 : 0;
     Problem &p0 = *ps[which[0]];
-    const int pred = (nprob == 1 && !graph) ? p0.su->stop_iter[pi][p0.pm][std::min(p0.cycles, 15)] : 0;
+    const int pred = nprob == 1 ? p0.su->stop_iter[pi][p0.pm][std::min(p0.cycles, 15)] : 0;
     while (it < maxit) {
         int cnt = graph ? period : std::min(period, maxit - it);
-        if (pred > it && pred - it < cnt) cnt = pred - it;
+        // (graph chunks are of even length: rounded up, so that the check comes
+        // at or after the predicted stop, never one iteration before it, where
+        // the stagnation test could fire on the FP32 plateau)
+        if (pred > it && pred - it < cnt) cnt = graph ? (pred - it + 1) & ~1 : pred - it;
         if (graph) {
-            const hipError_t le = hipGraphLaunch(exec, s);
-            if (le != hipSuccess) {
-                result = Status::err(CUTH_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
-                break;
+            hipGraphExec_t ex = exec;
+            if (cnt != period) {
+                if (!exec2) CUTH_TRY(chunk_graph(2, exec2));
+                ex = exec2;
             }
+            for (int q = 0; q < (cnt == period ? 1 : cnt / 2); ++q) {
+                const hipError_t le = hipGraphLaunch(ex, s);
+                if (le != hipSuccess) {
+                    result = Status::err(CUTH_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(le));
+                    break;
+                }
+            }
+            if (result.bad()) break;
         } else {
             enqueue_iterations<T>(E, nprob, nb, pc, cs, pm, sh, k, it, cnt, zfin, red, s, prof);
         }
@@ -762,7 +791,6 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         }
         if (all_done) break;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
     CUTH_TRY(sync_stream(s));
     CUTH_TRY(result);
     if (nprob == 1 && p0.stop == 1) p0.su->stop_iter[pi][p0.pm][std::min(p0.cycles, 15)] = hs[0].iter;
@@ -1873,7 +1901,8 @@ Status solve_system(Grid &g, double dt, const double *P, const double *Tn, const
     p.th_out = g.thA;
     std::vector<Problem *> ps{&p};
     const int period = o.check_period > 0 ? o.check_period : (transient_defaults ? 5 : 20);
-    const bool use_graph = graph_env() == 1 && !g.prof;
+    const int ge = graph_env();
+    const bool use_graph = !g.prof && (ge == 1 || (ge < 0 && g.N <= kGraphMaxN));
     Shape sh32 = g.sh32;
     if (o.precision != CUTH_FP64 && fuse_env() != 0) {
         // fused pairs of general sweeps where they are faster on this grid
@@ -2053,14 +2082,14 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
     }
     const bool pc = ps[0]->g->per_cell, h16 = pc && ps[0]->h16, jac = ps[0]->pm == CUTH_PC_CHEBYSHEV_JACOBI;
     const hipStream_t s = E.own;
-    hipEvent_t e0, e1;
-    CUTH_HIP(hipEventCreate(&e0));
-    CUTH_HIP(hipEventCreate(&e1));
+    constexpr int kRounds = 5;
+    hipEvent_t ev[kRounds + 1];
+    for (hipEvent_t &e : ev) CUTH_HIP(hipEventCreate(&e));
     for (Problem *p : ps) p->inner = true;
     Status st = Status::ok();
     // milliseconds per general sweep of shape c with launches of `width`
-    // sweeps (1, 2 or 3), from three timed rounds after a warm-up round; a
-    // negative value if the shape does not fit or its launch fails
+    // sweeps (1, 2 or 3), from timed rounds after a warm-up round; a negative
+    // value if the shape does not fit or its launch fails
     auto per_sweep = [&](const Shape &c, int width) -> float {
         std::vector<int> which;
         const int nb = build_inner<T>(E, ps, c, which);
@@ -2093,16 +2122,24 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         };
         round();
         if (hipGetLastError() != hipSuccess) return -1.f;   // e.g. more LDS than a launch may take
-        (void)hipEventRecord(e0, s);
-        for (int rep = 0; rep < 3; ++rep) round();
-        (void)hipEventRecord(e1, s);
+        // the median of kRounds separately timed rounds (one slow round, e.g.
+        // a clock change, does not move it)
+        (void)hipEventRecord(ev[0], s);
+        for (int rep = 0; rep < kRounds; ++rep) {
+            round();
+            (void)hipEventRecord(ev[rep + 1], s);
+        }
         if (hipStreamSynchronize(s) != hipSuccess) {
             st = Status::err(CUTH_E_DEVICE, "tune_fuse: timing launch failed");
             return -1.f;
         }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const float sw = ms / 3 / (width == 1 ? 4 : 2 * width);
+        float t[kRounds];
+        for (int rep = 0; rep < kRounds; ++rep) {
+            t[rep] = 0.f;
+            (void)hipEventElapsedTime(&t[rep], ev[rep], ev[rep + 1]);
+        }
+        std::sort(t, t + kRounds);
+        const float sw = t[kRounds / 2] / (width == 1 ? 4 : 2 * width);
         if (log_on())
             std::fprintf(stderr, "cuth: fuse width %d shape %d,%d,%d %.4f ms per sweep\n", width,
                          width == 3 ? c.tr : c.fr, width == 3 ? c.tzc : c.fzc,
@@ -2137,18 +2174,21 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
             best = c;
         }
     }
-    // fused triples where pairs run and a triple fits before the last sweep
-    // (degree 6 and up: the first triple covers sweeps 2-4 and ends before the
-    // last sweep); forced triples bring pairs for the rest where single sweeps won
-    if (!st.bad() && f3 == 1 && best.fr == 0) {
-        Shape c = best;
-        if (fuse_fit(c, max_nx, 2, 8)) best = c;
-    }
-    if (!st.bad() && best.fr > 0 && f3 != 0 && k >= 6) {
+    // fused triples where a triple fits before the last sweep (degree 6 and
+    // up: the first triple covers sweeps 2-4 and ends before the last sweep),
+    // timed against the winner so far, single sweeps or pairs.  Triples run
+    // with pairs for the sweeps a triple does not fill: where single sweeps
+    // won, a candidate brings the pairs of the smallest shape (any leftover is
+    // at most one launch per application)
+    Shape base3 = best;
+    bool have3 = best.fr > 0;
+    if (!have3) have3 = fuse_fit(base3, max_nx, 2, 8);
+    if (!st.bad() && f3 == 1 && best.fr == 0 && have3) best = base3;
+    if (!st.bad() && have3 && f3 != 0 && k >= 6) {
         const int cand3[][3] = {{4, 8, 0}, {2, 8, 0}, {4, 16, 0}, {12, 10, 1}, {12, 20, 1},
                                 {8, 20, 1}, {8, 10, 1}, {4, 10, 2}};
         for (const auto &cd : cand3) {
-            Shape c = best;
+            Shape c = base3;
             if (!fuse3_fit(c, max_nx, cd[0], cd[1], cd[2]) || seen(c, true)) continue;
             const float sw = per_sweep(c, 3);
             if (st.bad()) break;
@@ -2163,8 +2203,7 @@ Status tune_fuse(Engine &E, std::vector<Problem *> &ps, int k, Shape &sh, const 
         std::fprintf(stderr, "cuth: fuse choice pairs %d,%d,%d triples %d,%d,%d\n", best.fr, best.fzc,
                      best.fwpr, best.tr, best.tzc, best.twpr);
     for (Problem *p : ps) p->inner = false;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
     if (st.bad()) return st;
     sh = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -1016,3 +1016,37 @@ def test_run_twice_bitwise_identical():
     T2, _ = g.solve(t64(P), precision="mixed")
     assert torch.equal(T1, T2)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replays_match_eager(monkeypatch, prec):
+    """Single solves replay captured chunks of CG iterations (kept by the
+    handle between solves): three graph solves, with eager solves and
+    synchronisations between them, each against the eager result and the
+    oracle; the graph replays agree with each other bit for bit."""
+    say(f"graph replays {prec}")
+    st, P = w.config0()
+    ref = st.t_amb + direct.solve_separable(st, P.ravel())
+    g = grid_of(st)
+    Pt = t64(P)
+    monkeypatch.setenv("CUTH_GRAPH", "0")
+    T_eager, _ = g.solve(Pt, precision=prec)
+    T_eager = T_eager.clone()
+    first = None
+    for rep in range(3):
+        monkeypatch.setenv("CUTH_GRAPH", "1")
+        T, s = g.solve(Pt, precision=prec)
+        torch.cuda.synchronize()
+        T = T.clone()
+        assert rise_err(T.cpu().numpy(), ref, st.t_amb) <= (1e-8 if prec == "mixed" else 1e-10)
+        assert float((T - T_eager).abs().max()) <= 1e-12 * float((T_eager - st.t_amb).abs().max())
+        if first is None:
+            first = T
+        else:
+            assert torch.equal(T, first), rep
+        # eager work between the replays
+        monkeypatch.setenv("CUTH_GRAPH", "0")
+        T2, _ = g.solve(Pt, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(T2, T_eager)
+    g.close()
