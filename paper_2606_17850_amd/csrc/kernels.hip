@@ -1097,35 +1097,49 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
         xc = xup;
     };
 
-    // every iteration of the loop holds a stage A; the two closing layers of
-    // stages B and C follow it (no load sits under a branch)
-    int l = la0;
-    for (; l < la1; ++l, c += plane) {
-        Vec<T, VX> zn, rv, gxp = zero, gyp = zero, gym = zero;
-        T gxl = T(0);
-        // ---- stage A: z_{j+1} at layer l (loads as in the pair)
-        const LayerCoef<T> L = gldc(op.lc + l);
-        const Vec<T, VX> xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
-        const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
-        const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
-        const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
-        const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
-        [[maybe_unused]] LatRaw<T, VX, CS> lat;
-        if constexpr (PC) lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
-        rv = vload<T, VX>(r + c);
-        Vec<T, VX> zm;
+    // stage A's loads of layer l (at in-bounds cells: see the column walker)
+    struct LoadsA {
+        Vec<T, VX> xup, xso, xno, rv, zm;
+        T west, east;
+        LatRaw<T, VX, CS> lat;
+    };
+    auto issue_a = [&](int l, int64_t cc) {
+        LoadsA q;
+        q.xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? cc + plane : cc));
+        q.xso = vload<T, VX>(zN + (has_s ? cc - nx : cc));
+        q.xno = vload<T, VX>(zN + (has_n ? cc + nx : cc));
+        // the edge lanes' x neighbours, loaded by every lane at an in-bounds
+        // cell (a load under a branch makes the waits at the join conservative,
+        // which would hold the prefetched loads)
+        const bool wl = lane == 0 && has_l, er = lane == kWave - 1 && has_r;
+        q.west = gld(zN + (wl ? cc - 1 : cc));
+        q.east = gld(zN + (er ? cc + VX : cc));
+        if (!wl) q.west = T(0);
+        if (!er) q.east = T(0);
+        if constexpr (PC) q.lat = lateral_load<T, VX, CS>(op, cc, lane, act, has_l, has_s);
+        q.rv = vload<T, VX>(r + cc);
         if constexpr (M2) {
 #pragma unroll
-            for (int e = 0; e < VX; ++e) zm.a[e] = rv.a[e] * inv_th;
+            for (int e = 0; e < VX; ++e) q.zm.a[e] = q.rv.a[e] * inv_th;
         } else {
-            zm = vload<T, VX>(zP + c);
+            q.zm = vload<T, VX>(zP + cc);
         }
+        return q;
+    };
+    // one layer: stage A of layer l from its loads q, then (after the barrier)
+    // stages B and C; `next` (when given) receives layer l + 1's loads, issued
+    // before the barrier so that they fly during stages B and C
+    auto layer = [&](int l, int64_t cc, const LoadsA &q, LoadsA *next) {
+        Vec<T, VX> zn, gxp = zero, gyp = zero, gym = zero;
+        T gxl = T(0);
+        // ---- stage A: z_{j+1} at layer l
+        const LayerCoef<T> L = gldc(op.lc + l);
         T left = lane_left(xc.a[VX - 1]);
         T right = lane_right(xc.a[0]);
-        if (lane == 0) left = west;
-        if (lane == kWave - 1) right = east;
+        if (lane == 0) left = q.west;
+        if (lane == kWave - 1) right = q.east;
         if constexpr (PC) {
-            lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+            lateral_finish<T, VX, CS>(q.lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
             // in an x window the lane at x = 0 need not be lane 0: its west
             // conductance came from an inactive lane and must vanish
             if (nwx > 1 && !has_l) gxl = T(0);
@@ -1150,17 +1164,42 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             T a = L.sink * x;
             if (PC || i > 0) a += gm * (x - xl);
             if (PC || i < nx - 1) a += gp * (x - xr);
-            a += gs * (x - xso.a[e]);
-            a += gn * (x - xno.a[e]);
+            a += gs * (x - q.xso.a[e]);
+            a += gn * (x - q.xno.a[e]);
             a += L.gzd * (x - xdn.a[e]);
-            a += L.gzu * (x - xup.a[e]);
-            T res = rv.a[e] - a;
+            a += L.gzu * (x - q.xup.a[e]);
+            T res = q.rv.a[e] - a;
             if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, l, nz));
-            zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
+            zn.a[e] = x + c1a * (x - q.zm.a[e]) + c2a * res;
         }
         lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
+        if (next) {
+            const bool more = l + 1 < la1;
+            *next = issue_a(more ? l + 1 : l, more ? cc + plane : cc);
+        }
         __syncthreads();
-        stage_bc(l, c, zn, rv, gxp, gyp, gym, gxl, xup);
+        stage_bc(l, cc, zn, q.rv, gxp, gyp, gym, gxl, q.xup);
+    };
+    // every iteration of the loop holds a stage A; the two closing layers of
+    // stages B and C follow it.  PF (the matrix-free sweeps, whose registers
+    // leave room for a second set of loads): layer l + 1's loads are issued
+    // right after layer l's stage A, before the barrier, so that they fly
+    // during stages B and C; they are issued unconditionally (the last layer
+    // loads its own cells again), since a load under a branch makes the waits
+    // where the paths join conservative.  With per-cell conductances a second
+    // set would pass the register budget of a 16-wavefront workgroup, and
+    // each layer issues its own loads.
+    constexpr bool PF = !PC;
+    int l = la0;
+    if constexpr (PF) {
+        LoadsA q = issue_a(l, c);
+        for (; l < la1; ++l, c += plane) {
+            LoadsA nq;
+            layer(l, c, q, &nq);
+            q = nq;
+        }
+    } else {
+        for (; l < la1; ++l, c += plane) layer(l, c, issue_a(l, c), nullptr);
     }
     for (int q = 0; q < 2; ++q, ++l, c += plane) {
         __syncthreads();
