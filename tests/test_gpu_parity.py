@@ -653,10 +653,13 @@ def test_fused_sweep_pairs(monkeypatch, case, shape):
 def test_fused_sweep_triples(monkeypatch, case, shape):
     """General Chebyshev sweeps fused in threes (z_{j+1} kept on chip, two halo
     rows and layers per side): the FP32 preconditioner against the oracle's
-    polynomial and against single sweeps, for degrees with no triple (6), one
-    triple (7), a triple and a single sweep (8), a triple and a pair (9) and
-    the default (30), and workgroup shapes from one row and one layer to
-    chunks deeper than the stack."""
+    polynomial and against single sweeps.  Sweep 1 is always single and the
+    last sweep (which forms the r^T z partials) too; triples start at sweep 2
+    (forming z_1 = r / theta themselves) and pairs fill what a triple cannot:
+    degree 6 runs one triple (2-4), 7 one triple and a single sweep (5), 8 a
+    triple and a pair (5-6), 9 two triples (2-4, 5-7) and 30 nine triples
+    (2-28); workgroup shapes from one row and one layer to chunks deeper than
+    the stack."""
     say(f"fused triples {case} shape {shape}")
     st = CASES[case]()
     A = assembly.assemble(st)
@@ -859,9 +862,10 @@ def test_fused_sweep_solves(monkeypatch):
 @pytest.mark.parametrize("fuse", ["0", "1", "3"])
 def test_kernel_timing_blocks(monkeypatch, fuse):
     """The measurement hook times whole back-to-back runs of the general FP32
-    kernel: at k = 30 every preconditioner application contributes 8 fused
-    triples (j = 3..26), 13 fused pairs (j = 3..28) or 26 single sweeps
-    (j = 3..28), so the launch count is a multiple of that, and the bytes per
+    kernel from sweep 3 on: at k = 30 every preconditioner application
+    contributes 8 fused triples (sweeps 5-28; the first triple, 2-4, forms z_1
+    itself and is not in the block), 13 fused pairs (sweeps 3-28) or 26 single
+    sweeps (3-28), so the launch count is a multiple of that, and the bytes per
     launch are those of the kernel timed (28, 28 or 24 B per unknown on a
     per-cell grid)."""
     say(f"kernel timing blocks, fusion {fuse}")
