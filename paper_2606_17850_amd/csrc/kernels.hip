@@ -538,10 +538,13 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             // Terms of missing neighbours add exactly zero without a test:
             // per-cell conductances, the +x one is 0 on the last column and
             // lane 0's west conductance and value are 0 on the first; a
-            // missing y or z neighbour was loaded at the cell itself.
+            // missing y or z neighbour was loaded at the cell itself.  With
+            // per-layer conductances only a lane's edge cells can miss an x
+            // neighbour (vx divides nx), so the test is the lane's has_l /
+            // has_r, one select per side instead of one per cell.
             T a = L.sink * x;
-            if (PC || i > 0) a += gm * (x - xl);
-            if (PC || i < nx - 1) a += gp * (x - xr);
+            if (PC || e > 0 || has_l) a += gm * (x - xl);
+            if (PC || e < VX - 1 || has_r) a += gp * (x - xr);
             a += gs * (x - xso.a[e]);
             a += gn * (x - xno.a[e]);
             a += L.gzd * (x - xdn.a[e]);
@@ -827,8 +830,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             // bottom layer and gzu on the top one, where the neighbour
             // registers hold zeros
             T a = L.sink * x;
-            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
-            if (PC || i < nx - 1) a += gp * (x - xr);
+            if (PC || e > 0 || has_l) a += gm * (x - xl);   // (see the column walker)
+            if (PC || e < VX - 1 || has_r) a += gp * (x - xr);
             a += gs * (x - so.a[e]);
             a += gn * (x - no.a[e]);
             a += L.gzd * (x - zA_m2.a[e]);
@@ -886,8 +889,8 @@ __global__ __launch_bounds__(1024) void k_cheb2_b(const InnerProb<T> *__restrict
             // a missing y or z neighbour was loaded at the cell itself, so
             // its term vanishes without a test
             T a = L.sink * x;
-            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
-            if (PC || i < nx - 1) a += gp * (x - xr);
+            if (PC || e > 0 || has_l) a += gm * (x - xl);   // (see the column walker)
+            if (PC || e < VX - 1 || has_r) a += gp * (x - xr);
             a += gs * (x - xso.a[e]);
             a += gn * (x - xno.a[e]);
             a += L.gzd * (x - xdn.a[e]);
@@ -1041,8 +1044,8 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             }
             // the z conductances are zero where dn / up do not exist
             T a = L.sink * x;
-            if (PC || i > 0) a += gm * (x - xl);   // (see the column walker)
-            if (PC || i < nx - 1) a += gp * (x - xr);
+            if (PC || e > 0 || has_l) a += gm * (x - xl);   // (see the column walker)
+            if (PC || e < VX - 1 || has_r) a += gp * (x - xr);
             a += gs * (x - so.a[e]);
             a += gn * (x - no.a[e]);
             a += L.gzd * (x - dn.a[e]);
@@ -1162,8 +1165,8 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             }
             // missing y and z neighbours were loaded at the cell itself
             T a = L.sink * x;
-            if (PC || i > 0) a += gm * (x - xl);
-            if (PC || i < nx - 1) a += gp * (x - xr);
+            if (PC || e > 0 || has_l) a += gm * (x - xl);
+            if (PC || e < VX - 1 || has_r) a += gp * (x - xr);
             a += gs * (x - q.xso.a[e]);
             a += gn * (x - q.xno.a[e]);
             a += L.gzd * (x - xdn.a[e]);
