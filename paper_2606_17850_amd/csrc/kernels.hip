@@ -432,16 +432,25 @@ __device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T
 }
 
 // March the VX cells of one lane through its layers; emit(l, c, x, A x, ex) per
-// layer (active lanes only).  XV(q) fetches VX consecutive values of the operand
-// starting at cell q, XS(q) one value, PRE(c) whatever else emit needs at cell c
-// (fetched right before emit).  Every lane of the wavefront must call this (the
+// layer (active lanes only).  XV(q) fetches the raw loads of VX consecutive
+// values of the operand starting at cell q and fin(raw) forms the values (by
+// default XV returns them and fin is the identity: an operand formed from
+// several streams keeps its arithmetic out of XV, so that the loads of the next
+// layer can fly while the current one is computed), XS(q) one value, PRE(c)
+// whatever else emit needs at cell c (fetched with the layer's loads).  Every lane of the wavefront must call this (the
 // x halo comes through cross-lane shuffles), except with CS_CSR.  Two variants
 // measured slower on gfx950 and are not used: issuing the next layer's loads
 // before computing the current one (more registers, no gain in overlap), and
 // guarding the loads with branches instead of selects (about 15 % slower sweeps).
-template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E>
+struct IdentFin {
+    template <typename V>
+    __device__ __forceinline__ const V &operator()(const V &v) const { return v; }
+};
+
+template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E,
+          typename FX = IdentFin>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
-                                           FP &&PRE, E &&emit) {
+                                           FP &&PRE, E &&emit, FX &&fin = FX{}) {
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const bool act = ln.act;
@@ -452,7 +461,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         if (!act) return;
         int64_t c = ln.i0 + (int64_t)nx * ln.j + plane * ln.l0;
         for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
-            const Vec<T, VX> xc = XV(c);
+            const Vec<T, VX> xc = fin(XV(c));
             Vec<T, VX> ax;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
@@ -484,8 +493,9 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     // sit at cells (l - l0) * plane, and a missing neighbour is not loaded,
     // so every address is in bounds.
     using Pre = decltype(PRE(int64_t(0)));
+    using Raw = std::decay_t<decltype(XV(int64_t(0)))>;
     struct Loads {
-        Vec<T, VX> xup, xso, xno;
+        Raw xup, xso, xno;
         T west, east;
         LatRaw<T, VX, CS> lat;
         Pre pre;
@@ -501,12 +511,12 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         q.pre = PRE(cc);
         return q;
     };
-    Vec<T, VX> xdn = XV((act && ln.l0 > 0) ? c - plane : c);
-    Vec<T, VX> xc = XV(c);
+    Vec<T, VX> xdn = fin(XV((act && ln.l0 > 0) ? c - plane : c));
+    Vec<T, VX> xc = fin(XV(c));
     // layer l's body with its loads already in registers (cur)
     auto layer = [&](int l, int64_t c, const Loads &cur) {
         const LayerCoef<T> L = gldc(op.lc + l);
-        const Vec<T, VX> &xup = cur.xup, &xso = cur.xso, &xno = cur.xno;
+        const Vec<T, VX> xup = fin(cur.xup), xso = fin(cur.xso), xno = fin(cur.xno);
         const auto &pre = cur.pre;
         T left = lane_left(xc.a[VX - 1]);
         T right = lane_right(xc.a[0]);
@@ -554,7 +564,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         }
         if (act) emit(l, c, xc, ax, pre, dg);
         xdn = xc;
-        xc = cur.xup;
+        xc = xup;
     };
     if constexpr (sizeof(T) == 4) {
         // two sets alternate (unrolled by hand: a copy from one set to the
@@ -673,14 +683,16 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
     const T *__restrict__ z = P.z[zsel & 3];
     T *zo = P.z[zsel >> 2];
     T acc[1] = {T(0)};
-    auto XV = [&](int64_t q) -> Vec<T, VX> {
+    // (mode 1 scales r by 1/theta where the values are used, not at the load)
+    auto XV = [&](int64_t q) -> Vec<T, VX> { return vload<T, VX>((MODE == 1 ? r : z) + q); };
+    auto fin = [&](const Vec<T, VX> &v) -> Vec<T, VX> {
         if constexpr (MODE == 1) {
-            Vec<T, VX> v = vload<T, VX>(r + q);
+            Vec<T, VX> w;
 #pragma unroll
-            for (int e = 0; e < VX; ++e) v.a[e] *= inv_th;
-            return v;
+            for (int e = 0; e < VX; ++e) w.a[e] = v.a[e] * inv_th;
+            return w;
         } else {
-            return vload<T, VX>(z + q);
+            return v;
         }
     };
     auto XS = [&](int64_t q) -> T {
@@ -715,7 +727,8 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
                               if constexpr (LAST) acc[0] += rc.a[e] * zn.a[e];
                           }
                           vstore<T, VX>(zo + c, zn);
-                      });
+                      },
+                      fin);
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
@@ -1184,17 +1197,18 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
         stage_bc(l, cc, zn, q.rv, gxp, gyp, gym, gxl, q.xup);
     };
     // every iteration of the loop holds a stage A; the two closing layers of
-    // stages B and C follow it.  PF (the matrix-free sweeps, whose registers
-    // leave room for a second set of loads): layer l + 1's loads are issued
+    // stages B and C follow it.  Matrix-free (the per-layer conductances leave
+    // registers for a second set of loads): layer l + 1's loads are issued
     // right after layer l's stage A, before the barrier, so that they fly
     // during stages B and C; they are issued unconditionally (the last layer
     // loads its own cells again), since a load under a branch makes the waits
     // where the paths join conservative.  With per-cell conductances a second
-    // set would pass the register budget of a 16-wavefront workgroup, and
-    // each layer issues its own loads.
-    constexpr bool PF = !PC;
+    // set would pass the register budget of a 16-wavefront workgroup: each
+    // layer issues its own loads, the edge lanes' x neighbours under their
+    // lane test (written out in the loop: folding this path into the lambdas
+    // above made the compiler reorder its loads and waits, 2-13 % slower)
     int l = la0;
-    if constexpr (PF) {
+    if constexpr (!PC) {
         LoadsA q = issue_a(l, c);
         for (; l < la1; ++l, c += plane) {
             LoadsA nq;
@@ -1202,7 +1216,57 @@ __global__ __launch_bounds__(1024) void k_cheb3_b(const InnerProb<T> *__restrict
             q = nq;
         }
     } else {
-        for (; l < la1; ++l, c += plane) layer(l, c, issue_a(l, c), nullptr);
+        for (; l < la1; ++l, c += plane) {
+            Vec<T, VX> zn, rv, gxp = zero, gyp = zero, gym = zero;
+            T gxl = T(0);
+            // ---- stage A: z_{j+1} at layer l
+            const LayerCoef<T> L = gldc(op.lc + l);
+            const Vec<T, VX> xup = vload<T, VX>(zN + ((act && l + 1 < nz) ? c + plane : c));
+            const Vec<T, VX> xso = vload<T, VX>(zN + (has_s ? c - nx : c));
+            const Vec<T, VX> xno = vload<T, VX>(zN + (has_n ? c + nx : c));
+            const T west = (lane == 0 && has_l) ? gld(zN + c - 1) : T(0);
+            const T east = (lane == kWave - 1 && has_r) ? gld(zN + c + VX) : T(0);
+            const LatRaw<T, VX, CS> lat = lateral_load<T, VX, CS>(op, c, lane, act, has_l, has_s);
+            rv = vload<T, VX>(r + c);
+            Vec<T, VX> zm;
+            if constexpr (M2) {
+#pragma unroll
+                for (int e = 0; e < VX; ++e) zm.a[e] = rv.a[e] * inv_th;
+            } else {
+                zm = vload<T, VX>(zP + c);
+            }
+            T left = lane_left(xc.a[VX - 1]);
+            T right = lane_right(xc.a[0]);
+            if (lane == 0) left = west;
+            if (lane == kWave - 1) right = east;
+            lateral_finish<T, VX, CS>(lat, L, lane, act, has_l, has_s, gxp, gyp, gym, gxl);
+            // in an x window the lane at x = 0 need not be lane 0: its west
+            // conductance came from an inactive lane and must vanish
+            if (nwx > 1 && !has_l) gxl = T(0);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const int i = xg + e;
+                const T x = xc.a[e];
+                const T xl = (e == 0) ? left : xc.a[e > 0 ? e - 1 : 0];
+                const T xr = (e == VX - 1) ? right : xc.a[e + 1 < VX ? e + 1 : 0];
+                const T gm = (e == 0) ? gxl : gxp.a[e > 0 ? e - 1 : 0];
+                const T gp = gxp.a[e], gs = gym.a[e], gn = gyp.a[e];
+                // per-cell conductances: the terms of missing neighbours vanish
+                T a = L.sink * x;
+                a += gm * (x - xl);
+                a += gp * (x - xr);
+                a += gs * (x - xso.a[e]);
+                a += gn * (x - xno.a[e]);
+                a += L.gzd * (x - xdn.a[e]);
+                a += L.gzu * (x - xup.a[e]);
+                T res = rv.a[e] - a;
+                if constexpr (JAC) res *= recip(jac_diag(L, gm, gp, gs, gn, i, nx, jr, ny, l, nz));
+                zn.a[e] = x + c1a * (x - zm.a[e]) + c2a * res;
+            }
+            lds_store<T, VX>(ringA_at(l, rs) + xo, zn);
+            __syncthreads();
+            stage_bc(l, c, zn, rv, gxp, gyp, gym, gxl, xup);
+        }
     }
     for (int q = 0; q < 2; ++q, ++l, c += plane) {
         __syncthreads();
@@ -1302,14 +1366,40 @@ __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ 
     const OpView<T> op = P.op;
     const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     T acc[1] = {T(0)};
-    auto XV = [&](int64_t q) -> Vec<T, VX> {
-        Vec<T, VX> v = vload<T, VX>(z + q);
-        if (has_p) {
-            const Vec<T, VX> p = vload<T, VX>(pold + q);
+    // With per-cell conductances the operand p = z + beta p_old is formed
+    // where the values are used, from the raw loads of z and p_old (p_old read
+    // also on the first iteration, where it is not used: no load under a
+    // branch), so that the next layer's loads fly during the current one
+    // (512x512x16: 21.5 -> 19.2 us).  Matrix-free, the extra registers of the
+    // raw set cost more occupancy than the overlap gains (1024x1024x20: 74.6
+    // -> 83.8 us), and XV forms p at the load.
+    struct Raw {
+        Vec<T, VX> z, p;
+    };
+    auto XV = [&](int64_t q) {
+        if constexpr (PC) {
+            return Raw{vload<T, VX>(z + q), vload<T, VX>(pold + q)};
+        } else {
+            Vec<T, VX> v = vload<T, VX>(z + q);
+            if (has_p) {
+                const Vec<T, VX> p = vload<T, VX>(pold + q);
 #pragma unroll
-            for (int e = 0; e < VX; ++e) v.a[e] += beta * p.a[e];
+                for (int e = 0; e < VX; ++e) v.a[e] += beta * p.a[e];
+            }
+            return v;
         }
-        return v;
+    };
+    auto fin = [&](const auto &w) -> Vec<T, VX> {
+        if constexpr (PC) {
+            Vec<T, VX> v = w.z;
+            if (has_p) {
+#pragma unroll
+                for (int e = 0; e < VX; ++e) v.a[e] += beta * w.p.a[e];
+            }
+            return v;
+        } else {
+            return w;
+        }
     };
     auto XS = [&](int64_t q) -> T { return has_p ? gld(z + q) + beta * gld(pold + q) : gld(z + q); };
     column_pre<T, PC, VX, CS>(op, ln, XV, XS, [](int64_t) { return NoEx{}; },
@@ -1319,7 +1409,8 @@ __global__ __launch_bounds__(512) void k_dir_b(const InnerProb<T> *__restrict__ 
                           vstore<T, VX>(mu + c, ap);
 #pragma unroll
                           for (int e = 0; e < VX; ++e) acc[0] += p.a[e] * ap.a[e];
-                      });
+                      },
+                      fin);
     block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
