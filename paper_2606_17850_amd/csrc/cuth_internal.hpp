@@ -246,10 +246,20 @@ void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int c
                     T *part_out, hipStream_t s);
 
 // FP64 outer residual; partials of ||r||^2, ||b||^2, max|delta|, max|theta_out|,
-// count of non-finite r.
+// count of non-finite r.  flags: the streams every problem of the launch has
+// (residual_flags), or -1 where they differ.
 template <typename TD, typename TI>
 void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool pc, int vx, int by,
-                       double *part_out, hipStream_t s);
+                       int flags, double *part_out, hipStream_t s);
+// bit 0 theta_in, bit 1 delta, bit 2 T_n, bit 3 r64 as the only output (else
+// theta_out, r_in and rhat, all present); -1 for any other combination
+template <typename TD, typename TI>
+inline int residual_flags(const OuterProb<TD, TI> &o) {
+    const bool out_api = o.r64 && !o.th_out && !o.r_in && !o.rhat;
+    const bool out_outer = !o.r64 && o.th_out && o.r_in && o.rhat;
+    if (!out_api && !out_outer) return -1;
+    return (o.th_in ? 1 : 0) | (o.delta ? 2 : 0) | (o.Tn ? 4 : 0) | (out_api ? 8 : 0);
+}
 constexpr int kResidualValues = 5;
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s);

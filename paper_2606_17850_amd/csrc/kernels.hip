@@ -442,13 +442,19 @@ __device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T
 // measured slower on gfx950 and are not used: issuing the next layer's loads
 // before computing the current one (more registers, no gain in overlap), and
 // guarding the loads with branches instead of selects (about 15 % slower sweeps).
+// EDGE_ALL: every lane loads the west and east values (see issue below), for
+// an XS with arithmetic, which would otherwise wait for its loads inside the
+// branch.  EMIT_ALL: inactive lanes call emit too (emit tests Lane::act
+// itself), for an emit whose inputs would otherwise be loaded under the
+// branch around it.
 struct IdentFin {
     template <typename V>
     __device__ __forceinline__ const V &operator()(const V &v) const { return v; }
 };
 
-template <typename T, bool PC, int VX, int CS, typename FV, typename FS, typename FP, typename E,
-          typename FX = IdentFin>
+template <typename T, bool PC, int VX, int CS, bool EDGE_ALL = false, bool EMIT_ALL = false,
+          typename FV, typename FS,
+          typename FP, typename E, typename FX = IdentFin>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
                                            FP &&PRE, E &&emit, FX &&fin = FX{}) {
     const int nx = op.nx, ny = op.ny, nz = op.nz;
@@ -505,8 +511,15 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         q.xup = XV((act && l + 1 < nz) ? cc + plane : cc);
         q.xso = XV(has_s ? cc - nx : cc);
         q.xno = XV(has_n ? cc + nx : cc);
-        q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : T(0);
-        q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : T(0);
+        if constexpr (EDGE_ALL) {
+            // every lane loads (at its own cell where it has no such
+            // neighbour): XS's arithmetic then waits outside any branch
+            q.west = XS((ln.lane == 0 && has_l) ? cc - 1 : cc);
+            q.east = XS((ln.lane == kWave - 1 && has_r) ? cc + VX : cc);
+        } else {
+            q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : T(0);
+            q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : T(0);
+        }
         if constexpr (PC) q.lat = lateral_load<T, VX, CS>(op, cc, ln.lane, act, has_l, has_s);
         q.pre = PRE(cc);
         return q;
@@ -562,7 +575,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             ax.a[e] = a;
             dg.a[e] = jac_diag(L, gm, gp, gs, gn, i, nx, ln.j, ny, l, nz);
         }
-        if (act) emit(l, c, xc, ax, pre, dg);
+        if (EMIT_ALL || act) emit(l, c, xc, ax, pre, dg);
         xdn = xc;
         xc = xup;
     };
@@ -1560,7 +1573,12 @@ __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict_
 }
 
 // ------------------------------------------------------- FP64 outer residual
-template <bool PC, int VX, typename TD, typename TI>
+// FL fixes at compile time which streams exist, so that no load sits under a
+// branch (the compiler would wait for each such load in turn): bit 0 theta_in,
+// bit 1 delta, bit 2 T_n, bit 3 r64 is the only output (else theta_out, r_in
+// and rhat are).  FL = -1 tests the pointers at run time (a launch whose
+// problems differ).
+template <bool PC, int VX, typename TD, typename TI, int FL>
 __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__restrict__ probs,
                                                     int nprob, double *__restrict__ part_out) {
     const int slot = xcd_slot();
@@ -1576,54 +1594,87 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
     TI *__restrict__ r_in = P.r_in;
     TI *__restrict__ rhat = P.rhat;
     const double in_off = P.in_off, tn_off = P.tn_off;
+    constexpr bool RT = FL < 0;
+    const bool has_th = RT ? th_in != nullptr : (FL & 1) != 0;
+    const bool has_d = RT ? delta != nullptr : (FL & 2) != 0;
+    const bool has_tn = RT ? tn != nullptr : (FL & 4) != 0;
+    const bool w_th = RT ? th_out != nullptr : (FL & 8) == 0;
+    const bool w_r64 = RT ? r64 != nullptr : (FL & 8) != 0;
+    const bool w_rin = RT ? r_in != nullptr : (FL & 8) == 0;
     double acc[kResidualValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // theta = theta_in - in_off + delta: the loads (XV) and the sum (fin)
+    // apart, so that a layer's loads are all in flight before the first sum
+    struct RawX {
+        Vec<double, VX> th;
+        Vec<TD, VX> d;
+    };
+    auto XV = [&](int64_t q) {
+        RawX v;
+        v.th = has_th ? vload<double, VX>(th_in + q) : vzero<double, VX>();
+        v.d = has_d ? vload<TD, VX>(delta + q) : vzero<TD, VX>();
+        return v;
+    };
+    auto fin = [&](const RawX &v) {
+        Vec<double, VX> x;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) {
+            x.a[e] = has_th ? v.th.a[e] - in_off : 0.0;
+            if (has_d) x.a[e] += (double)v.d.a[e];
+        }
+        return x;
+    };
     auto XS = [&](int64_t q) -> double {
-        double v = th_in ? gld(th_in + q) - in_off : 0.0;
-        if (delta) v += (double)gld(delta + q);
+        const double t = has_th ? gld(th_in + q) : 0.0;
+        const double d = has_d ? (double)gld(delta + q) : 0.0;
+        double v = has_th ? t - in_off : 0.0;
+        if (has_d) v += d;
         return v;
     };
-    auto XV = [&](int64_t q) -> Vec<double, VX> {
-        Vec<double, VX> v = th_in ? vload<double, VX>(th_in + q) : vzero<double, VX>();
-        if (th_in) {
-#pragma unroll
-            for (int e = 0; e < VX; ++e) v.a[e] -= in_off;
-        }
-        if (delta) {
-            const Vec<TD, VX> d = vload<TD, VX>(delta + q);
-#pragma unroll
-            for (int e = 0; e < VX; ++e) v.a[e] += (double)d.a[e];
-        }
-        return v;
+    // the cell's own streams, fetched with the layer's stencil loads
+    struct PreR {
+        Vec<double, VX> pv, tv;
+        Vec<TD, VX> dv;
     };
-    column<double, PC, VX>(
-        op, ln, XV, XS, [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath) {
+    auto PRE = [&](int64_t c) {
+        PreR q;
+        q.pv = vload<double, VX>(pw + c);
+        q.tv = has_tn ? vload<double, VX>(tn + c) : vzero<double, VX>();
+        q.dv = has_d ? vload<TD, VX>(delta + c) : vzero<TD, VX>();
+        return q;
+    };
+    column_pre<double, PC, VX, CS_OWN, !RT, !RT>(
+        op, ln, XV, XS, PRE,
+        [&](int l, int64_t c, const Vec<double, VX> &th, const Vec<double, VX> &ath, const PreR &pr,
+            const Vec<double, VX> &) {
+            // with FL >= 0 every lane comes here (inactive ones at in-bounds
+            // cells) and adds zeros, so that the layer's loads stay unguarded
+            const bool act = ln.act;
             const double cap = gldc(op.lc + l).cap;
-            const Vec<double, VX> pv = vload<double, VX>(pw + c);
-            const Vec<double, VX> tv = tn ? vload<double, VX>(tn + c) : vzero<double, VX>();
-            Vec<TD, VX> dv;
-            if (delta) dv = vload<TD, VX>(delta + c);
             Vec<double, VX> rv;
             Vec<TI, VX> rl;
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                double b = pv.a[e];
-                if (tn) b += cap * (tv.a[e] - tn_off);
+                double b = pr.pv.a[e];
+                if (has_tn) b += cap * (pr.tv.a[e] - tn_off);
                 const double rc = b - ath.a[e];
                 rv.a[e] = rc;
                 rl.a[e] = (TI)rc;
-                acc[0] += rc * rc;
-                acc[1] += b * b;
-                if (delta) acc[2] = fmax(acc[2], fabs((double)dv.a[e]));
-                acc[3] = fmax(acc[3], fabs(th.a[e]));
-                acc[4] += isfinite(rc) ? 0.0 : 1.0;
+                acc[0] += act ? rc * rc : 0.0;
+                acc[1] += act ? b * b : 0.0;
+                if (has_d) acc[2] = fmax(acc[2], act ? fabs((double)pr.dv.a[e]) : 0.0);
+                acc[3] = fmax(acc[3], act ? fabs(th.a[e]) : 0.0);
+                acc[4] += (act && !isfinite(rc)) ? 1.0 : 0.0;
             }
-            if (th_out) vstore<double, VX>(th_out + c, th);
-            if (r64) vstore<double, VX>(r64 + c, rv);
-            if (r_in) {
-                vstore<TI, VX>(r_in + c, rl);
-                vstore<TI, VX>(rhat + c, rl);
+            if (act) {
+                if (w_th) vstore<double, VX>(th_out + c, th);
+                if (w_r64) vstore<double, VX>(r64 + c, rv);
+                if (w_rin) {
+                    vstore<TI, VX>(r_in + c, rl);
+                    vstore<TI, VX>(rhat + c, rl);
+                }
             }
-        });
+        },
+        fin);
     block_partials<double, kResidualValues>(acc, (1u << 2) | (1u << 3), part_out, gridDim.x, slot);
 }
 
@@ -2206,10 +2257,31 @@ void launch_check_b(const InnerProb<T> *probs, int nprob, int nb, bool pc, int c
 
 template <typename TD, typename TI>
 void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool pc, int vx, int by,
-                       double *part_out, hipStream_t s) {
+                       int flags, double *part_out, hipStream_t s) {
     const dim3 g(nb), b(kWave, by);
-    CUTH_PC_VX_DISPATCH(double, pc, vx, (hipLaunchKernelGGL((k_residual_b<PC, VX, TD, TI>), g, b, 0,
-                                                            s, probs, nprob, part_out)));
+    // the stream sets the solver launches (see k_residual_b), at the default
+    // lane width; anything else takes the run-time tests
+#define CUTH_RES(FLV)                                                                               \
+    do {                                                                                           \
+        if (pc) hipLaunchKernelGGL((k_residual_b<true, 2, TD, TI, FLV>), g, b, 0, s, probs, nprob,  \
+                                   part_out);                                                      \
+        else hipLaunchKernelGGL((k_residual_b<false, 2, TD, TI, FLV>), g, b, 0, s, probs, nprob,    \
+                                part_out);                                                         \
+    } while (0)
+    if (vx == 2) {
+        switch (flags) {
+        case 0: CUTH_RES(0); return;
+        case 1: CUTH_RES(1); return;
+        case 3: CUTH_RES(3); return;
+        case 5: CUTH_RES(5); return;
+        case 7: CUTH_RES(7); return;
+        case 9: CUTH_RES(9); return;
+        default: break;
+        }
+    }
+#undef CUTH_RES
+    CUTH_PC_VX_DISPATCH(double, pc, vx, (hipLaunchKernelGGL((k_residual_b<PC, VX, TD, TI, -1>), g, b,
+                                                            0, s, probs, nprob, part_out)));
 }
 
 void launch_csr_fill(const OpView<double> &op, const int *ptr, int *col, double *val,
@@ -2337,9 +2409,9 @@ template void launch_reduce_conv<double>(const InnerProb<double> *, int, const d
                                          hipStream_t);
 
 template void launch_residual_b<float, float>(const OuterProb<float, float> *, int, int, bool, int,
-                                              int, double *, hipStream_t);
+                                              int, int, double *, hipStream_t);
 template void launch_residual_b<double, double>(const OuterProb<double, double> *, int, int, bool,
-                                                int, int, double *, hipStream_t);
+                                                int, int, int, double *, hipStream_t);
 
 // ------------------------------------------------ allocation-free scratch
 // Device memory of the allocation-free preconditioner entry point: one array

@@ -841,7 +841,7 @@ Status outer_step(Engine &E, std::vector<Problem *> &ps, const Shape &sh64, hipS
         h = reinterpret_cast<OuterProb<TI, TI> *>(E.h_out64);
         d = reinterpret_cast<OuterProb<TI, TI> *>(E.out64);
     }
-    int tile = 0, n = 0;
+    int tile = 0, n = 0, flags = -1;
     std::vector<int> which;
     for (size_t i = 0; i < ps.size(); ++i) {
         Problem &p = *ps[i];
@@ -863,6 +863,8 @@ Status outer_step(Engine &E, std::vector<Problem *> &ps, const Shape &sh64, hipS
         o.r64 = nullptr;
         o.r_in = w.r;
         o.rhat = w.rhat;
+        const int f = residual_flags(o);
+        flags = n == 0 ? f : (flags == f ? f : -1);
         h[n] = o;
         p.tile0 = tile;
         p.ntiles = o.ntiles;
@@ -876,7 +878,7 @@ Status outer_step(Engine &E, std::vector<Problem *> &ps, const Shape &sh64, hipS
         return Status::err(CUTH_E_DEVICE, "internal: residual launch does not fit the engine");
     const bool pc = ps[which[0]]->g->per_cell;
     CUTH_HIP(hipMemcpyAsync(d, h, sizeof(OuterProb<TI, TI>) * n, hipMemcpyHostToDevice, s));
-    launch_residual_b<TI, TI>(d, n, tile, pc, sh64.vx, sh64.by, eslot<double>(E, P_RES), s);
+    launch_residual_b<TI, TI>(d, n, tile, pc, sh64.vx, sh64.by, flags, eslot<double>(E, P_RES), s);
     CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<double>(E, P_RES),
                             sizeof(double) * kResidualValues * (size_t)tile, hipMemcpyDeviceToHost, s));
     CUTH_TRY(sync_stream(s));
@@ -2453,7 +2455,7 @@ Status residual(Grid &g, double dt, const double *b, const double *T, double *r)
     E.h_out64[0] = o;
     CUTH_HIP(hipMemcpyAsync(E.out64, E.h_out64, sizeof(o), hipMemcpyHostToDevice, g.stream));
     launch_residual_b<double, double>(E.out64, 1, o.ntiles, g.per_cell, g.sh64.vx, g.sh64.by,
-                                      eslot<double>(E, P_RES), g.stream);
+                                      residual_flags(o), eslot<double>(E, P_RES), g.stream);
     CUTH_HIP(hipGetLastError());
     return sync_stream(g.stream);
 }

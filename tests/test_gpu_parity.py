@@ -62,16 +62,20 @@ def test_apply_matches_csr(case, dt):
     g.close()
 
 
-@pytest.mark.parametrize("case", ["ragged_mult", "c0"])
-def test_residual_matches_oracle(case):
-    say(f"residual {case}")
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("dt", [None, 1e-4])
+def test_residual_matches_oracle(case, dt):
+    """Every grid shape: the even-width ones take the residual kernel built
+    for this call's streams, the odd-width ones (one cell per lane) the one
+    that tests its pointers at run time."""
+    say(f"residual {case} dt={dt}")
     st = CASES[case]()
-    A = assembly.assemble(st)
+    A = assembly.assemble(st, dt=dt)
     g = grid_of(st)
     rng = np.random.default_rng(4)
     th = rng.uniform(0, 50, st.n)
     b = rng.uniform(0, 1e-3, st.n)
-    r = g.residual(t64(b), t64(st.t_amb + th)).cpu().numpy()
+    r = g.residual(t64(b), t64(st.t_amb + th), dt=dt or 0.0).cpu().numpy()
     ref = b - A @ th
     scale = np.abs(b) + abs(A) @ np.abs(th)
     assert np.all(np.abs(r - ref) <= 2e-14 * scale)
