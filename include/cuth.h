@@ -224,6 +224,26 @@ cuth_status cuth_grid_create(const cuth_grid_desc *desc, void *hip_stream, cuth_
 /* Release every allocation of the handle (NULL is a no-op). */
 void cuth_grid_destroy(cuth_grid g);
 
+/* New layer conductivities for an existing grid, e.g. the steps of a design
+ * loop driven by the per-layer gradient of cuth_adjoint (the paper's use of
+ * the solver under automatic differentiation, Section 4.2).  The face
+ * conductances are rebuilt in place by the same kernels as cuth_grid_create,
+ * so every later call returns what a grid created with these values would
+ * return.  The handle keeps its buffers, captured graphs and launch shapes;
+ * the layer coefficients of every time step size used so far are recomputed,
+ * and the cached spectral intervals are dropped (the next solve reruns the
+ * Lanczos setup).  k_lat, k_vert: host double [nz], finite and > 0.
+ * k_lat_mult: device double [nx*ny*nz] lateral multiplier, required for a grid
+ * created with one (it need not be the same field) and NULL for a grid created
+ * without.  Waits for the handle's stream before it starts.  Errors:
+ * CUTH_E_INVALID for bad host values or a multiplier given or missing against
+ * the grid (the grid is unchanged); CUTH_E_INVALID also when the device check
+ * finds a multiplier entry <= 0 or not finite, after which the handle refuses
+ * every call except this one and cuth_grid_destroy until a call here
+ * succeeds. */
+cuth_status cuth_grid_set_conductivity(cuth_grid g, const double *k_lat, const double *k_vert,
+                                       const double *k_lat_mult);
+
 /* Steady solve G T = P (paper Section 3.2 eq. "steady-state"; PCG of
  * Algorithm 1 with the Chebyshev preconditioner).  P: device double [N] W per
  * cell; T: device double [N] K, output (input too if use_initial_guess).

@@ -111,6 +111,8 @@ class Grid:
         self._kv = _darr(k_vert, nz, "k_vert")
         self._cap = None if heat_cap is None else _darr(heat_cap, nz, "heat_cap")
         mult_ptr = _ptr(k_lat_mult, torch.float64, self.n, "k_lat_mult", self.device)
+        # kept for set_conductivity (the library does not hold the field)
+        self._mult = k_lat_mult
         d = _lib.GridDesc()
         d.nx, d.ny, d.nz = self.nx, self.ny, self.nz
         d.dx, d.dy = float(dx), float(dy)
@@ -123,6 +125,21 @@ class Grid:
         with torch.cuda.device(self.device):
             _check(lib.cuth_grid_create(ctypes.byref(d), _stream_handle(self.device), ctypes.byref(h)))
         self._h = h
+
+    def set_conductivity(self, k_lat, k_vert, k_lat_mult: Optional[torch.Tensor] = None):
+        """New layer conductivities in place (cuth_grid_set_conductivity): the
+        handle keeps its buffers; the next solve reruns the Lanczos setup.  A
+        per-cell grid takes k_lat_mult, else reuses the field it was built
+        with (or last given here)."""
+        kl = _darr(k_lat, self.nz, "k_lat")
+        kv = _darr(k_vert, self.nz, "k_vert")
+        mult = k_lat_mult if k_lat_mult is not None else self._mult
+        mult_ptr = _ptr(mult, torch.float64, self.n, "k_lat_mult", self.device)
+        with torch.cuda.device(self.device):
+            _check(library().cuth_grid_set_conductivity(
+                self._h, kl.ctypes.data_as(_lib.c_double_p), kv.ctypes.data_as(_lib.c_double_p),
+                mult_ptr))
+        self._kl, self._kv, self._mult = kl, kv, mult
 
     @classmethod
     def from_stack(cls, stack, device=None) -> "Grid":
@@ -299,17 +316,25 @@ def solve_batch(grids: Sequence[Grid], P: Sequence[torch.Tensor], T: Optional[Se
 class ThermalSolve(torch.autograd.Function):
     """T = solve(P, k) with gradients by one adjoint solve.
 
-    forward(P, k, grid_factory, opts): k is a [nz] tensor of layer
-    conductivities, each setting both the lateral and the vertical conductivity
-    of its layer (the lateral multiplier field, if any, stays fixed);
-    grid_factory(k) returns a Grid built with them.  backward returns the
-    library's dL/dP and its per-layer dL/dk unchanged.
+    forward(P, k, grid, opts): k is a [nz] tensor of layer conductivities, each
+    setting both the lateral and the vertical conductivity of its layer (the
+    lateral multiplier field, if any, stays fixed).  grid is a Grid, whose
+    conductivities are set to k in place (set_conductivity: no new buffers,
+    so a loop over k reuses one handle), or a callable that returns a Grid
+    built with k.  backward returns the library's dL/dP and its per-layer
+    dL/dk unchanged.
     """
 
     @staticmethod
-    def forward(ctx, P, k, grid_factory, opts=None):
-        g = grid_factory(k.detach().cpu().numpy())
+    def forward(ctx, P, k, grid, opts=None):
+        kh = k.detach().cpu().numpy()
+        if isinstance(grid, Grid):
+            g = grid
+            g.set_conductivity(kh, kh)
+        else:
+            g = grid(kh)
         T, _ = g.solve(P.contiguous(), opts=opts)
+        ctx.k = kh
         ctx.grid = g
         ctx.opts = opts
         ctx.k_device = k.device
@@ -319,5 +344,9 @@ class ThermalSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gT):
         (T,) = ctx.saved_tensors
-        dP, dk, _ = ctx.grid.adjoint(T, gT.contiguous(), opts=ctx.opts)
+        g = ctx.grid
+        # a later forward on the same Grid may have set other conductivities
+        if not (np.array_equal(g._kl, ctx.k) and np.array_equal(g._kv, ctx.k)):
+            g.set_conductivity(ctx.k, ctx.k)
+        dP, dk, _ = g.adjoint(T, gT.contiguous(), opts=ctx.opts)
         return dP, dk.to(ctx.k_device), None, None

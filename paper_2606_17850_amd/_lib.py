@@ -28,7 +28,8 @@ STORAGES = {"stencil": 0, "csr": 1}
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BREAKDOWN"}
 
 EXPORTED = (
-    "cuth_default_options", "cuth_grid_create", "cuth_grid_destroy", "cuth_solve",
+    "cuth_default_options", "cuth_grid_create", "cuth_grid_destroy",
+    "cuth_grid_set_conductivity", "cuth_solve",
     "cuth_transient_step", "cuth_solve_batch", "cuth_adjoint", "cuth_last_error",
     "cuth_apply", "cuth_apply_csr", "cuth_residual", "cuth_precond_apply",
     "cuth_precond_apply_noalloc", "cuth_spectral_bounds",
@@ -91,6 +92,7 @@ def load() -> ctypes.CDLL:
         "cuth_default_options": (None, [ctypes.POINTER(Options)]),
         "cuth_grid_create": (ctypes.c_int, [ctypes.POINTER(GridDesc), vp, ctypes.POINTER(vp)]),
         "cuth_grid_destroy": (None, [vp]),
+        "cuth_grid_set_conductivity": (ctypes.c_int, [vp, c_double_p, c_double_p, vp]),
         "cuth_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
         "cuth_transient_step": (ctypes.c_int, [vp, dbl, vp, vp, vp, ctypes.POINTER(Options),
                                                ctypes.POINTER(Stats)]),

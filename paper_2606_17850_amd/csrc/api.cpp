@@ -93,6 +93,9 @@ cuth_options resolve(const cuth_options *o, bool &ok) {
 
 cuth_status check_handle(cuth_grid g) {
     if (!g || !g->g) return fail(CUTH_E_INVALID, "grid handle is NULL");
+    if (!g->g->valid)
+        return fail(CUTH_E_INVALID, "grid conductivities are invalid: the last "
+                                    "cuth_grid_set_conductivity was rejected on the device");
     return CUTH_OK;
 }
 
@@ -149,6 +152,23 @@ void cuth_grid_destroy(cuth_grid g) {
     if (!g) return;
     cuth::grid_destroy(g->g);
     delete g;
+}
+
+cuth_status cuth_grid_set_conductivity(cuth_grid h, const double *k_lat, const double *k_vert,
+                                       const double *k_lat_mult) {
+    return guarded([&]() -> cuth_status {
+        if (!h || !h->g) return fail(CUTH_E_INVALID, "grid handle is NULL");
+        cuth::Grid &g = *h->g;
+        if (!k_lat || !k_vert) return fail(CUTH_E_INVALID, "k_lat and k_vert are required");
+        for (int l = 0; l < g.nz; ++l)
+            if (!finite_pos(k_lat[l]) || !finite_pos(k_vert[l]))
+                return fail(CUTH_E_INVALID, "k_lat[l] and k_vert[l] must be finite and > 0");
+        if (g.per_cell && !k_lat_mult)
+            return fail(CUTH_E_INVALID, "the grid was created with k_lat_mult: it is required");
+        if (!g.per_cell && k_lat_mult)
+            return fail(CUTH_E_INVALID, "the grid was created without k_lat_mult: pass NULL");
+        return report(cuth::grid_set_conductivity(g, k_lat, k_vert, k_lat_mult));
+    });
 }
 
 cuth_status cuth_solve(cuth_grid h, const double *P, double *T, const cuth_options *opt,

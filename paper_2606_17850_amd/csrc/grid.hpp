@@ -116,6 +116,8 @@ struct Grid {
     uint16_t *hx = nullptr, *hy = nullptr;   // FP16 planes (per-cell grids)
     std::vector<double> lat_rowmax;    // per layer, per-cell grids only
     std::vector<int> e16;              // per-layer FP16 scale exponent e_l
+    double *build_tmp = nullptr;       // per-layer inputs and maxima of the plane build
+    bool valid = true;                 // false after a rejected multiplier (set_conductivity)
 
     std::deque<Setup> setups;         // a deque: Setup pointers stay valid as dt's are added
     Work<float> w32;
@@ -154,6 +156,9 @@ Status prof_flush(Grid &g, int valid_below = 1 << 30);
 
 Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out);
 void grid_destroy(Grid *g);
+// New layer conductivities for an existing grid, rebuilt in place (mult: the
+// per-cell multiplier, required for per-cell grids and ignored otherwise).
+Status grid_set_conductivity(Grid &g, const double *k_lat, const double *k_vert, const double *mult);
 
 Setup *get_setup(Grid &g, double dt, Status &st);
 // scaled: the interval of D^{-1} A (Lanczos on D^{-1/2} A D^{-1/2}), for the

@@ -1405,6 +1405,85 @@ void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b
 }
 
 // ----------------------------------------------------------------- handle
+// adjoint factors: 1/k_lat[l], and dg/dk_vert[l] of the faces above / below layer l
+// (g = dx dy / (dz_a/(2 k_a) + dz_b/(2 k_b)) gives dg/dk_a = g^2 dz_a / (2 k_a^2 dx dy))
+static Status upload_adj_factors(Grid &g) {
+    const int nz = g.nz;
+    std::vector<double> fac((size_t)3 * nz, 0.0);
+    const double dxdy = g.dx * g.dy;
+    for (int l = 0; l < nz; ++l) {
+        fac[l] = 1.0 / g.k_lat[l];
+        const double kv = g.k_vert[l];
+        if (l + 1 < nz) {
+            const double gz = dxdy / (g.dz[l] / (2.0 * kv) + g.dz[l + 1] / (2.0 * g.k_vert[l + 1]));
+            fac[nz + l] = gz * gz * g.dz[l] / (2.0 * kv * kv * dxdy);
+        }
+        if (l > 0) {
+            const double gz = dxdy / (g.dz[l - 1] / (2.0 * g.k_vert[l - 1]) + g.dz[l] / (2.0 * kv));
+            fac[2 * nz + l] = gz * gz * g.dz[l] / (2.0 * kv * kv * dxdy);
+        }
+    }
+    if (hipMemcpy(g.adj_fac, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return Status::err(CUTH_E_DEVICE, "hipMemcpy failed");
+    return Status::ok();
+}
+
+// Per-cell grids: the face conductance planes from k_lat and the multiplier
+// (FP64, FP32, and FP16 scaled per layer by 2^e_l), with the per-layer maxima
+// of the lateral row sums; then the adjoint factors (every grid).  Writes the
+// grid's allocations only (planes and build_tmp: dz, k_lat and the FP16 scales
+// per layer, then the two maxima per layer and the bad-entry flag).
+static Status build_coefficients(Grid &g, const double *mult) {
+    CUTH_TRY(upload_adj_factors(g));
+    if (!g.per_cell) return Status::ok();
+    const int nz = g.nz;
+    double *ddz = g.build_tmp, *dkl = ddz + nz, *dscale = dkl + nz;
+    unsigned long long *dmax = reinterpret_cast<unsigned long long *>(dscale + nz);
+    unsigned int *dbad = reinterpret_cast<unsigned int *>(dmax + 2 * nz);
+    // dmax[0, nz): max lateral row sum per layer; dmax[nz, 2 nz): max single g
+    std::vector<unsigned long long> hmax(2 * (size_t)nz, 0ull);
+    unsigned int hbad = 0;
+    bool ok = hipMemcpy(ddz, g.dz.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(dkl, g.k_lat.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(dmax, 0, 2 * nz * sizeof(unsigned long long)) == hipSuccess &&
+              hipMemset(dbad, 0, sizeof(unsigned int)) == hipSuccess;
+    if (ok) {
+        launch_build_lateral(g.nx, g.ny, nz, g.dx, g.dy, ddz, dkl, mult, g.gx64, g.gy64, g.gx32,
+                             g.gy32, dmax, dmax + nz, dbad, g.stream);
+        ok = hipStreamSynchronize(g.stream) == hipSuccess &&
+             hipMemcpy(hmax.data(), dmax, 2 * nz * sizeof(unsigned long long), hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(&hbad, dbad, sizeof(unsigned int), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    if (ok && !hbad) {
+        g.lat_rowmax.resize(nz);
+        g.e16.assign(nz, 0);
+        std::vector<double> scale(nz, 1.0);
+        for (int l = 0; l < nz; ++l) {
+            double v, m;
+            std::memcpy(&v, &hmax[l], sizeof(double));
+            std::memcpy(&m, &hmax[nz + l], sizeof(double));
+            g.lat_rowmax[l] = v;
+            // FP16 storage scale 2^e_l with e_l = 14 - ceil(log2(max g)):
+            // frexp gives m = f 2^x with f in [0.5, 1), so ceil(log2 m) is
+            // x, or x - 1 when f is exactly 0.5
+            if (m > 0.0) {
+                int x = 0;
+                const double f = std::frexp(m, &x);
+                g.e16[l] = 14 - (f == 0.5 ? x - 1 : x);
+            }
+            scale[l] = std::ldexp(1.0, g.e16[l]);
+        }
+        ok = hipMemcpy(dscale, scale.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+        if (ok) {
+            launch_build_fp16(g.nx, g.ny, nz, g.gx64, g.gy64, dscale, g.hx, g.hy, g.stream);
+            ok = hipStreamSynchronize(g.stream) == hipSuccess;
+        }
+    }
+    if (!ok) return Status::err(CUTH_E_DEVICE, "coefficient build failed");
+    if (hbad) return Status::err(CUTH_E_INVALID, "k_lat_mult has entries <= 0 or non-finite");
+    return Status::ok();
+}
+
 Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
     Grid *g = new Grid();
     *out = nullptr;
@@ -1455,28 +1534,6 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
         hipEventCreate(&g->ev2) != hipSuccess)
         return fail(Status::err(CUTH_E_DEVICE, "hipEventCreate failed"));
 
-    // adjoint factors: 1/k_lat[l], and dg/dk_vert[l] of the faces above / below layer l
-    // (g = dx dy / (dz_a/(2 k_a) + dz_b/(2 k_b)) gives dg/dk_a = g^2 dz_a / (2 k_a^2 dx dy))
-    {
-        const int nz = g->nz;
-        std::vector<double> fac((size_t)3 * nz, 0.0);
-        const double dxdy = g->dx * g->dy;
-        for (int l = 0; l < nz; ++l) {
-            fac[l] = 1.0 / g->k_lat[l];
-            const double kv = g->k_vert[l];
-            if (l + 1 < nz) {
-                const double gz = dxdy / (g->dz[l] / (2.0 * kv) + g->dz[l + 1] / (2.0 * g->k_vert[l + 1]));
-                fac[nz + l] = gz * gz * g->dz[l] / (2.0 * kv * kv * dxdy);
-            }
-            if (l > 0) {
-                const double gz = dxdy / (g->dz[l - 1] / (2.0 * g->k_vert[l - 1]) + g->dz[l] / (2.0 * kv));
-                fac[2 * nz + l] = gz * gz * g->dz[l] / (2.0 * kv * kv * dxdy);
-            }
-        }
-        if (hipMemcpy(g->adj_fac, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(Status::err(CUTH_E_DEVICE, "hipMemcpy failed"));
-    }
-
     if (g->per_cell) {
         const int64_t N = g->N;
         if ((st = dev_alloc(&g->gx64, (size_t)N)).bad()) return fail(st);
@@ -1485,62 +1542,9 @@ Status grid_create(const cuth_grid_desc &d, hipStream_t s, Grid **out) {
         if ((st = dev_alloc(&g->gy32, (size_t)N)).bad()) return fail(st);
         if ((st = dev_alloc(&g->hx, (size_t)N)).bad()) return fail(st);
         if ((st = dev_alloc(&g->hy, (size_t)N)).bad()) return fail(st);
-        const int nz = g->nz;
-        double *ddz = nullptr, *dkl = nullptr, *dscale = nullptr;
-        unsigned long long *dmax = nullptr;
-        unsigned int *dbad = nullptr;
-        auto free_tmp = [&] {
-            dev_free(ddz); dev_free(dkl); dev_free(dscale); dev_free(dmax); dev_free(dbad);
-        };
-        if ((st = dev_alloc(&ddz, (size_t)nz)).bad() || (st = dev_alloc(&dkl, (size_t)nz)).bad() ||
-            (st = dev_alloc(&dscale, (size_t)nz)).bad() || (st = dev_alloc(&dmax, (size_t)2 * nz)).bad() ||
-            (st = dev_alloc(&dbad, 1)).bad()) {
-            free_tmp();
-            return fail(st);
-        }
-        // dmax[0, nz): max lateral row sum per layer; dmax[nz, 2 nz): max single g
-        std::vector<unsigned long long> hmax(2 * (size_t)nz, 0ull);
-        unsigned int hbad = 0;
-        bool ok = hipMemcpy(ddz, g->dz.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemcpy(dkl, g->k_lat.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemset(dmax, 0, 2 * nz * sizeof(unsigned long long)) == hipSuccess &&
-                  hipMemset(dbad, 0, sizeof(unsigned int)) == hipSuccess;
-        if (ok) {
-            launch_build_lateral(g->nx, g->ny, nz, g->dx, g->dy, ddz, dkl, d.k_lat_mult, g->gx64,
-                                 g->gy64, g->gx32, g->gy32, dmax, dmax + nz, dbad, g->stream);
-            ok = hipStreamSynchronize(g->stream) == hipSuccess &&
-                 hipMemcpy(hmax.data(), dmax, 2 * nz * sizeof(unsigned long long), hipMemcpyDeviceToHost) == hipSuccess &&
-                 hipMemcpy(&hbad, dbad, sizeof(unsigned int), hipMemcpyDeviceToHost) == hipSuccess;
-        }
-        if (ok && !hbad) {
-            g->lat_rowmax.resize(nz);
-            g->e16.assign(nz, 0);
-            std::vector<double> scale(nz, 1.0);
-            for (int l = 0; l < nz; ++l) {
-                double v, m;
-                std::memcpy(&v, &hmax[l], sizeof(double));
-                std::memcpy(&m, &hmax[nz + l], sizeof(double));
-                g->lat_rowmax[l] = v;
-                // FP16 storage scale 2^e_l with e_l = 14 - ceil(log2(max g)):
-                // frexp gives m = f 2^x with f in [0.5, 1), so ceil(log2 m) is
-                // x, or x - 1 when f is exactly 0.5
-                if (m > 0.0) {
-                    int x = 0;
-                    const double f = std::frexp(m, &x);
-                    g->e16[l] = 14 - (f == 0.5 ? x - 1 : x);
-                }
-                scale[l] = std::ldexp(1.0, g->e16[l]);
-            }
-            ok = hipMemcpy(dscale, scale.data(), nz * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
-            if (ok) {
-                launch_build_fp16(g->nx, g->ny, nz, g->gx64, g->gy64, dscale, g->hx, g->hy, g->stream);
-                ok = hipStreamSynchronize(g->stream) == hipSuccess;
-            }
-        }
-        free_tmp();
-        if (!ok) return fail(Status::err(CUTH_E_DEVICE, "coefficient build failed"));
-        if (hbad) return fail(Status::err(CUTH_E_INVALID, "k_lat_mult has entries <= 0 or non-finite"));
+        if ((st = dev_alloc(&g->build_tmp, (size_t)5 * g->nz + 1)).bad()) return fail(st);
     }
+    if ((st = build_coefficients(*g, d.k_lat_mult)).bad()) return fail(st);
     *out = g;
     return Status::ok();
 }
@@ -1572,6 +1576,7 @@ void grid_destroy(Grid *g) {
     dev_free(g->gy32);
     dev_free(g->hx);
     dev_free(g->hy);
+    dev_free(g->build_tmp);
     free_work(g->w32);
     free_work(g->w64);
     dev_free(g->thA);
@@ -1667,6 +1672,39 @@ Setup *get_setup(Grid &g, double dt, Status &status) {
     }
     g.setups.push_back(su);
     return &g.setups.back();
+}
+
+Status grid_set_conductivity(Grid &g, const double *k_lat, const double *k_vert, const double *mult) {
+    // nothing in flight may read the planes or coefficients being replaced
+    CUTH_TRY(sync_stream(g.stream));
+    g.valid = false;
+    g.k_lat.assign(k_lat, k_lat + g.nz);
+    g.k_vert.assign(k_vert, k_vert + g.nz);
+    CUTH_TRY(build_coefficients(g, g.per_cell ? mult : nullptr));
+    // every operator the handle holds (one per dt used so far): its layer
+    // coefficients in place, its spectral intervals and stop predictions
+    // dropped, the Jacobi scaling recomputed, the CSR copy rebuilt on next use
+    for (Setup &su : g.setups) {
+        layer_coefs(g, su.dt, su.hlc, su.gersh);
+        const std::vector<LayerCoef<float>> h32 = layer_coefs32(su.hlc);
+        if (hipMemcpy(su.lc64, su.hlc.data(), g.nz * sizeof(LayerCoef<double>), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(su.lc32, h32.data(), g.nz * sizeof(LayerCoef<float>), hipMemcpyHostToDevice) != hipSuccess)
+            return Status::err(CUTH_E_DEVICE, "hipMemcpy of layer coefficients failed");
+        su.have_bounds = false;
+        su.bounds_steps = 0;
+        su.have_jbounds = false;
+        su.jbounds_steps = 0;
+        if (su.dis) launch_jacobi_dis(view64(g, su), su.dis, g.stream);
+        dev_free(su.csr_ptr);
+        dev_free(su.csr_col);
+        dev_free(su.csr_val);
+        su.csr_nnz = 0;
+        std::memset(su.stop_iter, 0, sizeof(su.stop_iter));
+    }
+    CUTH_HIP(hipGetLastError());
+    CUTH_TRY(sync_stream(g.stream));
+    g.valid = true;
+    return Status::ok();
 }
 
 // FP32 Lanczos on the FP32 operator (Section 4.4, component-wise precision of

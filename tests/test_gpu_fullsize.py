@@ -288,27 +288,43 @@ def test_batch_config3_subset():
         gg.close()
 
 
-def test_autograd_function_matches_oracle():
+@pytest.mark.parametrize("mode", ["factory", "grid"])
+def test_autograd_function_matches_oracle(mode):
+    """ThermalSolve with a new grid per call (factory), and with one Grid whose
+    conductivities are set in place: two descent steps on k, the second after
+    set_conductivity, each gradient against the oracle's at that k."""
+    import copy
+
     import paper_2606_17850_amd as cuth
-    say("autograd")
-    st, P = w.config4_small()
-    mask = torch.as_tensor(st.si_mask().ravel(), device=dev())
+    say(f"autograd {mode}")
+    st0, P = w.config4_small()
+    mask = torch.as_tensor(st0.si_mask().ravel(), device=dev())
     beta = 0.5
-    mult = torch.as_tensor(st.k_lat_mult.ravel(), device=dev())
+    mult = torch.as_tensor(st0.k_lat_mult.ravel(), device=dev())
 
     def factory(k):
-        return cuth.Grid(st.nx, st.ny, st.nz, st.dx, st.dy, st.dz, k, k, k_lat_mult=mult,
-                         heat_cap=st.heat_cap, h_top=st.h_top, t_amb=st.t_amb, device=dev())
+        return cuth.Grid(st0.nx, st0.ny, st0.nz, st0.dx, st0.dy, st0.dz, k, k, k_lat_mult=mult,
+                         heat_cap=st0.heat_cap, h_top=st0.h_top, t_amb=st0.t_amb, device=dev())
 
-    assert np.array_equal(st.k_lat, st.k_vert)
-    Pt = t64(P).requires_grad_(True)
-    s = torch.tensor(st.k_lat, dtype=torch.float64, requires_grad=True)
-    T = cuth.ThermalSolve.apply(Pt, s, factory, None)
-    L = torch.logsumexp(beta * T[mask], 0) / beta
-    L.backward()
-    Tn = T.detach().cpu().numpy()
-    gT = oadj.lse_grad(Tn, st.si_mask(), beta)
-    ref = oadj.gradient(st, Tn - st.t_amb, gT, direct.solve_splu)
-    assert np.abs(Pt.grad.cpu().numpy() - ref.dP).max() <= 1e-6 * np.abs(ref.dP).max()
-    np.testing.assert_allclose(s.grad.cpu().numpy(), ref.dk_layer, rtol=1e-6,
-                               atol=1e-9 * np.abs(ref.dk_layer).max())
+    assert np.array_equal(st0.k_lat, st0.k_vert)
+    grid = factory(np.asarray(st0.k_lat)) if mode == "grid" else factory
+    k = np.asarray(st0.k_lat, dtype=np.float64)
+    for it in range(2 if mode == "grid" else 1):
+        st = copy.deepcopy(st0)
+        st.k_lat = k.copy()
+        st.k_vert = k.copy()
+        Pt = t64(P).requires_grad_(True)
+        s = torch.tensor(k, dtype=torch.float64, requires_grad=True)
+        T = cuth.ThermalSolve.apply(Pt, s, grid, None)
+        L = torch.logsumexp(beta * T[mask], 0) / beta
+        L.backward()
+        Tn = T.detach().cpu().numpy()
+        gT = oadj.lse_grad(Tn, st.si_mask(), beta)
+        ref = oadj.gradient(st, Tn - st.t_amb, gT, direct.solve_splu)
+        assert np.abs(Pt.grad.cpu().numpy() - ref.dP).max() <= 1e-6 * np.abs(ref.dP).max()
+        np.testing.assert_allclose(s.grad.cpu().numpy(), ref.dk_layer, rtol=1e-6,
+                                   atol=1e-9 * np.abs(ref.dk_layer).max())
+        # a descent step on log k (dL/dk < 0 raises k), at most 20 % per layer
+        k = k * np.exp(np.clip(-0.2 * np.sign(ref.dk_layer), -0.2, 0.2))
+    if mode == "grid":
+        grid.close()

@@ -1058,3 +1058,93 @@ def test_graph_replays_match_eager(monkeypatch, prec):
         torch.cuda.synchronize()
         assert torch.equal(T2, T_eager)
     g.close()
+
+
+@pytest.mark.parametrize("mult", [True, False])
+def test_set_conductivity_matches_new_grid(mult):
+    """New layer conductivities set in place answer as a grid built with them:
+    the FP64, FP32 and FP16-plane products of the steady and transient
+    operators (both cached before the change), the residual, the spectral
+    interval, a mixed solve, the Jacobi-scaled preconditioner and the adjoint,
+    bit for bit; the solve also against the oracle at the new values."""
+    import copy
+
+    import paper_2606_17850_amd as cuth
+    say(f"set_conductivity mult={mult}")
+    st0 = ragged_stack(70, 9, mult=mult)
+    rng = np.random.default_rng(21)
+    P = np.zeros(st0.shape)
+    P[0] = rng.uniform(0, 2e-3, (st0.ny, st0.nx))
+    x = rng.uniform(-1, 1, st0.n) + 2.0
+    dt = 1e-4
+    g = grid_of(st0)
+    # operators, bounds, graphs and stop predictions of the old values
+    for d in (0.0, dt):
+        g.apply(t64(x), dt=d)
+    g.solve(t64(P), precision="mixed")
+    g.solve(t64(P), precision="mixed", preconditioner="chebyshev_jacobi")
+    st1 = copy.deepcopy(st0)
+    st1.k_lat = st0.k_lat * rng.uniform(0.5, 2.0, st0.nz)
+    st1.k_vert = st0.k_vert * rng.uniform(0.5, 2.0, st0.nz)
+    g.set_conductivity(st1.k_lat, st1.k_vert)
+    g1 = grid_of(st1)
+    for d in (0.0, dt):
+        assert torch.equal(g.apply(t64(x), dt=d), g1.apply(t64(x), dt=d))
+        x32 = t64(x).float()
+        assert torch.equal(g.apply(x32, dt=d), g1.apply(x32, dt=d))
+        if mult:
+            assert torch.equal(g.apply(x32, dt=d, fp16_coef=True), g1.apply(x32, dt=d, fp16_coef=True))
+        b = t64(P)
+        Tx = t64(st0.t_amb + x)
+        assert torch.equal(g.residual(b, Tx, dt=d), g1.residual(b, Tx, dt=d))
+    sb, sb1 = g.spectral_bounds(), g1.spectral_bounds()
+    assert sb["lmin"] == sb1["lmin"] and sb["lmax"] == sb1["lmax"]
+    T, s = g.solve(t64(P), precision="mixed")
+    T1, s1 = g1.solve(t64(P), precision="mixed")
+    assert torch.equal(T, T1) and s["cg_iters"] == s1["cg_iters"]
+    assert rise_err(T.cpu().numpy(), _ref_steady(st1, P), st1.t_amb) <= 1e-8
+    Tj, _ = g.solve(t64(P), precision="mixed", preconditioner="chebyshev_jacobi")
+    Tj1, _ = g1.solve(t64(P), precision="mixed", preconditioner="chebyshev_jacobi")
+    assert torch.equal(Tj, Tj1)
+    gT = t64(rng.uniform(0, 1, st0.n))
+    dP, dk, _ = g.adjoint(T, gT)
+    dP1, dk1, _ = g1.adjoint(T1, gT)
+    assert torch.equal(dP, dP1) and torch.equal(dk, dk1)
+    g1.close()
+    g.close()
+
+
+def test_set_conductivity_rejections():
+    """Host checks leave the grid as it was; a multiplier that the device check
+    rejects leaves it refusing calls until a valid set."""
+    import paper_2606_17850_amd as cuth
+    st = ragged_stack(70, 9, mult=True)
+    g = grid_of(st)
+    x = t64(np.random.default_rng(22).uniform(1, 2, st.n))
+    y0 = g.apply(x)
+    bad_k = np.array(st.k_lat, dtype=np.float64)
+    bad_k[1] = -1.0
+    for kl, kv in ((bad_k, st.k_vert), (st.k_lat, np.full(st.nz, np.nan))):
+        with pytest.raises(cuth.CuthError) as e:
+            g.set_conductivity(kl, kv)
+        assert e.value.status == cuth._lib.CUTH_E_INVALID
+    assert torch.equal(g.apply(x), y0)
+    # a uniform grid takes no multiplier
+    gu = grid_of(ragged_stack(70, 9, mult=False))
+    with pytest.raises(cuth.CuthError) as e:
+        gu.set_conductivity(st.k_lat, st.k_vert, k_lat_mult=t64(np.ones(st.n)))
+    assert e.value.status == cuth._lib.CUTH_E_INVALID
+    gu.close()
+    # a multiplier with a zero entry, found by the build kernel's own check
+    m = np.ascontiguousarray(st.k_lat_mult, dtype=np.float64).ravel().copy()
+    m[17] = 0.0
+    with pytest.raises(cuth.CuthError) as e:
+        g.set_conductivity(st.k_lat, st.k_vert, k_lat_mult=t64(m))
+    assert e.value.status == cuth._lib.CUTH_E_INVALID
+    with pytest.raises(cuth.CuthError) as e:
+        g.apply(x)
+    assert e.value.status == cuth._lib.CUTH_E_INVALID
+    g.set_conductivity(st.k_lat, st.k_vert,
+                       k_lat_mult=t64(np.ascontiguousarray(st.k_lat_mult, dtype=np.float64).ravel()))
+    assert torch.equal(g.apply(x), y0)
+    g.close()
