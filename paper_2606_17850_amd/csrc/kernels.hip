@@ -446,17 +446,26 @@ __device__ __forceinline__ T jac_diag(const LayerCoef<T> &L, T gm, T gp, T gs, T
 // an XS with arithmetic, which would otherwise wait for its loads inside the
 // branch.  EMIT_ALL: inactive lanes call emit too (emit tests Lane::act
 // itself), for an emit whose inputs would otherwise be loaded under the
-// branch around it.
+// branch around it.  XS may likewise return raw loads, which fins forms into
+// the value (default: the identity).  pro() runs after the first layer's loads
+// are issued and before any is used: the kernel's own prologue (a sum of the
+// previous kernel's partials, say) then overlaps them; the march stops at once
+// if it returns false.  A pro that the loads depend on cannot be passed here.
 struct IdentFin {
     template <typename V>
     __device__ __forceinline__ const V &operator()(const V &v) const { return v; }
 };
+struct NoPro {
+    __device__ __forceinline__ bool operator()() const { return true; }
+};
 
 template <typename T, bool PC, int VX, int CS, bool EDGE_ALL = false, bool EMIT_ALL = false,
           typename FV, typename FS,
-          typename FP, typename E, typename FX = IdentFin>
+          typename FP, typename E, typename FX = IdentFin, typename FXS = IdentFin,
+          typename PRO = NoPro>
 __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, FV &&XV, FS &&XS,
-                                           FP &&PRE, E &&emit, FX &&fin = FX{}) {
+                                           FP &&PRE, E &&emit, FX &&fin = FX{},
+                                           FXS &&fins = FXS{}, PRO &&pro = PRO{}) {
     const int nx = op.nx, ny = op.ny, nz = op.nz;
     const int64_t plane = (int64_t)nx * ny;
     const bool act = ln.act;
@@ -464,7 +473,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         // the CSR baseline: each of the lane's rows walks its own entries and
         // gathers the operand at their columns (no neighbour exchange between
         // lanes, so inactive lanes may leave at once)
-        if (!act) return;
+        if (!pro() || !act) return;
         int64_t c = ln.i0 + (int64_t)nx * ln.j + plane * ln.l0;
         for (int l = ln.l0; l < ln.l1; ++l, c += plane) {
             const Vec<T, VX> xc = fin(XV(c));
@@ -474,7 +483,7 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
                 const int k1 = gld(op.csr_ptr + c + e + 1);
                 T a = T(0);
                 for (int k = gld(op.csr_ptr + c + e); k < k1; ++k)
-                    a += (T)gld(op.csr_val + k) * XS(gld(op.csr_col + k));
+                    a += (T)gld(op.csr_val + k) * fins(XS(gld(op.csr_col + k)));
                 ax.a[e] = a;
             }
             emit(l, c, xc, ax, PRE(c), vzero<T, VX>());
@@ -500,9 +509,10 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
     // so every address is in bounds.
     using Pre = decltype(PRE(int64_t(0)));
     using Raw = std::decay_t<decltype(XV(int64_t(0)))>;
+    using RawS = std::decay_t<decltype(XS(int64_t(0)))>;
     struct Loads {
         Raw xup, xso, xno;
-        T west, east;
+        RawS west, east;
         LatRaw<T, VX, CS> lat;
         Pre pre;
     };
@@ -517,15 +527,17 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             q.west = XS((ln.lane == 0 && has_l) ? cc - 1 : cc);
             q.east = XS((ln.lane == kWave - 1 && has_r) ? cc + VX : cc);
         } else {
-            q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : T(0);
-            q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : T(0);
+            q.west = (ln.lane == 0 && has_l) ? XS(cc - 1) : RawS{};
+            q.east = (ln.lane == kWave - 1 && has_r) ? XS(cc + VX) : RawS{};
         }
         if constexpr (PC) q.lat = lateral_load<T, VX, CS>(op, cc, ln.lane, act, has_l, has_s);
         q.pre = PRE(cc);
         return q;
     };
-    Vec<T, VX> xdn = fin(XV((act && ln.l0 > 0) ? c - plane : c));
-    Vec<T, VX> xc = fin(XV(c));
+    // the column's first two operand values, formed after pro()
+    const Raw xdn0 = XV((act && ln.l0 > 0) ? c - plane : c);
+    const Raw xc0 = XV(c);
+    Vec<T, VX> xdn, xc;
     // layer l's body with its loads already in registers (cur)
     auto layer = [&](int l, int64_t c, const Loads &cur) {
         const LayerCoef<T> L = gldc(op.lc + l);
@@ -533,8 +545,8 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         const auto &pre = cur.pre;
         T left = lane_left(xc.a[VX - 1]);
         T right = lane_right(xc.a[0]);
-        if (ln.lane == 0) left = cur.west;
-        if (ln.lane == kWave - 1) right = cur.east;
+        if (ln.lane == 0) left = fins(cur.west);
+        if (ln.lane == kWave - 1) right = fins(cur.east);
         Vec<T, VX> gxp, gyp, gym;
         T gxl = T(0);
         if constexpr (PC)
@@ -587,6 +599,9 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
         Loads qa, qb;
         int l = ln.l0;
         if (l < ln.l1) qa = issue(l, c);
+        if (!pro()) return;
+        xdn = fin(xdn0);
+        xc = fin(xc0);
         while (l < ln.l1) {
             if (l + 1 >= ln.l1) {
                 layer(l, c, qa);
@@ -606,6 +621,9 @@ __device__ __forceinline__ void column_pre(const OpView<T> &op, const Lane &ln, 
             c += plane;
         }
     } else {
+        if (!pro()) return;
+        xdn = fin(xdn0);
+        xc = fin(xc0);
         for (int l = ln.l0; l < ln.l1; ++l, c += plane) layer(l, c, issue(l, c));
     }
 }
@@ -683,13 +701,20 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
     // the sweep's constants are fetched together with the stop flag
     const T inv_th = P.cheb[0], c1 = P.cheb[1 + j], c2 = P.cheb[1 + P.kcap + j];
     const int done = st->done;
-    if constexpr (CHK) {
-        // the partial sums are fetched while the stop flag is in flight
-        const bool stop = conv_test(st, part_in, red, pidx, P, !done && slot == P.tile0);
-        if (done || stop) return;
-    } else {
+    if constexpr (!CHK) {
         if (done) return;
     }
+    // the convergence test after a CG update (CHK) runs inside the march, once
+    // the first layer's loads are in flight; its partial sums are fetched while
+    // the stop flag is in flight too
+    bool go = true;
+    auto prologue = [&]() {
+        if constexpr (CHK) {
+            const bool stop = conv_test(st, part_in, red, pidx, P, !done && slot == P.tile0);
+            go = !(done || stop);
+        }
+        return go;
+    };
     const OpView<T> op = P.op;
     const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
     const T *__restrict__ r = P.r;
@@ -708,9 +733,10 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
             return v;
         }
     };
-    auto XS = [&](int64_t q) -> T {
-        if constexpr (MODE == 1) return gld(r + q) * inv_th;
-        else return gld(z + q);
+    auto XS = [&](int64_t q) -> T { return gld((MODE == 1 ? r : z) + q); };
+    auto fins = [&](T v) -> T {
+        if constexpr (MODE == 1) return v * inv_th;
+        else return v;
     };
     struct Ex {
         Vec<T, VX> r, zm;
@@ -741,7 +767,8 @@ __global__ __launch_bounds__(512) void k_cheb_b(const InnerProb<T> *__restrict__
                           }
                           vstore<T, VX>(zo + c, zn);
                       },
-                      fin);
+                      fin, fins, prologue);
+    if (!go) return;   // the same for every wavefront of the workgroup
     if constexpr (LAST) block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
@@ -1439,14 +1466,6 @@ __global__ __launch_bounds__(512) void k_update_b(const InnerProb<T> *__restrict
     CgState<T> *st = P.st;
     const int done = st->done;
     const T rz = st->rz[par], rz_prev = st->rz[1 - par];
-    const T pmu = prev_sum(part_in, red, pidx, P);
-    if (done) return;
-    const bool bad = !(pmu > T(0)) || !finite_val(pmu);
-    if (bad) {
-        if (slot == P.tile0 && tid_lin() == 0) st->done = 4;
-        return;
-    }
-    const T alpha = rz / pmu;
     const bool first = isinf(rz_prev);
     const T *__restrict__ p = P.p[par];
     const T *__restrict__ mu = P.mu;
@@ -1455,23 +1474,83 @@ __global__ __launch_bounds__(512) void k_update_b(const InnerProb<T> *__restrict
     float *__restrict__ r_lo = P.r_lo;
     const OpView<T> op = P.op;
     const Lane ln = lane_at<VX>(op, slot - P.tile0, P.ntx, P.ntz);
+    const int64_t plane = (int64_t)op.nx * op.ny;
+    // The lane's layers stream through two alternating load sets, the first
+    // issued before the partial sums of p^T A p are fetched, so that the
+    // stream starts at once and two layers are in flight.  x is read at p on
+    // the first iteration, where it is scaled by 0 (x starts at 0): no load
+    // depends on a test.  The layer count is the workgroup's, so the loop's
+    // branches are uniform; inactive lanes load at in-bounds cells (k planes
+    // from cell 0), add nothing and store nothing.
+    const T *__restrict__ xsrc = first ? p : x;
+    const T keep = first ? T(0) : T(1);
+    struct Set {
+        Vec<T, VX> p, m, r, x;
+    };
+    auto issue = [&](int64_t c) {
+        Set q;
+        q.p = vload<T, VX>(p + c);
+        q.m = vload<T, VX>(mu + c);
+        q.r = vload<T, VX>(r + c);
+        q.x = vload<T, VX>(xsrc + c);
+        return q;
+    };
+    int64_t c = ln.act ? ln.i0 + (int64_t)op.nx * ln.j + plane * ln.l0 : 0;
+    const int nl = ln.l1 - ln.l0;
+    Set qa = issue(c), qb;
+    const T pmu = prev_sum(part_in, red, pidx, P);
+    if (done) return;
+    const bool bad = !(pmu > T(0)) || !finite_val(pmu);
+    if (bad) {
+        if (slot == P.tile0 && tid_lin() == 0) st->done = 4;
+        return;
+    }
+    const T alpha = rz / pmu;
     T acc[1] = {T(0)};
-    cells<T, VX>(op, ln, [&](int, int64_t c) {
-        const Vec<T, VX> pv = vload<T, VX>(p + c), mv = vload<T, VX>(mu + c);
-        Vec<T, VX> rv = vload<T, VX>(r + c);
-        Vec<T, VX> xv = first ? vzero<T, VX>() : vload<T, VX>(x + c);
-        Vec<float, VX> rl;
+    // ALL: every lane of the wavefront is active (every wavefront of a tile
+    // inside the grid), so the stores need no test: a store under a branch
+    // leaves the loads before it unwaited on the other path, and the compiler
+    // then waits for them before reusing their registers
+    auto march = [&](auto all_tag) {
+        constexpr bool ALL = decltype(all_tag)::value;
+        auto layer = [&](int64_t cc, const Set &q) {
+            Vec<T, VX> xv, rv;
+            Vec<float, VX> rl;
 #pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            xv.a[e] += alpha * pv.a[e];
-            rv.a[e] -= alpha * mv.a[e];
-            acc[0] += rv.a[e] * rv.a[e];
-            rl.a[e] = (float)rv.a[e];
+            for (int e = 0; e < VX; ++e) {
+                // the same contractions as an unmasked x += a p, r -= a mu,
+                // acc += r r (one rounding each): the mask scales a factor
+                xv.a[e] = keep * q.x.a[e];
+                xv.a[e] += alpha * q.p.a[e];
+                rv.a[e] = q.r.a[e] - alpha * q.m.a[e];
+                const T rm = (ALL || ln.act) ? rv.a[e] : T(0);
+                acc[0] += rm * rv.a[e];
+                rl.a[e] = (float)rv.a[e];
+            }
+            if (ALL || ln.act) {
+                vstore<T, VX>(x + cc, xv);
+                vstore<T, VX>(r + cc, rv);
+                if (r_lo) vstore<float, VX>(r_lo + cc, rl);
+            }
+        };
+        // unrolled by hand as in the column walker (a copy between the sets
+        // would make the wavefront wait for the loads in flight); every set
+        // is issued, the one after the last layer at the current layer (an
+        // L2 hit), since a load under a branch makes the compiler wait for
+        // all loads where the paths meet
+        for (int k = 0; k < nl; k += 2, c += 2 * plane) {
+            if (k + 1 >= nl) {
+                layer(c, qa);
+                break;
+            }
+            qb = issue(c + plane);
+            layer(c, qa);
+            qa = issue(k + 2 < nl ? c + 2 * plane : c);
+            layer(c + plane, qb);
         }
-        vstore<T, VX>(x + c, xv);
-        vstore<T, VX>(r + c, rv);
-        if (r_lo) vstore<float, VX>(r_lo + c, rl);
-    });
+    };
+    if (__all(ln.act)) march(std::true_type{});
+    else march(std::false_type{});
     block_partials<T, 1>(acc, 0u, part_out, gridDim.x, slot);
 }
 
@@ -1659,8 +1738,10 @@ __global__ __launch_bounds__(512) void k_residual_b(const OuterProb<TD, TI> *__r
                 const double rc = b - ath.a[e];
                 rv.a[e] = rc;
                 rl.a[e] = (TI)rc;
-                acc[0] += act ? rc * rc : 0.0;
-                acc[1] += act ? b * b : 0.0;
+                // masked factors keep the sums' contractions (one rounding
+                // per term, as unmasked)
+                acc[0] += (act ? rc : 0.0) * rc;
+                acc[1] += (act ? b : 0.0) * b;
                 if (has_d) acc[2] = fmax(acc[2], act ? fabs((double)pr.dv.a[e]) : 0.0);
                 acc[3] = fmax(acc[3], act ? fabs(th.a[e]) : 0.0);
                 acc[4] += (act && !isfinite(rc)) ? 1.0 : 0.0;
