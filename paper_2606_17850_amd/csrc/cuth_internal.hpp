@@ -261,6 +261,11 @@ inline int residual_flags(const OuterProb<TD, TI> &o) {
     return (o.th_in ? 1 : 0) | (o.delta ? 2 : 0) | (o.Tn ? 4 : 0) | (out_api ? 8 : 0);
 }
 constexpr int kResidualValues = 5;
+// Per-problem totals of launch_residual_b's partials (ntot: its workgroups), in
+// a fixed order: out[p * kResidualValues + v].
+template <typename TD, typename TI>
+void launch_reduce_outer(const OuterProb<TD, TI> *probs, int nprob, const double *part, int ntot,
+                         double *out, hipStream_t s);
 
 void launch_add_scalar(int64_t n, const double *x, double a, double *y, hipStream_t s);
 // y = (float) x

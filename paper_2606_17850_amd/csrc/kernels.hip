@@ -1616,6 +1616,72 @@ __global__ __launch_bounds__(256) void k_reduce_b(const InnerProb<T> *__restrict
     if (tid_lin() == 0) red_out[blockIdx.x] = s;
 }
 
+// Per-problem totals of the FP64 outer residual's partials (sums of ||r||^2,
+// ||b||^2 and the non-finite count, maxima of |delta| and |theta|), one
+// workgroup per problem in a fixed order: the host reads five values per
+// problem instead of every workgroup's (about 1 MB at 21 M unknowns, summed on
+// the host while the device waited).
+constexpr int kReduceOuterWaves = 16;   // wavefronts of a k_reduce_outer workgroup
+
+template <typename TD, typename TI>
+__global__ __launch_bounds__(1024) void k_reduce_outer(const OuterProb<TD, TI> *__restrict__ probs,
+                                                       const double *__restrict__ part, int ntot,
+                                                       double *__restrict__ out) {
+    const OuterProb<TD, TI> &P = probs[blockIdx.x];
+    constexpr int NV = kResidualValues, U = 4;
+    // value v is a maximum (non-negative: exact in any order) for |delta| and
+    // |theta|, else a sum (fixed order: per thread, then across lanes and
+    // wavefronts)
+    auto is_max = [](int v) { return v == 2 || v == 3; };
+    const int n = nthreads(), np = P.ntiles;
+    const double *base = part + P.tile0;
+    double acc[NV][U];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[v][u] = 0.0;
+    // U x NV independent loads in flight per thread and round
+    int q = tid_lin();
+    for (; q + (U - 1) * n < np; q += U * n) {
+        double x[NV][U];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[v][u] = base[(size_t)v * ntot + q + u * n];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                acc[v][u] = is_max(v) ? fmax(acc[v][u], x[v][u]) : acc[v][u] + x[v][u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool in = q + u * n < np;
+        const int qq = in ? q + u * n : 0;   // in-bounds load, discarded when out
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double x = np > 0 ? base[(size_t)v * ntot + qq] : 0.0;
+            if (in) acc[v][u] = is_max(v) ? fmax(acc[v][u], x) : acc[v][u] + x;
+        }
+    }
+    __shared__ double sh[NV][kReduceOuterWaves];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double a = acc[v][0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) a = is_max(v) ? fmax(a, acc[v][u]) : a + acc[v][u];
+        a = is_max(v) ? wave_max(a) : wave_sum(a);
+        if (threadIdx.x == 0) sh[v][threadIdx.y] = a;
+    }
+    __syncthreads();
+    if (tid_lin() < NV) {
+        const int v = tid_lin();
+        double s = sh[v][0];
+        for (int w = 1; w < (int)blockDim.y; ++w) s = is_max(v) ? fmax(s, sh[v][w]) : s + sh[v][w];
+        out[(size_t)blockIdx.x * NV + v] = s;
+    }
+}
+
 // ----------------------------------------------------- CG: true residual check
 template <typename T, bool PC, int VX, int CS>
 __global__ __launch_bounds__(512) void k_check_b(const InnerProb<T> *__restrict__ probs, int nprob,
@@ -2365,6 +2431,13 @@ void launch_residual_b(const OuterProb<TD, TI> *probs, int nprob, int nb, bool p
                                                             0, s, probs, nprob, part_out)));
 }
 
+template <typename TD, typename TI>
+void launch_reduce_outer(const OuterProb<TD, TI> *probs, int nprob, const double *part, int ntot,
+                         double *out, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_outer<TD, TI>), dim3(nprob), dim3(kWave, kReduceOuterWaves), 0, s, probs, part,
+                       ntot, out);
+}
+
 void launch_csr_fill(const OpView<double> &op, const int *ptr, int *col, double *val,
                      hipStream_t s) {
     const int64_t n = (int64_t)op.nx * op.ny * op.nz;
@@ -2489,6 +2562,10 @@ template void launch_promote_dot<double>(const InnerProb<double> *, int, int, in
 template void launch_reduce_conv<double>(const InnerProb<double> *, int, const double *,
                                          hipStream_t);
 
+template void launch_reduce_outer<float, float>(const OuterProb<float, float> *, int, const double *,
+                                                int, double *, hipStream_t);
+template void launch_reduce_outer<double, double>(const OuterProb<double, double> *, int,
+                                                  const double *, int, double *, hipStream_t);
 template void launch_residual_b<float, float>(const OuterProb<float, float> *, int, int, bool, int,
                                               int, int, double *, hipStream_t);
 template void launch_residual_b<double, double>(const OuterProb<double, double> *, int, int, bool,

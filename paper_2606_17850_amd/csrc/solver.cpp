@@ -350,7 +350,9 @@ int prob_tiles(const Grid &g, const Shape &sh) {
 Status engine_alloc(Engine &E, int cap, int kcap, size_t nb_max) {
     E.cap = cap;
     E.kcap = kcap;
-    E.slot_doubles = std::max<size_t>(8 * std::max<size_t>(nb_max, 1), (size_t)3 * cap);
+    // the reduce slot holds three sums per problem (red_rz, red_pmu, red_rr)
+    // and then the outer residual's totals (outer_totals)
+    E.slot_doubles = std::max<size_t>(8 * std::max<size_t>(nb_max, 1), (size_t)(3 + kResidualValues) * cap);
     const size_t nc = (size_t)cap * (1 + 2 * kcap);
     CUTH_TRY(dev_alloc(&E.in32, cap));
     CUTH_TRY(dev_alloc(&E.in64, cap));
@@ -532,6 +534,9 @@ template <typename T>
 T *red_pmu(Engine &E) { return eslot<T>(E, P_RED) + E.cap; }
 template <typename T>
 T *red_rr(Engine &E) { return eslot<T>(E, P_RED) + 2 * E.cap; }
+// per-problem totals of the outer residual, after the three sums above (in
+// doubles, past them in either precision)
+double *outer_totals(Engine &E) { return eslot<double>(E, P_RED) + 3 * E.cap; }
 
 // z = q(A) r for every problem of the launch; returns the buffer index of z.
 // chk: the first kernel also runs the convergence test on the update's r^T r.
@@ -879,19 +884,14 @@ Status outer_step(Engine &E, std::vector<Problem *> &ps, const Shape &sh64, hipS
     const bool pc = ps[which[0]]->g->per_cell;
     CUTH_HIP(hipMemcpyAsync(d, h, sizeof(OuterProb<TI, TI>) * n, hipMemcpyHostToDevice, s));
     launch_residual_b<TI, TI>(d, n, tile, pc, sh64.vx, sh64.by, flags, eslot<double>(E, P_RES), s);
-    CUTH_HIP(hipMemcpyAsync(E.h_part, eslot<double>(E, P_RES),
-                            sizeof(double) * kResidualValues * (size_t)tile, hipMemcpyDeviceToHost, s));
+    launch_reduce_outer<TI, TI>(d, n, eslot<double>(E, P_RES), tile, outer_totals(E), s);
+    CUTH_HIP(hipMemcpyAsync(E.h_part, outer_totals(E), sizeof(double) * kResidualValues * (size_t)n,
+                            hipMemcpyDeviceToHost, s));
     CUTH_TRY(sync_stream(s));
     for (int m = 0; m < n; ++m) {
         Problem &p = *ps[which[m]];
         double *o = &stats5[(size_t)which[m] * kResidualValues];
-        for (int q = p.tile0; q < p.tile0 + p.ntiles; ++q) {
-            o[0] += E.h_part[q];
-            o[1] += E.h_part[tile + q];
-            o[2] = std::max(o[2], E.h_part[2 * tile + q]);
-            o[3] = std::max(o[3], E.h_part[3 * tile + q]);
-            o[4] += E.h_part[4 * tile + q];
-        }
+        for (int v = 0; v < kResidualValues; ++v) o[v] = E.h_part[(size_t)m * kResidualValues + v];
         const double N = (double)p.g->N;
         p.bytes += ((p.th_in ? 8.0 : 0.0) + (p.have_delta ? (double)sizeof(TI) : 0.0) + 8.0 +
                     (p.Tn ? 8.0 : 0.0) + 8.0 + 2.0 * sizeof(TI) + (p.g->per_cell ? 16.0 : 0.0)) * N;
