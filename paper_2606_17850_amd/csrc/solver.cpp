@@ -258,6 +258,12 @@ struct Problem {
     bool have_delta = false;
     double *th_out = nullptr, *th_final = nullptr;
     double last_red = 1.0, d_prev = 1.0, est = 1.0, prev_relres = INFINITY;
+    // mixed refinement: the previous inner solve's residual reduction, and
+    // the largest measured ratio of error contraction to residual reduction
+    double red_prev = 1.0, lag = 1.0;
+    // mixed refinement: an inner solve has ended on the stagnation test, i.e.
+    // at the FP32 floor of this system
+    bool floor32 = false;
     // the Chebyshev sweeps read the FP16-stored lateral conductances
     bool h16 = false;
     // preconditioner: 0 Chebyshev, 1 Jacobi, 2 none (cuth_options.preconditioner)
@@ -272,7 +278,7 @@ struct Problem {
     bool csr = false;
     // per inner solve
     bool inner = false;
-    double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, true_rr = 0.0;
+    double rr0 = 0.0, tol2 = 0.0, true_prev = -1.0, low_prev = -1.0, true_rr = 0.0;
     int stop = 0;
     // results
     int cycles = 0, cg_iters = 0, reason = 0, drift_stops = 0, stag_stops = 0;
@@ -647,17 +653,21 @@ void enqueue_iterations(Engine &E, int nprob, int nb, bool pc, int cs, int pm, c
 
 // Host-side stop rule of an inner solve at a true-residual check (Section 4.4):
 // dev_done is the device's own stop (1 tolerance, 4 breakdown), tn the norm of
-// the true residual r_true = rhat - A x, dn the norm of r_true - r_low (r_low
-// the recursive residual), prev the true-residual norm of the previous check
-// (< 0 at the first).  Returns 0 to continue, 4 for a non-finite value, 2 for
-// drift (eq. switching c: dn >= 0.5 tn), 3 for stagnation (eq. switching b:
-// tn > 0.9 prev), 5 at the iteration limit.  Without tests (the fixed-FP32
-// baseline) only the device stop, non-finite values and the limit apply.
-int stop_rule(int dev_done, double tn, double dn, double prev, bool tests, bool at_limit) {
+// the true residual r_true = rhat - A x, dn the norm of r_true - r_low, ln the
+// norm of the recursive residual r_low, and prev / lprev the true and recursive
+// norms of the previous check (< 0 at the first).  Returns 0 to continue, 4 for
+// a non-finite value, 2 for drift (eq. switching c: dn >= 0.5 tn), 3 for
+// stagnation (eq. switching b: tn > 0.9 prev while the recursive residual
+// still fell, ln < lprev: a true residual that rises with the recursive one
+// is CG's own non-monotone residual, not stagnation), 5 at the iteration
+// limit.  Without tests (the fixed-FP32 baseline) only the device stop,
+// non-finite values and the limit apply.
+int stop_rule(int dev_done, double tn, double dn, double ln, double prev, double lprev, bool tests,
+              bool at_limit) {
     if (dev_done) return dev_done;
     if (!std::isfinite(tn)) return 4;
     if (tests && dn >= 0.5 * tn) return 2;
-    if (tests && prev >= 0.0 && tn > 0.9 * prev) return 3;
+    if (tests && prev >= 0.0 && tn > 0.9 * prev && ln < lprev) return 3;
     if (at_limit) return 5;
     return 0;
 }
@@ -696,6 +706,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
         st.tol2 = (T)p.tol2;
         st.done = p.rr0 > 0.0 ? 0 : 1;
         p.true_prev = -1.0;
+        p.low_prev = -1.0;
         p.stop = 0;
     }
     CUTH_HIP(hipMemcpyAsync(Sel<T>::ds(E), hs, sizeof(CgState<T>) * nprob, hipMemcpyHostToDevice, s));
@@ -786,7 +797,9 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
             }
             p.true_rr = a;
             const double tn = std::sqrt(a);
-            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), p.true_prev, !p.fixed32, it >= maxit);
+            const double ln = std::sqrt((double)hs[n].rr);
+            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), ln, p.true_prev, p.low_prev,
+                                      !p.fixed32, it >= maxit);
             if (why && !hs[n].done) {
                 // stop this problem on the device too (its launches exit early)
                 hs[n].done = why;
@@ -794,6 +807,7 @@ Status inner_solve(Engine &E, std::vector<Problem *> &ps, const Shape &sh, int k
                                         hipMemcpyHostToDevice, s));
             }
             p.true_prev = tn;
+            p.low_prev = ln;
             if (why) p.stop = why;
             else all_done = false;
         }
@@ -932,20 +946,56 @@ void decide(Problem &p, const double *o, bool mixed, int max_outer) {
         if (mixed) {
             if (cyc >= 1) {
                 const double d = thinf > 0 ? dinf / thinf : (dinf > 0 ? INFINITY : 0.0);
+                // d is about the error before the last correction, and the
+                // ratio of two successive corrections, q = d / d_prev, is the
+                // error contraction of the inner solve before the last one;
+                // against that solve's residual reduction it measures how far
+                // the error lags the residual (lag).  On well-conditioned
+                // stacks the error falls about as fast as the residual; with
+                // condition numbers near 1/u32 the residual falls mainly in
+                // the stiff modes and the error left in the smooth ones far
+                // less (on a 64-layer stack with condition number 3e6 a
+                // 6e3-fold residual cut came with a 20-fold error cut).
                 const double q = d / p.d_prev;
+                if (cyc >= 2) p.lag = std::max(p.lag, q / std::max(p.red_prev, 1e-6));
+                p.red_prev = p.last_red;
                 p.est = q * d;
                 p.err_est = d;
                 p.d_prev = d;
-                // d is about the error before the last correction; that
-                // correction's inner solve cut the residual by last_red, which
-                // leaves an error of about last_red * d, but never less than the
-                // FP32 rounding floor of the inner solve (about 16 ulps, 1e-6:
-                // an FP32 residual can be exactly zero while the correction is
-                // only FP32-accurate).  Stop when this is a tenth of tol, or when
-                // the correction itself is below tol and cut the residual at
-                // least tenfold.
-                const double red_eff = std::max(p.last_red, 1e-6);
-                if (red_eff * d <= 0.1 * p.tol || (d <= p.tol && p.last_red <= 0.1)) {
+                // An inner solve that met its own tolerance cut the error by
+                // about lag times its residual reduction, never below the FP32
+                // rounding floor of the inner solve (about 16 ulps, 1e-6: an
+                // FP32 residual can be exactly zero while the correction is
+                // only FP32-accurate); a margin of 10 covers lags up to 10.
+                // One stopped by the drift test (or the iteration limit) says
+                // little about the error through its residual: its contraction
+                // is taken as the last measured one, q, which needs two
+                // corrections after the first solve, and the remaining error
+                // as the geometric tail q / (1 - q) d.  Stop when the estimate
+                // is a tenth of tol (or tol over the lag), or when the
+                // correction itself is below tol and the inner solve cut the
+                // error at least tenfold.
+                //
+                // Once an inner solve has ended on the stagnation test, the
+                // FP32 system cannot resolve the error further in that solve
+                // (condition number times the FP32 unit roundoff near 1): the
+                // cycles then differ widely in what they achieve (one cut the
+                // error 60-fold, the next not at all), so no contraction is
+                // extrapolated; every later inner solve runs to the floor
+                // (tau 1e-5) and the refinement stops when the correction
+                // itself is a tenth of tol.
+                if (p.reason == 3) p.floor32 = true;
+                const double margin = std::max(p.lag, 10.0);
+                bool done;
+                if (p.floor32)
+                    done = d <= 0.1 * p.tol;
+                else if (p.reason == 1)
+                    done = margin * std::max(p.last_red, 1e-6) * d <= p.tol ||
+                           (d <= p.tol && margin * p.last_red <= 1.0);
+                else
+                    done = (cyc >= 3 && q < 1.0 && 10.0 * q / (1.0 - q) * d <= p.tol) ||
+                           (d <= p.tol && margin * p.last_red <= 1.0);
+                if (done) {
                     p.finished = true;
                     return;
                 }
@@ -978,7 +1028,12 @@ void decide(Problem &p, const double *o, bool mixed, int max_outer) {
     }
     p.inner = true;
     if (mixed) {
-        const double tau = cyc == 0 ? 1e-5 : std::min(0.1, std::max(1e-5, 0.1 * p.tol / p.est));
+        // the inner tolerance that would bring the estimated error to a tenth
+        // of tol, tightened by a lag beyond the margin
+        const double tau =
+            cyc == 0 || p.floor32
+                ? 1e-5
+                : std::min(0.1, std::max(1e-5, 0.1 * p.tol / (p.est * std::max(1.0, 0.1 * p.lag))));
         p.rr0 = (double)(float)rr;
         p.tol2 = tau * tau * p.rr0;
     } else {
@@ -1002,9 +1057,13 @@ Status run_refinement(Engine &E, std::vector<Problem *> &ps, const Shape &sh_in,
             Problem &p = *ps[i];
             if (p.finished) continue;
             decide(p, &st5[i * kResidualValues], mixed, o.max_outer);
-            if (log_on() && p.inner)
-                std::fprintf(stderr, "cuth: problem %zu cycle %d relres %.3e last reduction %.3e est %.3e\n",
-                             i, p.cycles, p.relres, p.last_red, p.est);
+            if (log_on())
+                std::fprintf(stderr,
+                             "cuth: problem %zu cycle %d relres %.3e last reduction %.3e est %.3e "
+                             "correction %.3e inner stop %d lag %.2f%s%s\n",
+                             i, p.cycles, p.relres, p.last_red, p.est, p.err_est, p.reason, p.lag,
+                             p.floor32 ? " floor" : "",
+                             p.inner ? "" : " -> done");
             any = any || p.inner;
         }
         if (!any) break;
@@ -1077,6 +1136,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
         hs[n].done = p.rr0 > 0.0 ? 0 : 1;
         hs32[n].done = hs[n].done;
         p.true_prev = -1.0;
+        p.low_prev = -1.0;
         p.stop = 0;
     }
     CUTH_HIP(hipMemcpyAsync(E.st64, hs, sizeof(CgState<double>) * nprob, hipMemcpyHostToDevice, s));
@@ -1122,7 +1182,9 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
             }
             p.true_rr = a;
             const double tn = std::sqrt(a);
-            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), p.true_prev, true, it >= maxit);
+            const double ln = std::sqrt(hs[n].rr);
+            const int why = stop_rule(hs[n].done, tn, std::sqrt(b), ln, p.true_prev, p.low_prev, true,
+                                      it >= maxit);
             if (why && !hs[n].done) {
                 hs[n].done = why;
                 CUTH_HIP(hipMemcpyAsync(&E.st64[n].done, &hs[n].done, sizeof(int),
@@ -1131,6 +1193,7 @@ Status inner_solve_staged(Engine &E, std::vector<Problem *> &ps, const Shape &sh
                                         hipMemcpyHostToDevice, s));
             }
             p.true_prev = tn;
+            p.low_prev = ln;
             if (why) p.stop = why;
             else all_done = false;
         }

@@ -989,11 +989,13 @@ def test_inner_stop_on_drift():
 def test_inner_stop_on_stagnation(prec):
     """Eq. switching (b), stagnation: plain CG (no preconditioner) with the true
     residual checked after every iteration.  On this stack plain CG's residual
-    norm does not fall by a tenth from one iteration to the next (it first
-    rises several-fold), so every inner solve ends at its second check on
-    ||r_true|| > 0.9 ||r_true^prev||, and the refinement gives up
-    (NOT_CONVERGED).  The best iterate is returned: the relative residual the
-    call reports is that of the returned T, recomputed by the oracle."""
+    often falls by less than a tenth from one iteration to the next while the
+    recursive residual still falls, so every inner solve ends on
+    ||r_true|| > 0.9 ||r_true^prev|| with ||r_low|| < ||r_low^prev||, no
+    earlier than the second check (the first with a previous one), and the
+    refinement gives up (NOT_CONVERGED).  The best iterate is returned: the
+    relative residual the call reports is that of the returned T, recomputed
+    by the oracle."""
     import paper_2606_17850_amd as cuth
     say(f"stop rule: stagnation {prec}")
     st, P = w.config0()
@@ -1008,7 +1010,7 @@ def test_inner_stop_on_stagnation(prec):
     assert s["stop_reason"] == 3
     assert s["stagnation_stops"] == s["outer_cycles"] >= 1
     assert s["drift_stops"] == 0
-    assert s["cg_iters"] == 2 * s["outer_cycles"]
+    assert s["cg_iters"] >= 2 * s["outer_cycles"]
     th = T.cpu().numpy() - st.t_amb
     b = P.ravel()
     relres = np.linalg.norm(b - A @ th) / np.linalg.norm(b)
@@ -1147,4 +1149,61 @@ def test_set_conductivity_rejections():
     g.set_conductivity(st.k_lat, st.k_vert,
                        k_lat_mult=t64(np.ascontiguousarray(st.k_lat_mult, dtype=np.float64).ravel()))
     assert torch.equal(g.apply(x), y0)
+    g.close()
+
+
+def test_max_layer_count(monkeypatch):
+    """64 layers, the descriptor's limit (the adjoint's per-layer sums fill
+    their arrays): steady mixed and FP64 solves against the direct oracle, the
+    same with fused pairs and triples forced, a backward-Euler step, and the
+    adjoint's dL/dP and per-layer dL/dk against the oracle gradient.
+
+    With the heat sink on top only, 64 layers in series give a condition
+    number near 3e6, so condition number times the FP32 unit roundoff is about
+    0.2 and the error of an FP32 inner solve can lag its residual by orders of
+    magnitude; CG's residual also rises for stretches here, which the
+    stagnation test must not take for stagnation.  The mixed solves (fixed and
+    automatic Chebyshev degree) must still meet the 1e-8 bar, and the FP64
+    adjoint its default tolerance."""
+    import paper_2606_17850_amd as cuth
+    from oracle import adjoint as oadj
+    layers = (["Si", "BEOL", "bond", "TIM"] * 16)[:63] + ["Cu"]
+    st = ragged_stack(20, 12, layers=layers, mult=True, seed=31)
+    assert st.nz == 64
+    rng = np.random.default_rng(32)
+    P = np.zeros(st.shape)
+    for l, name in enumerate(layers):
+        if name == "Si":
+            P[l] = rng.uniform(0, 2e-5, (st.ny, st.nx))
+    A = assembly.assemble(st)
+    th_ref = direct.solve_splu(A, P.ravel())
+    g = grid_of(st)
+    for prec, kw in (("mixed", {}), ("mixed", {"cheb_degree": "auto"}), ("fp64", {})):
+        T, s = g.solve(t64(P), precision=prec, **kw)
+        err = rise_err(T.cpu().numpy(), st.t_amb + th_ref, st.t_amb)
+        say(f"64 layers {prec} {kw} err {err:.2e} cycles {s['outer_cycles']} "
+            f"stagnation stops {s['stagnation_stops']}")
+        assert err <= 1e-8
+    monkeypatch.setenv("CUTH_FUSE", "1")
+    monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
+    monkeypatch.setenv("CUTH_FUSE3", "1")
+    monkeypatch.setenv("CUTH_FUSE3_SHAPE", "2,8")
+    Tf, _ = g.solve(t64(P), precision="mixed")
+    assert rise_err(Tf.cpu().numpy(), st.t_amb + th_ref, st.t_amb) <= 1e-8
+    for k in ("CUTH_FUSE", "CUTH_FUSE_SHAPE", "CUTH_FUSE3", "CUTH_FUSE3_SHAPE"):
+        monkeypatch.delenv(k)
+    dt = 1e-4
+    th0 = rng.uniform(0, 5.0, st.n)
+    ref_tr = transient.step(st, P.ravel(), th0, dt)
+    Tt, _ = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision="mixed")
+    assert np.abs(Tt.cpu().numpy() - st.t_amb - ref_tr).max() <= 1e-8 * np.abs(ref_tr).max()
+    T, _ = g.solve(t64(P), precision="fp64")
+    Tn = T.cpu().numpy()
+    gT = oadj.lse_grad(Tn, st.si_mask(), 0.5)
+    dP, dk, _ = g.adjoint(T, t64(gT), precision="fp64")
+    ref = oadj.gradient(st, Tn - st.t_amb, gT, direct.solve_splu)
+    assert np.abs(dP.cpu().numpy() - ref.dP).max() <= 1e-6 * np.abs(ref.dP).max()
+    assert dk.shape == (64,)
+    np.testing.assert_allclose(dk.cpu().numpy(), ref.dk_layer, rtol=1e-6,
+                               atol=1e-9 * np.abs(ref.dk_layer).max())
     g.close()
