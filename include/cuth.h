@@ -202,7 +202,7 @@ typedef struct {
                                     eq. switching c: ||r_true - r_low|| >= 0.5 ||r_true||) */
     int32_t stagnation_stops;    /* inner solves stopped by the stagnation test (eq.
                                     switching b: ||r_true|| > 0.9 ||r_true|| of the
-                                    previous check)                                    */
+                                    previous check while ||r_low|| fell since it)     */
     double rel_residual;         /* final ||b - A theta||_2 / ||b||_2 (FP64)           */
     double err_est;              /* mixed: last correction ||delta||_inf/||theta||_inf */
     double setup_ms;             /* coefficient/Lanczos setup inside this call         */

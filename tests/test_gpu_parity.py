@@ -1178,12 +1178,22 @@ def test_max_layer_count(monkeypatch):
     A = assembly.assemble(st)
     th_ref = direct.solve_splu(A, P.ravel())
     g = grid_of(st)
-    for prec, kw in (("mixed", {}), ("mixed", {"cheb_degree": "auto"}), ("fp64", {})):
+    for prec, kw, bar in (("mixed", {}, 1e-8), ("mixed", {"cheb_degree": "auto"}, 1e-8),
+                          ("mixed16", {}, 1e-8), ("fp64", {}, 1e-10), ("adaptive", {}, 1e-10)):
         T, s = g.solve(t64(P), precision=prec, **kw)
         err = rise_err(T.cpu().numpy(), st.t_amb + th_ref, st.t_amb)
         say(f"64 layers {prec} {kw} err {err:.2e} cycles {s['outer_cycles']} "
             f"stagnation stops {s['stagnation_stops']}")
-        assert err <= 1e-8
+        assert err <= bar
+    # batched with a 5-layer stack: each system keeps its own stop decisions
+    st5 = ragged_stack(70, 9, mult=True)
+    P5 = np.zeros(st5.shape)
+    P5[0] = 1e-5
+    g5 = grid_of(st5)
+    Tb, _ = cuth.solve_batch([g, g5], [t64(P), t64(P5)], nrhs=1, precision="mixed")
+    assert rise_err(Tb[0].cpu().numpy(), st.t_amb + th_ref, st.t_amb) <= 1e-8
+    assert rise_err(Tb[1].cpu().numpy(), _ref_steady(st5, P5), st5.t_amb) <= 1e-8
+    g5.close()
     monkeypatch.setenv("CUTH_FUSE", "1")
     monkeypatch.setenv("CUTH_FUSE_SHAPE", "2,8")
     monkeypatch.setenv("CUTH_FUSE3", "1")
