@@ -172,7 +172,11 @@ typedef struct {
                                     relative error of the rise T - T_amb (inf-norm),
                                     default 1e-8.  CUTH_FP64, CUTH_ADAPTIVE: relative
                                     residual ||b - A T|| / ||b||, default 1e-10 for
-                                    steady and 1e-12 for transient solves.            */
+                                    steady and 1e-12 for transient solves; a
+                                    transient solve at the default whose residual
+                                    stops falling between the two ends without
+                                    error (a stiff step, large dt, can have an
+                                    FP64 floor above 1e-12).                          */
     int32_t cheb_degree;         /* Chebyshev degree k, 1..256 (default 30), or
                                     CUTH_DEGREE_AUTO: the smallest k >= 2 with
                                     2 s^k <= 0.3, s = (sqrt(c) - 1)/(sqrt(c) + 1),
