@@ -1223,3 +1223,52 @@ def test_max_layer_count(monkeypatch):
     np.testing.assert_allclose(dk.cpu().numpy(), ref.dk_layer, rtol=1e-6,
                                atol=1e-9 * np.abs(ref.dk_layer).max())
     g.close()
+
+
+def _extreme_stack(name):
+    """Stacks at the edges of the solver's range (condition numbers from the
+    oracle's sparse eigensolver in the comments)."""
+    eight = ["Si", "BEOL", "bond", "Si", "BEOL", "bond", "TIM", "Cu"]
+    if name == "column64":        # one column of 64 layers (1.3e4)
+        return ragged_stack(1, 1, layers=(["Si", "BEOL", "bond", "TIM"] * 16)[:63] + ["Cu"], mult=False)
+    if name == "bottom_sink":     # the heat leaves through the bottom only (5.6e4)
+        st = ragged_stack(70, 9, mult=True)
+        st.h_top, st.h_bottom = 0.0, 1e4
+        return st
+    if name == "both_sinks":      # both faces cooled (4.7e4)
+        st = ragged_stack(70, 9, mult=True)
+        st.h_bottom = 1e3
+        return st
+    st = ragged_stack(40, 24, layers=eight, mult=True)
+    if name == "contrast":        # lognormal lateral multipliers, sigma 2 (4.5e6)
+        st.k_lat_mult = np.exp(2.0 * np.random.default_rng(5).standard_normal(st.shape))
+    elif name == "weak_layer":    # a TIM layer of 0.01 W/(m K) (2.5e6)
+        st.k_vert = np.array(st.k_vert, float)
+        st.k_lat = np.array(st.k_lat, float)
+        st.k_vert[6] = st.k_lat[6] = 0.01
+    elif name == "thin_layers":   # layers from 1 um to 1 mm thick (1.3e6)
+        st.dz = np.array([5e-5, 2e-6, 1e-6, 5e-5, 2e-6, 1e-6, 2e-5, 1e-3])
+    return st
+
+
+@pytest.mark.parametrize("name", ["column64", "bottom_sink", "both_sinks", "contrast",
+                                  "weak_layer", "thin_layers"])
+def test_extreme_stacks(name):
+    """Steady solves in every precision against the direct oracle on stacks
+    with one cooled face or two, extreme conductivity contrast, a near-
+    insulating layer and a thousandfold spread of layer thicknesses: the mixed
+    modes to 1e-8 and the FP64 ones to 1e-10 rise error."""
+    st = _extreme_stack(name)
+    rng = np.random.default_rng(3)
+    P = np.zeros(st.shape)
+    for l, m in enumerate(st.layers):
+        if m == "Si":
+            P[l] = rng.uniform(0, 2e-5, (st.ny, st.nx))
+    ref = _ref_steady(st, P)
+    g = grid_of(st)
+    for prec, bar in (("mixed", 1e-8), ("mixed16", 1e-8), ("fp64", 1e-10), ("adaptive", 1e-10)):
+        T, s = g.solve(t64(P), precision=prec)
+        err = rise_err(T.cpu().numpy(), ref, st.t_amb)
+        say(f"  {name} {prec} err {err:.2e} cycles {s['outer_cycles']} cg {s['cg_iters']}")
+        assert err <= bar
+    g.close()
