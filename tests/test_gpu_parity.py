@@ -1257,7 +1257,10 @@ def test_extreme_stacks(name):
     """Steady solves in every precision against the direct oracle on stacks
     with one cooled face or two, extreme conductivity contrast, a near-
     insulating layer and a thousandfold spread of layer thicknesses: the mixed
-    modes to 1e-8 and the FP64 ones to 1e-10 rise error."""
+    modes to 1e-8 and the FP64 ones to 1e-10 rise error.  Then the adjoint
+    (mixed and FP64) against the oracle gradient of the log-sum-exp of the
+    silicon temperatures, to the bars of the small adjoint test."""
+    from oracle import adjoint as oadj
     st = _extreme_stack(name)
     rng = np.random.default_rng(3)
     P = np.zeros(st.shape)
@@ -1271,4 +1274,14 @@ def test_extreme_stacks(name):
         err = rise_err(T.cpu().numpy(), ref, st.t_amb)
         say(f"  {name} {prec} err {err:.2e} cycles {s['outer_cycles']} cg {s['cg_iters']}")
         assert err <= bar
+    Tn = ref                       # the adjoint linearises at the exact state
+    gT = oadj.lse_grad(Tn, st.si_mask(), 0.5)
+    gref = oadj.gradient(st, Tn - st.t_amb, gT, direct.solve_splu)
+    for prec in ("mixed", "fp64"):
+        dP, dk, _ = g.adjoint(t64(Tn), t64(gT), precision=prec)
+        eP = np.abs(dP.cpu().numpy() - gref.dP).max() / np.abs(gref.dP).max()
+        say(f"  {name} adjoint {prec} dP err {eP:.2e}")
+        assert eP <= 1e-6
+        np.testing.assert_allclose(dk.cpu().numpy(), gref.dk_layer, rtol=1e-6,
+                                   atol=1e-9 * np.abs(gref.dk_layer).max())
     g.close()
