@@ -1285,3 +1285,31 @@ def test_extreme_stacks(name):
         np.testing.assert_allclose(dk.cpu().numpy(), gref.dk_layer, rtol=1e-6,
                                    atol=1e-9 * np.abs(gref.dk_layer).max())
     g.close()
+
+
+def test_extreme_stacks_batched():
+    """All six edge stacks in one batched call (a matrix-free group and a
+    per-cell group), mixed and FP64: each problem keeps its own spectral
+    interval, inner tolerance and stop decisions, and meets the single-solve
+    bars against the direct oracle."""
+    import paper_2606_17850_amd as cuth
+    names = ["column64", "bottom_sink", "both_sinks", "contrast", "weak_layer", "thin_layers"]
+    stacks = [_extreme_stack(n) for n in names]
+    rng = np.random.default_rng(4)
+    Ps, refs = [], []
+    for st in stacks:
+        P = np.zeros(st.shape)
+        for l, m in enumerate(st.layers):
+            if m == "Si":
+                P[l] = rng.uniform(0, 2e-5, (st.ny, st.nx))
+        Ps.append(P)
+        refs.append(_ref_steady(st, P))
+    grids = [grid_of(st) for st in stacks]
+    for prec, bar in (("mixed", 1e-8), ("fp64", 1e-10)):
+        T, stats = cuth.solve_batch(grids, [t64(P) for P in Ps], nrhs=1, precision=prec)
+        for name, st, t, ref, s in zip(names, stacks, T, refs, stats):
+            err = rise_err(t.cpu().numpy(), ref, st.t_amb)
+            say(f"  batched {name} {prec} err {err:.2e} cycles {s['outer_cycles']} cg {s['cg_iters']}")
+            assert err <= bar
+    for g in grids:
+        g.close()
