@@ -644,3 +644,68 @@ def test_jacobi_chebyshev_pcg(c0):
     ref = direct.solve_separable(st, b)
     assert np.abs(xj - ref).max() <= 1e-8 * np.abs(ref).max()
     assert kj < kc
+
+
+def _two_sided_column(dz, kv, dxdy, h_top, h_bot, l, q):
+    """Rise of a laterally uniform column cooled on both faces, heated by q per
+    cell in layer l only: a resistor chain whose two ends lead to ambient.
+    The heat splits between the two paths in inverse proportion to their
+    resistances; along each path the rise falls with the resistance left."""
+    nz = len(dz)
+    link = [(dz[m] / 2.0) / (kv[m] * dxdy) + (dz[m + 1] / 2.0) / (kv[m + 1] * dxdy)
+            for m in range(nz - 1)]
+    # resistance from layer m to ambient through the top and through the bottom
+    up = [sum(link[m:]) + 1.0 / (h_top * dxdy) for m in range(nz)]
+    dn = [sum(link[:m]) + 1.0 / (h_bot * dxdy) for m in range(nz)]
+    th_l = q * up[l] * dn[l] / (up[l] + dn[l])
+    q_up, q_dn = th_l / up[l], th_l / dn[l]
+    th = np.array([q_up * up[m] if m >= l else q_dn * dn[m] for m in range(nz)])
+    return th, q_up, q_dn
+
+
+@pytest.mark.parametrize("l", [0, 2, 5])
+def test_two_sided_cooling_closed_form(l):
+    """Both faces cooled (the bottom convection term, which no hand example
+    exercises): the solve matches the two-path resistor network, and the heat
+    leaving each face is the network's split of the injected power."""
+    layers = ["Si", "BEOL", "bond", "Si", "TIM", "Cu"]
+    st = w.uniform_stack(4, 3, layers)
+    st.dz = np.array([60e-6, 8e-6, 3e-6, 90e-6, 40e-6, 500e-6])
+    st.h_top, st.h_bottom = 2e4, 3e3
+    q = 1.5e-3
+    P = np.zeros(st.shape)
+    P[l] = q
+    th = direct.solve_dense(assembly.assemble(st), P.ravel()).reshape(st.shape)
+    dxdy = st.dx * st.dy
+    exp, q_up, q_dn = _two_sided_column(st.dz, st.k_vert, dxdy, st.h_top, st.h_bottom, l, q)
+    np.testing.assert_allclose(th, np.broadcast_to(exp[:, None, None], st.shape), rtol=1e-12)
+    cells = st.nx * st.ny
+    out_top = math.fsum((st.h_top * dxdy * th[-1]).ravel())
+    out_bot = math.fsum((st.h_bottom * dxdy * th[0]).ravel())
+    assert out_top == pytest.approx(cells * q_up, rel=1e-12)
+    assert out_bot == pytest.approx(cells * q_dn, rel=1e-12)
+    assert out_top + out_bot == pytest.approx(cells * q, rel=1e-12)
+
+
+def test_single_layer_both_faces():
+    """One layer cooled on both faces: the two convective conductances act on
+    the same cells, so the rise is q / ((h_top + h_bottom) dx dy)."""
+    st = w.uniform_stack(3, 2, ["Si"])
+    st.h_top, st.h_bottom = 1e4, 2.5e3
+    q = 2e-3
+    th = direct.solve_dense(assembly.assemble(st), np.full(st.n, q))
+    np.testing.assert_allclose(th, q / ((st.h_top + st.h_bottom) * st.dx * st.dy), rtol=1e-13)
+
+
+def test_separable_two_sided_matches_lu():
+    """The separable solver and eigenvalues with both faces cooled (its own
+    sink term) against the assembled matrix: LU solve and dense spectrum."""
+    st = w.uniform_stack(6, 5, ["Si", "BEOL", "bond", "TIM", "Cu"])
+    st.h_top, st.h_bottom = 1e4, 4e3
+    A = assembly.assemble(st)
+    b = np.random.default_rng(9).uniform(0, 1e-3, st.n)
+    x_lu = direct.solve_splu(A, b)
+    x_sep = direct.solve_separable(st, b)
+    assert np.abs(x_sep - x_lu).max() <= 1e-12 * np.abs(x_lu).max()
+    ev = np.linalg.eigvalsh(A.toarray())
+    np.testing.assert_allclose(direct.all_eigenvalues(st), ev, rtol=1e-10, atol=1e-12 * ev[-1])
