@@ -1208,7 +1208,7 @@ def test_max_layer_count(monkeypatch):
     th0 = rng.uniform(0, 5.0, st.n)
     for dt in (1e-4, 1.0, 100.0):
         ref_tr = transient.step(st, P.ravel(), th0, dt)
-        for prec, bar in (("mixed", 1e-8), ("fp64", 1e-10), ("adaptive", 1e-10)):
+        for prec, bar in (("mixed", 1e-8), ("mixed16", 1e-8), ("fp64", 1e-10), ("adaptive", 1e-10)):
             Tt, s = g.transient_step(dt, t64(P), t64(st.t_amb + th0), precision=prec)
             err = np.abs(Tt.cpu().numpy() - st.t_amb - ref_tr).max() / np.abs(ref_tr).max()
             say(f"64 layers dt {dt:g} {prec} err {err:.2e} relres {s['rel_residual']:.1e}")
