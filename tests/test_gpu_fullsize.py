@@ -14,6 +14,8 @@
 * batch: uneven stacks with several right-hand sides against the oracle and against
   single-system solves; and the whole 64-stack x 4-map workload (config 3) in one
   batched solve, all 256 results against the exact separable oracle.
+* a grid past 2^31 cells: stencil products and a Chebyshev application sampled at
+  its boundaries and beyond index 2^31, each sample from the oracle on a patch.
 """
 
 import json
@@ -360,3 +362,97 @@ def test_autograd_function_matches_oracle(mode):
         k = k * np.exp(np.clip(-0.2 * np.sign(ref.dk_layer), -0.2, 0.2))
     if mode == "grid":
         grid.close()
+
+
+def _int_field(l, i, j):
+    """Integer test values in [-8, 8], exact in FP32 and FP64 on both sides.
+    Quadratic in i and j: on a field linear in them the terms a truncated
+    patch drops cancel in pairs, so a patch too small would go unnoticed."""
+    return ((7 * i * i + 3 * j * j + i * j + 5 * l) % 17 - 8).astype(np.float64)
+
+
+@pytest.mark.timeout(600)
+def test_past_2_31_cells():
+    """A 23172 x 23170 x 4 grid (2,147,580,960 cells, past 2^31), the grid and
+    its work vectors about 105 GB of HBM: the FP64 and FP32 stencil products
+    and an FP32 Chebyshev application of degree 3, sampled at cells on every
+    boundary and at the cells beyond index 2^31 (the last rows of the top
+    layer).  On a per-layer-uniform stack a cell's row of A, and the degree-3
+    polynomial's value at a cell, depend only on the cells within 1 and 2 steps,
+    so the oracle computes each sample on a small patch with the same layers
+    (clipped where the grid ends, so that the patch has the same boundaries)."""
+    from oracle import krylov
+    layers = ["Si", "BEOL", "TIM", "Cu"]
+    nx, ny = 23172, 23170
+    st = w.uniform_stack(nx, ny, layers)
+    N = st.n
+    assert N > 2 ** 31
+    say(f"past 2^31: {nx}x{ny}x{len(layers)} = {N} cells")
+    torch.cuda.empty_cache()      # memory cached by earlier tests of the process
+    g = grid_of(st)
+    xd = torch.empty(N, dtype=torch.float64, device=dev())
+    xv = xd.view(st.nz, ny, nx)
+    ii = torch.arange(nx, device=dev(), dtype=torch.int64)
+    jj = torch.arange(ny, device=dev(), dtype=torch.int64)
+    for l in range(st.nz):
+        xv[l] = ((7 * ii[None, :] ** 2 + 3 * jj[:, None] ** 2 + ii[None, :] * jj[:, None] + 5 * l)
+                 % 17 - 8).to(torch.float64)
+    del ii, jj
+    # samples: the eight corners, edge midpoints, the rows past 2^31, random cells
+    rng = np.random.default_rng(21)
+    pts = [(i, j, l) for i in (0, nx - 1) for j in (0, ny - 1) for l in (0, st.nz - 1)]
+    pts += [(nx // 2, 0, 1), (nx // 2, ny - 1, 2), (0, ny // 2, 1), (nx - 1, ny // 2, 2)]
+    first_big = (2 ** 31 - (st.nz - 1) * nx * ny) // nx      # first row holding cells past 2^31
+    pts += [(int(i), int(j), st.nz - 1) for i, j in zip(rng.integers(0, nx, 8),
+                                                          rng.integers(first_big, ny, 8))]
+    pts += [(int(i), int(j), int(l)) for i, j, l in zip(rng.integers(0, nx, 8), rng.integers(0, ny, 8),
+                                                          rng.integers(0, st.nz, 8))]
+    assert any(l * nx * ny + j * nx + i >= 2 ** 31 for i, j, l in pts)
+    idx = torch.tensor([l * nx * ny + j * nx + i for i, j, l in pts], device=dev())
+
+    def patch(i, j, rad):
+        i0, i1 = max(0, i - rad), min(nx - 1, i + rad)
+        j0, j1 = max(0, j - rad), min(ny - 1, j + rad)
+        ps = w.uniform_stack(i1 - i0 + 1, j1 - j0 + 1, layers)
+        I, J = np.meshgrid(np.arange(i0, i1 + 1), np.arange(j0, j1 + 1))
+        xp = np.stack([_int_field(l, I, J) for l in range(st.nz)]).ravel()
+        return ps, xp, (i - i0, j - j0)
+
+    def centre(ps, c, l):
+        return l * ps.nx * ps.ny + c[1] * ps.nx + c[0]
+
+    y64 = g.apply(xd)[idx].cpu().numpy()
+    x32 = xd.float()
+    del xd
+    torch.cuda.empty_cache()
+    y32 = g.apply(x32)[idx].double().cpu().numpy()
+    # an interval near this operator's spectrum (Gershgorin: 1.65e-3), where
+    # the cells two steps away weigh in the polynomial's value
+    lmin, lmax = 1e-5, 1.7e-3
+    z32 = g.precond_apply(x32, lmin, lmax, 3)[idx].double().cpu().numpy()
+    del x32
+    torch.cuda.empty_cache()
+    for s, (i, j, l) in enumerate(pts):
+        ps, xp, c = patch(i, j, 1)
+        A = assembly.assemble(ps)
+        k = centre(ps, c, l)
+        ref = float((A[k] @ xp)[0])
+        scale = float(abs(A[k]).dot(np.abs(xp))[0])
+        assert abs(y64[s] - ref) <= 1e-13 * scale, (i, j, l)
+        assert abs(y32[s] - ref) <= 4e-6 * scale, (i, j, l)
+        ps, xp, c = patch(i, j, 2)
+        A = assembly.assemble(ps)
+        zref = krylov.chebyshev_precondition(lambda v: A @ v, xp, lmin, lmax, 3)
+        # FP32 bar: 16 times the oracle's own FP32 spread over the patch's
+        # cells of this layer (the layers' values differ by orders of
+        # magnitude), at least one FP32 unit of their largest value
+        A32 = A.astype(np.float32)
+        z32ref = krylov.chebyshev_precondition(lambda v: A32 @ v, xp.astype(np.float32), lmin, lmax, 3,
+                                               dtype=np.float32)
+        lay = slice(l * ps.nx * ps.ny, (l + 1) * ps.nx * ps.ny)
+        bar = 16.0 * max(float(np.abs(z32ref[lay] - zref[lay]).max()),
+                         2.0 ** -24 * float(np.abs(zref[lay]).max()))
+        k = centre(ps, c, l)
+        assert abs(z32[s] - zref[k]) <= bar, (i, j, l)
+    say(f"  {len(pts)} sampled cells match (largest index {int(idx.max())})")
+    g.close()
